@@ -1,0 +1,253 @@
+"""CPU oracle for IDR(s)stab(l) / M(s)stab(l) (FP64).
+
+TEST INFRASTRUCTURE ONLY: the tests, the smoke check and the CPU-baseline leg
+of the benchmark may import this package; the HIP library and its binding
+never do.  The arithmetic lives in ``oracle.c`` (plain sequential C, compiled
+without FMA contraction) and, for the learned initial guess, in ``cnn.py``
+(NumPy FP64).  Nothing here shares code with the GPU path.
+
+Functions follow the paper (Neuenhofen, arXiv 1604.06043):
+
+* :func:`solve` -- Algorithm 1 (IDR(s)stab(l)) with the recycling protocol of
+  Section 4.2 (M(s)stab(l): pass P, U, V of a former solve as inputs) and the
+  fetching of U, V at a cycle end (Section 5, preliminaries);
+* :func:`bicgstab` -- textbook BiCGStab, which the IDR cycle of Section 2.3
+  reproduces for s = l = 1;
+* :func:`assemble_convdiff`, :func:`spmv` -- the upwind finite-difference
+  matrices of the synthetic workloads and the plain CSR product.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+OK, NOT_CONVERGED, E_INVALID, E_NOMEM, E_BREAKDOWN, E_NONFINITE = 0, 1, -1, -3, -4, -5
+MSTAB, IDRSTAB = 0, 1
+FETCH_THRESHOLD, FETCH_AT_LEVEL, FETCH_AT_END, FETCH_ONCE, FETCH_NEVER = 0, 1, 2, 3, 4
+
+
+def build(force: bool = True) -> str:
+    """Compile oracle.c into liboracle.so (plain gcc, no FMA contraction)."""
+    src = os.path.join(_HERE, "oracle.c")
+    if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(src):
+        tmp = _SO + ".tmp"
+        subprocess.run(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
+                        "-std=c11", "-Wall", "-o", tmp, src, "-lm"], check=True)
+        os.replace(tmp, _SO)
+    return _SO
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_SO):
+            build(force=False)
+        _lib = ctypes.CDLL(_SO)
+        P = ctypes.c_void_p
+        i64, i32, f64 = ctypes.c_int64, ctypes.c_int, ctypes.c_double
+        _lib.orc_convdiff_nnz.restype = i64
+        _lib.orc_convdiff_nnz.argtypes = [i32, i64]
+        _lib.orc_assemble_convdiff.restype = None
+        _lib.orc_assemble_convdiff.argtypes = [i32, i64, P, f64, P, P, P, P]
+        _lib.orc_spmv.restype = None
+        _lib.orc_spmv.argtypes = [i64, P, P, P, P, P]
+        _lib.orc_solve.restype = i32
+        _lib.orc_solve.argtypes = [i64, P, P, P, i32, i32, P, f64, i64, i32, i32, f64, i64, i32,
+                                   P, P, P, P, P, P, P, P, P, P, i64, P, i64, P]
+        _lib.orc_bicgstab.restype = i32
+        _lib.orc_bicgstab.argtypes = [i64, P, P, P, P, P, P, i32]
+    return _lib
+
+
+def _ptr(a: np.ndarray | None):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+@dataclass
+class CSR:
+    row_ptr: np.ndarray
+    col: np.ndarray
+    val: np.ndarray
+
+    @property
+    def n(self) -> int:
+        return self.row_ptr.shape[0] - 1
+
+    @property
+    def nnz(self) -> int:
+        return int(self.row_ptr[-1])
+
+    def dense(self) -> np.ndarray:
+        D = np.zeros((self.n, self.n))
+        for i in range(self.n):
+            for k in range(self.row_ptr[i], self.row_ptr[i + 1]):
+                D[i, self.col[k]] += self.val[k]
+        return D
+
+    def scipy(self):
+        import scipy.sparse as sp
+        return sp.csr_matrix((self.val, self.col, self.row_ptr), shape=(self.n, self.n))
+
+
+def assemble_convdiff(dim: int, n: int, beta, inv_dt: float, kappa=None) -> CSR:
+    lib = _load()
+    N = n ** dim
+    nnz = int(lib.orc_convdiff_nnz(dim, n))
+    rp = np.zeros(N + 1, dtype=np.int32)
+    ci = np.zeros(nnz, dtype=np.int32)
+    va = np.zeros(nnz, dtype=np.float64)
+    b3 = np.zeros(3)
+    b3[:dim] = np.asarray(beta, dtype=np.float64)[:dim]
+    kap = None if kappa is None else np.ascontiguousarray(kappa, dtype=np.float64)
+    lib.orc_assemble_convdiff(dim, n, _ptr(b3), float(inv_dt), _ptr(kap), _ptr(rp), _ptr(ci), _ptr(va))
+    return CSR(rp, ci, va)
+
+
+def spmv(A: CSR, x: np.ndarray) -> np.ndarray:
+    lib = _load()
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    y = np.empty(A.n)
+    lib.orc_spmv(A.n, _ptr(A.row_ptr), _ptr(A.col), _ptr(A.val), _ptr(x), _ptr(y))
+    return y
+
+
+@dataclass
+class Recycle:
+    """Recycled data of M(s)stab: U, V (n x s, column-major) and their level."""
+    U: np.ndarray
+    V: np.ndarray
+    level: int = 0
+    have: bool = False
+
+    @staticmethod
+    def empty(n: int, s: int) -> "Recycle":
+        return Recycle(np.zeros((n, s), order="F"), np.zeros((n, s), order="F"), 0, False)
+
+    def copy(self) -> "Recycle":
+        return Recycle(self.U.copy(order="F"), self.V.copy(order="F"), self.level, self.have)
+
+
+@dataclass
+class Info:
+    status: int
+    mv: int
+    mv_check: int
+    cycles: int
+    level: int
+    fetched: int
+    converged: bool
+    recycled: bool
+    restarts: int
+    replacements: int
+    relres_rec: float
+    relres_true: float
+    hist_mv: np.ndarray = field(repr=False)
+    hist_res: np.ndarray = field(repr=False)
+
+    @property
+    def mv_total(self) -> int:
+        return self.mv + self.mv_check
+
+
+def solve(A: CSR, b, x0, s: int, ell: int, P: np.ndarray, tol: float = 1e-8,
+          max_mv: int = 10 ** 9, method: int = MSTAB, fetch: int = FETCH_THRESHOLD,
+          fetch_rel: float | None = None, fetch_level: int = -1, max_repl: int = 3,
+          recycle: Recycle | None = None, dump_cycle: int = -1):
+    """Run Algorithm 1 on A x = b from x0.  Returns (x, info, recycle, dump).
+
+    ``recycle`` is updated in place (fetched data) and also returned.
+    ``dump`` (if dump_cycle >= 0) is a dict with the state after the level
+    loop of that cycle and after its update.
+    """
+    lib = _load()
+    n = A.n
+    P = np.asfortranarray(P, dtype=np.float64)
+    if P.shape != (n, s):
+        raise ValueError("P must be n x s")
+    b = np.ascontiguousarray(b, dtype=np.float64)
+    x = np.array(x0, dtype=np.float64, copy=True)
+    if recycle is None:
+        recycle = Recycle.empty(n, s)
+    if fetch_rel is None:
+        fetch_rel = float(np.sqrt(tol))
+    lvl = np.array([recycle.level], dtype=np.int64)
+    have = np.array([1 if recycle.have else 0], dtype=np.int32)
+    oi = np.zeros(9, dtype=np.int64)
+    of = np.zeros(2)
+    cap = 100000
+    hmv = np.zeros(cap, dtype=np.int64)
+    hres = np.zeros(cap)
+    hl = np.zeros(1, dtype=np.int64)
+    dump = None
+    if dump_cycle >= 0:
+        dump = np.zeros(n * (2 + ell + s * (ell + 2)) + ell + n * (2 + 2 * s))
+    st = lib.orc_solve(n, _ptr(A.row_ptr), _ptr(A.col), _ptr(A.val), s, ell, _ptr(P),
+                       float(tol), int(max_mv), int(method), int(fetch), float(fetch_rel),
+                       int(fetch_level), int(max_repl), _ptr(b), _ptr(x),
+                       _ptr(recycle.U), _ptr(recycle.V), _ptr(lvl), _ptr(have),
+                       _ptr(oi), _ptr(of), _ptr(hmv), _ptr(hres), cap, _ptr(hl),
+                       int(dump_cycle), _ptr(dump))
+    recycle.level = int(lvl[0])
+    recycle.have = bool(have[0])
+    h = int(min(hl[0], cap))
+    info = Info(int(st), int(oi[0]), int(oi[1]), int(oi[2]), int(oi[3]), int(oi[4]), bool(oi[5]),
+                bool(oi[6]), int(oi[7]), int(oi[8]), float(of[0]), float(of[1]),
+                hmv[:h].copy(), hres[:h].copy())
+    dd = None
+    if dump is not None:
+        o = 0
+        def take(k):
+            nonlocal o
+            v = dump[o:o + k]
+            o += k
+            return v
+        x_l = take(n).copy()
+        R = take(n * (ell + 1)).reshape(ell + 1, n).copy()
+        W = take(n * s * (ell + 2)).reshape(ell + 2, s, n).copy()
+        tau = take(ell).copy()
+        x_u = take(n).copy()
+        r_u = take(n).copy()
+        U_u = take(n * s).reshape(s, n).copy()
+        V_u = take(n * s).reshape(s, n).copy()
+        dd = dict(x=x_l, R=R, W=W, tau=tau, x_after=x_u, r_after=r_u, U_after=U_u, V_after=V_u)
+    return x, info, recycle, dd
+
+
+def bicgstab(A: CSR, b, x0, rhat, iters: int) -> np.ndarray:
+    lib = _load()
+    x = np.array(x0, dtype=np.float64, copy=True)
+    b = np.ascontiguousarray(b, dtype=np.float64)
+    rhat = np.ascontiguousarray(rhat, dtype=np.float64)
+    st = lib.orc_bicgstab(A.n, _ptr(A.row_ptr), _ptr(A.col), _ptr(A.val), _ptr(b), _ptr(x),
+                          _ptr(rhat), int(iters))
+    if st != OK:
+        raise RuntimeError("bicgstab failed")
+    return x
+
+
+def rhs_step(x: np.ndarray, inv_dt: float, f: np.ndarray) -> np.ndarray:
+    """Implicit Euler right-hand side b = x inv_dt + f (multiply, then add)."""
+    return x * inv_dt + f
+
+
+def solve_sequence(A: CSR, f, inv_dt: float, s: int, ell: int, P, systems: int,
+                   method: int = MSTAB, tol: float = 1e-8, fetch: int = FETCH_THRESHOLD, **kw):
+    """Time-stepping sequence: b^(k+1) = x^(k) inv_dt + f, x0 = x^(k), x^(0) = 0."""
+    x = np.zeros(A.n)
+    rec = Recycle.empty(A.n, s)
+    xs, infos = [], []
+    for _ in range(systems):
+        b = rhs_step(x, inv_dt, f)
+        x, info, rec, _ = solve(A, b, x, s, ell, P, tol=tol, method=method, fetch=fetch,
+                                recycle=rec, **kw)
+        xs.append(x.copy())
+        infos.append(info)
+    return xs, infos

@@ -1,0 +1,607 @@
+/*
+ * CPU oracle for IDR(s)stab(l) and M(s)stab(l) in FP64.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the tests, the smoke check and the CPU
+ * baseline leg of the benchmark may load this code.  It shares no source with
+ * the HIP library: it is a plain, slow, sequential restatement of the paper
+ * (Neuenhofen, "M(s)stab(l): A Generalization of IDR(s)stab(l) for Sequences
+ * of Linear Systems", arXiv 1604.06043), written for checking by eye.
+ *
+ * Readings of the paper that this file commits to (listed again, with the
+ * reasons, in the design notes of the repository):
+ *   - The stopping test of Algorithm 1 is relative: ||r|| <= tol ||b||,
+ *     compared on squares.  The loop runs on the recursive residual; on exit
+ *     the true residual b - A x is formed (one counted check MV) and, while it
+ *     still exceeds tol, it replaces r and the loop continues (at most
+ *     max_repl times), as the ocean experiment of Section 5.1 replaces the
+ *     residual after the solution update.
+ *   - The solution update of Algorithm 1 sums over i = 1..l (the printed
+ *     lower index is a typo).  x and u_q use the level vectors from before
+ *     r and v_q are overwritten.
+ *   - "Choose gamma / eta such that ... is orthogonal to P" is the s x s system
+ *     (P^T B) c = P^T y, solved by LU with partial pivoting; the system is
+ *     declared singular when a pivot is <= 1e-14 times the largest entry of
+ *     its column.
+ *   - tau = Z^+ r^(0) is solved through the normal equations (Cholesky, then
+ *     LU if Cholesky fails); a singular Gram matrix is a breakdown.
+ *   - For IDR(s)stab the input U, V are the Arnoldi basis of level s of the
+ *     initial residual (Section 5, preliminaries): u_1 = r/||r||, v_q = A u_q,
+ *     u_{q+1} = MGS-orthonormalized v_q; s MVs.
+ *   - M(s)stab is Algorithm 1 called with the P, U, V fetched from a former
+ *     solve (Section 4.2).  Fetching copies U, V at the end of a cycle
+ *     (Section 5, preliminaries); the policy decides which cycle end.
+ *   - Every product with A is counted: the initial residual, the Arnoldi MVs,
+ *     l(s+1) per cycle (Table 1), and the true-residual checks separately.
+ *   - A breakdown (singular small system) drops U, V and restarts from the
+ *     true residual b - A x (one counted MV) with an Arnoldi basis, at most
+ *     twice per solve; a third breakdown is returned as an error.
+ *
+ * Build: gcc -O2 -ffp-contract=off -fPIC -shared (no FMA contraction, so every
+ * a*b+c below rounds twice, as written).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_OK 0
+#define ORC_NOT_CONVERGED 1
+#define ORC_E_INVALID (-1)
+#define ORC_E_NOMEM (-3)
+#define ORC_E_BREAKDOWN (-4)
+#define ORC_E_NONFINITE (-5)
+
+#define ORC_MSTAB 0
+#define ORC_IDRSTAB 1
+
+#define ORC_FETCH_THRESHOLD 0
+#define ORC_FETCH_AT_LEVEL 1
+#define ORC_FETCH_AT_END 2
+#define ORC_FETCH_ONCE 3
+#define ORC_FETCH_NEVER 4
+
+#define ORC_MAX_RESTARTS 2
+
+/* ------------------------------------------------------------------------ */
+/* Matrix assembly: upwind finite differences for                            */
+/*   A = I/dt - div(kappa grad .) + beta . grad                              */
+/* on n^dim interior nodes of the unit square/cube, x fastest, Dirichlet.    */
+/* ------------------------------------------------------------------------ */
+
+int64_t orc_convdiff_nnz(int dim, int64_t n)
+{
+    int64_t cells = 1, faces = 1;
+    for (int d = 0; d < dim; ++d) cells *= n;
+    faces = (n - 1);
+    for (int d = 1; d < dim; ++d) faces *= n;
+    return cells + 2 * dim * faces;
+}
+
+static double face_kappa(const double *kappa, int64_t a, int64_t b, int interior)
+{
+    if (!kappa) return 1.0;
+    if (!interior) return kappa[a];
+    double ka = kappa[a], kb = kappa[b];
+    return (2.0 * ka * kb) / (ka + kb);
+}
+
+/*
+ * Row i, in column order: -z, -y, -x, diagonal, +x, +y, +z (those that exist).
+ * Face coefficient kf (1, or the harmonic mean of the two node values; the
+ * node's own value at a boundary face).  Convection uses the backward
+ * difference for beta_d > 0 and the forward difference otherwise.
+ *   diag  = inv_dt, then += kf*h^-2 for faces -x,+x,-y,+y,-z,+z in that order,
+ *           then += |beta_d| h^-1 for d = x, y, z
+ *   minus neighbour (-d):  -(kf h^-2) - max(beta_d, 0) h^-1
+ *   plus  neighbour (+d):  -(kf h^-2) + min(beta_d, 0) h^-1
+ */
+void orc_assemble_convdiff(int dim, int64_t n, const double *beta, double inv_dt,
+                           const double *kappa, int32_t *row_ptr, int32_t *col, double *val)
+{
+    double hinv = (double)(n + 1);
+    double hinv2 = hinv * hinv;
+    int64_t stride[3] = {1, n, n * n};
+    int64_t N = 1;
+    for (int d = 0; d < dim; ++d) N *= n;
+    int64_t pos = 0;
+    for (int64_t i = 0; i < N; ++i) {
+        int64_t c[3] = {i % n, (i / n) % n, (dim == 3) ? i / (n * n) : 0};
+        row_ptr[i] = (int32_t)pos;
+        /* face coefficients in order -x,+x,-y,+y,-z,+z */
+        double kf[3][2];
+        for (int d = 0; d < dim; ++d) {
+            kf[d][0] = face_kappa(kappa, i, i - stride[d], c[d] > 0);
+            kf[d][1] = face_kappa(kappa, i, i + stride[d], c[d] < n - 1);
+        }
+        double diag = inv_dt;
+        for (int d = 0; d < dim; ++d) {
+            diag = diag + kf[d][0] * hinv2;
+            diag = diag + kf[d][1] * hinv2;
+        }
+        for (int d = 0; d < dim; ++d) diag = diag + fabs(beta[d]) * hinv;
+        /* lower neighbours, highest stride first */
+        for (int d = dim - 1; d >= 0; --d) {
+            if (c[d] > 0) {
+                double bp = beta[d] > 0.0 ? beta[d] : 0.0;
+                col[pos] = (int32_t)(i - stride[d]);
+                val[pos] = -(kf[d][0] * hinv2) - bp * hinv;
+                ++pos;
+            }
+        }
+        col[pos] = (int32_t)i;
+        val[pos] = diag;
+        ++pos;
+        for (int d = 0; d < dim; ++d) {
+            if (c[d] < n - 1) {
+                double bm = beta[d] < 0.0 ? beta[d] : 0.0;
+                col[pos] = (int32_t)(i + stride[d]);
+                val[pos] = -(kf[d][1] * hinv2) + bm * hinv;
+                ++pos;
+            }
+        }
+    }
+    row_ptr[N] = (int32_t)pos;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Dense helpers                                                             */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    int64_t n;
+    const int32_t *rp, *ci;
+    const double *va;
+    int64_t mv; /* products with A performed */
+} Mat;
+
+static void matvec(Mat *A, const double *x, double *y)
+{
+    for (int64_t i = 0; i < A->n; ++i) {
+        double acc = 0.0;
+        for (int64_t k = A->rp[i]; k < A->rp[i + 1]; ++k) acc += A->va[k] * x[A->ci[k]];
+        y[i] = acc;
+    }
+    A->mv++;
+}
+
+void orc_spmv(int64_t n, const int32_t *rp, const int32_t *ci, const double *va,
+              const double *x, double *y)
+{
+    Mat A = {n, rp, ci, va, 0};
+    matvec(&A, x, y);
+}
+
+static double dot(int64_t n, const double *a, const double *b)
+{
+    double s = 0.0;
+    for (int64_t i = 0; i < n; ++i) s += a[i] * b[i];
+    return s;
+}
+
+/* Solve the m x m system M c = g (M row-major, copied) by Gaussian elimination
+ * with partial pivoting.  Returns 0, or 1 when a pivot is <= 1e-14 times the
+ * largest magnitude in its column of M (a column-scale-invariant test: the
+ * columns of P^T V can differ by many orders of magnitude when recycled data
+ * meet a fresh residual). */
+static int lu_solve(int m, const double *Min, const double *g, double *c)
+{
+    double M[64], y[8], cmax[8];
+    for (int j = 0; j < m; ++j) cmax[j] = 0.0;
+    for (int i = 0; i < m; ++i)
+        for (int j = 0; j < m; ++j) {
+            M[i * m + j] = Min[i * m + j];
+            if (fabs(M[i * m + j]) > cmax[j]) cmax[j] = fabs(M[i * m + j]);
+        }
+    for (int i = 0; i < m; ++i) y[i] = g[i];
+    for (int k = 0; k < m; ++k) {
+        int piv = k;
+        for (int i = k + 1; i < m; ++i)
+            if (fabs(M[i * m + k]) > fabs(M[piv * m + k])) piv = i;
+        if (!(fabs(M[piv * m + k]) > 1e-14 * cmax[k])) return 1;
+        if (piv != k) {
+            for (int j = 0; j < m; ++j) {
+                double t = M[k * m + j]; M[k * m + j] = M[piv * m + j]; M[piv * m + j] = t;
+            }
+            double t = y[k]; y[k] = y[piv]; y[piv] = t;
+        }
+        for (int i = k + 1; i < m; ++i) {
+            double f = M[i * m + k] / M[k * m + k];
+            for (int j = k + 1; j < m; ++j) M[i * m + j] -= f * M[k * m + j];
+            y[i] -= f * y[k];
+        }
+    }
+    for (int i = m - 1; i >= 0; --i) {
+        double acc = y[i];
+        for (int j = i + 1; j < m; ++j) acc -= M[i * m + j] * c[j];
+        c[i] = acc / M[i * m + i];
+    }
+    return 0;
+}
+
+/* Least squares through the normal equations G t = c (G SPD, row-major). */
+static int spd_solve(int m, const double *G, const double *c, double *t)
+{
+    double L[64], y[8];
+    int ok = 1;
+    memset(L, 0, sizeof(L));
+    for (int j = 0; j < m && ok; ++j) {
+        double d = G[j * m + j];
+        for (int k = 0; k < j; ++k) d -= L[j * m + k] * L[j * m + k];
+        if (!(d > 0.0)) { ok = 0; break; }
+        L[j * m + j] = sqrt(d);
+        for (int i = j + 1; i < m; ++i) {
+            double e = G[i * m + j];
+            for (int k = 0; k < j; ++k) e -= L[i * m + k] * L[j * m + k];
+            L[i * m + j] = e / L[j * m + j];
+        }
+    }
+    if (!ok) return lu_solve(m, G, c, t);
+    for (int i = 0; i < m; ++i) {
+        double acc = c[i];
+        for (int k = 0; k < i; ++k) acc -= L[i * m + k] * y[k];
+        y[i] = acc / L[i * m + i];
+    }
+    for (int i = m - 1; i >= 0; --i) {
+        double acc = y[i];
+        for (int k = i + 1; k < m; ++k) acc -= L[k * m + i] * t[k];
+        t[i] = acc / L[i * m + i];
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Algorithm 1 with the recycling protocol                                   */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    Mat A;
+    int s, ell;
+    int64_t n;
+    const double *P;   /* n x s, column-major */
+    double *W;         /* levels -1..ell of the s auxiliary vectors */
+    double *R;         /* levels 0..ell of the residual */
+} Work;
+
+#define WCOL(w, i, q) ((w)->W + ((int64_t)((i) + 1) * (w)->s + (q)) * (w)->n)
+#define RCOL(w, i) ((w)->R + (int64_t)(i) * (w)->n)
+
+/* out[a] = p_a . y */
+static void project(const Work *w, const double *y, double *out)
+{
+    for (int a = 0; a < w->s; ++a) out[a] = dot(w->n, w->P + (int64_t)a * w->n, y);
+}
+
+/* Arnoldi basis of level s for the residual r: U orthonormal, V = A U. */
+static int arnoldi(Work *w, const double *r)
+{
+    int64_t n = w->n;
+    int s = w->s;
+    double nr = sqrt(dot(n, r, r));
+    if (!(nr > 0.0)) return 1;
+    double *u1 = WCOL(w, -1, 0);
+    for (int64_t e = 0; e < n; ++e) u1[e] = r[e] / nr;
+    for (int q = 0; q < s; ++q) {
+        double *uq = WCOL(w, -1, q), *vq = WCOL(w, 0, q);
+        matvec(&w->A, uq, vq);
+        if (q + 1 < s) {
+            double *un = WCOL(w, -1, q + 1);
+            memcpy(un, vq, (size_t)n * sizeof(double));
+            for (int j = 0; j <= q; ++j) {
+                const double *uj = WCOL(w, -1, j);
+                double h = dot(n, uj, un);
+                for (int64_t e = 0; e < n; ++e) un[e] -= h * uj[e];
+            }
+            double nn = sqrt(dot(n, un, un));
+            if (!(nn > 1e-14 * sqrt(dot(n, vq, vq)))) return 1;
+            for (int64_t e = 0; e < n; ++e) un[e] /= nn;
+        }
+    }
+    return 0;
+}
+
+/*
+ * One cycle of Algorithm 1 (the while-loop body), in place.
+ * On entry R[0] = r, x = x, W[-1] = U, W[0] = V.  On exit R[0] = new r,
+ * W[-1] = new U, W[0] = new V, x updated.  Returns 0 or 1 (breakdown).
+ * If dump != NULL the state after the level loop is copied there before the
+ * degree-l minimization, followed by tau.
+ */
+static int cycle(Work *w, double *x, double *dump)
+{
+    const int s = w->s, ell = w->ell;
+    const int64_t n = w->n;
+    double M[64], g[8], c[8], colp[8][8];
+
+    for (int k = 0; k < ell; ++k) {
+        /* gamma: r^(k) - V^(k) gamma orthogonal to P */
+        for (int q = 0; q < s; ++q) project(w, WCOL(w, k, q), colp[q]);
+        for (int a = 0; a < s; ++a)
+            for (int q = 0; q < s; ++q) M[a * s + q] = colp[q][a];
+        project(w, RCOL(w, k), g);
+        if (lu_solve(s, M, g, c)) return 1;
+        for (int i = 0; i <= k; ++i) {
+            double *ri = RCOL(w, i);
+            for (int q = 0; q < s; ++q) {
+                const double *vq = WCOL(w, i, q);
+                for (int64_t e = 0; e < n; ++e) ri[e] -= c[q] * vq[e];
+            }
+        }
+        for (int q = 0; q < s; ++q) {
+            const double *uq = WCOL(w, -1, q);
+            for (int64_t e = 0; e < n; ++e) x[e] += c[q] * uq[e];
+        }
+        matvec(&w->A, RCOL(w, k), RCOL(w, k + 1));
+
+        for (int q = 0; q < s; ++q) {
+            /* eta_q: r^(k+1) - [V^(k+1)_{1:q-1}, V^(k)_{q:s}] eta orthogonal to P */
+            for (int p = 0; p < s; ++p) project(w, WCOL(w, p < q ? k + 1 : k, p), colp[p]);
+            for (int a = 0; a < s; ++a)
+                for (int p = 0; p < s; ++p) M[a * s + p] = colp[p][a];
+            project(w, RCOL(w, k + 1), g);
+            if (lu_solve(s, M, g, c)) return 1;
+            /* v_q^(i) := r^(i+1) - [V^(i+1)_{1:q-1}, V^(i)_{q:s}] eta, i = -1..k */
+            for (int i = -1; i <= k; ++i) {
+                double *vq = WCOL(w, i, q);
+                const double *rr = RCOL(w, i + 1);
+                for (int64_t e = 0; e < n; ++e) {
+                    double acc = rr[e];
+                    for (int p = 0; p < s; ++p) {
+                        const double *src = (p < q) ? WCOL(w, i + 1, p) : WCOL(w, i, p);
+                        acc -= c[p] * src[e];
+                    }
+                    vq[e] = acc;
+                }
+            }
+            matvec(&w->A, WCOL(w, k, q), WCOL(w, k + 1, q));
+        }
+    }
+
+    /* degree-l residual minimization: tau = Z^+ r^(0), Z = [r^(1..l)] */
+    double G[64], t[8], cc[8];
+    for (int i = 0; i < ell; ++i) {
+        for (int j = 0; j < ell; ++j) G[i * ell + j] = dot(n, RCOL(w, i + 1), RCOL(w, j + 1));
+        cc[i] = dot(n, RCOL(w, i + 1), RCOL(w, 0));
+    }
+    if (spd_solve(ell, G, cc, t)) return 1;
+
+    if (dump) {
+        double *d = dump;
+        memcpy(d, x, (size_t)n * sizeof(double)); d += n;
+        memcpy(d, w->R, (size_t)n * (ell + 1) * sizeof(double)); d += n * (ell + 1);
+        memcpy(d, w->W, (size_t)n * s * (ell + 2) * sizeof(double)); d += (int64_t)n * s * (ell + 2);
+        for (int i = 0; i < ell; ++i) d[i] = t[i];
+    }
+
+    /* x := x^(0) + sum_i tau_i r^(i-1)        (before r^(0) changes) */
+    for (int i = 1; i <= ell; ++i) {
+        const double *ri = RCOL(w, i - 1);
+        for (int64_t e = 0; e < n; ++e) x[e] += t[i - 1] * ri[e];
+    }
+    /* u_q := v_q^(-1) - sum_i tau_i v_q^(i-1) (before v_q^(0) changes) */
+    for (int q = 0; q < s; ++q) {
+        double *uq = WCOL(w, -1, q);
+        for (int i = 1; i <= ell; ++i) {
+            const double *vi = WCOL(w, i - 1, q);
+            for (int64_t e = 0; e < n; ++e) uq[e] -= t[i - 1] * vi[e];
+        }
+    }
+    /* v_q := v_q^(0) - sum_i tau_i v_q^(i) */
+    for (int q = 0; q < s; ++q) {
+        double *vq = WCOL(w, 0, q);
+        for (int i = 1; i <= ell; ++i) {
+            const double *vi = WCOL(w, i, q);
+            for (int64_t e = 0; e < n; ++e) vq[e] -= t[i - 1] * vi[e];
+        }
+    }
+    /* r := r^(0) - sum_i tau_i r^(i) */
+    {
+        double *r0 = RCOL(w, 0);
+        for (int i = 1; i <= ell; ++i) {
+            const double *ri = RCOL(w, i);
+            for (int64_t e = 0; e < n; ++e) r0[e] -= t[i - 1] * ri[e];
+        }
+    }
+    return 0;
+}
+
+/*
+ * Solve A x = b (x holds x0 on entry).
+ *
+ * Recycle state (U, V: n x s column-major, *rec_level, *rec_have) is read when
+ * method == ORC_MSTAB and *rec_have, and written at the fetch point chosen by
+ * `fetch` (left unchanged if the policy never fires).
+ *
+ * out_i64[0..8]: mv (initial + Arnoldi + cycles), mv_check, cycles, level of
+ *                the final U,V, fetched level (-1 if none), converged,
+ *                recycled (started from recycled data), restarts, replacements
+ * out_f64[0..1]: final recursive and true relative residual
+ * hist: (total MVs, recursive relative residual) after the initial residual
+ *       and after every cycle.
+ * dump: if dump_cycle >= 0, the state after the level loop of that cycle:
+ *       x, R[0..l], W[-1..l] (n each) then tau (l values); after it, the
+ *       state after the same cycle's update: x, r, U, V.
+ */
+int orc_solve(int64_t n, const int32_t *rp, const int32_t *ci, const double *va,
+              int s, int ell, const double *P,
+              double tol, int64_t max_mv, int method, int fetch, double fetch_rel,
+              int64_t fetch_level, int max_repl,
+              const double *b, double *x,
+              double *U, double *V, int64_t *rec_level, int *rec_have,
+              int64_t *out_i64, double *out_f64,
+              int64_t *hist_mv, double *hist_res, int64_t hist_cap, int64_t *hist_len,
+              int64_t dump_cycle, double *dump)
+{
+    if (n <= 0 || s < 1 || s > 8 || ell < 1 || ell > 8 || n <= s) return ORC_E_INVALID;
+    Work w;
+    w.A.n = n; w.A.rp = rp; w.A.ci = ci; w.A.va = va; w.A.mv = 0;
+    w.s = s; w.ell = ell; w.n = n; w.P = P;
+    w.W = (double *)calloc((size_t)n * s * (ell + 2), sizeof(double));
+    w.R = (double *)calloc((size_t)n * (ell + 1), sizeof(double));
+    double *t = (double *)calloc((size_t)n, sizeof(double));
+    if (!w.W || !w.R || !t) { free(w.W); free(w.R); free(t); return ORC_E_NOMEM; }
+
+    int64_t mv_check = 0, cycles = 0, hl = 0, fetched = -1, level = 0;
+    int converged = 0, recycled = 0, restarts = 0, repl = 0, status = ORC_OK;
+    double rr = 0.0, relres_true = -1.0;
+    const double tol2 = tol * tol;
+
+#define HIST(res) do { if (hl < hist_cap) { hist_mv[hl] = w.A.mv + mv_check; hist_res[hl] = (res); } ++hl; } while (0)
+
+    double nb2 = dot(n, b, b);
+    if (!isfinite(nb2)) { status = ORC_E_NONFINITE; goto done; }
+    if (nb2 == 0.0) {
+        memset(x, 0, (size_t)n * sizeof(double));
+        converged = 1; rr = 0.0; relres_true = 0.0;
+        goto done;
+    }
+
+    double *r = RCOL(&w, 0);
+    matvec(&w.A, x, r);
+    for (int64_t e = 0; e < n; ++e) r[e] = b[e] - r[e];
+    rr = dot(n, r, r);
+    int r_is_true = 1;
+    HIST(sqrt(rr / nb2));
+    if (!isfinite(rr)) { status = ORC_E_NONFINITE; goto done; }
+
+    int have_uv = 0;
+    if (method == ORC_MSTAB && *rec_have) {
+        memcpy(WCOL(&w, -1, 0), U, (size_t)n * s * sizeof(double));
+        memcpy(WCOL(&w, 0, 0), V, (size_t)n * s * sizeof(double));
+        level = *rec_level;
+        have_uv = 1;
+        recycled = 1;
+    }
+
+    for (;;) {
+        while (rr > tol2 * nb2 && w.A.mv < max_mv) {
+            if (!have_uv) {
+                if (arnoldi(&w, r)) { status = ORC_E_BREAKDOWN; goto done; }
+                have_uv = 1;
+                level = 0;
+                continue; /* re-check the MV budget */
+            }
+            int bd = cycle(&w, x, (cycles == dump_cycle) ? dump : NULL);
+            if (bd) {
+                if (restarts < ORC_MAX_RESTARTS) {
+                    /* drop U, V (recycled or not) and restart from the true
+                     * residual of the current x with a fresh Arnoldi basis */
+                    ++restarts;
+                    have_uv = 0;
+                    matvec(&w.A, x, r);
+                    for (int64_t e = 0; e < n; ++e) r[e] = b[e] - r[e];
+                    r_is_true = 1;
+                    rr = dot(n, r, r);
+                    if (!isfinite(rr)) { status = ORC_E_NONFINITE; goto done; }
+                    continue;
+                }
+                status = ORC_E_BREAKDOWN;
+                goto done;
+            }
+            ++cycles;
+            level += ell;
+            r_is_true = 0;
+            rr = dot(n, r, r);
+            if (!isfinite(rr)) { status = ORC_E_NONFINITE; goto done; }
+            if (cycles - 1 == dump_cycle && dump) {
+                double *d = dump + (int64_t)n * (2 + ell + s * (ell + 2)) + ell;
+                memcpy(d, x, (size_t)n * sizeof(double)); d += n;
+                memcpy(d, r, (size_t)n * sizeof(double)); d += n;
+                memcpy(d, WCOL(&w, -1, 0), (size_t)n * 2 * s * sizeof(double));
+            }
+            HIST(sqrt(rr / nb2));
+            double rel = sqrt(rr / nb2);
+            int fire = 0;
+            switch (fetch) {
+            case ORC_FETCH_THRESHOLD: fire = (fetched < 0 && rel <= fetch_rel); break;
+            case ORC_FETCH_AT_LEVEL: fire = (level == fetch_level); break;
+            case ORC_FETCH_ONCE: fire = (!*rec_have && fetched < 0 && rel <= fetch_rel); break;
+            default: break;
+            }
+            if (fire) {
+                memcpy(U, WCOL(&w, -1, 0), (size_t)n * s * sizeof(double));
+                memcpy(V, WCOL(&w, 0, 0), (size_t)n * s * sizeof(double));
+                fetched = level;
+            }
+        }
+        /* finish: the true residual decides */
+        if (r_is_true) {
+            relres_true = sqrt(rr / nb2);
+            converged = rr <= tol2 * nb2;
+            break;
+        }
+        Mat Ac = w.A;
+        matvec(&Ac, x, t);
+        ++mv_check;
+        for (int64_t e = 0; e < n; ++e) t[e] = b[e] - t[e];
+        double tt = dot(n, t, t);
+        relres_true = sqrt(tt / nb2);
+        if (!isfinite(tt)) { status = ORC_E_NONFINITE; goto done; }
+        if (tt <= tol2 * nb2) { converged = 1; break; }
+        if (rr <= tol2 * nb2 && repl < max_repl && w.A.mv < max_mv) {
+            memcpy(r, t, (size_t)n * sizeof(double));
+            rr = tt;
+            r_is_true = 1;
+            ++repl;
+            continue;
+        }
+        break;
+    }
+    if (!converged && status == ORC_OK) status = ORC_NOT_CONVERGED;
+    if (cycles > 0 && fetched < 0 && (fetch == ORC_FETCH_AT_END ||
+                                      (fetch == ORC_FETCH_THRESHOLD) ||
+                                      (fetch == ORC_FETCH_ONCE && !*rec_have))) {
+        memcpy(U, WCOL(&w, -1, 0), (size_t)n * s * sizeof(double));
+        memcpy(V, WCOL(&w, 0, 0), (size_t)n * s * sizeof(double));
+        fetched = level;
+    }
+    if (fetched >= 0) { *rec_level = fetched; *rec_have = 1; }
+
+done:
+    out_i64[0] = w.A.mv;
+    out_i64[1] = mv_check;
+    out_i64[2] = cycles;
+    out_i64[3] = level;
+    out_i64[4] = fetched;
+    out_i64[5] = converged;
+    out_i64[6] = recycled;
+    out_i64[7] = restarts;
+    out_i64[8] = repl;
+    out_f64[0] = nb2 > 0.0 ? sqrt(rr / nb2) : 0.0;
+    out_f64[1] = relres_true;
+    *hist_len = hl;
+    free(w.W); free(w.R); free(t);
+    return status;
+#undef HIST
+}
+
+/* ------------------------------------------------------------------------ */
+/* Textbook BiCGStab (van der Vorst 1992) with shadow vector rhat, `iters`    */
+/* iterations, no stopping test: the s = l = 1 special case pins the cycle.  */
+/* ------------------------------------------------------------------------ */
+int orc_bicgstab(int64_t n, const int32_t *rp, const int32_t *ci, const double *va,
+                 const double *b, double *x, const double *rhat, int iters)
+{
+    Mat A = {n, rp, ci, va, 0};
+    double *r = calloc((size_t)n, sizeof(double)), *p = calloc((size_t)n, sizeof(double));
+    double *v = calloc((size_t)n, sizeof(double)), *sv = calloc((size_t)n, sizeof(double));
+    double *tv = calloc((size_t)n, sizeof(double));
+    if (!r || !p || !v || !sv || !tv) { free(r); free(p); free(v); free(sv); free(tv); return ORC_E_NOMEM; }
+    matvec(&A, x, r);
+    for (int64_t e = 0; e < n; ++e) r[e] = b[e] - r[e];
+    double rho_old = 1.0, alpha = 1.0, omega = 1.0;
+    for (int it = 0; it < iters; ++it) {
+        double rho = dot(n, rhat, r);
+        double beta = (rho / rho_old) * (alpha / omega);
+        for (int64_t e = 0; e < n; ++e) p[e] = r[e] + beta * (p[e] - omega * v[e]);
+        matvec(&A, p, v);
+        alpha = rho / dot(n, rhat, v);
+        for (int64_t e = 0; e < n; ++e) sv[e] = r[e] - alpha * v[e];
+        matvec(&A, sv, tv);
+        omega = dot(n, tv, sv) / dot(n, tv, tv);
+        for (int64_t e = 0; e < n; ++e) x[e] += alpha * p[e] + omega * sv[e];
+        for (int64_t e = 0; e < n; ++e) r[e] = sv[e] - omega * tv[e];
+        rho_old = rho;
+    }
+    free(r); free(p); free(v); free(sv); free(tv);
+    return ORC_OK;
+}
