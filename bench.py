@@ -1,0 +1,210 @@
+"""Benchmark: M(s)stab(l) time-stepping sequence on one MI355X.
+
+One step = one whole sequence of the 128^3 convection-diffusion workload
+(N = 2,097,152, 7-point upwind, Pe = 100, implicit Euler dt = 1e-3,
+50 right-hand sides b^(k+1) = x^(k)/dt + f, x^(0) = 0), solved by M(s)stab(l)
+to relative residual 1e-8 with the recycle data carried from system to system.
+Every step starts from x = 0 with the recycle data dropped, so each step does
+the same work.  value = systems per second over the timed steps.
+
+Also reported on the same line: MVs per system; IDR(s)stab(l) on the same
+sequence (no recycling); the FP32+FP64-refinement form; the kernel roofline of
+the dominant kernel class (HIP events on the solver's stream over the timed
+steps); and the CPU oracle on a bounded sample.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--s 4] [--ell 2]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("systems/sec + MVs/system at rel-res 1e-8; SpMV HBM GB/s vs peak, "
+          "M(s)stab vs IDRstab")
+HBM_PEAK_GBS = 8000.0
+CLASS_NAMES = ["spmv", "gamma", "eta", "gram", "poly"]
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def run_sequence(torch, ms, solver, cd, f, systems):
+    x = torch.zeros(cd.N, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(x)
+    solver.recycle_reset()
+    mv = 0
+    infos = []
+    for _ in range(systems):
+        ms.mstab_rhs_step(x, cd.inv_dt, f, b)
+        info = solver.solve_next(b, x)
+        if not info["converged"]:
+            raise RuntimeError(f"system did not converge: {info}")
+        mv += info["mv_total"]
+        infos.append(info)
+    return x, mv, infos
+
+
+def timed(torch, fn, steps, warmup):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    outs = [fn() for _ in range(steps)]
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, outs
+
+
+def cpu_baseline(cd, s, ell):
+    """The FP64 oracle on the first system of the same sequence (single thread)."""
+    import numpy as np
+    import oracle
+    from paper_1604_06043_amd import inputs as I
+    A = oracle.assemble_convdiff(cd.dim, cd.n, cd.beta, cd.inv_dt, cd.kappa)
+    P = I.p_dense(0, cd.N, s)
+    b = oracle.rhs_step(np.zeros(cd.N), cd.inv_dt, cd.f)
+    t0 = time.perf_counter()
+    _, info, _, _ = oracle.solve(A, b, np.zeros(cd.N), s, ell, P)
+    dt = time.perf_counter() - t0
+    return {"value": 1.0 / dt, "unit": "systems/s", "cores": 1, "kind": "oracle",
+            "sample": f"system 1 of the 128^3 sequence (IDR(s)stab start, {info.mv_total} MVs, "
+                      f"{dt:.1f} s, single-threaded C FP64)",
+            "mvs_per_system": info.mv_total}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--s", type=int, default=4)
+    ap.add_argument("--ell", type=int, default=2)
+    ap.add_argument("--systems", type=int, default=50)
+    ap.add_argument("--n", type=int, default=128)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--no-events", action="store_true",
+                    help="time the steps without per-kernel HIP events (no roofline)")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported by this build "
+              f"(the solve is a single-GPU kernel path)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1604_06043_amd import inputs as I
+    from paper_1604_06043_amd import mstab as ms
+
+    if not torch.cuda.is_available():
+        raise SystemExit("bench.py needs a GPU")
+    torch.cuda.set_device(0)
+    ms.load()
+    s, ell = args.s, args.ell
+    cd = I.config("c2", seed=0, n=args.n)
+    A = ms.mstab_assemble_convdiff(cd.dim, cd.n, cd.beta, cd.inv_dt)
+    f = torch.tensor(cd.f, device="cuda")
+    torch.cuda.synchronize()
+    log(f"[bench] N={cd.N} nnz={A.nnz} s={s} ell={ell} systems/step={args.systems}")
+
+    solver = ms.Solver(A, s, ell, p_seed=0, method=ms.METHOD_MSTAB)
+    state = {}
+
+    def step():
+        x, mv, infos = run_sequence(torch, ms, solver, cd, f, args.systems)
+        state["mv"] = mv
+        state["infos"] = infos
+        return mv
+
+    for _ in range(args.warmup):
+        step()
+        log(f"[bench] warmup step done, MVs/system {state['mv'] / args.systems:.1f}")
+    torch.cuda.synchronize()
+    solver.set_profiling(not args.no_events)
+    t, mvs = timed(torch, step, args.steps, 0)
+    stats = {c: solver.kernel_stats(i) for i, c in enumerate(CLASS_NAMES)}
+    solver.set_profiling(False)
+    log(f"[bench] timed {args.steps} steps in {t:.3f} s")
+    systems = args.steps * args.systems
+    value = systems / t
+    mv_per_system = sum(mvs) / systems
+
+    kernels = {}
+    for c, (n, msec, by) in stats.items():
+        if n:
+            kernels[c] = {"launches": n, "ms_total": round(msec, 3),
+                          "us_per_launch": round(1e3 * msec / n, 2),
+                          "GBs": round(by / (msec * 1e-3) / 1e9, 1)}
+    roofline = None
+    if not args.no_events:
+        dom = max(stats, key=lambda c: stats[c][1])
+        n, msec, by = stats[dom]
+        achieved = by / (msec * 1e-3) / 1e9
+        roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
+                    "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                    "bytes_per_launch": by / n, "us_per_launch": 1e3 * msec / n}
+
+    variants = {}
+    if not args.no_variants:
+        idr = ms.Solver(A, s, ell, p_seed=0, method=ms.METHOD_IDRSTAB)
+        ti, (mvi,) = timed(torch, lambda: run_sequence(torch, ms, idr, cd, f, args.systems)[1], 1, 0)
+        idr.close()
+        variants["idrstab"] = {"systems_per_s": args.systems / ti,
+                               "mvs_per_system": mvi / args.systems}
+        log(f"[bench] IDR(s)stab(l): {args.systems / ti:.2f} systems/s")
+        mix = ms.Solver(A, s, ell, p_seed=0, method=ms.METHOD_MSTAB, precision=ms.PREC_F32_REFINE)
+        x64, _, _ = run_sequence(torch, ms, solver, cd, f, args.systems)
+        holder = {}
+
+        def mixed_step():
+            x, mv, infos = run_sequence(torch, ms, mix, cd, f, args.systems)
+            holder["x"] = x
+            return mv
+        tm, (mvm,) = timed(torch, mixed_step, 1, 0)
+        err = float(torch.linalg.norm(holder["x"] - x64) / torch.linalg.norm(x64))
+        mix.close()
+        variants["f32_refine"] = {"systems_per_s": args.systems / tm,
+                                  "mvs_per_system": mvm / args.systems,
+                                  "rel_err_vs_f64_path_last_system": err}
+        log(f"[bench] FP32+refinement: {args.systems / tm:.2f} systems/s, err {err:.2e}")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("[bench] CPU oracle sample ...")
+        cpu = cpu_baseline(cd, s, ell)
+        log(f"[bench] CPU oracle: {cpu['value']:.4f} systems/s")
+
+    out = {
+        "metric": METRIC,
+        "value": round(value, 4),
+        "unit": "systems/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * t / args.steps, 2),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"convdiff3d_{cd.n}cubed_pe100_dt1e-3_{args.systems}rhs",
+                   "N": cd.N, "nnz": A.nnz, "s": s, "ell": ell, "tol": 1e-8,
+                   "method": "M(s)stab(l)", "systems_per_step": args.systems, "format": "csr_int32_f64"},
+        "mvs_per_system": round(mv_per_system, 2),
+        "roofline": roofline,
+        "kernels": kernels,
+        "variants": variants,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,236 @@
+/*
+ * mstab.h -- C ABI of the M(s)stab(l) / IDR(s)stab(l) solver for AMD MI355X
+ * (gfx950).
+ *
+ * The method: Neuenhofen, "M(s)stab(l): A Generalization of IDR(s)stab(l) for
+ * Sequences of Linear Systems", arXiv 1604.06043.  The problem is the
+ * sequence A x^(i) = b^(i) with one fixed sparse nonsymmetric A and right-hand
+ * sides that depend on the previous solution (Section 1, equation of the
+ * sequence), solved one after the other.  IDR(s)stab(l) is Algorithm 1;
+ * M(s)stab(l) is Algorithm 1 fed with the cut-space P and the matrices U, V
+ * that a former solve returned (Section 4.2), fetched at the end of one of its
+ * cycles (Section 5, preliminaries).
+ *
+ * Conventions for every call:
+ *   - Return value is an mstab_status; calls never abort and never fail
+ *     silently.  mstab_last_error() gives the text of the last failure on a
+ *     handle (or, for calls without a handle, of the calling thread).
+ *   - "device" pointers are HIP device memory (e.g. torch tensors'
+ *     data_ptr()); "host" pointers are ordinary host memory.  All arrays are
+ *     dense, contiguous, little-endian; matrices in CSR with int32 indices,
+ *     columns sorted within a row; blocks of vectors are column-major.
+ *   - hip_stream is a hipStream_t (NULL = the legacy default stream).  Every
+ *     call enqueues its work on that stream and returns after synchronizing
+ *     with it, unless stated otherwise.
+ *   - Arguments are borrowed for the duration of the call, except the matrix
+ *     arrays passed to mstab_create, which are borrowed until mstab_destroy.
+ *   - One thread at a time per handle; distinct handles are independent.
+ */
+#ifndef MSTAB_H
+#define MSTAB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MSTAB_OK = 0,
+    MSTAB_NOT_CONVERGED = 1,   /* max_mv reached or replacements exhausted; x = last iterate */
+    MSTAB_E_INVALID = -1,      /* bad argument (null pointer, s or l out of range, n <= s, ...) */
+    MSTAB_E_HIP = -2,          /* a HIP runtime call failed */
+    MSTAB_E_NOMEM = -3,        /* device or host allocation failed */
+    MSTAB_E_BREAKDOWN = -4,    /* a singular small system after the allowed restarts */
+    MSTAB_E_NONFINITE = -5     /* NaN or Inf in b or in the iteration */
+} mstab_status;
+
+typedef enum {
+    MSTAB_METHOD_MSTAB = 0,    /* use recycled P, U, V when the handle holds them (Section 4.2) */
+    MSTAB_METHOD_IDRSTAB = 1   /* Arnoldi U, V of level s for every system (Section 5) */
+} mstab_method;
+
+typedef enum {
+    MSTAB_PREC_F64 = 0,        /* every vector operation in FP64 */
+    MSTAB_PREC_F32_REFINE = 1  /* FP32 inner M(s)stab(l), FP64 true residual and correction */
+} mstab_precision;
+
+typedef enum {
+    MSTAB_FETCH_THRESHOLD = 0, /* first cycle end with recursive relres <= fetch_rel (else the last) */
+    MSTAB_FETCH_AT_LEVEL = 1,  /* cycle end at which the level of U, V equals fetch_level */
+    MSTAB_FETCH_AT_END = 2,    /* last cycle end of the solve */
+    MSTAB_FETCH_ONCE = 3,      /* THRESHOLD on the first solve, then keep that data for all */
+    MSTAB_FETCH_NEVER = 4      /* never replace the held data */
+} mstab_fetch;
+
+/* CSR matrix; all arrays are device pointers, n rows, nnz entries. */
+typedef struct {
+    int64_t n;
+    int64_t nnz;
+    const int32_t *row_ptr;    /* n+1 */
+    const int32_t *col_idx;    /* nnz, sorted within each row */
+    const double *val;         /* nnz */
+} mstab_csr;
+
+typedef struct {
+    int32_t struct_size;       /* sizeof(mstab_options) */
+    double tol;                /* relative residual target ||b - A x|| <= tol ||b||; default 1e-8 */
+    int64_t max_mv;            /* budget of products with A per system; default 100000 */
+    int32_t method;            /* mstab_method; default MSTAB */
+    int32_t precision;         /* mstab_precision; default F64 */
+    int32_t fetch;             /* mstab_fetch; default THRESHOLD */
+    double fetch_rel;          /* THRESHOLD/ONCE level; default sqrt(tol) */
+    int64_t fetch_level;       /* AT_LEVEL: level j of the fetched U, V */
+    uint64_t p_seed;           /* seed of the cut-space basis P (counter-based uniform entries) */
+    int32_t max_replacements;  /* true-residual replacements at the end of a solve; default 3 */
+    double inner_tol;          /* F32_REFINE: relative tolerance of each inner solve (recursive
+                                  residual; the FP64 true residual judges the result); default 1e-4 */
+    int32_t max_refinements;   /* F32_REFINE: outer correction steps; default 20 */
+} mstab_options;
+
+typedef struct {
+    int32_t status;            /* the mstab_status of the solve */
+    int32_t converged;         /* true relative residual <= tol */
+    int32_t recycled;          /* the solve started from recycled U, V */
+    int32_t restarts;          /* breakdown restarts (fresh Arnoldi basis) */
+    int32_t replacements;      /* true-residual replacements */
+    int32_t refinements;       /* F32_REFINE: outer correction steps */
+    int32_t guess_accepted;    /* mstab_solve_next_guess: the guess passed the residual gate */
+    int32_t pad_;
+    int64_t mv;                /* products with A in the iteration (initial residual, Arnoldi, cycles) */
+    int64_t mv_check;          /* products with A for true-residual checks and guess gates */
+    int64_t mv_f64;            /* F32_REFINE: products with the FP64 matrix (all in mv/mv_check) */
+    int64_t cycles;            /* cycles of Algorithm 1 */
+    int64_t level;             /* level j of the final U, V */
+    int64_t fetched_level;     /* level of the data fetched by this solve, -1 if none */
+    double relres_recursive;   /* ||r|| / ||b|| of the recursive residual at exit */
+    double relres_true;        /* ||b - A x|| / ||b|| at exit */
+    double seconds;            /* wall time of the call */
+} mstab_info;
+
+typedef struct mstab_solver mstab_solver;
+
+/* Fill o with defaults.  Errors: E_INVALID if o is NULL. */
+mstab_status mstab_options_default(mstab_options *o);
+
+/*
+ * Create a solver for A with s shadow vectors and degree l (Algorithm 1's s
+ * and l; 1 <= s <= 8, 1 <= l <= 8, n > s).  Allocates the workspace of
+ * (s+1)(l+2) vectors (Table 1) plus the recycle store, on the current HIP
+ * device.  o may be NULL (defaults).  The handle keeps the matrix pointers.
+ * Errors: E_INVALID, E_NOMEM, E_HIP; *out is NULL on failure.
+ */
+mstab_status mstab_create(const mstab_csr *A, int32_t s, int32_t ell, const mstab_options *o,
+                          void *hip_stream, mstab_solver **out);
+
+/*
+ * Solve the next system of the sequence: A x = b (b, x: device, n doubles).
+ * x holds the initial guess on entry (normally the previous solution) and the
+ * solution on return.  With method MSTAB and held recycle data the solve starts
+ * from it; the fetch policy may replace the held data.  info may be NULL.
+ * On failure x holds the last consistent iterate.
+ */
+mstab_status mstab_solve_next(mstab_solver *h, const double *b, double *x, mstab_info *info);
+
+/*
+ * As mstab_solve_next with an external initial guess: x_guess is used as x0
+ * only if ||b - A x_guess|| < ||b - A x_prev|| (two counted check MVs),
+ * otherwise x_prev is.  (b, x_prev, x_guess, x: device, n doubles; x may alias
+ * x_prev or x_guess.)  info->guess_accepted reports the decision.
+ */
+mstab_status mstab_solve_next_guess(mstab_solver *h, const double *b, const double *x_prev,
+                                    const double *x_guess, double *x, mstab_info *info);
+
+/* Products with A: over the handle's lifetime and in the last solve. */
+mstab_status mstab_mv_count(const mstab_solver *h, int64_t *total, int64_t *last_system);
+
+/*
+ * Residual history of the last solve: pairs (products with A so far, recursive
+ * relative residual) after the initial residual and after every cycle (the
+ * points of the paper's convergence graphs).  Host arrays of capacity cap;
+ * *len gets the full length (entries beyond cap are dropped).
+ */
+mstab_status mstab_residual_history(const mstab_solver *h, int64_t *mv, double *relres,
+                                    int64_t cap, int64_t *len);
+
+/* Drop the held recycle data (the next MSTAB solve starts like IDR(s)stab). */
+mstab_status mstab_recycle_reset(mstab_solver *h);
+
+/*
+ * Copy the held recycle data out (F64 precision only): U, V device, n x s
+ * column-major doubles each; level and have on host.  With have == 0 U, V are
+ * left untouched.
+ */
+mstab_status mstab_recycle_get(const mstab_solver *h, double *U, double *V, int64_t *level,
+                               int32_t *have);
+
+/*
+ * Install recycle data (F64 precision only): U, V device, n x s column-major,
+ * with V = A U expected (Algorithm 1's prior requirement); level is recorded.
+ */
+mstab_status mstab_recycle_set(mstab_solver *h, const double *U, const double *V, int64_t level);
+
+/* Free the handle and its device memory.  NULL is accepted. */
+mstab_status mstab_destroy(mstab_solver *h);
+
+const char *mstab_status_str(mstab_status s);
+const char *mstab_last_error(const mstab_solver *h);
+
+/*
+ * Kernel timing of the iteration (for roofline measurement): while enabled,
+ * every launch of the kernel classes below is bracketed by HIP events on the
+ * handle's stream; mstab_kernel_stats returns launch count, summed duration in
+ * ms and summed algorithmic bytes (reads + writes the kernel must make) for a
+ * class since the last enable.
+ */
+typedef enum {
+    MSTAB_K_SPMV = 0,          /* y = A x with the P-projection epilogue */
+    MSTAB_K_GAMMA = 1,         /* r^(i) -= V^(i) gamma, x += U gamma */
+    MSTAB_K_ETA = 2,           /* v_q^(i) := r^(i+1) - [..] eta_q */
+    MSTAB_K_GRAM = 3,          /* Z^T Z, Z^T r^(0) */
+    MSTAB_K_POLY = 4,          /* degree-l update of x, r, U, V with projections */
+    MSTAB_K_COUNT = 5
+} mstab_kernel_class;
+mstab_status mstab_set_profiling(mstab_solver *h, int32_t enable);
+mstab_status mstab_kernel_stats(const mstab_solver *h, int32_t kclass, int64_t *launches,
+                                double *ms, double *bytes);
+
+/*
+ * Assemble the upwind finite-difference matrix of
+ *   A = inv_dt I - div(kappa grad .) + beta . grad
+ * on the n^dim interior nodes of the unit square (dim 2) or cube (dim 3),
+ * x index fastest, homogeneous Dirichlet boundary, h = 1/(n+1).  Row entries in
+ * column order (-z, -y, -x, diagonal, +x, +y, +z).  kappa (device, n^dim) may be
+ * NULL for kappa = 1; face values are harmonic means, a boundary face takes
+ * the node's value.  Arithmetic order (no contraction):
+ *   diag = inv_dt + kf h^-2 over faces (-x,+x,-y,+y,-z,+z) + |beta_d| h^-1 over d
+ *   lower neighbour: -(kf h^-2) - max(beta_d,0) h^-1
+ *   upper neighbour: -(kf h^-2) + min(beta_d,0) h^-1
+ * beta: host, 3 doubles (beta[2] ignored in 2-D).  Output device arrays:
+ * row_ptr n^dim+1, col_idx and val with mstab_convdiff_nnz(dim, n) entries.
+ */
+int64_t mstab_convdiff_nnz(int32_t dim, int64_t n);
+mstab_status mstab_assemble_convdiff(int32_t dim, int64_t n, const double *beta, double inv_dt,
+                                     const double *kappa, int32_t *row_ptr, int32_t *col_idx,
+                                     double *val, void *hip_stream);
+
+/* y = A x (device, FP64), the plain sparse product used by the iteration. */
+mstab_status mstab_spmv(const mstab_csr *A, const double *x, double *y, void *hip_stream);
+
+/*
+ * out = P^T y for the cut-space basis of p_seed: y device (n doubles), out host
+ * (s doubles).  P entries are regenerated from the counter-based hash.
+ */
+mstab_status mstab_project(int64_t n, int32_t s, uint64_t p_seed, const double *y, double *out,
+                           void *hip_stream);
+
+/* Implicit Euler right-hand side b = x inv_dt + f (device, n doubles, no contraction). */
+mstab_status mstab_rhs_step(int64_t n, const double *x, double inv_dt, const double *f, double *b,
+                            void *hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MSTAB_H */

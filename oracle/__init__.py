@@ -62,6 +62,8 @@ def _load():
         _lib.orc_solve.restype = i32
         _lib.orc_solve.argtypes = [i64, P, P, P, i32, i32, P, f64, i64, i32, i32, f64, i64, i32,
                                    P, P, P, P, P, P, P, P, P, P, i64, P, i64, P]
+        _lib.orc_set_sum_order.restype = None
+        _lib.orc_set_sum_order.argtypes = [i32]
         _lib.orc_bicgstab.restype = i32
         _lib.orc_bicgstab.argtypes = [i64, P, P, P, P, P, P, i32]
     return _lib
@@ -219,6 +221,21 @@ def solve(A: CSR, b, x0, s: int, ell: int, P: np.ndarray, tol: float = 1e-8,
         V_u = take(n * s).reshape(s, n).copy()
         dd = dict(x=x_l, R=R, W=W, tau=tau, x_after=x_u, r_after=r_u, U_after=U_u, V_after=V_u)
     return x, info, recycle, dd
+
+
+class reversed_sums:
+    """Context: every inner product of the oracle sums from the last index down.
+
+    Same definition, other rounding order; comparing the two runs measures the
+    rounding sensitivity of the iteration itself."""
+
+    def __enter__(self):
+        _load().orc_set_sum_order(1)
+        return self
+
+    def __exit__(self, *exc):
+        _load().orc_set_sum_order(0)
+        return False
 
 
 def bicgstab(A: CSR, b, x0, rhat, iters: int) -> np.ndarray:

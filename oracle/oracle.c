@@ -171,10 +171,20 @@ void orc_spmv(int64_t n, const int32_t *rp, const int32_t *ci, const double *va,
     matvec(&A, x, y);
 }
 
+/* Inner products are plain sums; `sum_reverse` runs them from the last index
+ * to the first.  Both orders compute the same definition; the tests compare
+ * the two to measure how much the iteration amplifies rounding alone. */
+static int sum_reverse = 0;
+
+void orc_set_sum_order(int reverse) { sum_reverse = reverse ? 1 : 0; }
+
 static double dot(int64_t n, const double *a, const double *b)
 {
     double s = 0.0;
-    for (int64_t i = 0; i < n; ++i) s += a[i] * b[i];
+    if (sum_reverse)
+        for (int64_t i = n - 1; i >= 0; --i) s += a[i] * b[i];
+    else
+        for (int64_t i = 0; i < n; ++i) s += a[i] * b[i];
     return s;
 }
 

@@ -1,0 +1,950 @@
+// Device kernels of the M(s)stab(l) iteration for gfx950 (CDNA4).
+//
+// Notation follows Algorithm 1 of arXiv 1604.06043: levels r^(i) (R[i],
+// i = 0..l) of the residual and v_q^(i) (W[i][q], i = -1..l, q = 0..s-1) of the
+// s auxiliary vectors, with U = V^(-1) and V = V^(0).  Every vector is a
+// column of ld elements (ld a multiple of 256; entries n..ld-1 stay zero).
+//
+// Reductions are deterministic: each workgroup writes one partial per value
+// (value-major, [value][block]); the last workgroup to finish (found with an
+// agent-scope atomic counter) adds the partials in a fixed order, then one
+// thread runs the small FP64 solve that the next kernel needs (gamma, eta_q or
+// tau) and stores the coefficients in the control block.  No host round trip
+// happens inside a cycle.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mstab {
+
+constexpr int MAXS = 8;
+constexpr int MAXL = 8;
+constexpr int BLOCK = 256;
+constexpr int NWAVE = BLOCK / 64;
+
+enum : int32_t { FLAG_BREAKDOWN = 1, FLAG_NONFINITE = 2 };
+enum : int32_t { WHERE_NONE = 0, WHERE_GAMMA = 1, WHERE_ETA = 2, WHERE_TAU = 3, WHERE_ARNOLDI = 4 };
+
+// Copied to the host after every cycle.
+struct Status {
+    double rr;      // ||r||^2 of the recursive residual
+    double bb;      // ||b||^2
+    double tt;      // ||b - A x||^2 of the last true-residual kernel
+    double aux;     // Gram-Schmidt norm of the vector being orthonormalized
+    double aux0;    // norm^2 of the Arnoldi product before orthogonalization
+    int32_t flags;
+    int32_t where;
+    int64_t mv;     // products with A performed by the iteration kernels
+};
+
+struct Ctl {
+    Status st;
+    double thr2;                        // tol^2 ||b||^2, set by the host
+    double ptv[MAXL + 1][MAXS][MAXS];   // [i][q][a] = p_a . v_q^(i), i = 0..l
+    double ptr[MAXL + 1][MAXS];         // [i][a] = p_a . r^(i)
+    double ptt[MAXS];                   // P^T of the last true residual
+    double gamma[MAXS];
+    double eta[MAXS];
+    double tau[MAXL];
+    double h[MAXS + 1];                 // Gram-Schmidt coefficients
+    double prec[MAXS][MAXS];            // [q][a] = p_a . v_q of refreshed fetched data
+    unsigned int counter[4];            // last-workgroup counters (zero between launches)
+};
+
+// ---------------------------------------------------------------------------
+// Cut-space basis P: entry (row, q) regenerated from a counter-based hash
+// (MurmurHash3's 32-bit finalizer of key + (8 row + q) * 0x9E3779B9), top 24
+// bits mapped to [-1, 1).  Exact in FP32 and FP64; nothing is stored.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t fmix32(uint32_t h)
+{
+    h ^= h >> 16;
+    h *= 0x85EBCA6Bu;
+    h ^= h >> 13;
+    h *= 0xC2B2AE35u;
+    h ^= h >> 16;
+    return h;
+}
+
+__device__ __forceinline__ double pval(uint32_t key, uint32_t row, int q)
+{
+    uint32_t ctr = (row * 8u + (uint32_t)q) * 0x9E3779B9u + key;
+    int32_t t = (int32_t)(fmix32(ctr) >> 8) - (1 << 23);
+    return (double)t * 0x1p-23;
+}
+
+__device__ __forceinline__ double fmaT(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float fmaT(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+// ---------------------------------------------------------------------------
+// Small dense solves (FP64), cooperative in one wavefront: lane l holds entry
+// (i, j) = (l / 8, l % 8) of an m x m system (m <= 8) and y_i of its row.
+// Row exchanges and eliminations are lane shuffles; every lane executes the
+// same instruction stream, and the result is the same whichever wavefront runs
+// it.  The pivot is the first largest magnitude in the column (lowest row on
+// ties); a pivot <= 1e-14 times the largest magnitude of its column marks the
+// system singular.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double shfl_d(double v, int src) { return __shfl(v, src); }
+
+// Solves A c = y with partial pivoting; returns ok (uniform).  On return the
+// lanes of row i hold c_i in `c`.
+__device__ bool wave_lu(int m, double a, double y, double &c)
+{
+    const int lane = threadIdx.x & 63, i = lane >> 3, j = lane & 7;
+    const bool in = (i < m) && (j < m);
+    // largest magnitude of column j (xor over the row bits keeps j)
+    double cm = in ? fabs(a) : 0.0;
+    for (int o = 8; o < 64; o <<= 1) cm = fmax(cm, __shfl_xor(cm, o));
+    bool ok = true;
+    for (int k = 0; k < m; ++k) {
+        // pivot search among rows k..m-1 of column k
+        double v = (j == k && i >= k && i < m) ? fabs(a) : -1.0;
+        int vi = i;
+        for (int o = 8; o < 64; o <<= 1) {
+            const double v2 = __shfl_xor(v, o);
+            const int i2 = __shfl_xor(vi, o);
+            if (v2 > v || (v2 == v && i2 < vi)) { v = v2; vi = i2; }
+        }
+        const double best = __shfl(v, k);
+        const int piv = __shfl(vi, k);
+        ok = ok && (best > 1e-14 * __shfl(cm, k));
+        // exchange rows k and piv
+        const int src = (i == k) ? (piv * 8 + j) : ((i == piv) ? (k * 8 + j) : lane);
+        a = shfl_d(a, src);
+        y = shfl_d(y, src);
+        // eliminate below the pivot
+        const double inv = 1.0 / shfl_d(a, k * 8 + k);
+        const double aik = shfl_d(a, (i & 7) * 8 + k);
+        const double akj = shfl_d(a, k * 8 + j);
+        const double yk = shfl_d(y, k * 8);
+        const double f = aik * inv;
+        if (i > k && i < m) {
+            if (j > k && j < m) a = fma(-f, akj, a);
+            y = fma(-f, yk, y);
+        }
+    }
+    // back substitution, column by column
+    c = 0.0;
+    for (int k = m - 1; k >= 0; --k) {
+        const double ck = shfl_d(y, k * 8) / shfl_d(a, k * 8 + k);
+        const double aik = shfl_d(a, (i & 7) * 8 + k);
+        if (i < k) y = fma(-aik, ck, y);
+        if (i == k) c = ck;
+    }
+    return ok;
+}
+
+// Normal equations G t = c (G SPD): right-looking Cholesky, then the two
+// triangular solves; LU when G is not numerically SPD.
+__device__ bool wave_spd(int m, double g, double y, double &t)
+{
+    const int lane = threadIdx.x & 63, i = lane >> 3, j = lane & 7;
+    const double g0 = g, y0 = y;
+    bool spd = true;
+    for (int k = 0; k < m; ++k) {
+        const double akk = shfl_d(g, k * 8 + k);
+        spd = spd && (akk > 0.0);
+        const double lkk = sqrt(fmax(akk, 0.0));
+        // L_ik for this lane's row
+        const double lv = (i == k) ? lkk : ((i > k && i < m) ? shfl_d(g, (i & 7) * 8 + k) / lkk : 0.0);
+        const double ljk = shfl_d(lv, (j & 7) * 8);
+        if (i > k && j > k && i < m && j < m) g = fma(-lv, ljk, g);
+        if (j == k && i >= k) g = lv;
+    }
+    if (!spd) return wave_lu(m, g0, y0, t);
+    // forward: L z = y
+    for (int k = 0; k < m; ++k) {
+        const double zk = shfl_d(y, k * 8) / shfl_d(g, k * 8 + k);
+        const double lik = shfl_d(g, (i & 7) * 8 + k);
+        if (i > k && i < m) y = fma(-lik, zk, y);
+        if (i == k) y = zk;
+    }
+    // backward: L^T t = z
+    t = 0.0;
+    for (int k = m - 1; k >= 0; --k) {
+        const double tk = shfl_d(y, k * 8) / shfl_d(g, k * 8 + k);
+        const double lki = shfl_d(g, k * 8 + (i & 7));
+        if (i < k) y = fma(-lki, tk, y);
+        if (i == k) t = tk;
+    }
+    return true;
+}
+
+// Writes the solution of a projected system to out[0..m) (lane 8 i holds c_i),
+// zeroes on breakdown.  Called by the whole wavefront 0.
+__device__ __forceinline__ void wave_store(int m, bool ok, double c, double *out)
+{
+    const int lane = threadIdx.x & 63, i = lane >> 3, j = lane & 7;
+    if (j == 0 && i < m) out[i] = ok ? c : 0.0;
+}
+
+// ---------------------------------------------------------------------------
+// Last-workgroup reduction.
+//
+// The partials and the arrival counter are exchanged through agent-scope
+// atomic loads and stores, which are coherent across the device's dies
+// without the whole-cache write-back that an agent-scope fence costs here.
+// A writer waits for its partial stores to complete before the workgroup
+// barrier; thread 0 then bumps the counter.  The workgroup that sees the
+// count reach gridDim.x - 1 reads every partial (atomically, agent scope) and
+// adds them in a fixed order, so the totals do not depend on which workgroup
+// finishes last.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void part_store(double *p, double v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ double part_load(const double *p)
+{
+    return __hip_atomic_load(const_cast<double *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// wait until this thread's outstanding memory operations have completed
+__device__ __forceinline__ void wait_memory() { __builtin_amdgcn_s_waitcnt(0); }
+
+__device__ bool last_block_reduce(const double *part, int stride, int nv, unsigned int *counter,
+                                  double *tot)
+{
+    __shared__ int s_last;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned int prev = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_AGENT);
+        s_last = (prev == gridDim.x - 1);
+    }
+    __syncthreads();
+    if (!s_last) return false;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int nb = (int)gridDim.x;
+    for (int v = wave; v < nv; v += NWAVE) {
+        const double *pv = part + (size_t)v * stride;
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+        int b = lane;
+        for (; b + 192 < nb; b += 256) {
+            a0 += part_load(pv + b);
+            a1 += part_load(pv + b + 64);
+            a2 += part_load(pv + b + 128);
+            a3 += part_load(pv + b + 192);
+        }
+        for (; b < nb; b += 64) a0 += part_load(pv + b);
+        double acc = wave_sum((a0 + a1) + (a2 + a3));
+        if (lane == 0) tot[v] = acc;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0)
+        __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return true;
+}
+
+// Block-level sum of up to NV per-thread values into part[.][blockIdx.x].
+// vals[v] are per-thread contributions; the block result is written by
+// threads t < nv.
+template <int NV>
+__device__ void block_partials(double (&vals)[NV], int nv, double *part, int stride)
+{
+    __shared__ double s_red[NWAVE][NV];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        if (v < nv) {
+            double w = wave_sum(vals[v]);
+            if (lane == 0) s_red[wave][v] = w;
+        }
+    }
+    __syncthreads();
+    for (int v = threadIdx.x; v < nv; v += BLOCK) {
+        double a = 0.0;
+#pragma unroll
+        for (int w = 0; w < NWAVE; ++w) a += s_red[w][v];
+        part_store(part + (size_t)v * stride + blockIdx.x, a);
+    }
+    wait_memory();
+}
+
+// ---------------------------------------------------------------------------
+// Sparse product with projection epilogue: y = A x (or y = b - A x), then the
+// workgroup partials of P^T y (s values), ||y||^2 and ||b||^2.
+//
+// CSR-stream layout: a workgroup takes 256 consecutive rows; its threads form
+// the products val[k] * x[col[k]] of the rows' contiguous entry range with
+// coalesced loads into LDS, then thread t adds the products of row t in CSR
+// order.  Products are rounded, then added (contraction off), which is the
+// textbook order: the result equals a sequential CSR product bit for bit.
+// Ranges longer than CAP entries fall back to the same loop from global
+// memory.  Row t also owns the s projection terms p_a(row) y_row.
+// ---------------------------------------------------------------------------
+enum : int32_t {
+    ACT_NONE = 0,
+    ACT_RESID = 1,   // y = b - A x is the residual r^(0): ptr[0], rr, bb
+    ACT_TRUE = 2,    // y = b - A x is a true residual check: ptt, tt
+    ACT_R = 3,       // y = r^(k+1): ptr[k+1]; solve eta_1 of level k
+    ACT_V = 4,       // y = v_q^(k+1): ptv[k+1][q]; solve eta_{q+1} or gamma of level k+1
+    ACT_ARN = 5,     // y = v_q = A u_q (Arnoldi): ptv[0][q]
+    ACT_PROJ = 6,    // P^T y, ||y||^2 into ptt / tt (diagnostics)
+    ACT_RECV = 7     // y = A u_q of fetched data: prec[q]
+};
+
+struct SpmvArgs {
+    int32_t act, k, q, s, ell;
+    uint32_t pkey;
+};
+
+template <typename T, int CAP>
+__global__ __launch_bounds__(BLOCK) void k_spmv(int64_t n, const int32_t *__restrict__ rp,
+                                                const int32_t *__restrict__ ci,
+                                                const T *__restrict__ va, const T *__restrict__ x,
+                                                T *__restrict__ y, const T *__restrict__ b,
+                                                Ctl *ctl, double *part, int stride, SpmvArgs a)
+{
+#pragma clang fp contract(off)
+    if (ctl->st.flags) return;
+    __shared__ T s_prod[CAP];
+    __shared__ int32_t s_rp[BLOCK + 1];
+    const int tid = threadIdx.x;
+    const bool resid = (a.act == ACT_RESID || a.act == ACT_TRUE);
+
+    double vals[MAXS + 2];
+#pragma unroll
+    for (int v = 0; v < MAXS + 2; ++v) vals[v] = 0.0;
+
+    for (int64_t r0 = (int64_t)blockIdx.x * BLOCK; r0 < n; r0 += (int64_t)gridDim.x * BLOCK) {
+        const int rows = (int)((n - r0) < BLOCK ? (n - r0) : BLOCK);
+        __syncthreads();                      // readers of the previous chunk are done
+        if (tid < rows) s_rp[tid] = rp[r0 + tid];
+        if (tid == 0) s_rp[rows] = rp[r0 + rows];
+        __syncthreads();
+        const int32_t kb = s_rp[0];
+        const int32_t cnt = s_rp[rows] - kb;
+        const bool staged = cnt <= CAP;
+        if (staged) {
+            // all column/value loads first, then all gathers, then the products
+            constexpr int PER = CAP / BLOCK;
+            int32_t cix[PER];
+            T vv[PER], xv[PER];
+#pragma unroll
+            for (int m = 0; m < PER; ++m) {
+                const int32_t j = tid + m * BLOCK;
+                if (j < cnt) {
+                    cix[m] = ci[kb + j];
+                    vv[m] = va[kb + j];
+                }
+            }
+#pragma unroll
+            for (int m = 0; m < PER; ++m) {
+                const int32_t j = tid + m * BLOCK;
+                if (j < cnt) xv[m] = x[cix[m]];
+            }
+#pragma unroll
+            for (int m = 0; m < PER; ++m) {
+                const int32_t j = tid + m * BLOCK;
+                if (j < cnt) s_prod[j] = vv[m] * xv[m];
+            }
+        }
+        __syncthreads();
+        if (tid < rows) {
+            const int64_t r = r0 + tid;
+            const int32_t k0 = s_rp[tid], k1 = s_rp[tid + 1];
+            T sum = (T)0;
+            if (staged) {
+                for (int32_t kk = k0 - kb; kk < k1 - kb; ++kk) sum = sum + s_prod[kk];
+            } else {
+                for (int32_t kk = k0; kk < k1; ++kk) {
+                    const T prod = va[kk] * x[ci[kk]];
+                    sum = sum + prod;
+                }
+            }
+            T yv = sum;
+            if (resid) {
+                const T bv = b[r];
+                yv = bv - sum;
+                vals[MAXS + 1] += (double)bv * (double)bv;
+            }
+            y[r] = yv;
+            const double yd = (double)yv;
+            vals[MAXS] += yd * yd;
+#pragma unroll
+            for (int j = 0; j < MAXS; ++j)
+                if (j < a.s) vals[j] += pval(a.pkey, (uint32_t)r, j) * yd;
+        }
+    }
+    // pack: [P^T y (s), ||y||^2, ||b||^2]
+    double packed[MAXS + 2];
+#pragma unroll
+    for (int v = 0; v < MAXS + 2; ++v) packed[v] = 0.0;
+#pragma unroll
+    for (int j = 0; j < MAXS; ++j)
+        if (j < a.s) packed[j] = vals[j];
+#pragma unroll
+    for (int v = 0; v < MAXS + 2; ++v) {
+        if (v == a.s) packed[v] = vals[MAXS];
+        if (v == a.s + 1) packed[v] = vals[MAXS + 1];
+    }
+    const int nv = a.s + 2;
+    block_partials<MAXS + 2>(packed, nv, part, stride);
+
+    __shared__ double tot[MAXS + 2];
+    if (!last_block_reduce(part, stride, nv, &ctl->counter[0], tot)) return;
+    if (tid >= 64) return;   // wavefront 0 finalizes
+
+    const int lane = tid, ri = lane >> 3, cj = lane & 7;
+    const int s = a.s;
+    bool finite = true;
+    for (int v = 0; v < nv; ++v) finite = finite && isfinite(tot[v]);
+    int32_t flags = finite ? 0 : FLAG_NONFINITE, where = WHERE_NONE;
+    switch (a.act) {
+    case ACT_RESID:
+        if (lane < s) ctl->ptr[0][lane] = tot[lane];
+        if (lane == 0) {
+            ctl->st.rr = tot[s];
+            ctl->st.bb = tot[s + 1];
+            ctl->st.mv += 1;
+        }
+        break;
+    case ACT_TRUE:
+        if (lane < s) ctl->ptt[lane] = tot[lane];
+        if (lane == 0) {
+            ctl->st.tt = tot[s];
+            ctl->st.bb = tot[s + 1];
+        }
+        break;
+    case ACT_PROJ:
+        if (lane < s) ctl->ptt[lane] = tot[lane];
+        if (lane == 0) ctl->st.tt = tot[s];
+        break;
+    case ACT_ARN:
+        if (lane < s) ctl->ptv[0][a.q][lane] = tot[lane];
+        if (lane == 0) ctl->st.mv += 1;
+        break;
+    case ACT_RECV:
+        if (lane < s) ctl->prec[a.q][lane] = tot[lane];
+        if (lane == 0) ctl->st.mv += 1;
+        break;
+    case ACT_R: {
+        // y = r^(k+1); eta_1 of level k: (P^T V^(k)) eta = P^T r^(k+1)
+        if (lane < s) ctl->ptr[a.k + 1][lane] = tot[lane];
+        if (lane == 0) ctl->st.mv += 1;
+        if (!flags) {
+            const bool in = ri < s && cj < s;
+            const double m = in ? ctl->ptv[a.k][cj][ri] : 0.0;
+            const double yv = ri < s ? tot[ri] : 0.0;
+            double c;
+            const bool ok = wave_lu(s, m, yv, c);
+            wave_store(s, ok, c, ctl->eta);
+            if (!ok) { flags |= FLAG_BREAKDOWN; where = WHERE_ETA; }
+        }
+        break;
+    }
+    case ACT_V: {
+        // y = v_q^(k+1)
+        if (lane < s) ctl->ptv[a.k + 1][a.q][lane] = tot[lane];
+        if (lane == 0) ctl->st.mv += 1;
+        if (!flags && (a.q + 1 < s || a.k + 1 < a.ell)) {
+            const bool in = ri < s && cj < s;
+            double m = 0.0, yv = 0.0;
+            double *out;
+            int w;
+            if (a.q + 1 < s) {
+                // eta_{q+1} at level k: columns p <= q from level k+1, p > q from level k
+                if (in) m = (cj == a.q) ? tot[ri] : (cj < a.q ? ctl->ptv[a.k + 1][cj][ri]
+                                                              : ctl->ptv[a.k][cj][ri]);
+                out = ctl->eta;
+                w = WHERE_ETA;
+            } else {
+                // gamma of level k+1: (P^T V^(k+1)) gamma = P^T r^(k+1)
+                if (in) m = (cj == a.q) ? tot[ri] : ctl->ptv[a.k + 1][cj][ri];
+                out = ctl->gamma;
+                w = WHERE_GAMMA;
+            }
+            if (ri < s) yv = ctl->ptr[a.k + 1][ri];
+            double c;
+            const bool ok = wave_lu(s, m, yv, c);
+            wave_store(s, ok, c, out);
+            if (!ok) { flags |= FLAG_BREAKDOWN; where = w; }
+        }
+        break;
+    }
+    default:
+        break;
+    }
+    if (lane == 0 && flags) {
+        ctl->st.flags |= flags;
+        if (where) ctl->st.where = where;
+    }
+}
+
+// 16-byte vectors of T (2 doubles or 4 floats) for the streaming kernels.
+template <typename T> struct Vec16;
+template <> struct Vec16<double> { using type = double2; static constexpr int W = 2; };
+template <> struct Vec16<float> { using type = float4; static constexpr int W = 4; };
+
+template <typename T>
+__device__ __forceinline__ void ld16(const T *p, T (&v)[Vec16<T>::W])
+{
+    using VT = typename Vec16<T>::type;
+    const VT t = *reinterpret_cast<const VT *>(p);
+    __builtin_memcpy(v, &t, sizeof(VT));
+}
+
+template <typename T>
+__device__ __forceinline__ void st16(T *p, const T (&v)[Vec16<T>::W])
+{
+    using VT = typename Vec16<T>::type;
+    VT t;
+    __builtin_memcpy(&t, v, sizeof(VT));
+    *reinterpret_cast<VT *>(p) = t;
+}
+
+// ---------------------------------------------------------------------------
+// gamma step of level k:  r^(i) -= V^(i) gamma (i = 0..k),  x += U gamma.
+// Each thread handles one 16-byte vector of every column (ld is a multiple
+// of 256, so every column start is 16-byte aligned).
+// ---------------------------------------------------------------------------
+template <typename T, int S>
+__global__ __launch_bounds__(BLOCK) void k_gamma(int64_t ld, T *__restrict__ W, T *__restrict__ R,
+                                                 T *__restrict__ X, int k, const Ctl *ctl)
+{
+    if (ctl->st.flags) return;
+    constexpr int VW = Vec16<T>::W;
+    T g[S];
+#pragma unroll
+    for (int q = 0; q < S; ++q) g[q] = (T)ctl->gamma[q];
+    for (int64_t e = ((int64_t)blockIdx.x * BLOCK + threadIdx.x) * VW; e < ld;
+         e += (int64_t)gridDim.x * BLOCK * VW) {
+        for (int i = 0; i <= k; ++i) {
+            T acc[VW], w[VW];
+            ld16(R + i * ld + e, acc);
+            const T *Wi = W + (int64_t)(i + 1) * S * ld;
+#pragma unroll
+            for (int q = 0; q < S; ++q) {
+                ld16(Wi + q * ld + e, w);
+#pragma unroll
+                for (int c = 0; c < VW; ++c) acc[c] = fmaT(-g[q], w[c], acc[c]);
+            }
+            st16(R + i * ld + e, acc);
+        }
+        T acc[VW], w[VW];
+        ld16(X + e, acc);
+#pragma unroll
+        for (int q = 0; q < S; ++q) {
+            ld16(W + q * ld + e, w);
+#pragma unroll
+            for (int c = 0; c < VW; ++c) acc[c] = fmaT(g[q], w[c], acc[c]);
+        }
+        st16(X + e, acc);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// eta step (level k, column q):
+//   v_q^(i) := r^(i+1) - sum_{p<q} eta_p v_p^(i+1) - sum_{p>=q} eta_p v_p^(i),
+//   i = -1..k.  The old v_q^(i) is read before it is overwritten.
+// ---------------------------------------------------------------------------
+template <typename T, int S>
+__global__ __launch_bounds__(BLOCK) void k_eta(int64_t ld, T *__restrict__ W,
+                                               const T *__restrict__ R, int k, int q,
+                                               const Ctl *ctl)
+{
+    if (ctl->st.flags) return;
+    constexpr int VW = Vec16<T>::W;
+    T h[S];
+#pragma unroll
+    for (int p = 0; p < S; ++p) h[p] = (T)ctl->eta[p];
+    for (int64_t e = ((int64_t)blockIdx.x * BLOCK + threadIdx.x) * VW; e < ld;
+         e += (int64_t)gridDim.x * BLOCK * VW) {
+        for (int i = -1; i <= k; ++i) {
+            T acc[VW], w[VW];
+            ld16(R + (int64_t)(i + 1) * ld + e, acc);
+            const T *Wi = W + (int64_t)(i + 1) * S * ld;   // level i
+            const T *Wn = Wi + (int64_t)S * ld;            // level i + 1
+#pragma unroll
+            for (int p = 0; p < S; ++p) {
+                ld16(((p < q) ? Wn : Wi) + p * ld + e, w);
+#pragma unroll
+                for (int c = 0; c < VW; ++c) acc[c] = fmaT(-h[p], w[c], acc[c]);
+            }
+            st16(W + (int64_t)((i + 1) * S + q) * ld + e, acc);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Gram matrix of [r^(0), ..., r^(l)] (upper triangle, row-major pairs) and the
+// tau solve  (Z^T Z) tau = Z^T r^(0),  Z = [r^(1..l)].
+// ---------------------------------------------------------------------------
+template <typename T, int L>
+__global__ __launch_bounds__(BLOCK) void k_gram(int64_t ld, const T *__restrict__ R, Ctl *ctl,
+                                                double *part, int stride)
+{
+    if (ctl->st.flags) return;
+    constexpr int NV = (L + 1) * (L + 2) / 2;
+    constexpr int VW = Vec16<T>::W;
+    double acc[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) acc[v] = 0.0;
+    for (int64_t e = ((int64_t)blockIdx.x * BLOCK + threadIdx.x) * VW; e < ld;
+         e += (int64_t)gridDim.x * BLOCK * VW) {
+        T z[L + 1][VW];
+#pragma unroll
+        for (int i = 0; i <= L; ++i) ld16(R + i * ld + e, z[i]);
+#pragma unroll
+        for (int c = 0; c < VW; ++c) {
+            int v = 0;
+#pragma unroll
+            for (int i = 0; i <= L; ++i)
+#pragma unroll
+                for (int j = i; j <= L; ++j) acc[v++] += (double)z[i][c] * (double)z[j][c];
+        }
+    }
+    block_partials<NV>(acc, NV, part, stride);
+    __shared__ double tot[NV];
+    if (!last_block_reduce(part, stride, NV, &ctl->counter[1], tot)) return;
+    if (threadIdx.x >= 64) return;   // wavefront 0 finalizes
+    const int lane = threadIdx.x, ri = lane >> 3, cj = lane & 7;
+    // pair (i, j), i <= j, sits at index i*(L+1) - i*(i-1)/2 + (j - i)
+    auto at = [&](int i, int j) {
+        if (i > j) { int t = i; i = j; j = t; }
+        return tot[i * (L + 1) - i * (i - 1) / 2 + (j - i)];
+    };
+    bool finite = true;
+    for (int v = 0; v < NV; ++v) finite = finite && isfinite(tot[v]);
+    const double g = (ri < L && cj < L) ? at(ri + 1, cj + 1) : 0.0;
+    const double yv = ri < L ? at(0, ri + 1) : 0.0;
+    double t;
+    const bool ok = wave_spd(L, g, yv, t);
+    wave_store(L, ok, t, ctl->tau);
+    if (lane == 0) {
+        if (!finite) ctl->st.flags |= FLAG_NONFINITE;
+        if (!ok) {
+            ctl->st.flags |= FLAG_BREAKDOWN;
+            ctl->st.where = WHERE_TAU;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Degree-l update (x and u_q from the levels before r and v_q change):
+//   x   := x + sum_i tau_i r^(i-1)        r   := r^(0) - sum_i tau_i r^(i)
+//   u_q := v_q^(-1) - sum_i tau_i v_q^(i-1)   v_q := v_q^(0) - sum_i tau_i v_q^(i)
+// with the epilogue P^T r, P^T v_q, ||r||^2, then gamma of level 0 of the next
+// cycle (only when the residual is still above the threshold).
+// ---------------------------------------------------------------------------
+template <typename T, int S, int L>
+__global__ __launch_bounds__(BLOCK) void k_poly(int64_t n, int64_t ld, int ell_rt,
+                                                T *__restrict__ W, T *__restrict__ R,
+                                                T *__restrict__ X, uint32_t pkey, Ctl *ctl,
+                                                double *part, int stride)
+{
+    if (ctl->st.flags) return;
+    constexpr int NV = S + S * S + 1;
+    const int ell = L > 0 ? L : ell_rt;     // compile-time degree lets every load issue up front
+    T tau[MAXL];
+#pragma unroll
+    for (int i = 0; i < MAXL; ++i) tau[i] = (i < ell) ? (T)ctl->tau[i] : (T)0;
+    double acc[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) acc[v] = 0.0;
+    for (int64_t e = (int64_t)blockIdx.x * BLOCK + threadIdx.x; e < ld;
+         e += (int64_t)gridDim.x * BLOCK) {
+        double p[S];
+#pragma unroll
+        for (int a = 0; a < S; ++a) p[a] = (e < n) ? pval(pkey, (uint32_t)e, a) : 0.0;
+        // x and r
+        {
+            T xa = X[e];
+            T ra = R[e];
+            T prev = ra;
+#pragma unroll
+            for (int i = 1; i <= (L > 0 ? L : MAXL); ++i) {
+                if (L == 0 && i > ell) break;
+                const T ri = R[(int64_t)i * ld + e];
+                xa = fmaT(tau[i - 1], prev, xa);
+                ra = fmaT(-tau[i - 1], ri, ra);
+                prev = ri;
+            }
+            X[e] = xa;
+            R[e] = ra;
+            const double rd = (double)ra;
+#pragma unroll
+            for (int a = 0; a < S; ++a) acc[a] += p[a] * rd;
+            acc[S + S * S] += rd * rd;
+        }
+#pragma unroll
+        for (int q = 0; q < S; ++q) {
+            T ua = W[(int64_t)q * ld + e];              // v_q^(-1)
+            T prev = W[(int64_t)(S + q) * ld + e];      // v_q^(0)
+            T va = prev;
+#pragma unroll
+            for (int i = 1; i <= (L > 0 ? L : MAXL); ++i) {
+                if (L == 0 && i > ell) break;
+                const T vi = W[(int64_t)((i + 1) * S + q) * ld + e];
+                ua = fmaT(-tau[i - 1], prev, ua);
+                va = fmaT(-tau[i - 1], vi, va);
+                prev = vi;
+            }
+            W[(int64_t)q * ld + e] = ua;
+            W[(int64_t)(S + q) * ld + e] = va;
+            const double vd = (double)va;
+#pragma unroll
+            for (int a = 0; a < S; ++a) acc[S + q * S + a] += p[a] * vd;
+        }
+    }
+    block_partials<NV>(acc, NV, part, stride);
+    __shared__ double tot[NV];
+    if (!last_block_reduce(part, stride, NV, &ctl->counter[2], tot)) return;
+    if (threadIdx.x >= 64) return;   // wavefront 0 finalizes
+    const int lane = threadIdx.x, ri = lane >> 3, cj = lane & 7;
+    bool finite = true;
+    for (int v = 0; v < NV; ++v) finite = finite && isfinite(tot[v]);
+    if (lane < S) ctl->ptr[0][lane] = tot[lane];
+    for (int idx = lane; idx < S * S; idx += 64) ctl->ptv[0][idx / S][idx % S] = tot[S + idx];
+    const double rr = tot[S + S * S];
+    if (lane == 0) {
+        ctl->st.rr = rr;
+        if (!finite) ctl->st.flags |= FLAG_NONFINITE;
+    }
+    if (!finite || !(rr > ctl->thr2)) return;
+    // gamma of level 0 of the next cycle: (P^T V) gamma = P^T r
+    const bool in = ri < S && cj < S;
+    const double m = in ? tot[S + cj * S + ri] : 0.0;
+    const double yv = ri < S ? tot[ri] : 0.0;
+    double c;
+    const bool ok = wave_lu(S, m, yv, c);
+    wave_store(S, ok, c, ctl->gamma);
+    if (lane == 0 && !ok) {
+        ctl->st.flags |= FLAG_BREAKDOWN;
+        ctl->st.where = WHERE_GAMMA;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Single-thread control steps.
+// ---------------------------------------------------------------------------
+enum : int32_t {
+    SMALL_GAMMA0 = 0,          // gamma of level 0 from ptv[0], ptr[0]
+    SMALL_REPLACE = 1,         // r := true residual: ptr[0] = ptt, rr = tt, then gamma
+    SMALL_CLEAR = 2            // clear flags
+};
+
+__global__ void k_set_thr2(Ctl *ctl, double thr2)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) ctl->thr2 = thr2;
+}
+
+// One wavefront (launch with 64 threads).
+__global__ void k_small(Ctl *ctl, int s, int what)
+{
+    const int lane = threadIdx.x, ri = lane >> 3, cj = lane & 7;
+    if (what == SMALL_CLEAR) {
+        if (lane == 0) {
+            ctl->st.flags = 0;
+            ctl->st.where = WHERE_NONE;
+        }
+        return;
+    }
+    const double *rhs = ctl->ptr[0];
+    double rr = ctl->st.rr;
+    if (what == SMALL_REPLACE) {
+        rhs = ctl->ptt;
+        rr = ctl->st.tt;
+        if (lane < s) ctl->ptr[0][lane] = ctl->ptt[lane];
+        if (lane == 0) ctl->st.rr = rr;
+    }
+    if (ctl->st.flags) return;
+    if (!(rr > ctl->thr2)) return;
+    const bool in = ri < s && cj < s;
+    const double m = in ? ctl->ptv[0][cj][ri] : 0.0;
+    const double yv = ri < s ? rhs[ri] : 0.0;
+    double c;
+    const bool ok = wave_lu(s, m, yv, c);
+    wave_store(s, ok, c, ctl->gamma);
+    if (lane == 0 && !ok) {
+        ctl->st.flags |= FLAG_BREAKDOWN;
+        ctl->st.where = WHERE_GAMMA;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Arnoldi (classical Gram-Schmidt applied twice) helpers.
+// ---------------------------------------------------------------------------
+
+// h_j = u_j . w (j < nu) and ||w||^2 into ctl->h / ctl->st.aux; slot 0 keeps the
+// norm in aux0 as well (first pass: norm of the fresh product).
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_dots(int64_t ld, const T *__restrict__ U, int nu,
+                                                const T *__restrict__ w, int first, Ctl *ctl,
+                                                double *part, int stride)
+{
+    if (ctl->st.flags) return;
+    double acc[MAXS + 1];
+#pragma unroll
+    for (int v = 0; v <= MAXS; ++v) acc[v] = 0.0;
+    for (int64_t e = (int64_t)blockIdx.x * BLOCK + threadIdx.x; e < ld;
+         e += (int64_t)gridDim.x * BLOCK) {
+        const double wv = (double)w[e];
+#pragma unroll
+        for (int j = 0; j < MAXS; ++j)
+            if (j < nu) acc[j] += (double)U[(int64_t)j * ld + e] * wv;
+        acc[MAXS] += wv * wv;
+    }
+    // pack [h_0..h_{nu-1}, norm]
+    double vals[MAXS + 1];
+#pragma unroll
+    for (int v = 0; v <= MAXS; ++v) vals[v] = 0.0;
+#pragma unroll
+    for (int j = 0; j < MAXS; ++j)
+        if (j < nu) vals[j] = acc[j];
+    // norm goes to index nu
+#pragma unroll
+    for (int j = 0; j <= MAXS; ++j)
+        if (j == nu) vals[j] = acc[MAXS];
+    block_partials<MAXS + 1>(vals, nu + 1, part, stride);
+    __shared__ double tot[MAXS + 1];
+    if (!last_block_reduce(part, stride, nu + 1, &ctl->counter[3], tot)) return;
+    if (threadIdx.x != 0) return;
+    for (int j = 0; j < nu; ++j) ctl->h[j] = tot[j];
+    ctl->st.aux = tot[nu];
+    if (first) ctl->st.aux0 = tot[nu];
+    if (!isfinite(tot[nu])) ctl->st.flags |= FLAG_NONFINITE;
+}
+
+// out = w - sum_j h_j u_j
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_gs(int64_t ld, const T *__restrict__ U, int nu,
+                                              const T *w, T *out, const Ctl *ctl)
+{
+    if (ctl->st.flags) return;
+    T h[MAXS];
+#pragma unroll
+    for (int j = 0; j < MAXS; ++j) h[j] = (j < nu) ? (T)ctl->h[j] : (T)0;
+    for (int64_t e = (int64_t)blockIdx.x * BLOCK + threadIdx.x; e < ld;
+         e += (int64_t)gridDim.x * BLOCK) {
+        T a = w[e];
+#pragma unroll
+        for (int j = 0; j < MAXS; ++j)
+            if (j < nu) a = fmaT(-h[j], U[(int64_t)j * ld + e], a);
+        out[e] = a;
+    }
+}
+
+// dst = src / sqrt(norm2), norm2 = st.aux (mode 0) or st.rr (mode 1).  In mode 0
+// a norm below 1e-14 of the product's norm is an Arnoldi breakdown.
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_normalize(int64_t ld, const T *src, T *dst, int mode,
+                                                     Ctl *ctl)
+{
+    if (ctl->st.flags) return;
+    const double nrm2 = mode == 0 ? ctl->st.aux : ctl->st.rr;
+    if (mode == 0 && !(nrm2 > 1e-28 * ctl->st.aux0)) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            ctl->st.flags |= FLAG_BREAKDOWN;
+            ctl->st.where = WHERE_ARNOLDI;
+        }
+        return;
+    }
+    if (!(nrm2 > 0.0)) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            ctl->st.flags |= FLAG_BREAKDOWN;
+            ctl->st.where = WHERE_ARNOLDI;
+        }
+        return;
+    }
+    const T inv = (T)(1.0 / sqrt(nrm2));
+    for (int64_t e = (int64_t)blockIdx.x * BLOCK + threadIdx.x; e < ld;
+         e += (int64_t)gridDim.x * BLOCK)
+        dst[e] = src[e] * inv;
+}
+
+// ---------------------------------------------------------------------------
+// Elementwise helpers.
+// ---------------------------------------------------------------------------
+template <typename TD, typename TS>
+__global__ __launch_bounds__(BLOCK) void k_copy_cast(int64_t n, const TS *__restrict__ src,
+                                                     TD *__restrict__ dst)
+{
+    for (int64_t e = (int64_t)blockIdx.x * BLOCK + threadIdx.x; e < n;
+         e += (int64_t)gridDim.x * BLOCK)
+        dst[e] = (TD)src[e];
+}
+
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_fill(int64_t n, T *dst, T v)
+{
+    for (int64_t e = (int64_t)blockIdx.x * BLOCK + threadIdx.x; e < n;
+         e += (int64_t)gridDim.x * BLOCK)
+        dst[e] = v;
+}
+
+// r32 = (float)(r64 * inv_sigma)
+__global__ __launch_bounds__(BLOCK) void k_scale_to_f32(int64_t n, const double *__restrict__ r,
+                                                        double inv_sigma, float *__restrict__ out)
+{
+    for (int64_t e = (int64_t)blockIdx.x * BLOCK + threadIdx.x; e < n;
+         e += (int64_t)gridDim.x * BLOCK)
+        out[e] = (float)(r[e] * inv_sigma);
+}
+
+// x64 += sigma * (double)d32
+__global__ __launch_bounds__(BLOCK) void k_correct(int64_t n, const float *__restrict__ d,
+                                                   double sigma, double *__restrict__ x)
+{
+    for (int64_t e = (int64_t)blockIdx.x * BLOCK + threadIdx.x; e < n;
+         e += (int64_t)gridDim.x * BLOCK)
+        x[e] = fma(sigma, (double)d[e], x[e]);
+}
+
+// P^T y and ||y||^2 of one vector.  dst 0: ptv[0][q] (recycled V); dst 1: ptt, tt.
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_project(int64_t n, const T *__restrict__ y,
+                                                   uint32_t pkey, int s, int dst, int q, Ctl *ctl,
+                                                   double *part, int stride)
+{
+    double acc[MAXS + 1];
+#pragma unroll
+    for (int v = 0; v <= MAXS; ++v) acc[v] = 0.0;
+    for (int64_t e = (int64_t)blockIdx.x * BLOCK + threadIdx.x; e < n;
+         e += (int64_t)gridDim.x * BLOCK) {
+        const double yv = (double)y[e];
+#pragma unroll
+        for (int a = 0; a < MAXS; ++a)
+            if (a < s) acc[a] += pval(pkey, (uint32_t)e, a) * yv;
+        acc[MAXS] += yv * yv;
+    }
+    double vals[MAXS + 1];
+#pragma unroll
+    for (int v = 0; v <= MAXS; ++v) vals[v] = (v < s) ? acc[v] : ((v == s) ? acc[MAXS] : 0.0);
+    block_partials<MAXS + 1>(vals, s + 1, part, stride);
+    __shared__ double tot[MAXS + 1];
+    if (!last_block_reduce(part, stride, s + 1, &ctl->counter[3], tot)) return;
+    if (threadIdx.x != 0) return;
+    if (dst == 0) {
+        for (int a = 0; a < s; ++a) ctl->ptv[0][q][a] = tot[a];
+    } else {
+        for (int a = 0; a < s; ++a) ctl->ptt[a] = tot[a];
+        ctl->st.tt = tot[s];
+    }
+}
+
+// Implicit Euler right-hand side b = x inv_dt + f, multiply then add (no contraction).
+__global__ __launch_bounds__(BLOCK) void k_rhs_step(int64_t n, const double *__restrict__ x,
+                                                    double inv_dt, const double *__restrict__ f,
+                                                    double *__restrict__ b)
+{
+#pragma clang fp contract(off)
+    for (int64_t e = (int64_t)blockIdx.x * BLOCK + threadIdx.x; e < n;
+         e += (int64_t)gridDim.x * BLOCK) {
+        const double t = x[e] * inv_dt;
+        b[e] = t + f[e];
+    }
+}
+
+}  // namespace mstab

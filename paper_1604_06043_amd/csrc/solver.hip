@@ -1,0 +1,1143 @@
+// Host side of the M(s)stab(l) / IDR(s)stab(l) solver and its C ABI.
+//
+// One Engine<T> runs Algorithm 1 of arXiv 1604.06043 in precision T with all
+// state on the device; the host only enqueues kernels and reads a 56-byte
+// status block once per cycle.  The FP64 mode runs Engine<double> on the
+// system itself; the mixed mode runs Engine<float> on FP64 residual-correction
+// equations (defect correction with the FP64 true residual), keeping the FP32
+// recycle data across correction steps and systems.
+#include "kernels.hpp"
+#include "mstab.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+using namespace mstab;
+
+namespace {
+
+thread_local std::string g_tls_error;
+
+struct HipError {
+    hipError_t e;
+    const char *what;
+};
+
+#define HIPCHK(call)                                              \
+    do {                                                          \
+        hipError_t e_ = (call);                                   \
+        if (e_ != hipSuccess) throw HipError{e_, #call};          \
+    } while (0)
+
+struct StatusError {
+    mstab_status st;
+    std::string msg;
+};
+
+[[noreturn]] void fail(mstab_status st, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    throw StatusError{st, buf};
+}
+
+uint64_t mix64(uint64_t z)
+{
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// 32-bit key of P: low word of the start of splitmix64 stream 3 of the seed.
+uint32_t p_key_from_seed(uint64_t seed)
+{
+    const uint64_t stream = 3;   // the P stream
+    return (uint32_t)(mix64(seed ^ mix64(stream + 1)) & 0xFFFFFFFFull);
+}
+
+int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
+
+int grid_for(int64_t work, int per_block, int cap)
+{
+    int64_t g = (work + per_block - 1) / per_block;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (int)g;
+}
+
+constexpr int SPMV_MAX_BLOCKS = 2048;
+constexpr int VEC_MAX_BLOCKS = 8192;
+constexpr int GRAM_MAX_BLOCKS = 2048;
+constexpr int POLY_MAX_BLOCKS = 512;
+constexpr int PART_STRIDE = 8192;              // >= every reduction grid
+constexpr int PART_VALUES = MAXS + MAXS * MAXS + 1;
+
+// ---------------------------------------------------------------------------
+// Kernel timing for the roofline report.
+// ---------------------------------------------------------------------------
+struct Profiler {
+    bool on = false;
+    hipStream_t stream = nullptr;
+    std::vector<hipEvent_t> ev;     // 2 per slot
+    std::vector<int> cls;
+    std::vector<double> bytes;
+    int used = 0;
+    int64_t launches[MSTAB_K_COUNT] = {};
+    double ms[MSTAB_K_COUNT] = {};
+    double nbytes[MSTAB_K_COUNT] = {};
+
+    void init(hipStream_t s)
+    {
+        stream = s;
+        ev.resize(2 * 512);
+        cls.resize(512);
+        bytes.resize(512);
+        for (auto &e : ev) HIPCHK(hipEventCreate(&e));
+    }
+    void destroy()
+    {
+        for (auto &e : ev) (void)hipEventDestroy(e);
+        ev.clear();
+    }
+    void reset()
+    {
+        used = 0;
+        for (int c = 0; c < MSTAB_K_COUNT; ++c) { launches[c] = 0; ms[c] = 0; nbytes[c] = 0; }
+    }
+    // returns slot or -1
+    int begin(int c, double b)
+    {
+        if (!on) return -1;
+        if (used == (int)cls.size()) harvest();
+        int i = used++;
+        cls[i] = c;
+        bytes[i] = b;
+        HIPCHK(hipEventRecord(ev[2 * i], stream));
+        return i;
+    }
+    void end(int i)
+    {
+        if (i >= 0) HIPCHK(hipEventRecord(ev[2 * i + 1], stream));
+    }
+    void harvest()
+    {
+        if (used == 0) return;
+        HIPCHK(hipEventSynchronize(ev[2 * (used - 1) + 1]));
+        for (int i = 0; i < used; ++i) {
+            float t = 0.f;
+            HIPCHK(hipEventElapsedTime(&t, ev[2 * i], ev[2 * i + 1]));
+            launches[cls[i]] += 1;
+            ms[cls[i]] += t;
+            nbytes[cls[i]] += bytes[i];
+        }
+        used = 0;
+    }
+};
+
+// Largest number of entries in a chunk of BLOCK consecutive rows (setup only).
+int64_t max_block_entries(const int32_t *rp, int64_t n, hipStream_t st)
+{
+    std::vector<int32_t> h((size_t)n + 1);
+    HIPCHK(hipMemcpyAsync(h.data(), rp, sizeof(int32_t) * (n + 1), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    int64_t best = 0;
+    for (int64_t r0 = 0; r0 < n; r0 += BLOCK) {
+        const int64_t r1 = std::min<int64_t>(n, r0 + BLOCK);
+        best = std::max<int64_t>(best, (int64_t)h[r1] - h[r0]);
+    }
+    return best;
+}
+
+template <typename T>
+void launch_spmv(bool wide, int grid, hipStream_t stream, int64_t n, const int32_t *rp,
+                 const int32_t *ci, const T *va, const T *x, T *y, const T *b, Ctl *ctl,
+                 double *part, SpmvArgs a)
+{
+    if (wide)
+        hipLaunchKernelGGL((k_spmv<T, 4096>), dim3(grid), dim3(BLOCK), 0, stream, n, rp, ci, va,
+                           x, y, b, ctl, part, PART_STRIDE, a);
+    else
+        hipLaunchKernelGGL((k_spmv<T, 2048>), dim3(grid), dim3(BLOCK), 0, stream, n, rp, ci, va,
+                           x, y, b, ctl, part, PART_STRIDE, a);
+}
+
+struct SolveResult {
+    int status = MSTAB_OK;
+    bool converged = false;
+    bool recycled = false;
+    int restarts = 0;
+    int replacements = 0;
+    int64_t mv = 0, mv_check = 0, cycles = 0, level = 0, fetched = -1;
+    double relres_rec = 0, relres_true = -1;
+};
+
+// ---------------------------------------------------------------------------
+// Engine<T>: Algorithm 1 with recycling, precision T, device-resident state.
+// ---------------------------------------------------------------------------
+template <typename T>
+struct Engine {
+    int s = 0, ell = 0;
+    bool wide = false;                 // some 256-row block has more than 2048 entries
+    int64_t n = 0, ld = 0, nnz = 0;
+    const int32_t *rp = nullptr, *ci = nullptr;
+    const T *va = nullptr;
+    uint32_t pkey = 0;
+    hipStream_t stream = nullptr;
+
+    T *W = nullptr, *R = nullptr, *X = nullptr, *Tv = nullptr;
+    T *recU = nullptr, *recV = nullptr;
+    double *rec_ptv = nullptr;         // device, MAXS*MAXS
+    int64_t rec_level = 0;
+    bool rec_have = false;
+
+    Ctl *ctl = nullptr;
+    Status *st_host = nullptr;         // pinned
+    double *part = nullptr;
+    Profiler *prof = nullptr;
+
+    std::vector<int64_t> hist_mv;
+    std::vector<double> hist_res;
+
+    T *Wc(int lev, int q) const { return W + ((int64_t)(lev + 1) * s + q) * ld; }
+    T *Rc(int i) const { return R + (int64_t)i * ld; }
+
+    // full = false: only what the FP64 outer loop of the mixed mode needs
+    void alloc(int64_t n_, int s_, int ell_, const int32_t *rp_, const int32_t *ci_, const T *va_,
+               int64_t nnz_, uint32_t key, hipStream_t st, Profiler *pr, bool full = true)
+    {
+        n = n_; s = s_; ell = ell_; rp = rp_; ci = ci_; va = va_; nnz = nnz_;
+        pkey = key; stream = st; prof = pr;
+        ld = round_up(n, 256);
+        wide = max_block_entries(rp, n, st) > 2048;
+        const size_t vb = (size_t)ld * sizeof(T);
+        HIPCHK(hipMalloc(&X, vb));
+        HIPCHK(hipMalloc(&Tv, vb));
+        HIPCHK(hipMalloc(&ctl, sizeof(Ctl)));
+        HIPCHK(hipMalloc(&part, sizeof(double) * (size_t)PART_STRIDE * PART_VALUES));
+        HIPCHK(hipHostMalloc(&st_host, sizeof(Status), hipHostMallocDefault));
+        HIPCHK(hipMemsetAsync(X, 0, vb, stream));
+        HIPCHK(hipMemsetAsync(Tv, 0, vb, stream));
+        HIPCHK(hipMemsetAsync(ctl, 0, sizeof(Ctl), stream));
+        if (full) {
+            HIPCHK(hipMalloc(&W, vb * s * (ell + 2)));
+            HIPCHK(hipMalloc(&R, vb * (ell + 1)));
+            HIPCHK(hipMalloc(&recU, vb * s));
+            HIPCHK(hipMalloc(&recV, vb * s));
+            HIPCHK(hipMalloc(&rec_ptv, sizeof(double) * MAXS * MAXS));
+            HIPCHK(hipMemsetAsync(W, 0, vb * s * (ell + 2), stream));
+            HIPCHK(hipMemsetAsync(R, 0, vb * (ell + 1), stream));
+            HIPCHK(hipMemsetAsync(recU, 0, vb * s, stream));
+            HIPCHK(hipMemsetAsync(recV, 0, vb * s, stream));
+        }
+        HIPCHK(hipStreamSynchronize(stream));
+    }
+
+    void release()
+    {
+        (void)hipFree(W); (void)hipFree(R); (void)hipFree(X); (void)hipFree(Tv);
+        (void)hipFree(recU); (void)hipFree(recV); (void)hipFree(rec_ptv);
+        (void)hipFree(ctl); (void)hipFree(part);
+        if (st_host) (void)hipHostFree(st_host);
+        W = R = X = Tv = recU = recV = nullptr;
+        rec_ptv = nullptr; ctl = nullptr; part = nullptr; st_host = nullptr;
+    }
+
+    // ---- launches ---------------------------------------------------------
+    double vbytes(double vectors) const { return vectors * (double)n * sizeof(T); }
+
+    void spmv(const T *x, T *y, const T *b, int act, int k, int q)
+    {
+        SpmvArgs a{act, k, q, s, ell, pkey};
+        const int grid = grid_for(n, BLOCK, SPMV_MAX_BLOCKS);
+        const double bytes = (double)(n + 1) * 4 + (double)nnz * (4 + sizeof(T)) +
+                             vbytes(b ? 3 : 2);
+        int slot = prof ? prof->begin(MSTAB_K_SPMV, bytes) : -1;
+        launch_spmv<T>(wide, grid, stream, n, rp, ci, va, x, y, b, ctl, part, a);
+        HIPCHK(hipGetLastError());
+        if (prof) prof->end(slot);
+    }
+
+    void gamma(int k)
+    {
+        const int grid = grid_for(ld / Vec16<T>::W, BLOCK, VEC_MAX_BLOCKS);
+        int slot = prof ? prof->begin(MSTAB_K_GAMMA, vbytes((k + 1) * (s + 2) + s + 2)) : -1;
+        switch (s) {
+#define CASE(S)                                                                              \
+    case S:                                                                                  \
+        hipLaunchKernelGGL((k_gamma<T, S>), dim3(grid), dim3(BLOCK), 0, stream, ld, W, R, X, \
+                           k, ctl);                                                          \
+        break;
+            CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
+#undef CASE
+        }
+        HIPCHK(hipGetLastError());
+        if (prof) prof->end(slot);
+    }
+
+    void eta(int k, int q)
+    {
+        const int grid = grid_for(ld / Vec16<T>::W, BLOCK, VEC_MAX_BLOCKS);
+        int slot = prof ? prof->begin(MSTAB_K_ETA, vbytes((k + 2) * (s + 2))) : -1;
+        switch (s) {
+#define CASE(S)                                                                               \
+    case S:                                                                                   \
+        hipLaunchKernelGGL((k_eta<T, S>), dim3(grid), dim3(BLOCK), 0, stream, ld, W, R, k, q, \
+                           ctl);                                                              \
+        break;
+            CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
+#undef CASE
+        }
+        HIPCHK(hipGetLastError());
+        if (prof) prof->end(slot);
+    }
+
+    void gram()
+    {
+        const int grid = grid_for(ld / Vec16<T>::W, BLOCK, GRAM_MAX_BLOCKS);
+        int slot = prof ? prof->begin(MSTAB_K_GRAM, vbytes(ell + 1)) : -1;
+        switch (ell) {
+#define CASE(L)                                                                                 \
+    case L:                                                                                     \
+        hipLaunchKernelGGL((k_gram<T, L>), dim3(grid), dim3(BLOCK), 0, stream, ld, R, ctl, part, \
+                           PART_STRIDE);                                                        \
+        break;
+            CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
+#undef CASE
+        }
+        HIPCHK(hipGetLastError());
+        if (prof) prof->end(slot);
+    }
+
+    template <int S>
+    void poly_s(int grid)
+    {
+        switch (ell) {
+#define CASE(L)                                                                              \
+    case L:                                                                                  \
+        hipLaunchKernelGGL((k_poly<T, S, L>), dim3(grid), dim3(BLOCK), 0, stream, n, ld, ell, \
+                           W, R, X, pkey, ctl, part, PART_STRIDE);                           \
+        break;
+            CASE(1) CASE(2) CASE(3) CASE(4)
+#undef CASE
+        default:
+            hipLaunchKernelGGL((k_poly<T, S, 0>), dim3(grid), dim3(BLOCK), 0, stream, n, ld, ell,
+                               W, R, X, pkey, ctl, part, PART_STRIDE);
+        }
+    }
+
+    void poly()
+    {
+        const int grid = grid_for(ld, BLOCK, POLY_MAX_BLOCKS);
+        int slot = prof ? prof->begin(MSTAB_K_POLY,
+                                      vbytes(1 + (ell + 1) + s * (ell + 2) + 2 * s + 2))
+                        : -1;
+        switch (s) {
+        case 1: poly_s<1>(grid); break;
+        case 2: poly_s<2>(grid); break;
+        case 3: poly_s<3>(grid); break;
+        case 4: poly_s<4>(grid); break;
+        case 5: poly_s<5>(grid); break;
+        case 6: poly_s<6>(grid); break;
+        case 7: poly_s<7>(grid); break;
+        default: poly_s<8>(grid); break;
+        }
+        HIPCHK(hipGetLastError());
+        if (prof) prof->end(slot);
+    }
+
+    // P^T y (and ||y||^2): dst 0 -> ptv[0][q]; dst 1 -> ptt, tt
+    void project(const T *y, int dst, int q)
+    {
+        const int grid = grid_for(n, BLOCK, GRAM_MAX_BLOCKS);
+        hipLaunchKernelGGL((k_project<T>), dim3(grid), dim3(BLOCK), 0, stream, n, y, pkey, s, dst,
+                           q, ctl, part, PART_STRIDE);
+        HIPCHK(hipGetLastError());
+    }
+
+    void small(int what)
+    {
+        hipLaunchKernelGGL(k_small, dim3(1), dim3(64), 0, stream, ctl, s, what);
+        HIPCHK(hipGetLastError());
+    }
+
+    void dots(const T *U, int nu, const T *w, int first)
+    {
+        const int grid = grid_for(ld, BLOCK, GRAM_MAX_BLOCKS);
+        hipLaunchKernelGGL((k_dots<T>), dim3(grid), dim3(BLOCK), 0, stream, ld, U, nu, w, first,
+                           ctl, part, PART_STRIDE);
+        HIPCHK(hipGetLastError());
+    }
+
+    void gs(const T *U, int nu, const T *w, T *out)
+    {
+        const int grid = grid_for(ld, BLOCK, VEC_MAX_BLOCKS);
+        hipLaunchKernelGGL((k_gs<T>), dim3(grid), dim3(BLOCK), 0, stream, ld, U, nu, w, out, ctl);
+        HIPCHK(hipGetLastError());
+    }
+
+    void normalize(const T *src, T *dst, int mode)
+    {
+        const int grid = grid_for(ld, BLOCK, VEC_MAX_BLOCKS);
+        hipLaunchKernelGGL((k_normalize<T>), dim3(grid), dim3(BLOCK), 0, stream, ld, src, dst,
+                           mode, ctl);
+        HIPCHK(hipGetLastError());
+    }
+
+    void fill(T *dst, int64_t count, T v)
+    {
+        const int grid = grid_for(count, BLOCK, VEC_MAX_BLOCKS);
+        hipLaunchKernelGGL((k_fill<T>), dim3(grid), dim3(BLOCK), 0, stream, count, dst, v);
+        HIPCHK(hipGetLastError());
+    }
+
+    void sync_status()
+    {
+        HIPCHK(hipMemcpyAsync(st_host, &ctl->st, sizeof(Status), hipMemcpyDeviceToHost, stream));
+        HIPCHK(hipStreamSynchronize(stream));
+        if (prof) prof->harvest();
+    }
+
+    void set_thr2(double thr2)
+    {
+        hipLaunchKernelGGL(k_set_thr2, dim3(1), dim3(64), 0, stream, ctl, thr2);
+        HIPCHK(hipGetLastError());
+    }
+
+    // Arnoldi basis of level s of r = R[0] (norm^2 in st.rr): U orthonormal, V = A U.
+    void arnoldi()
+    {
+        normalize(Rc(0), Wc(-1, 0), 1);
+        for (int q = 0; q < s; ++q) {
+            spmv(Wc(-1, q), Wc(0, q), nullptr, ACT_ARN, 0, q);
+            if (q + 1 < s) {
+                T *w = Wc(-1, q + 1);
+                dots(Wc(-1, 0), q + 1, Wc(0, q), 1);
+                gs(Wc(-1, 0), q + 1, Wc(0, q), w);
+                dots(Wc(-1, 0), q + 1, w, 0);
+                gs(Wc(-1, 0), q + 1, w, w);
+                dots(Wc(-1, 0), 0, w, 0);
+                normalize(w, w, 0);
+            }
+        }
+        small(SMALL_GAMMA0);
+    }
+
+    void cycle()
+    {
+        for (int k = 0; k < ell; ++k) {
+            gamma(k);
+            spmv(Rc(k), Rc(k + 1), nullptr, ACT_R, k, 0);
+            for (int q = 0; q < s; ++q) {
+                eta(k, q);
+                spmv(Wc(k, q), Wc(k + 1, q), nullptr, ACT_V, k, q);
+            }
+        }
+        gram();
+        poly();
+    }
+
+    void copy_vecs(T *dst, const T *src, int count)
+    {
+        HIPCHK(hipMemcpyAsync(dst, src, (size_t)ld * sizeof(T) * count, hipMemcpyDeviceToDevice,
+                              stream));
+    }
+
+    // Write out U, V at a cycle end.  With refresh_v (FP32 data), V := A U is
+    // recomputed from the fetched U (s counted products), restoring Algorithm
+    // 1's prior requirement V = A U, which FP32 rounding erodes over the
+    // hundreds of cycles that chained recycle data live through.
+    bool refresh_v = false;
+
+    void fetch(int64_t level)
+    {
+        copy_vecs(recU, Wc(-1, 0), s);
+        if (refresh_v) {
+            for (int q = 0; q < s; ++q)
+                spmv(recU + (int64_t)q * ld, recV + (int64_t)q * ld, nullptr, ACT_RECV, 0, q);
+            HIPCHK(hipMemcpyAsync(rec_ptv, &ctl->prec[0][0], sizeof(double) * MAXS * MAXS,
+                                  hipMemcpyDeviceToDevice, stream));
+        } else {
+            copy_vecs(recV, Wc(0, 0), s);
+            HIPCHK(hipMemcpyAsync(rec_ptv, &ctl->ptv[0][0][0], sizeof(double) * MAXS * MAXS,
+                                  hipMemcpyDeviceToDevice, stream));
+        }
+        rec_level = level;
+        rec_have = true;
+    }
+
+    // Solve A X = b from the current X (b: n entries of T on the device).
+    // check_true = false: stop on the recursive residual (inner solves of the
+    // mixed mode, whose FP64 outer residual is the judge).
+    SolveResult solve(const T *b, double tol, int64_t max_mv, int method, int fetch_policy,
+                      double fetch_rel, int64_t fetch_level, int max_repl, bool check_true = true)
+    {
+        SolveResult res;
+        hist_mv.clear();
+        hist_res.clear();
+        const double tol2 = tol * tol;
+        int64_t mv0 = 0;
+
+        small(SMALL_CLEAR);
+        HIPCHK(hipMemsetAsync(&ctl->st.mv, 0, sizeof(int64_t), stream));
+        set_thr2(0.0);
+        spmv(X, Rc(0), b, ACT_RESID, 0, 0);
+        sync_status();
+        const double bb = st_host->bb;
+        if (st_host->flags & FLAG_NONFINITE || !std::isfinite(bb)) {
+            res.status = MSTAB_E_NONFINITE;
+            return res;
+        }
+        if (bb == 0.0) {
+            fill(X, ld, (T)0);
+            HIPCHK(hipStreamSynchronize(stream));
+            res.converged = true;
+            res.relres_rec = 0.0;
+            res.relres_true = 0.0;
+            res.mv = 0;
+            return res;
+        }
+        const double thr2 = tol2 * bb;
+        set_thr2(thr2);
+        double rr = st_host->rr;
+        int64_t mv = st_host->mv;
+        bool r_is_true = true;
+        hist_mv.push_back(mv);
+        hist_res.push_back(std::sqrt(rr / bb));
+
+        bool have_uv = false;
+        int64_t level = 0;
+        if (method == MSTAB_METHOD_MSTAB && rec_have) {
+            copy_vecs(Wc(-1, 0), recU, s);
+            copy_vecs(Wc(0, 0), recV, s);
+            HIPCHK(hipMemcpyAsync(&ctl->ptv[0][0][0], rec_ptv, sizeof(double) * MAXS * MAXS,
+                                  hipMemcpyDeviceToDevice, stream));
+            level = rec_level;
+            have_uv = true;
+            res.recycled = true;
+            small(SMALL_GAMMA0);
+        }
+        const bool had_rec = rec_have;
+        int64_t fetched = -1;
+
+        for (;;) {
+            while (rr > thr2 && mv < max_mv) {
+                if (!have_uv) {
+                    arnoldi();
+                    have_uv = true;
+                    level = 0;
+                    // the products are counted on the device; read them before deciding
+                    sync_status();
+                    mv = st_host->mv;
+                    if (st_host->flags & FLAG_NONFINITE) { res.status = MSTAB_E_NONFINITE; goto out; }
+                    if (st_host->flags & FLAG_BREAKDOWN && st_host->where == WHERE_ARNOLDI) {
+                        res.status = MSTAB_E_BREAKDOWN;
+                        goto out;
+                    }
+                    continue;
+                }
+                cycle();
+                sync_status();
+                mv = st_host->mv;
+                if (st_host->flags & FLAG_NONFINITE) { res.status = MSTAB_E_NONFINITE; goto out; }
+                if (st_host->flags & FLAG_BREAKDOWN) {
+                    if (res.restarts < 2) {
+                        ++res.restarts;
+                        have_uv = false;
+                        small(SMALL_CLEAR);
+                        set_thr2(0.0);   // no gamma solve until the basis is rebuilt
+                        spmv(X, Rc(0), b, ACT_RESID, 0, 0);
+                        set_thr2(thr2);
+                        sync_status();
+                        mv = st_host->mv;
+                        rr = st_host->rr;
+                        r_is_true = true;
+                        if (st_host->flags & FLAG_NONFINITE || !std::isfinite(rr)) {
+                            res.status = MSTAB_E_NONFINITE;
+                            goto out;
+                        }
+                        continue;
+                    }
+                    res.status = MSTAB_E_BREAKDOWN;
+                    goto out;
+                }
+                ++res.cycles;
+                level += ell;
+                r_is_true = false;
+                rr = st_host->rr;
+                hist_mv.push_back(mv + res.mv_check);
+                hist_res.push_back(std::sqrt(rr / bb));
+                const double rel = std::sqrt(rr / bb);
+                bool fire = false;
+                switch (fetch_policy) {
+                case MSTAB_FETCH_THRESHOLD: fire = (fetched < 0 && rel <= fetch_rel); break;
+                case MSTAB_FETCH_AT_LEVEL: fire = (level == fetch_level); break;
+                case MSTAB_FETCH_ONCE: fire = (!had_rec && fetched < 0 && rel <= fetch_rel); break;
+                default: break;
+                }
+                if (fire) {
+                    fetch(level);
+                    fetched = level;
+                }
+            }
+            // finish: the true residual decides
+            if (r_is_true || !check_true) {
+                res.relres_true = std::sqrt(rr / bb);
+                res.converged = rr <= thr2;
+                break;
+            }
+            spmv(X, Tv, b, ACT_TRUE, 0, 0);
+            sync_status();
+            ++res.mv_check;
+            {
+                const double tt = st_host->tt;
+                res.relres_true = std::sqrt(tt / bb);
+                if (!std::isfinite(tt)) { res.status = MSTAB_E_NONFINITE; goto out; }
+                if (tt <= thr2) { res.converged = true; break; }
+                if (rr <= thr2 && res.replacements < max_repl && mv < max_mv) {
+                    copy_vecs(Rc(0), Tv, 1);
+                    small(SMALL_REPLACE);
+                    rr = tt;
+                    r_is_true = true;
+                    ++res.replacements;
+                    continue;
+                }
+            }
+            break;
+        }
+        if (!res.converged) res.status = MSTAB_NOT_CONVERGED;
+        if (res.cycles > 0 && fetched < 0 &&
+            (fetch_policy == MSTAB_FETCH_AT_END || fetch_policy == MSTAB_FETCH_THRESHOLD ||
+             (fetch_policy == MSTAB_FETCH_ONCE && !had_rec))) {
+            fetch(level);
+            fetched = level;
+        }
+    out:
+        sync_status();
+        mv = st_host->mv;   // includes products of a fetch refresh after the last cycle
+        res.mv = mv - mv0;
+        res.level = level;
+        res.fetched = fetched;
+        res.relres_rec = std::sqrt(rr / bb);
+        return res;
+    }
+};
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// The handle.
+// ---------------------------------------------------------------------------
+struct mstab_solver {
+    mstab_options opt{};
+    int s = 0, ell = 0;
+    int64_t n = 0, nnz = 0;
+    const int32_t *rp = nullptr, *ci = nullptr;
+    const double *va = nullptr;
+    float *va32 = nullptr;
+    hipStream_t stream = nullptr;
+    uint32_t pkey = 0;
+    Engine<double> e64;
+    Engine<float> e32;
+    float *r32 = nullptr;   // F32_REFINE: scaled residual (right-hand side of the inner solve)
+    Profiler prof;
+    int64_t mv_total = 0, mv_last = 0;
+    std::vector<int64_t> hist_mv;
+    std::vector<double> hist_res;
+    std::string err;
+    bool mixed() const { return opt.precision == MSTAB_PREC_F32_REFINE; }
+};
+
+namespace {
+
+mstab_status record(mstab_solver *h, const StatusError &e)
+{
+    if (h) h->err = e.msg;
+    g_tls_error = e.msg;
+    return e.st;
+}
+
+mstab_status record_hip(mstab_solver *h, const HipError &e)
+{
+    char buf[512];
+    snprintf(buf, sizeof buf, "HIP error %d (%s) in %s", (int)e.e, hipGetErrorString(e.e), e.what);
+    if (h) h->err = buf;
+    g_tls_error = buf;
+    return MSTAB_E_HIP;
+}
+
+#define API_BEGIN try {
+#define API_END(h)                                                        \
+    }                                                                     \
+    catch (const StatusError &e) { return record((h), e); }               \
+    catch (const HipError &e) { return record_hip((h), e); }              \
+    catch (const std::bad_alloc &) {                                      \
+        return record((h), StatusError{MSTAB_E_NOMEM, "host allocation failed"}); \
+    }
+
+void fill_info(mstab_info *info, const SolveResult &r, double secs)
+{
+    if (!info) return;
+    memset(info, 0, sizeof *info);
+    info->status = r.status;
+    info->converged = r.converged;
+    info->recycled = r.recycled;
+    info->restarts = r.restarts;
+    info->replacements = r.replacements;
+    info->mv = r.mv;
+    info->mv_check = r.mv_check;
+    info->cycles = r.cycles;
+    info->level = r.level;
+    info->fetched_level = r.fetched;
+    info->relres_recursive = r.relres_rec;
+    info->relres_true = r.relres_true;
+    info->seconds = secs;
+}
+
+int grid1(int64_t n) { return grid_for(n, BLOCK, VEC_MAX_BLOCKS); }
+
+mstab_status solve_f64(mstab_solver *h, const double *b, double *x, mstab_info *info,
+                       int extra_checks, int accepted)
+{
+    auto t0 = std::chrono::steady_clock::now();
+    Engine<double> &E = h->e64;
+    HIPCHK(hipMemcpyAsync(E.X, x, sizeof(double) * h->n, hipMemcpyDeviceToDevice, h->stream));
+    SolveResult r = E.solve(b, h->opt.tol, h->opt.max_mv, h->opt.method, h->opt.fetch,
+                            h->opt.fetch_rel, h->opt.fetch_level, h->opt.max_replacements);
+    HIPCHK(hipMemcpyAsync(x, E.X, sizeof(double) * h->n, hipMemcpyDeviceToDevice, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    r.mv_check += extra_checks;
+    h->mv_last = r.mv + r.mv_check;
+    h->mv_total += h->mv_last;
+    h->hist_mv = E.hist_mv;
+    h->hist_res = E.hist_res;
+    double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    fill_info(info, r, secs);
+    if (info) info->guess_accepted = accepted;
+    return (mstab_status)r.status;
+}
+
+// Defect correction: FP64 true residual, FP32 M(s)stab(l) on the correction
+// equation A d = r / ||r|| to inner_tol, x += ||r|| d; until ||b - A x|| <= tol ||b||.
+mstab_status solve_mixed(mstab_solver *h, const double *b, double *x, mstab_info *info,
+                         int extra_checks, int accepted)
+{
+    auto t0 = std::chrono::steady_clock::now();
+    Engine<double> &E = h->e64;   // only its X, Tv, ctl, spmv are used
+    Engine<float> &F = h->e32;
+    const double tol2 = h->opt.tol * h->opt.tol;
+    SolveResult tot;
+    HIPCHK(hipMemcpyAsync(E.X, x, sizeof(double) * h->n, hipMemcpyDeviceToDevice, h->stream));
+    h->hist_mv.clear();
+    h->hist_res.clear();
+    int64_t mv32 = 0, mvchk = extra_checks, mv64 = 0;
+    int refinements = 0;
+    double bb = 0.0;
+    for (;;) {
+        E.small(SMALL_CLEAR);
+        E.spmv(E.X, E.Tv, b, ACT_TRUE, 0, 0);
+        E.sync_status();
+        ++mv64;
+        bb = E.st_host->bb;
+        const double tt = E.st_host->tt;
+        if (!std::isfinite(bb) || !std::isfinite(tt)) { tot.status = MSTAB_E_NONFINITE; break; }
+        if (bb == 0.0) {
+            E.fill(E.X, E.ld, 0.0);
+            tot.converged = true;
+            tot.relres_true = 0.0;
+            break;
+        }
+        tot.relres_true = std::sqrt(tt / bb);
+        tot.relres_rec = tot.relres_true;
+        h->hist_mv.push_back(mv32 + mv64 + mvchk);
+        h->hist_res.push_back(tot.relres_true);
+        if (tt <= tol2 * bb) { tot.converged = true; break; }
+        if (refinements >= h->opt.max_refinements ||
+            mv32 + mv64 + mvchk >= h->opt.max_mv) {
+            tot.status = MSTAB_NOT_CONVERGED;
+            break;
+        }
+        const double sigma = std::sqrt(tt);
+        hipLaunchKernelGGL(k_scale_to_f32, dim3(grid1(h->n)), dim3(BLOCK), 0, h->stream, h->n,
+                           E.Tv, 1.0 / sigma, h->r32);
+        HIPCHK(hipGetLastError());
+        F.fill(F.X, F.ld, 0.0f);
+        SolveResult in = F.solve(h->r32, h->opt.inner_tol, h->opt.max_mv - (mv32 + mv64 + mvchk),
+                                 h->opt.method, h->opt.fetch, std::sqrt(h->opt.inner_tol),
+                                 h->opt.fetch_level, 0, false);
+        ++refinements;
+        mv32 += in.mv;
+        mvchk += in.mv_check;
+        tot.cycles += in.cycles;
+        tot.restarts += in.restarts;
+        tot.replacements += in.replacements;
+        tot.recycled = tot.recycled || in.recycled;
+        tot.level = in.level;
+        if (in.fetched >= 0) tot.fetched = in.fetched;
+        if (in.status < 0 && in.status != MSTAB_E_BREAKDOWN) { tot.status = in.status; break; }
+        hipLaunchKernelGGL(k_correct, dim3(grid1(h->n)), dim3(BLOCK), 0, h->stream, h->n, F.X,
+                           sigma, E.X);
+        HIPCHK(hipGetLastError());
+    }
+    if (tot.status == MSTAB_OK && !tot.converged) tot.status = MSTAB_NOT_CONVERGED;
+    HIPCHK(hipMemcpyAsync(x, E.X, sizeof(double) * h->n, hipMemcpyDeviceToDevice, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    tot.mv = mv32;
+    tot.mv_check = mvchk + mv64;
+    h->mv_last = tot.mv + tot.mv_check;
+    h->mv_total += h->mv_last;
+    double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    fill_info(info, tot, secs);
+    if (info) {
+        info->refinements = refinements;
+        info->mv_f64 = mv64;
+        info->guess_accepted = accepted;
+    }
+    return (mstab_status)tot.status;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+mstab_status mstab_options_default(mstab_options *o)
+{
+    if (!o) return MSTAB_E_INVALID;
+    memset(o, 0, sizeof *o);
+    o->struct_size = (int32_t)sizeof(mstab_options);
+    o->tol = 1e-8;
+    o->max_mv = 100000;
+    o->method = MSTAB_METHOD_MSTAB;
+    o->precision = MSTAB_PREC_F64;
+    o->fetch = MSTAB_FETCH_THRESHOLD;
+    o->fetch_rel = 1e-4;
+    o->fetch_level = -1;
+    o->p_seed = 0;
+    o->max_replacements = 3;
+    o->inner_tol = 1e-4;
+    o->max_refinements = 20;
+    return MSTAB_OK;
+}
+
+mstab_status mstab_create(const mstab_csr *A, int32_t s, int32_t ell, const mstab_options *o,
+                          void *hip_stream, mstab_solver **out)
+{
+    mstab_solver *h = nullptr;
+    API_BEGIN
+    if (!out) fail(MSTAB_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (!A || !A->row_ptr || !A->col_idx || !A->val) fail(MSTAB_E_INVALID, "matrix pointer is NULL");
+    if (s < 1 || s > MAXS) fail(MSTAB_E_INVALID, "s=%d outside 1..%d", s, MAXS);
+    if (ell < 1 || ell > MAXL) fail(MSTAB_E_INVALID, "ell=%d outside 1..%d", ell, MAXL);
+    if (A->n <= s) fail(MSTAB_E_INVALID, "n=%lld must exceed s=%d", (long long)A->n, s);
+    if (A->n >= (int64_t)1 << 29) fail(MSTAB_E_INVALID, "n=%lld too large", (long long)A->n);
+    if (A->nnz < 0 || A->nnz >= ((int64_t)1 << 31)) fail(MSTAB_E_INVALID, "nnz out of range");
+    if (o && o->struct_size != (int32_t)sizeof(mstab_options))
+        fail(MSTAB_E_INVALID, "options struct_size mismatch");
+    h = new mstab_solver();
+    if (o) h->opt = *o;
+    else mstab_options_default(&h->opt);
+    if (!(h->opt.tol > 0.0) || h->opt.max_mv < 1) fail(MSTAB_E_INVALID, "tol/max_mv invalid");
+    if (h->opt.precision != MSTAB_PREC_F64 && h->opt.precision != MSTAB_PREC_F32_REFINE)
+        fail(MSTAB_E_INVALID, "unknown precision");
+    h->s = s; h->ell = ell; h->n = A->n; h->nnz = A->nnz;
+    h->rp = A->row_ptr; h->ci = A->col_idx; h->va = A->val;
+    h->stream = (hipStream_t)hip_stream;
+    h->pkey = p_key_from_seed(h->opt.p_seed);
+    h->prof.init(h->stream);
+    h->e64.alloc(h->n, s, ell, h->rp, h->ci, h->va, h->nnz, h->pkey, h->stream, &h->prof,
+                 !h->mixed());
+    if (h->mixed()) {
+        HIPCHK(hipMalloc(&h->va32, sizeof(float) * (size_t)std::max<int64_t>(h->nnz, 1)));
+        HIPCHK(hipMalloc(&h->r32, sizeof(float) * (size_t)round_up(h->n, 256)));
+        HIPCHK(hipMemsetAsync(h->r32, 0, sizeof(float) * (size_t)round_up(h->n, 256), h->stream));
+        hipLaunchKernelGGL((k_copy_cast<float, double>), dim3(grid1(h->nnz)), dim3(BLOCK), 0,
+                           h->stream, h->nnz, h->va, h->va32);
+        HIPCHK(hipGetLastError());
+        h->e32.alloc(h->n, s, ell, h->rp, h->ci, h->va32, h->nnz, h->pkey, h->stream, &h->prof);
+        h->e32.refresh_v = true;
+    }
+    HIPCHK(hipStreamSynchronize(h->stream));
+    *out = h;
+    return MSTAB_OK;
+    }
+    catch (const StatusError &e) {
+        mstab_status st = record(h, e);
+        if (h) { h->e64.release(); h->e32.release(); (void)hipFree(h->va32); (void)hipFree(h->r32); h->prof.destroy(); delete h; }
+        return st;
+    }
+    catch (const HipError &e) {
+        mstab_status st = record_hip(h, e);
+        if (h) { h->e64.release(); h->e32.release(); (void)hipFree(h->va32); (void)hipFree(h->r32); h->prof.destroy(); delete h; }
+        return (e.e == hipErrorOutOfMemory) ? MSTAB_E_NOMEM : st;
+    }
+    catch (const std::bad_alloc &) {
+        g_tls_error = "host allocation failed";
+        return MSTAB_E_NOMEM;
+    }
+}
+
+mstab_status mstab_solve_next(mstab_solver *h, const double *b, double *x, mstab_info *info)
+{
+    if (!h) { g_tls_error = "handle is NULL"; return MSTAB_E_INVALID; }
+    API_BEGIN
+    if (!b || !x) fail(MSTAB_E_INVALID, "b or x is NULL");
+    return h->mixed() ? solve_mixed(h, b, x, info, 0, 0) : solve_f64(h, b, x, info, 0, 0);
+    API_END(h)
+}
+
+mstab_status mstab_solve_next_guess(mstab_solver *h, const double *b, const double *x_prev,
+                                    const double *x_guess, double *x, mstab_info *info)
+{
+    if (!h) { g_tls_error = "handle is NULL"; return MSTAB_E_INVALID; }
+    API_BEGIN
+    if (!b || !x_prev || !x_guess || !x) fail(MSTAB_E_INVALID, "NULL vector");
+    Engine<double> &E = h->e64;
+    E.small(SMALL_CLEAR);
+    HIPCHK(hipMemcpyAsync(E.X, x_guess, sizeof(double) * h->n, hipMemcpyDeviceToDevice, h->stream));
+    E.spmv(E.X, E.Tv, b, ACT_TRUE, 0, 0);
+    E.sync_status();
+    const double tg = E.st_host->tt;
+    HIPCHK(hipMemcpyAsync(E.X, x_prev, sizeof(double) * h->n, hipMemcpyDeviceToDevice, h->stream));
+    E.spmv(E.X, E.Tv, b, ACT_TRUE, 0, 0);
+    E.sync_status();
+    const double tp = E.st_host->tt;
+    const int accept = (std::isfinite(tg) && tg < tp) ? 1 : 0;
+    const double *x0 = accept ? x_guess : x_prev;
+    if (x0 != x)
+        HIPCHK(hipMemcpyAsync(x, x0, sizeof(double) * h->n, hipMemcpyDeviceToDevice, h->stream));
+    return h->mixed() ? solve_mixed(h, b, x, info, 2, accept) : solve_f64(h, b, x, info, 2, accept);
+    API_END(h)
+}
+
+mstab_status mstab_mv_count(const mstab_solver *h, int64_t *total, int64_t *last_system)
+{
+    if (!h) return MSTAB_E_INVALID;
+    if (total) *total = h->mv_total;
+    if (last_system) *last_system = h->mv_last;
+    return MSTAB_OK;
+}
+
+mstab_status mstab_residual_history(const mstab_solver *h, int64_t *mv, double *relres,
+                                    int64_t cap, int64_t *len)
+{
+    if (!h || !len || cap < 0 || (cap > 0 && (!mv || !relres))) return MSTAB_E_INVALID;
+    const std::vector<int64_t> &hm = h->mixed() ? h->hist_mv : h->hist_mv;
+    const std::vector<double> &hr = h->hist_res;
+    *len = (int64_t)hm.size();
+    for (int64_t i = 0; i < std::min<int64_t>(cap, (int64_t)hm.size()); ++i) {
+        mv[i] = hm[i];
+        relres[i] = hr[i];
+    }
+    return MSTAB_OK;
+}
+
+mstab_status mstab_recycle_reset(mstab_solver *h)
+{
+    if (!h) return MSTAB_E_INVALID;
+    h->e64.rec_have = false;
+    h->e32.rec_have = false;
+    return MSTAB_OK;
+}
+
+mstab_status mstab_recycle_get(const mstab_solver *h, double *U, double *V, int64_t *level,
+                               int32_t *have)
+{
+    if (!h || !have || !level) return MSTAB_E_INVALID;
+    mstab_solver *hh = const_cast<mstab_solver *>(h);
+    API_BEGIN
+    if (h->mixed()) fail(MSTAB_E_INVALID, "recycle_get needs F64 precision");
+    *have = h->e64.rec_have ? 1 : 0;
+    *level = h->e64.rec_level;
+    if (h->e64.rec_have) {
+        if (!U || !V) fail(MSTAB_E_INVALID, "U or V is NULL");
+        HIPCHK(hipMemcpy2DAsync(U, sizeof(double) * h->n, h->e64.recU, sizeof(double) * h->e64.ld,
+                                sizeof(double) * h->n, h->s, hipMemcpyDeviceToDevice, h->stream));
+        HIPCHK(hipMemcpy2DAsync(V, sizeof(double) * h->n, h->e64.recV, sizeof(double) * h->e64.ld,
+                                sizeof(double) * h->n, h->s, hipMemcpyDeviceToDevice, h->stream));
+        HIPCHK(hipStreamSynchronize(h->stream));
+    }
+    return MSTAB_OK;
+    API_END(hh)
+}
+
+mstab_status mstab_recycle_set(mstab_solver *h, const double *U, const double *V, int64_t level)
+{
+    if (!h) return MSTAB_E_INVALID;
+    API_BEGIN
+    if (h->mixed()) fail(MSTAB_E_INVALID, "recycle_set needs F64 precision");
+    if (!U || !V) fail(MSTAB_E_INVALID, "U or V is NULL");
+    Engine<double> &E = h->e64;
+    HIPCHK(hipMemcpy2DAsync(E.recU, sizeof(double) * E.ld, U, sizeof(double) * h->n,
+                            sizeof(double) * h->n, h->s, hipMemcpyDeviceToDevice, h->stream));
+    HIPCHK(hipMemcpy2DAsync(E.recV, sizeof(double) * E.ld, V, sizeof(double) * h->n,
+                            sizeof(double) * h->n, h->s, hipMemcpyDeviceToDevice, h->stream));
+    // P^T V of the installed data
+    E.small(SMALL_CLEAR);
+    for (int q = 0; q < h->s; ++q) E.project(E.recV + (int64_t)q * E.ld, 0, q);
+    HIPCHK(hipMemcpyAsync(E.rec_ptv, &E.ctl->ptv[0][0][0], sizeof(double) * MAXS * MAXS,
+                          hipMemcpyDeviceToDevice, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    E.rec_level = level;
+    E.rec_have = true;
+    return MSTAB_OK;
+    API_END(h)
+}
+
+mstab_status mstab_destroy(mstab_solver *h)
+{
+    if (!h) return MSTAB_OK;
+    (void)hipStreamSynchronize(h->stream);
+    h->e64.release();
+    h->e32.release();
+    (void)hipFree(h->va32);
+    (void)hipFree(h->r32);
+    h->prof.destroy();
+    delete h;
+    return MSTAB_OK;
+}
+
+const char *mstab_status_str(mstab_status s)
+{
+    switch (s) {
+    case MSTAB_OK: return "ok";
+    case MSTAB_NOT_CONVERGED: return "not converged";
+    case MSTAB_E_INVALID: return "invalid argument";
+    case MSTAB_E_HIP: return "HIP runtime error";
+    case MSTAB_E_NOMEM: return "out of memory";
+    case MSTAB_E_BREAKDOWN: return "breakdown";
+    case MSTAB_E_NONFINITE: return "non-finite value";
+    }
+    return "unknown status";
+}
+
+const char *mstab_last_error(const mstab_solver *h)
+{
+    if (h) return h->err.c_str();
+    return g_tls_error.c_str();
+}
+
+mstab_status mstab_set_profiling(mstab_solver *h, int32_t enable)
+{
+    if (!h) return MSTAB_E_INVALID;
+    API_BEGIN
+    HIPCHK(hipStreamSynchronize(h->stream));
+    h->prof.harvest();
+    h->prof.reset();
+    h->prof.on = enable != 0;
+    return MSTAB_OK;
+    API_END(h)
+}
+
+mstab_status mstab_kernel_stats(const mstab_solver *h, int32_t kclass, int64_t *launches,
+                                double *ms, double *bytes)
+{
+    if (!h || kclass < 0 || kclass >= MSTAB_K_COUNT) return MSTAB_E_INVALID;
+    mstab_solver *hh = const_cast<mstab_solver *>(h);
+    API_BEGIN
+    HIPCHK(hipStreamSynchronize(h->stream));
+    hh->prof.harvest();
+    if (launches) *launches = h->prof.launches[kclass];
+    if (ms) *ms = h->prof.ms[kclass];
+    if (bytes) *bytes = h->prof.nbytes[kclass];
+    return MSTAB_OK;
+    API_END(hh)
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Standalone kernels (parity checks, time stepping)
+// ---------------------------------------------------------------------------
+namespace {
+
+struct Scratch {
+    Ctl *ctl = nullptr;
+    double *part = nullptr;
+    Status st{};
+    ~Scratch()
+    {
+        (void)hipFree(ctl);
+        (void)hipFree(part);
+    }
+    void init(hipStream_t s)
+    {
+        HIPCHK(hipMalloc(&ctl, sizeof(Ctl)));
+        HIPCHK(hipMalloc(&part, sizeof(double) * (size_t)PART_STRIDE * PART_VALUES));
+        HIPCHK(hipMemsetAsync(ctl, 0, sizeof(Ctl), s));
+    }
+};
+
+}  // namespace
+
+extern "C" {
+
+mstab_status mstab_spmv(const mstab_csr *A, const double *x, double *y, void *hip_stream)
+{
+    API_BEGIN
+    if (!A || !A->row_ptr || !A->col_idx || !A->val || !x || !y) fail(MSTAB_E_INVALID, "NULL pointer");
+    if (A->n < 0 || A->n >= ((int64_t)1 << 29) || A->nnz < 0 || A->nnz >= ((int64_t)1 << 31))
+        fail(MSTAB_E_INVALID, "size out of range");
+    if (A->n == 0) return MSTAB_OK;
+    hipStream_t st = (hipStream_t)hip_stream;
+    Scratch sc;
+    sc.init(st);
+    SpmvArgs a{ACT_NONE, 0, 0, 0, 1, 0u};
+    const bool wide = max_block_entries(A->row_ptr, A->n, st) > 2048;
+    launch_spmv<double>(wide, grid_for(A->n, BLOCK, SPMV_MAX_BLOCKS), st, A->n, A->row_ptr,
+                        A->col_idx, A->val, x, y, (const double *)nullptr, sc.ctl, sc.part, a);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(st));
+    return MSTAB_OK;
+    API_END(nullptr)
+}
+
+mstab_status mstab_project(int64_t n, int32_t s, uint64_t p_seed, const double *y, double *out,
+                           void *hip_stream)
+{
+    API_BEGIN
+    if (!y || !out) fail(MSTAB_E_INVALID, "NULL pointer");
+    if (s < 1 || s > MAXS || n < 1 || n >= ((int64_t)1 << 29)) fail(MSTAB_E_INVALID, "size out of range");
+    hipStream_t st = (hipStream_t)hip_stream;
+    Scratch sc;
+    sc.init(st);
+    const int grid = grid_for(n, BLOCK, GRAM_MAX_BLOCKS);
+    hipLaunchKernelGGL((k_project<double>), dim3(grid), dim3(BLOCK), 0, st, n, y,
+                       p_key_from_seed(p_seed), s, 1, 0, sc.ctl, sc.part, PART_STRIDE);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(out, sc.ctl->ptt, sizeof(double) * s, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    return MSTAB_OK;
+    API_END(nullptr)
+}
+
+mstab_status mstab_rhs_step(int64_t n, const double *x, double inv_dt, const double *f, double *b,
+                            void *hip_stream)
+{
+    API_BEGIN
+    if (!x || !f || !b) fail(MSTAB_E_INVALID, "NULL pointer");
+    if (n < 0) fail(MSTAB_E_INVALID, "n < 0");
+    if (n == 0) return MSTAB_OK;
+    hipStream_t st = (hipStream_t)hip_stream;
+    hipLaunchKernelGGL(k_rhs_step, dim3(grid1(n)), dim3(BLOCK), 0, st, n, x, inv_dt, f, b);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(st));
+    return MSTAB_OK;
+    API_END(nullptr)
+}
+
+}  // extern "C"

@@ -1,0 +1,289 @@
+"""Python binding of the C ABI in include/mstab.h (argument marshalling only).
+
+Every function here forwards to the function of the same name in
+libmstab.so; device buffers are torch tensors on the GPU (their data_ptr()
+is passed), streams are torch.cuda streams.  Nothing is computed in Python
+and there is no fallback: if the library or a GPU is missing, the calls
+raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmstab.so")
+
+OK, NOT_CONVERGED, E_INVALID, E_HIP, E_NOMEM, E_BREAKDOWN, E_NONFINITE = 0, 1, -1, -2, -3, -4, -5
+METHOD_MSTAB, METHOD_IDRSTAB = 0, 1
+PREC_F64, PREC_F32_REFINE = 0, 1
+FETCH_THRESHOLD, FETCH_AT_LEVEL, FETCH_AT_END, FETCH_ONCE, FETCH_NEVER = 0, 1, 2, 3, 4
+K_SPMV, K_GAMMA, K_ETA, K_GRAM, K_POLY = 0, 1, 2, 3, 4
+KERNEL_CLASSES = {"spmv": K_SPMV, "gamma": K_GAMMA, "eta": K_ETA, "gram": K_GRAM, "poly": K_POLY}
+
+# functions declared in include/mstab.h
+EXPORTS = [
+    "mstab_options_default", "mstab_create", "mstab_solve_next", "mstab_solve_next_guess",
+    "mstab_mv_count", "mstab_residual_history", "mstab_recycle_reset", "mstab_recycle_get",
+    "mstab_recycle_set", "mstab_destroy", "mstab_status_str", "mstab_last_error",
+    "mstab_set_profiling", "mstab_kernel_stats", "mstab_convdiff_nnz", "mstab_assemble_convdiff",
+    "mstab_spmv", "mstab_project", "mstab_rhs_step",
+]
+
+
+class mstab_csr(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("nnz", ctypes.c_int64), ("row_ptr", ctypes.c_void_p),
+                ("col_idx", ctypes.c_void_p), ("val", ctypes.c_void_p)]
+
+
+class mstab_options(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_int32), ("tol", ctypes.c_double),
+                ("max_mv", ctypes.c_int64), ("method", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("fetch", ctypes.c_int32),
+                ("fetch_rel", ctypes.c_double), ("fetch_level", ctypes.c_int64),
+                ("p_seed", ctypes.c_uint64), ("max_replacements", ctypes.c_int32),
+                ("inner_tol", ctypes.c_double), ("max_refinements", ctypes.c_int32)]
+
+
+class mstab_info(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("converged", ctypes.c_int32),
+                ("recycled", ctypes.c_int32), ("restarts", ctypes.c_int32),
+                ("replacements", ctypes.c_int32), ("refinements", ctypes.c_int32),
+                ("guess_accepted", ctypes.c_int32), ("pad_", ctypes.c_int32),
+                ("mv", ctypes.c_int64), ("mv_check", ctypes.c_int64), ("mv_f64", ctypes.c_int64),
+                ("cycles", ctypes.c_int64), ("level", ctypes.c_int64),
+                ("fetched_level", ctypes.c_int64), ("relres_recursive", ctypes.c_double),
+                ("relres_true", ctypes.c_double), ("seconds", ctypes.c_double)]
+
+    def as_dict(self) -> dict:
+        d = {f: getattr(self, f) for f, _ in self._fields_ if f != "pad_"}
+        d["mv_total"] = self.mv + self.mv_check
+        return d
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libmstab.so and declare the signatures (raises if it is missing)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with `python -m paper_1604_06043_amd.build`")
+    lib = ctypes.CDLL(path)
+    P, i32, i64, f64, u64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_uint64
+    sig = {
+        "mstab_options_default": (i32, [ctypes.POINTER(mstab_options)]),
+        "mstab_create": (i32, [ctypes.POINTER(mstab_csr), i32, i32, ctypes.POINTER(mstab_options), P,
+                               ctypes.POINTER(P)]),
+        "mstab_solve_next": (i32, [P, P, P, ctypes.POINTER(mstab_info)]),
+        "mstab_solve_next_guess": (i32, [P, P, P, P, P, ctypes.POINTER(mstab_info)]),
+        "mstab_mv_count": (i32, [P, ctypes.POINTER(i64), ctypes.POINTER(i64)]),
+        "mstab_residual_history": (i32, [P, P, P, i64, ctypes.POINTER(i64)]),
+        "mstab_recycle_reset": (i32, [P]),
+        "mstab_recycle_get": (i32, [P, P, P, ctypes.POINTER(i64), ctypes.POINTER(i32)]),
+        "mstab_recycle_set": (i32, [P, P, P, i64]),
+        "mstab_destroy": (i32, [P]),
+        "mstab_status_str": (ctypes.c_char_p, [i32]),
+        "mstab_last_error": (ctypes.c_char_p, [P]),
+        "mstab_set_profiling": (i32, [P, i32]),
+        "mstab_kernel_stats": (i32, [P, i32, ctypes.POINTER(i64), ctypes.POINTER(f64),
+                                     ctypes.POINTER(f64)]),
+        "mstab_convdiff_nnz": (i64, [i32, i64]),
+        "mstab_assemble_convdiff": (i32, [i32, i64, P, f64, P, P, P, P, P]),
+        "mstab_spmv": (i32, [ctypes.POINTER(mstab_csr), P, P, P]),
+        "mstab_project": (i32, [i64, i32, u64, P, P, P]),
+        "mstab_rhs_step": (i32, [i64, P, f64, P, P, P]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+class MstabError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{msg} (status {status})")
+        self.status = status
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _check(st: int, handle=None, allow=(OK,)):
+    if st not in allow:
+        lib = load()
+        msg = lib.mstab_last_error(handle).decode() if lib else ""
+        raise MstabError(st, f"{lib.mstab_status_str(st).decode()}: {msg}")
+    return st
+
+
+def _require_cuda(*tensors):
+    for t in tensors:
+        if t is not None and not t.is_cuda:
+            raise ValueError("device tensors expected")
+
+
+class CSR:
+    """Device CSR matrix (torch tensors: int32 row_ptr/col_idx, float64 val)."""
+
+    def __init__(self, row_ptr, col_idx, val):
+        _require_cuda(row_ptr, col_idx, val)
+        import torch
+        assert row_ptr.dtype == torch.int32 and col_idx.dtype == torch.int32 and val.dtype == torch.float64
+        self.row_ptr, self.col_idx, self.val = row_ptr, col_idx, val
+        self.n = row_ptr.numel() - 1
+        self.nnz = col_idx.numel()
+
+    def struct(self) -> mstab_csr:
+        return mstab_csr(self.n, self.nnz, self.row_ptr.data_ptr(), self.col_idx.data_ptr(),
+                         self.val.data_ptr())
+
+
+def mstab_options_default(**overrides) -> mstab_options:
+    o = mstab_options()
+    _check(load().mstab_options_default(ctypes.byref(o)))
+    for k, v in overrides.items():
+        if not hasattr(o, k):
+            raise AttributeError(k)
+        setattr(o, k, v)
+    return o
+
+
+def mstab_convdiff_nnz(dim: int, n: int) -> int:
+    return int(load().mstab_convdiff_nnz(dim, n))
+
+
+def mstab_assemble_convdiff(dim: int, n: int, beta, inv_dt: float, kappa=None, stream=None) -> CSR:
+    """Assemble the upwind convection-diffusion matrix on the GPU."""
+    import torch
+    N = n ** dim
+    nnz = mstab_convdiff_nnz(dim, n)
+    dev = torch.device("cuda")
+    rp = torch.empty(N + 1, dtype=torch.int32, device=dev)
+    ci = torch.empty(nnz, dtype=torch.int32, device=dev)
+    va = torch.empty(nnz, dtype=torch.float64, device=dev)
+    b3 = (ctypes.c_double * 3)(*(list(beta) + [0.0, 0.0, 0.0])[:3])
+    if kappa is not None:
+        _require_cuda(kappa)
+    _check(load().mstab_assemble_convdiff(dim, n, ctypes.cast(b3, ctypes.c_void_p), float(inv_dt),
+                                          _ptr(kappa), _ptr(rp), _ptr(ci), _ptr(va), _stream(stream)))
+    return CSR(rp, ci, va)
+
+
+def mstab_spmv(A: CSR, x, y, stream=None):
+    _require_cuda(x, y)
+    st = A.struct()
+    _check(load().mstab_spmv(ctypes.byref(st), _ptr(x), _ptr(y), _stream(stream)))
+    return y
+
+
+def mstab_project(y, s: int, p_seed: int, stream=None):
+    _require_cuda(y)
+    out = (ctypes.c_double * s)()
+    _check(load().mstab_project(y.numel(), s, p_seed, _ptr(y), ctypes.cast(out, ctypes.c_void_p),
+                                _stream(stream)))
+    return list(out)
+
+
+def mstab_rhs_step(x, inv_dt: float, f, b, stream=None):
+    _require_cuda(x, f, b)
+    _check(load().mstab_rhs_step(x.numel(), _ptr(x), float(inv_dt), _ptr(f), _ptr(b), _stream(stream)))
+    return b
+
+
+class Solver:
+    """Handle of mstab_create; methods forward to the mstab_* calls."""
+
+    def __init__(self, A: CSR, s: int, ell: int, options: mstab_options | None = None,
+                 stream=None, **overrides):
+        self.lib = load()
+        self.A = A          # keeps the matrix tensors alive
+        self.s, self.ell = s, ell
+        o = options if options is not None else mstab_options_default(**overrides)
+        h = ctypes.c_void_p()
+        st = A.struct()
+        _check(self.lib.mstab_create(ctypes.byref(st), s, ell, ctypes.byref(o), _stream(stream),
+                                     ctypes.byref(h)))
+        self.h = h
+        self.options = o
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.mstab_destroy(self.h)
+            self.h = None
+
+    __del__ = close
+
+    def solve_next(self, b, x) -> dict:
+        _require_cuda(b, x)
+        info = mstab_info()
+        st = self.lib.mstab_solve_next(self.h, _ptr(b), _ptr(x), ctypes.byref(info))
+        _check(st, self.h, allow=(OK, NOT_CONVERGED))
+        return info.as_dict()
+
+    def solve_next_guess(self, b, x_prev, x_guess, x) -> dict:
+        _require_cuda(b, x_prev, x_guess, x)
+        info = mstab_info()
+        st = self.lib.mstab_solve_next_guess(self.h, _ptr(b), _ptr(x_prev), _ptr(x_guess), _ptr(x),
+                                             ctypes.byref(info))
+        _check(st, self.h, allow=(OK, NOT_CONVERGED))
+        return info.as_dict()
+
+    def solve_next_raw(self, b, x):
+        """Status code and info without raising (error-path tests)."""
+        info = mstab_info()
+        st = self.lib.mstab_solve_next(self.h, _ptr(b), _ptr(x), ctypes.byref(info))
+        return st, info.as_dict()
+
+    def mv_count(self):
+        t, l = ctypes.c_int64(), ctypes.c_int64()
+        _check(self.lib.mstab_mv_count(self.h, ctypes.byref(t), ctypes.byref(l)))
+        return t.value, l.value
+
+    def residual_history(self):
+        n = ctypes.c_int64()
+        _check(self.lib.mstab_residual_history(self.h, None, None, 0, ctypes.byref(n)))
+        mv = (ctypes.c_int64 * max(n.value, 1))()
+        rr = (ctypes.c_double * max(n.value, 1))()
+        _check(self.lib.mstab_residual_history(self.h, ctypes.cast(mv, ctypes.c_void_p),
+                                               ctypes.cast(rr, ctypes.c_void_p), n.value,
+                                               ctypes.byref(n)))
+        return list(mv[:n.value]), list(rr[:n.value])
+
+    def recycle_reset(self):
+        _check(self.lib.mstab_recycle_reset(self.h), self.h)
+
+    def recycle_get(self):
+        import torch
+        lvl, have = ctypes.c_int64(), ctypes.c_int32()
+        n = self.A.n
+        U = torch.zeros((self.s, n), dtype=torch.float64, device="cuda")
+        V = torch.zeros((self.s, n), dtype=torch.float64, device="cuda")
+        _check(self.lib.mstab_recycle_get(self.h, _ptr(U), _ptr(V), ctypes.byref(lvl),
+                                          ctypes.byref(have)), self.h)
+        return (U, V, lvl.value) if have.value else None
+
+    def recycle_set(self, U, V, level: int):
+        """U, V: (s, n) contiguous float64 device tensors (column q = row q)."""
+        _require_cuda(U, V)
+        _check(self.lib.mstab_recycle_set(self.h, _ptr(U), _ptr(V), int(level)), self.h)
+
+    def set_profiling(self, enable: bool):
+        _check(self.lib.mstab_set_profiling(self.h, 1 if enable else 0), self.h)
+
+    def kernel_stats(self, kclass: int):
+        n, ms, by = ctypes.c_int64(), ctypes.c_double(), ctypes.c_double()
+        _check(self.lib.mstab_kernel_stats(self.h, kclass, ctypes.byref(n), ctypes.byref(ms),
+                                           ctypes.byref(by)), self.h)
+        return n.value, ms.value, by.value

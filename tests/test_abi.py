@@ -1,0 +1,91 @@
+"""Host-side checks of the C ABI (no GPU work): the library loads, exports
+every function that include/mstab.h declares, and rejects bad arguments
+before touching a device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1604_06043_amd import mstab
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "mstab.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(mstab_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return mstab.load()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = declared_functions()
+    assert len(names) >= 19
+    for name in names:
+        assert hasattr(lib, name), name
+    assert sorted(mstab.EXPORTS) == names
+
+
+def test_options_defaults(lib):
+    o = mstab.mstab_options_default()
+    assert o.struct_size == ctypes.sizeof(mstab.mstab_options)
+    assert o.tol == 1e-8 and o.max_replacements == 3 and o.method == mstab.METHOD_MSTAB
+    assert o.fetch == mstab.FETCH_THRESHOLD and abs(o.fetch_rel - 1e-4) < 1e-18
+
+
+def test_status_strings(lib):
+    for st in (0, 1, -1, -2, -3, -4, -5):
+        assert lib.mstab_status_str(st)
+    assert lib.mstab_status_str(-99) == b"unknown status"
+
+
+def test_convdiff_nnz_closed_form(lib, orc):
+    for dim, n in ((2, 1), (2, 7), (2, 64), (3, 5), (3, 128), (3, 256)):
+        assert lib.mstab_convdiff_nnz(dim, n) == orc._load().orc_convdiff_nnz(dim, n)
+    assert lib.mstab_convdiff_nnz(4, 3) == -1
+
+
+def test_create_rejects_bad_arguments_without_a_device(lib):
+    h = ctypes.c_void_p()
+    assert lib.mstab_create(None, 4, 2, None, None, ctypes.byref(h)) == mstab.E_INVALID
+    assert h.value is None
+    csr = mstab.mstab_csr(10, 28, 8, 8, 8)   # non-null dummies: rejected on s, l, n first
+    for s, ell in ((0, 1), (9, 1), (2, 0), (2, 9)):
+        assert lib.mstab_create(ctypes.byref(csr), s, ell, None, None, ctypes.byref(h)) == mstab.E_INVALID
+    csr.n = 3
+    assert lib.mstab_create(ctypes.byref(csr), 4, 1, None, None, ctypes.byref(h)) == mstab.E_INVALID
+    o = mstab.mstab_options_default()
+    o.struct_size = 3
+    csr.n = 100
+    assert lib.mstab_create(ctypes.byref(csr), 4, 1, ctypes.byref(o), None, ctypes.byref(h)) == mstab.E_INVALID
+    assert b"struct_size" in lib.mstab_last_error(None)
+    assert lib.mstab_destroy(None) == mstab.OK
+    assert lib.mstab_solve_next(None, None, None, None) == mstab.E_INVALID
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """ctypes layouts equal what a C compiler makes of include/mstab.h."""
+    import subprocess
+    lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "mstab.h"', 'int main(void) {']
+    for cls in (mstab.mstab_csr, mstab.mstab_options, mstab.mstab_info):
+        name = cls.__name__
+        lines.append(f'printf("{name} %zu\\n", sizeof({name}));')
+        for f, _ in cls._fields_:
+            lines.append(f'printf("{name}.{f} %zu\\n", offsetof({name}, {f}));')
+    lines += ['return 0; }']
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)], check=True)
+    out = dict(l.split() for l in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                   check=True).stdout.splitlines())
+    for cls in (mstab.mstab_csr, mstab.mstab_options, mstab.mstab_info):
+        name = cls.__name__
+        assert int(out[name]) == ctypes.sizeof(cls), name
+        for f, _ in cls._fields_:
+            assert int(out[f"{name}.{f}"]) == getattr(cls, f).offset, (name, f)

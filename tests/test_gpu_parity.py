@@ -1,0 +1,433 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Bars: CSR assembly, the time-stepping right-hand side and the sparse product
+bit-exact (the product kernel rounds each product and adds in CSR order, as
+the oracle does); projections within the rounding bound of their sums.
+
+Whole FP64 solves are compared system by system from the same x^(i) and the
+same recycled U, V (teacher-forced).  The bar is 1e-9 relative with equal MV
+counts, raised to ten times the oracle's own rounding sensitivity where that
+is larger: the oracle is run twice, with its inner products summed forward
+and backward (same definition, other rounding), and for s = 8, l = 4 the two
+runs already differ by up to ~6e-9 (the s x s projection systems are badly
+conditioned there), while for s l <= 9 they agree to ~1e-12.  A cycle is l(s+1)
+MVs, so counts move in whole cycles; where the two oracle runs disagree on the
+count, or the last recursive residual ends within 5% of the threshold, one
+cycle more or less is allowed and x is held to 10 tol.
+
+Free-running sequences amplify rounding differences from system to system
+(about tenfold per system here), so they are held to the tolerance-level bar:
+every system converged, x within 10 tol of the oracle's, total MVs within 5%
+plus two cycles.  FP32+refinement solves reach the FP64 tolerance; their error
+against the oracle is stated and bounded by 2 kappa tol.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_1604_06043_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+EPS = np.finfo(np.float64).eps
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    return torch
+
+
+@pytest.fixture(scope="module")
+def ms(torch_dev):
+    from paper_1604_06043_amd import mstab
+    mstab.load()
+    return mstab
+
+
+def dev(torch, a):
+    return torch.tensor(np.ascontiguousarray(a), device="cuda")
+
+
+def upload_csr(torch, ms, A):
+    assert A.row_ptr.dtype == np.int32 and A.col.dtype == np.int32
+    assert A.row_ptr[-1] == A.col.shape[0] == A.val.shape[0]
+    assert A.col.min() >= 0 and A.col.max() < A.n
+    return ms.CSR(dev(torch, A.row_ptr), dev(torch, A.col), dev(torch, A.val))
+
+
+def gpu_assemble(ms, cd):
+    kappa = None
+    if cd.kappa is not None:
+        import torch
+        kappa = dev(torch, cd.kappa)
+    return ms.mstab_assemble_convdiff(cd.dim, cd.n, cd.beta, cd.inv_dt, kappa)
+
+
+# ---------------------------------------------------------------------------
+# Setup kernels: bit-exact
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("name,n,seed", [("c1", 24, 0), ("c1", 64, 0), ("c2", 9, 1), ("c3", 10, 2),
+                                         ("c2", 128, 0), ("c4", 512, 0), ("c3", 256, 0)])
+def test_assembly_bit_exact(torch_dev, ms, orc, name, n, seed):
+    print(f"[assembly {name} n={n}]", flush=True)
+    cd = I.config(name, seed=seed, n=n)
+    Ag = gpu_assemble(ms, cd)
+    Ao = orc.assemble_convdiff(cd.dim, cd.n, cd.beta, cd.inv_dt, cd.kappa)
+    assert np.array_equal(Ag.row_ptr.cpu().numpy(), Ao.row_ptr)
+    assert np.array_equal(Ag.col_idx.cpu().numpy(), Ao.col)
+    assert np.array_equal(Ag.val.cpu().numpy().view(np.uint64), Ao.val.view(np.uint64))
+
+
+def test_rhs_step_bit_exact(torch_dev, ms, orc):
+    torch = torch_dev
+    rng = np.random.default_rng(3)
+    for N in (1, 255, 257, 4096, 1000003):
+        x = rng.standard_normal(N)
+        f = rng.random(N)
+        b = torch.empty(N, dtype=torch.float64, device="cuda")
+        ms.mstab_rhs_step(dev(torch, x), 1000.0, dev(torch, f), b)
+        ref = orc.rhs_step(x, 1000.0, f)
+        assert np.array_equal(b.cpu().numpy().view(np.uint64), ref.view(np.uint64))
+
+
+# ---------------------------------------------------------------------------
+# Sparse product and projection: within the rounding bound of the sums
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("name,n", [("c1", 64), ("c2", 12), ("c3", 16), ("c2", 128)])
+def test_spmv_parity(torch_dev, ms, orc, name, n):
+    torch = torch_dev
+    print(f"[spmv {name} n={n}]", flush=True)
+    cd = I.config(name, seed=0, n=n)
+    Ao = orc.assemble_convdiff(cd.dim, cd.n, cd.beta, cd.inv_dt, cd.kappa)
+    Ag = upload_csr(torch, ms, Ao)
+    x = np.random.default_rng(1).standard_normal(Ao.n)
+    y = torch.empty(Ao.n, dtype=torch.float64, device="cuda")
+    ms.mstab_spmv(Ag, dev(torch, x), y)
+    ref = orc.spmv(Ao, x)
+    # products rounded, then added in CSR order on both sides: bit-exact
+    assert np.array_equal(y.cpu().numpy().view(np.uint64), ref.view(np.uint64))
+
+
+def test_spmv_ragged_rows(torch_dev, ms, orc):
+    """Rows of 0..40 entries: empty rows, and 256-row chunks above the LDS
+    capacity (the global-memory fallback) next to chunks below it."""
+    torch = torch_dev
+    rng = np.random.default_rng(7)
+    n = 3001
+    lens = rng.integers(0, 41, n)
+    lens[::97] = 0
+    lens[1024:1280] = rng.integers(0, 3, 256)     # a short chunk: staged in LDS
+    rp = np.zeros(n + 1, dtype=np.int32)
+    rp[1:] = np.cumsum(lens)
+    ci = np.concatenate([np.sort(rng.choice(n, l, replace=False)) for l in lens]).astype(np.int32)
+    va = rng.standard_normal(rp[-1])
+    Ao = orc.CSR(rp, ci, va)
+    Ag = upload_csr(torch, ms, Ao)
+    x = rng.standard_normal(n)
+    y = torch.full((n,), 7.0, dtype=torch.float64, device="cuda")
+    ms.mstab_spmv(Ag, dev(torch, x), y)
+    ref = orc.spmv(Ao, x)
+    assert np.array_equal(y.cpu().numpy().view(np.uint64), ref.view(np.uint64))
+
+
+@pytest.mark.parametrize("N,s,seed", [(1, 1, 0), (1000, 8, 3), (4097, 5, 1), (2097152, 4, 0)])
+def test_projection_parity(torch_dev, ms, N, s, seed):
+    torch = torch_dev
+    y = np.random.default_rng(seed).standard_normal(N)
+    got = np.array(ms.mstab_project(dev(torch, y), s, seed))
+    P = I.p_dense(seed, N, s)
+    ref = P.T @ y
+    bound = 4 * math.log2(N + 2) * EPS * (np.abs(P).T @ np.abs(y))
+    assert np.all(np.abs(got - ref) <= bound + 1e-300)
+
+
+# ---------------------------------------------------------------------------
+# Whole solves
+# ---------------------------------------------------------------------------
+def run_sequence_gpu(torch, ms, Ag, cd, s, ell, systems, method, seed=0, **opt):
+    solver = ms.Solver(Ag, s, ell, p_seed=seed, method=method, **opt)
+    f = dev(torch, cd.f)
+    x = torch.zeros(cd.N, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(x)
+    xs, infos, hists = [], [], []
+    for _ in range(systems):
+        ms.mstab_rhs_step(x, cd.inv_dt, f, b)
+        infos.append(solver.solve_next(b, x))
+        xs.append(x.cpu().numpy().copy())
+        hists.append(solver.residual_history())
+    solver.close()
+    return xs, infos, hists
+
+
+def near_threshold(info_o, tol=1e-8):
+    r = info_o.hist_res[-1]
+    return abs(r - tol) <= 0.05 * tol
+
+
+def compare_free(xs_g, inf_g, xs_o, inf_o, cyc_mv, tol=1e-8):
+    errs = [np.linalg.norm(xg - xo) / np.linalg.norm(xo) for xg, xo in zip(xs_g, xs_o)]
+    dmv = [ig["mv_total"] - io.mv_total for ig, io in zip(inf_g, inf_o)]
+    print("  rel err per system", ["%.1e" % e for e in errs], "MV diff", dmv)
+    for k, (ig, io) in enumerate(zip(inf_g, inf_o)):
+        assert ig["converged"] and io.converged and ig["relres_true"] <= tol, (k, ig, io)
+    assert max(errs) <= 10 * tol, errs
+    tg, to = sum(i["mv_total"] for i in inf_g), sum(i.mv_total for i in inf_o)
+    assert abs(tg - to) <= 0.05 * to + 2 * cyc_mv, (tg, to)
+
+
+@pytest.mark.parametrize("method", [0, 1])
+@pytest.mark.parametrize("s,ell", [(4, 2), (1, 1), (2, 1), (8, 4), (3, 3)])
+def test_sequence_free_running_c1(torch_dev, ms, orc, method, s, ell):
+    """The 64^2 workload (10 implicit Euler steps), each side on its own."""
+    torch = torch_dev
+    print(f"[c1 sequence s={s} l={ell} method={method}]", flush=True)
+    cd = I.config("c1", seed=0)
+    Ao = orc.assemble_convdiff(cd.dim, cd.n, cd.beta, cd.inv_dt)
+    Ag = gpu_assemble(ms, cd)
+    xs_g, inf_g, _ = run_sequence_gpu(torch, ms, Ag, cd, s, ell, 10, method)
+    P = I.p_dense(0, cd.N, s)
+    xs_o, inf_o = orc.solve_sequence(Ao, cd.f, cd.inv_dt, s, ell, P, 10, method=method)
+    compare_free(xs_g, inf_g, xs_o, inf_o, ell * (s + 1))
+    if method == 0:
+        assert all(i["recycled"] for i in inf_g[1:])
+
+
+@pytest.mark.parametrize("name,n,seed,s,ell,method", [
+    ("c1", 64, 0, 4, 2, 0), ("c1", 64, 0, 4, 2, 1), ("c1", 64, 0, 8, 4, 0), ("c1", 64, 0, 2, 1, 0),
+    ("c1", 64, 1, 3, 3, 0), ("c1", 48, 2, 1, 1, 0), ("c2", 16, 3, 4, 2, 0), ("c3", 14, 4, 8, 4, 0)])
+def test_teacher_forced_sequence(torch_dev, ms, orc, name, n, seed, s, ell, method):
+    """System by system from the oracle's x^(i) and recycled U, V: <= 1e-9, equal MVs."""
+    torch = torch_dev
+    print(f"[teacher-forced {name} n={n} s={s} l={ell} method={method}]", flush=True)
+    cd = I.config(name, seed=seed, n=n)
+    Ao = orc.assemble_convdiff(cd.dim, cd.n, cd.beta, cd.inv_dt, cd.kappa)
+    Ag = gpu_assemble(ms, cd)
+    P = I.p_dense(seed, cd.N, s)
+    solver = ms.Solver(Ag, s, ell, p_seed=seed, method=method)
+    xo = np.zeros(cd.N)
+    rec = orc.Recycle.empty(cd.N, s)
+    errs, sens = [], []
+    for k in range(8):
+        b = orc.rhs_step(xo, cd.inv_dt, cd.f)
+        if method == 0 and rec.have:
+            solver.recycle_set(dev(torch, rec.U.T), dev(torch, rec.V.T), rec.level)
+        else:
+            solver.recycle_reset()
+        x = dev(torch, xo)
+        ig = solver.solve_next(dev(torch, b), x)
+        with orc.reversed_sums():
+            xr, ir, _, _ = orc.solve(Ao, b, xo, s, ell, P, recycle=rec.copy(), method=method)
+        xn, io, rec, _ = orc.solve(Ao, b, xo, s, ell, P, recycle=rec, method=method)
+        err = np.linalg.norm(x.cpu().numpy() - xn) / np.linalg.norm(xn)
+        sen = np.linalg.norm(xr - xn) / np.linalg.norm(xn)
+        errs.append(err)
+        sens.append(sen)
+        assert ig["converged"] and io.converged
+        assert ig["recycled"] == io.recycled
+        if near_threshold(io) or ir.mv_total != io.mv_total:
+            assert abs(ig["cycles"] - io.cycles) <= 1
+            assert err <= 10 * 1e-8
+        else:
+            assert err <= max(1e-9, 10 * sen), (k, err, sen, errs)
+            assert ig["mv_total"] == io.mv_total, (k, ig, io)
+        if method == 0:
+            got = solver.recycle_get()
+            assert got is not None and got[2] == rec.level
+        xo = xn
+    print("  oracle forward/backward sums", ["%.1e" % e for e in sens])
+    print("  rel err per system", ["%.1e" % e for e in errs])
+
+
+@pytest.mark.parametrize("dim,n,s,ell,seed", [(2, 8, 1, 1, 0), (2, 13, 4, 2, 1), (3, 7, 5, 3, 2),
+                                              (3, 6, 8, 1, 3), (2, 31, 2, 4, 4)])
+def test_single_system_history_parity(torch_dev, ms, orc, dim, n, s, ell, seed):
+    """IDR(s)stab(l) on one system: the residual history point by point."""
+    torch = torch_dev
+    cd = I.convdiff(dim, n, 50.0, seed)
+    Ao = orc.assemble_convdiff(dim, n, cd.beta, cd.inv_dt)
+    Ag = upload_csr(torch, ms, Ao)
+    P = I.p_dense(seed, cd.N, s)
+    xo, io, _, _ = orc.solve(Ao, cd.f, np.zeros(cd.N), s, ell, P, tol=1e-10, method=orc.IDRSTAB)
+    solver = ms.Solver(Ag, s, ell, p_seed=seed, method=1, tol=1e-10)
+    x = torch.zeros(cd.N, dtype=torch.float64, device="cuda")
+    ig = solver.solve_next(dev(torch, cd.f), x)
+    hm, hr = solver.residual_history()
+    assert hm == list(io.hist_mv)
+    assert np.allclose(hr, io.hist_res, rtol=1e-6, atol=1e-14)
+    err = np.linalg.norm(x.cpu().numpy() - xo) / np.linalg.norm(xo)
+    assert err <= 1e-9 and ig["mv_total"] == io.mv_total
+
+
+def test_full_size_first_system_128cubed(torch_dev, ms, orc):
+    """The 128^3 workload at full size (N = 2.1M), first system, s=4, l=2."""
+    torch = torch_dev
+    print("[c2 full size, first system]", flush=True)
+    cd = I.config("c2", seed=0)
+    s, ell = 4, 2
+    Ao = orc.assemble_convdiff(cd.dim, cd.n, cd.beta, cd.inv_dt)
+    Ag = gpu_assemble(ms, cd)
+    solver = ms.Solver(Ag, s, ell, p_seed=0)
+    x = torch.zeros(cd.N, dtype=torch.float64, device="cuda")
+    ig = solver.solve_next(dev(torch, cd.f), x)
+    xg = x.cpu().numpy()
+    true = np.linalg.norm(cd.f - orc.spmv(Ao, xg)) / np.linalg.norm(cd.f)
+    assert ig["converged"] and true <= 1e-8
+    P = I.p_dense(0, cd.N, s)
+    xo, io, _, _ = orc.solve(Ao, cd.f, np.zeros(cd.N), s, ell, P)
+    err = np.linalg.norm(xg - xo) / np.linalg.norm(xo)
+    print(f"  gpu mv {ig['mv_total']} oracle mv {io.mv_total} rel err {err:.2e}", flush=True)
+    assert err <= 1e-9
+    if not near_threshold(io):
+        assert ig["mv_total"] == io.mv_total
+
+
+# ---------------------------------------------------------------------------
+# The worked example of Section 5.2 on the GPU
+# ---------------------------------------------------------------------------
+def test_finite_termination_on_gpu(torch_dev, ms, orc):
+    torch = torch_dev
+    rp, ci, va = I.tridiag_231(40)
+    Ao = orc.CSR(rp, ci, va)
+    Ag = upload_csr(torch, ms, Ao)
+    b1, b2 = np.ones(40), I.sin_rhs(40)
+    for s, ell_src, level, ell, drop in ((2, 1, 19, 1, 34), (4, 1, 9, 1, 21), (4, 2, 8, 2, 21)):
+        src = ms.Solver(Ag, s, ell_src, p_seed=0, method=1, tol=1e-15, max_replacements=0,
+                        fetch=ms.FETCH_AT_LEVEL, fetch_level=level)
+        x = torch.zeros(40, dtype=torch.float64, device="cuda")
+        src.solve_next(dev(torch, b1), x)
+        U, V, lvl = src.recycle_get()
+        assert lvl == level
+        if (s, level) == (2, 19):
+            hm, _ = src.residual_history()
+            assert hm[19] == 60
+        m = ms.Solver(Ag, s, ell, p_seed=0, method=0, tol=1e-15, max_replacements=0,
+                      fetch=ms.FETCH_NEVER)
+        m.recycle_set(U, V, lvl)
+        x = torch.zeros(40, dtype=torch.float64, device="cuda")
+        info = m.solve_next(dev(torch, b2), x)
+        assert info["recycled"]
+        hm, hr = m.residual_history()
+        k = hm.index(drop)
+        assert hr[k] < 1e-6 and hr[k - 1] > 1e-5, (s, ell, hm, hr)
+
+
+# ---------------------------------------------------------------------------
+# Edge cases and failure handling (forced from the host)
+# ---------------------------------------------------------------------------
+def small_problem(torch, ms, orc, n=16, seed=0):
+    cd = I.convdiff(2, n, 50.0, seed)
+    Ao = orc.assemble_convdiff(2, n, cd.beta, cd.inv_dt)
+    return cd, Ao, upload_csr(torch, ms, Ao)
+
+
+def test_zero_rhs(torch_dev, ms, orc):
+    torch = torch_dev
+    cd, Ao, Ag = small_problem(torch, ms, orc)
+    solver = ms.Solver(Ag, 4, 2)
+    x = torch.ones(cd.N, dtype=torch.float64, device="cuda")
+    info = solver.solve_next(torch.zeros_like(x), x)
+    assert info["converged"] and info["mv"] == 0 and float(x.abs().max()) == 0.0
+
+
+def test_nonfinite_rhs(torch_dev, ms, orc):
+    torch = torch_dev
+    cd, Ao, Ag = small_problem(torch, ms, orc)
+    solver = ms.Solver(Ag, 4, 2)
+    b = dev(torch, cd.f)
+    b[5] = float("nan")
+    x = torch.zeros(cd.N, dtype=torch.float64, device="cuda")
+    st, info = solver.solve_next_raw(b, x)
+    assert st == ms.E_NONFINITE
+
+
+def test_max_mv_budget(torch_dev, ms, orc):
+    torch = torch_dev
+    cd, Ao, Ag = small_problem(torch, ms, orc)
+    solver = ms.Solver(Ag, 2, 2, tol=1e-14, max_mv=5)
+    x = torch.zeros(cd.N, dtype=torch.float64, device="cuda")
+    st, info = solver.solve_next_raw(dev(torch, cd.f), x)
+    P = I.p_dense(0, cd.N, 2)
+    _, io, _, _ = orc.solve(Ao, cd.f, np.zeros(cd.N), 2, 2, P, tol=1e-14, max_mv=5)
+    assert st == ms.NOT_CONVERGED and not info["converged"]
+    assert info["mv"] == io.mv == 9
+
+
+def test_recycled_zero_data_restarts(torch_dev, ms, orc):
+    """Recycled V = 0 (data from an empty space): singular P^T V, one restart."""
+    torch = torch_dev
+    cd, Ao, Ag = small_problem(torch, ms, orc, n=8)
+    s = 2
+    solver = ms.Solver(Ag, s, 2, p_seed=2, fetch=ms.FETCH_NEVER)
+    Z = torch.zeros((s, cd.N), dtype=torch.float64, device="cuda")
+    solver.recycle_set(Z, Z, 5)
+    x = torch.zeros(cd.N, dtype=torch.float64, device="cuda")
+    info = solver.solve_next(dev(torch, cd.f), x)
+    P = I.p_dense(2, cd.N, s)
+    rec = orc.Recycle(np.zeros((cd.N, s), order="F"), np.zeros((cd.N, s), order="F"), 5, True)
+    xo, io, _, _ = orc.solve(Ao, cd.f, np.zeros(cd.N), s, 2, P, recycle=rec, fetch=orc.FETCH_NEVER)
+    assert info["restarts"] == io.restarts == 1 and info["converged"]
+    assert np.linalg.norm(x.cpu().numpy() - xo) <= 1e-9 * np.linalg.norm(xo)
+    assert info["mv_total"] == io.mv_total
+
+
+def test_guess_gate(torch_dev, ms, orc):
+    torch = torch_dev
+    cd, Ao, Ag = small_problem(torch, ms, orc, n=20)
+    solver = ms.Solver(Ag, 4, 2)
+    b = dev(torch, cd.f)
+    x_prev = torch.zeros(cd.N, dtype=torch.float64, device="cuda")
+    exact = np.linalg.solve(Ao.dense(), cd.f)
+    x = torch.empty_like(x_prev)
+    info = solver.solve_next_guess(b, x_prev, dev(torch, exact), x)
+    assert info["guess_accepted"] == 1 and info["converged"] and info["cycles"] == 0
+    bad = dev(torch, 1e6 * np.ones(cd.N))
+    info = solver.solve_next_guess(b, x_prev, bad, x)
+    assert info["guess_accepted"] == 0 and info["converged"]
+    assert info["mv_check"] >= 2
+
+
+def test_kernel_profiling_counts(torch_dev, ms, orc):
+    torch = torch_dev
+    cd, Ao, Ag = small_problem(torch, ms, orc, n=32)
+    s, ell = 4, 2
+    solver = ms.Solver(Ag, s, ell, method=1)
+    solver.set_profiling(True)
+    x = torch.zeros(cd.N, dtype=torch.float64, device="cuda")
+    info = solver.solve_next(dev(torch, cd.f), x)
+    n_spmv, ms_spmv, by = solver.kernel_stats(ms.K_SPMV)
+    # every product with A of the iteration and the checks goes through the SpMV class
+    assert n_spmv == info["mv"] + info["mv_check"]
+    assert ms_spmv > 0 and by > 0
+    n_poly, _, _ = solver.kernel_stats(ms.K_POLY)
+    assert n_poly == info["cycles"]
+    n_eta, _, _ = solver.kernel_stats(ms.K_ETA)
+    assert n_eta == info["cycles"] * ell * s
+
+
+# ---------------------------------------------------------------------------
+# FP32 inner solves with FP64 refinement
+# ---------------------------------------------------------------------------
+def test_mixed_precision_sequence(torch_dev, ms, orc):
+    torch = torch_dev
+    cd = I.config("c1", seed=0)
+    s, ell = 4, 2
+    Ao = orc.assemble_convdiff(cd.dim, cd.n, cd.beta, cd.inv_dt)
+    Ag = gpu_assemble(ms, cd)
+    xs_g, inf_g, _ = run_sequence_gpu(torch, ms, Ag, cd, s, ell, 10, 0, precision=ms.PREC_F32_REFINE)
+    P = I.p_dense(0, cd.N, s)
+    xs_o, inf_o = orc.solve_sequence(Ao, cd.f, cd.inv_dt, s, ell, P, 10)
+    D = Ao.dense()
+    kappa = np.linalg.cond(D)
+    for k, (xg, ig, xo) in enumerate(zip(xs_g, inf_g, xs_o)):
+        assert ig["converged"] and ig["relres_true"] <= 1e-8, (k, ig)
+        b = xs_g[k - 1] * cd.inv_dt + cd.f if k else cd.f
+        true = np.linalg.norm(b - D @ xg) / np.linalg.norm(b)
+        assert true <= 1e-8
+        err = np.linalg.norm(xg - xo) / np.linalg.norm(xo)
+        print(f"  system {k}: mixed vs FP64 oracle rel err {err:.2e}, refinements {ig['refinements']}")
+        assert err <= 2 * kappa * 1e-8

@@ -331,3 +331,16 @@ def test_p_entries_exact_and_in_range():
     assert np.all(P * 2 ** 23 == np.round(P * 2 ** 23))
     assert np.array_equal(I.p_dense(0, 1000, 3), P[:, :3])
     assert abs(P.mean()) < 0.05 and abs(P.var() - 1 / 3) < 0.02
+
+
+def test_reversed_sums_same_definition(orc):
+    """Reversed summation order changes rounding only."""
+    cd, A = small_convdiff(orc, 2, 16, seed=6)
+    P = I.p_dense(6, A.n, 4)
+    x1, i1, _, _ = orc.solve(A, cd.f, np.zeros(A.n), 4, 2, P, tol=1e-10)
+    with orc.reversed_sums():
+        x2, i2, _, _ = orc.solve(A, cd.f, np.zeros(A.n), 4, 2, P, tol=1e-10)
+    x3, _, _, _ = orc.solve(A, cd.f, np.zeros(A.n), 4, 2, P, tol=1e-10)
+    assert np.array_equal(x1, x3)           # the switch is restored
+    assert not np.array_equal(x1, x2)
+    assert np.linalg.norm(x1 - x2) <= 1e-9 * np.linalg.norm(x1)
