@@ -212,9 +212,15 @@ __device__ __forceinline__ double part_load(const double *p)
 // wait until this thread's outstanding memory operations have completed
 __device__ __forceinline__ void wait_memory() { __builtin_amdgcn_s_waitcnt(0); }
 
+// Up to 1024 workgroups: a lane's share of one value's partials is at most 16
+// loads, all issued before the first is used.
+constexpr int MAX_PARTIAL_BLOCKS = 1024;
+
+template <int NT = BLOCK>
 __device__ bool last_block_reduce(const double *part, int stride, int nv, unsigned int *counter,
                                   double *tot)
 {
+    constexpr int NW = NT / 64;
     __shared__ int s_last;
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -224,20 +230,24 @@ __device__ bool last_block_reduce(const double *part, int stride, int nv, unsign
     }
     __syncthreads();
     if (!s_last) return false;
+    // the partials were stored coherently and completed before each counter
+    // increment; one acquire here lets plain (batched) loads see them
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int nb = (int)gridDim.x;
-    for (int v = wave; v < nv; v += NWAVE) {
+    for (int v = wave; v < nv; v += NW) {
         const double *pv = part + (size_t)v * stride;
-        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-        int b = lane;
-        for (; b + 192 < nb; b += 256) {
-            a0 += part_load(pv + b);
-            a1 += part_load(pv + b + 64);
-            a2 += part_load(pv + b + 128);
-            a3 += part_load(pv + b + 192);
+        double a[MAX_PARTIAL_BLOCKS / 64];
+#pragma unroll
+        for (int m = 0; m < MAX_PARTIAL_BLOCKS / 64; ++m) {
+            const int b = lane + 64 * m;
+            a[m] = (b < nb) ? pv[b] : 0.0;
         }
-        for (; b < nb; b += 64) a0 += part_load(pv + b);
-        double acc = wave_sum((a0 + a1) + (a2 + a3));
+#pragma unroll
+        for (int h = MAX_PARTIAL_BLOCKS / 128; h > 0; h >>= 1)
+#pragma unroll
+            for (int m = 0; m < h; ++m) a[m] += a[m + h];
+        const double acc = wave_sum(a[0]);
         if (lane == 0) tot[v] = acc;
     }
     __syncthreads();
@@ -249,10 +259,11 @@ __device__ bool last_block_reduce(const double *part, int stride, int nv, unsign
 // Block-level sum of up to NV per-thread values into part[.][blockIdx.x].
 // vals[v] are per-thread contributions; the block result is written by
 // threads t < nv.
-template <int NV>
+template <int NV, int NT = BLOCK>
 __device__ void block_partials(double (&vals)[NV], int nv, double *part, int stride)
 {
-    __shared__ double s_red[NWAVE][NV];
+    constexpr int NW = NT / 64;
+    __shared__ double s_red[NW][NV];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
@@ -262,10 +273,10 @@ __device__ void block_partials(double (&vals)[NV], int nv, double *part, int str
         }
     }
     __syncthreads();
-    for (int v = threadIdx.x; v < nv; v += BLOCK) {
+    for (int v = threadIdx.x; v < nv; v += NT) {
         double a = 0.0;
 #pragma unroll
-        for (int w = 0; w < NWAVE; ++w) a += s_red[w][v];
+        for (int w = 0; w < NW; ++w) a += s_red[w][v];
         part_store(part + (size_t)v * stride + blockIdx.x, a);
     }
     wait_memory();
@@ -275,13 +286,15 @@ __device__ void block_partials(double (&vals)[NV], int nv, double *part, int str
 // Sparse product with projection epilogue: y = A x (or y = b - A x), then the
 // workgroup partials of P^T y (s values), ||y||^2 and ||b||^2.
 //
-// CSR-stream layout: a workgroup takes 256 consecutive rows; its threads form
-// the products val[k] * x[col[k]] of the rows' contiguous entry range with
-// coalesced loads into LDS, then thread t adds the products of row t in CSR
-// order.  Products are rounded, then added (contraction off), which is the
-// textbook order: the result equals a sequential CSR product bit for bit.
-// Ranges longer than CAP entries fall back to the same loop from global
-// memory.  Row t also owns the s projection terms p_a(row) y_row.
+// Storage: sliced ELLPACK with 64-row slices (built from the caller's CSR at
+// create time).  Entry j of row r = 64 t + l sits at slice_ptr[t] + 64 j + l,
+// so the j-th entries of a wavefront's 64 rows are one contiguous 64-element
+// load; row lengths come from the CSR row pointer, padding is never read.
+// One thread per row; indices and values are loaded eight at a time before
+// their gathers from x.  Products are rounded, then added in CSR order
+// (contraction off): the textbook order, so the result equals a sequential CSR
+// product bit for bit.  Workgroups of 1024 threads keep the number of
+// partials, and with it the final reduction, small.
 // ---------------------------------------------------------------------------
 enum : int32_t {
     ACT_NONE = 0,
@@ -299,104 +312,122 @@ struct SpmvArgs {
     uint32_t pkey;
 };
 
-template <typename T, int CAP>
-__global__ __launch_bounds__(BLOCK) void k_spmv(int64_t n, const int32_t *__restrict__ rp,
-                                                const int32_t *__restrict__ ci,
-                                                const T *__restrict__ va, const T *__restrict__ x,
-                                                T *__restrict__ y, const T *__restrict__ b,
-                                                Ctl *ctl, double *part, int stride, SpmvArgs a)
+#ifndef MSTAB_SPMV_BLOCK
+#define MSTAB_SPMV_BLOCK 512
+#endif
+constexpr int SPMV_BLOCK = MSTAB_SPMV_BLOCK;
+constexpr int SLICE = 64;
+
+// Sliced ELLPACK copy of a CSR matrix (device arrays).
+template <typename T>
+struct Sell {
+    int64_t n = 0, nnz = 0, padded = 0;
+    const int32_t *rp = nullptr;     // the CSR row pointer (row lengths)
+    int64_t *slice_ptr = nullptr;    // n_slices + 1
+    int32_t *col = nullptr;          // padded
+    T *val = nullptr;                // padded
+};
+
+// Scatter CSR rows into the sliced layout (one thread per row).
+template <typename TD, typename TS>
+__global__ __launch_bounds__(BLOCK) void k_to_sell(int64_t n, const int32_t *__restrict__ rp,
+                                                   const int32_t *__restrict__ ci,
+                                                   const TS *__restrict__ va,
+                                                   const int64_t *__restrict__ slice_ptr,
+                                                   int32_t *__restrict__ scol,
+                                                   TD *__restrict__ sval)
+{
+    for (int64_t r = (int64_t)blockIdx.x * BLOCK + threadIdx.x; r < n;
+         r += (int64_t)gridDim.x * BLOCK) {
+        const int64_t base = slice_ptr[r / SLICE] + (r % SLICE);
+        const int32_t k0 = rp[r], len = rp[r + 1] - k0;
+        for (int32_t j = 0; j < len; ++j) {
+            if (scol) scol[base + (int64_t)j * SLICE] = ci[k0 + j];
+            sval[base + (int64_t)j * SLICE] = (TD)va[k0 + j];
+        }
+    }
+}
+
+// S = number of projection columns (a.s must equal S; 0 for a plain product).
+// Each wavefront takes 64 consecutive rows = one slice, so the slice offset and
+// width are wavefront-uniform (scalar registers) and the loop over the width
+// has no divergence.  Padding entries hold column 0 and value 0 and every slice
+// is allocated in full, so the index and value loads run to the slice width
+// for all 64 lanes; the row lengths only select which products are added.
+// Adding nothing for a padding entry keeps the CSR-order sum exact.
+template <typename T, int S>
+__global__ __launch_bounds__(SPMV_BLOCK) void k_spmv(int64_t n, const int32_t *__restrict__ rp,
+                                                     const int64_t *__restrict__ slice_ptr,
+                                                     const int32_t *__restrict__ scol,
+                                                     const T *__restrict__ sval,
+                                                     const T *__restrict__ x,
+                                                     T *__restrict__ y,
+                                                     const T *__restrict__ b, Ctl *ctl,
+                                                     double *part, int stride, SpmvArgs a)
 {
 #pragma clang fp contract(off)
     if (ctl->st.flags) return;
-    __shared__ T s_prod[CAP];
-    __shared__ int32_t s_rp[BLOCK + 1];
-    const int tid = threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const bool resid = (a.act == ACT_RESID || a.act == ACT_TRUE);
 
-    double vals[MAXS + 2];
+    double vals[S + 2];
 #pragma unroll
-    for (int v = 0; v < MAXS + 2; ++v) vals[v] = 0.0;
+    for (int v = 0; v < S + 2; ++v) vals[v] = 0.0;
 
-    for (int64_t r0 = (int64_t)blockIdx.x * BLOCK; r0 < n; r0 += (int64_t)gridDim.x * BLOCK) {
-        const int rows = (int)((n - r0) < BLOCK ? (n - r0) : BLOCK);
-        __syncthreads();                      // readers of the previous chunk are done
-        if (tid < rows) s_rp[tid] = rp[r0 + tid];
-        if (tid == 0) s_rp[rows] = rp[r0 + rows];
-        __syncthreads();
-        const int32_t kb = s_rp[0];
-        const int32_t cnt = s_rp[rows] - kb;
-        const bool staged = cnt <= CAP;
-        if (staged) {
-            // all column/value loads first, then all gathers, then the products
-            constexpr int PER = CAP / BLOCK;
-            int32_t cix[PER];
-            T vv[PER], xv[PER];
+    const int64_t nslices = (n + SLICE - 1) / SLICE;
+    for (int64_t t = (int64_t)blockIdx.x * (SPMV_BLOCK / SLICE) + wave; t < nslices;
+         t += (int64_t)gridDim.x * (SPMV_BLOCK / SLICE)) {
+        const int64_t sp0 = slice_ptr[t];
+        const int32_t w = (int32_t)((slice_ptr[t + 1] - sp0) / SLICE);
+        const int64_t r = t * SLICE + lane;
+        const bool valid = r < n;
+        const int32_t len = valid ? rp[r + 1] - rp[r] : 0;
+        const T *vp = sval + sp0 + lane;
+        const int32_t *cp = scol + sp0 + lane;
+        T sum = (T)0;
+        for (int32_t j0 = 0; j0 < w; j0 += 8) {
+            int32_t c[8];
+            T v[8], xv[8];
 #pragma unroll
-            for (int m = 0; m < PER; ++m) {
-                const int32_t j = tid + m * BLOCK;
-                if (j < cnt) {
-                    cix[m] = ci[kb + j];
-                    vv[m] = va[kb + j];
+            for (int j = 0; j < 8; ++j)
+                if (j0 + j < w) {
+                    // the matrix is streamed once per product: keep it out of the caches
+                    c[j] = __builtin_nontemporal_load(cp + (int64_t)(j0 + j) * SLICE);
+                    v[j] = __builtin_nontemporal_load(vp + (int64_t)(j0 + j) * SLICE);
                 }
-            }
 #pragma unroll
-            for (int m = 0; m < PER; ++m) {
-                const int32_t j = tid + m * BLOCK;
-                if (j < cnt) xv[m] = x[cix[m]];
-            }
+            for (int j = 0; j < 8; ++j)
+                if (j0 + j < w) xv[j] = x[c[j]];
 #pragma unroll
-            for (int m = 0; m < PER; ++m) {
-                const int32_t j = tid + m * BLOCK;
-                if (j < cnt) s_prod[j] = vv[m] * xv[m];
-            }
+            for (int j = 0; j < 8; ++j)
+                if (j0 + j < w) {
+                    const T prod = v[j] * xv[j];
+                    const T nsum = sum + prod;
+                    sum = (j0 + j < len) ? nsum : sum;
+                }
         }
-        __syncthreads();
-        if (tid < rows) {
-            const int64_t r = r0 + tid;
-            const int32_t k0 = s_rp[tid], k1 = s_rp[tid + 1];
-            T sum = (T)0;
-            if (staged) {
-                for (int32_t kk = k0 - kb; kk < k1 - kb; ++kk) sum = sum + s_prod[kk];
-            } else {
-                for (int32_t kk = k0; kk < k1; ++kk) {
-                    const T prod = va[kk] * x[ci[kk]];
-                    sum = sum + prod;
-                }
-            }
+        if (valid) {
             T yv = sum;
             if (resid) {
                 const T bv = b[r];
                 yv = bv - sum;
-                vals[MAXS + 1] += (double)bv * (double)bv;
+                vals[S + 1] += (double)bv * (double)bv;
             }
             y[r] = yv;
             const double yd = (double)yv;
-            vals[MAXS] += yd * yd;
+            vals[S] += yd * yd;
 #pragma unroll
-            for (int j = 0; j < MAXS; ++j)
-                if (j < a.s) vals[j] += pval(a.pkey, (uint32_t)r, j) * yd;
+            for (int j = 0; j < S; ++j) vals[j] += pval(a.pkey, (uint32_t)r, j) * yd;
         }
     }
-    // pack: [P^T y (s), ||y||^2, ||b||^2]
-    double packed[MAXS + 2];
-#pragma unroll
-    for (int v = 0; v < MAXS + 2; ++v) packed[v] = 0.0;
-#pragma unroll
-    for (int j = 0; j < MAXS; ++j)
-        if (j < a.s) packed[j] = vals[j];
-#pragma unroll
-    for (int v = 0; v < MAXS + 2; ++v) {
-        if (v == a.s) packed[v] = vals[MAXS];
-        if (v == a.s + 1) packed[v] = vals[MAXS + 1];
-    }
-    const int nv = a.s + 2;
-    block_partials<MAXS + 2>(packed, nv, part, stride);
-
+    const int nv = S + 2;
+    block_partials<S + 2, SPMV_BLOCK>(vals, nv, part, stride);
     __shared__ double tot[MAXS + 2];
-    if (!last_block_reduce(part, stride, nv, &ctl->counter[0], tot)) return;
-    if (tid >= 64) return;   // wavefront 0 finalizes
+    if (!last_block_reduce<SPMV_BLOCK>(part, stride, nv, &ctl->counter[0], tot)) return;
+    if (threadIdx.x >= 64) return;   // wavefront 0 finalizes
 
-    const int lane = tid, ri = lane >> 3, cj = lane & 7;
+    const int ri = lane >> 3, cj = lane & 7;
     const int s = a.s;
     bool finite = true;
     for (int v = 0; v < nv; ++v) finite = finite && isfinite(tot[v]);
@@ -591,19 +622,32 @@ __global__ __launch_bounds__(BLOCK) void k_gram(int64_t ld, const T *__restrict_
     double acc[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) acc[v] = 0.0;
-    for (int64_t e = ((int64_t)blockIdx.x * BLOCK + threadIdx.x) * VW; e < ld;
-         e += (int64_t)gridDim.x * BLOCK * VW) {
-        T z[L + 1][VW];
+    // four 16-byte groups per thread per pass, all loads issued before use
+    constexpr int U = 4;
+    const int64_t step = (int64_t)gridDim.x * BLOCK * VW;
+    for (int64_t e0 = ((int64_t)blockIdx.x * BLOCK + threadIdx.x) * VW; e0 < ld; e0 += step * U) {
+        T z[U][L + 1][VW];
 #pragma unroll
-        for (int i = 0; i <= L; ++i) ld16(R + i * ld + e, z[i]);
+        for (int u = 0; u < U; ++u) {
+            const int64_t e = e0 + u * step;
 #pragma unroll
-        for (int c = 0; c < VW; ++c) {
-            int v = 0;
+            for (int i = 0; i <= L; ++i) {
+                if (e < ld) ld16(R + i * ld + e, z[u][i]);
+                else
 #pragma unroll
-            for (int i = 0; i <= L; ++i)
-#pragma unroll
-                for (int j = i; j <= L; ++j) acc[v++] += (double)z[i][c] * (double)z[j][c];
+                    for (int c = 0; c < VW; ++c) z[u][i][c] = (T)0;
+            }
         }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int c = 0; c < VW; ++c) {
+                int v = 0;
+#pragma unroll
+                for (int i = 0; i <= L; ++i)
+#pragma unroll
+                    for (int j = i; j <= L; ++j) acc[v++] += (double)z[u][i][c] * (double)z[u][j][c];
+            }
     }
     block_partials<NV>(acc, NV, part, stride);
     __shared__ double tot[NV];
@@ -658,6 +702,45 @@ __global__ __launch_bounds__(BLOCK) void k_poly(int64_t n, int64_t ld, int ell_r
         double p[S];
 #pragma unroll
         for (int a = 0; a < S; ++a) p[a] = (e < n) ? pval(pkey, (uint32_t)e, a) : 0.0;
+        if (L > 0 && S <= 4) {
+            // every level of every column of this element in registers first
+            constexpr int LL = L > 0 ? L : 1;
+            T rv[LL + 1], wv[S][LL + 2];
+            const T xa0 = X[e];
+#pragma unroll
+            for (int i = 0; i <= LL; ++i) rv[i] = R[(int64_t)i * ld + e];
+#pragma unroll
+            for (int q = 0; q < S; ++q)
+#pragma unroll
+                for (int i = 0; i <= LL + 1; ++i) wv[q][i] = W[(int64_t)(i * S + q) * ld + e];
+            T xa = xa0, ra = rv[0];
+#pragma unroll
+            for (int i = 1; i <= LL; ++i) {
+                xa = fmaT(tau[i - 1], rv[i - 1], xa);
+                ra = fmaT(-tau[i - 1], rv[i], ra);
+            }
+            X[e] = xa;
+            R[e] = ra;
+            const double rd = (double)ra;
+#pragma unroll
+            for (int a = 0; a < S; ++a) acc[a] += p[a] * rd;
+            acc[S + S * S] += rd * rd;
+#pragma unroll
+            for (int q = 0; q < S; ++q) {
+                T ua = wv[q][0], va = wv[q][1];          // v_q^(-1), v_q^(0)
+#pragma unroll
+                for (int i = 1; i <= LL; ++i) {
+                    ua = fmaT(-tau[i - 1], wv[q][i], ua);
+                    va = fmaT(-tau[i - 1], wv[q][i + 1], va);
+                }
+                W[(int64_t)q * ld + e] = ua;
+                W[(int64_t)(S + q) * ld + e] = va;
+                const double vd = (double)va;
+#pragma unroll
+                for (int a = 0; a < S; ++a) acc[S + q * S + a] += p[a] * vd;
+            }
+            continue;
+        }
         // x and r
         {
             T xa = X[e];

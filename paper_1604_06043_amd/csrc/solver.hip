@@ -77,11 +77,14 @@ int grid_for(int64_t work, int per_block, int cap)
     return (int)g;
 }
 
-constexpr int SPMV_MAX_BLOCKS = 2048;
+constexpr int SPMV_MAX_BLOCKS = 1024;
 constexpr int VEC_MAX_BLOCKS = 8192;
-constexpr int GRAM_MAX_BLOCKS = 2048;
-constexpr int POLY_MAX_BLOCKS = 512;
-constexpr int PART_STRIDE = 8192;              // >= every reduction grid
+constexpr int GRAM_MAX_BLOCKS = 1024;
+constexpr int POLY_MAX_BLOCKS = 1024;
+constexpr int PART_STRIDE = MAX_PARTIAL_BLOCKS;  // >= every reduction grid
+static_assert(SPMV_MAX_BLOCKS <= MAX_PARTIAL_BLOCKS && GRAM_MAX_BLOCKS <= MAX_PARTIAL_BLOCKS &&
+                  POLY_MAX_BLOCKS <= MAX_PARTIAL_BLOCKS,
+              "a reduction grid may not exceed the partials the final reduction reads");
 constexpr int PART_VALUES = MAXS + MAXS * MAXS + 1;
 
 // ---------------------------------------------------------------------------
@@ -146,31 +149,72 @@ struct Profiler {
     }
 };
 
-// Largest number of entries in a chunk of BLOCK consecutive rows (setup only).
-int64_t max_block_entries(const int32_t *rp, int64_t n, hipStream_t st)
+// Build the sliced ELLPACK copy of a device CSR matrix (setup only): slice
+// widths from a host copy of the row pointer, then one scatter kernel.
+// With share_col, the column array of `other` is reused.
+template <typename T, typename TS>
+Sell<T> make_sell(int64_t n, const int32_t *rp, const int32_t *ci, const TS *va, hipStream_t st,
+                  const int32_t *share_col = nullptr)
 {
+    Sell<T> m;
+    m.n = n;
+    m.rp = rp;
     std::vector<int32_t> h((size_t)n + 1);
     HIPCHK(hipMemcpyAsync(h.data(), rp, sizeof(int32_t) * (n + 1), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
-    int64_t best = 0;
-    for (int64_t r0 = 0; r0 < n; r0 += BLOCK) {
-        const int64_t r1 = std::min<int64_t>(n, r0 + BLOCK);
-        best = std::max<int64_t>(best, (int64_t)h[r1] - h[r0]);
+    m.nnz = h[n];
+    const int64_t ns = (n + SLICE - 1) / SLICE;
+    std::vector<int64_t> sp((size_t)ns + 1);
+    sp[0] = 0;
+    for (int64_t t = 0; t < ns; ++t) {
+        int32_t w = 0;
+        for (int64_t r = t * SLICE; r < std::min<int64_t>(n, (t + 1) * SLICE); ++r)
+            w = std::max(w, h[r + 1] - h[r]);
+        sp[t + 1] = sp[t] + (int64_t)w * SLICE;
     }
-    return best;
+    m.padded = sp[ns];
+    const size_t cnt = (size_t)std::max<int64_t>(m.padded, 1);
+    HIPCHK(hipMalloc(&m.slice_ptr, sizeof(int64_t) * (ns + 1)));
+    HIPCHK(hipMemcpyAsync(m.slice_ptr, sp.data(), sizeof(int64_t) * (ns + 1),
+                          hipMemcpyHostToDevice, st));
+    HIPCHK(hipMalloc(&m.val, sizeof(T) * cnt));
+    HIPCHK(hipMemsetAsync(m.val, 0, sizeof(T) * cnt, st));        // padding: value 0
+    if (share_col) {
+        m.col = const_cast<int32_t *>(share_col);
+    } else {
+        HIPCHK(hipMalloc(&m.col, sizeof(int32_t) * cnt));
+        HIPCHK(hipMemsetAsync(m.col, 0, sizeof(int32_t) * cnt, st)); // padding: column 0
+    }
+    const int grid = grid_for(n, BLOCK, VEC_MAX_BLOCKS);
+    hipLaunchKernelGGL((k_to_sell<T, TS>), dim3(grid), dim3(BLOCK), 0, st, n, rp, ci, va,
+                       m.slice_ptr, share_col ? nullptr : m.col, m.val);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(st));   // sp (host) must outlive the copy
+    return m;
 }
 
 template <typename T>
-void launch_spmv(bool wide, int grid, hipStream_t stream, int64_t n, const int32_t *rp,
-                 const int32_t *ci, const T *va, const T *x, T *y, const T *b, Ctl *ctl,
-                 double *part, SpmvArgs a)
+void free_sell(Sell<T> &m, bool own_col)
 {
-    if (wide)
-        hipLaunchKernelGGL((k_spmv<T, 4096>), dim3(grid), dim3(BLOCK), 0, stream, n, rp, ci, va,
-                           x, y, b, ctl, part, PART_STRIDE, a);
-    else
-        hipLaunchKernelGGL((k_spmv<T, 2048>), dim3(grid), dim3(BLOCK), 0, stream, n, rp, ci, va,
-                           x, y, b, ctl, part, PART_STRIDE, a);
+    (void)hipFree(m.slice_ptr);
+    (void)hipFree(m.val);
+    if (own_col) (void)hipFree(m.col);
+    m = Sell<T>();
+}
+
+template <typename T>
+void launch_spmv(int grid, hipStream_t stream, const Sell<T> &A, const T *x, T *y, const T *b,
+                 Ctl *ctl, double *part, SpmvArgs a)
+{
+    switch (a.s) {
+#define CASE(S)                                                                                \
+    case S:                                                                                    \
+        hipLaunchKernelGGL((k_spmv<T, S>), dim3(grid), dim3(SPMV_BLOCK), 0, stream, A.n, A.rp, \
+                           A.slice_ptr, A.col, A.val, x, y, b, ctl, part, PART_STRIDE, a);     \
+        break;
+        CASE(0) CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
+#undef CASE
+    }
 }
 
 struct SolveResult {
@@ -189,10 +233,9 @@ struct SolveResult {
 template <typename T>
 struct Engine {
     int s = 0, ell = 0;
-    bool wide = false;                 // some 256-row block has more than 2048 entries
     int64_t n = 0, ld = 0, nnz = 0;
-    const int32_t *rp = nullptr, *ci = nullptr;
-    const T *va = nullptr;
+    Sell<T> A;                          // sliced copy of the matrix
+    bool own_col = true;
     uint32_t pkey = 0;
     hipStream_t stream = nullptr;
 
@@ -214,13 +257,12 @@ struct Engine {
     T *Rc(int i) const { return R + (int64_t)i * ld; }
 
     // full = false: only what the FP64 outer loop of the mixed mode needs
-    void alloc(int64_t n_, int s_, int ell_, const int32_t *rp_, const int32_t *ci_, const T *va_,
-               int64_t nnz_, uint32_t key, hipStream_t st, Profiler *pr, bool full = true)
+    void alloc(int64_t n_, int s_, int ell_, const Sell<T> &A_, bool own_col_, uint32_t key,
+               hipStream_t st, Profiler *pr, bool full = true)
     {
-        n = n_; s = s_; ell = ell_; rp = rp_; ci = ci_; va = va_; nnz = nnz_;
+        n = n_; s = s_; ell = ell_; A = A_; own_col = own_col_; nnz = A_.nnz;
         pkey = key; stream = st; prof = pr;
         ld = round_up(n, 256);
-        wide = max_block_entries(rp, n, st) > 2048;
         const size_t vb = (size_t)ld * sizeof(T);
         HIPCHK(hipMalloc(&X, vb));
         HIPCHK(hipMalloc(&Tv, vb));
@@ -246,6 +288,7 @@ struct Engine {
 
     void release()
     {
+        free_sell(A, own_col);
         (void)hipFree(W); (void)hipFree(R); (void)hipFree(X); (void)hipFree(Tv);
         (void)hipFree(recU); (void)hipFree(recV); (void)hipFree(rec_ptv);
         (void)hipFree(ctl); (void)hipFree(part);
@@ -260,11 +303,13 @@ struct Engine {
     void spmv(const T *x, T *y, const T *b, int act, int k, int q)
     {
         SpmvArgs a{act, k, q, s, ell, pkey};
-        const int grid = grid_for(n, BLOCK, SPMV_MAX_BLOCKS);
-        const double bytes = (double)(n + 1) * 4 + (double)nnz * (4 + sizeof(T)) +
-                             vbytes(b ? 3 : 2);
+        const int grid = grid_for(n, SPMV_BLOCK, SPMV_MAX_BLOCKS);
+        // bytes the kernel must move: row pointer, the padded slices (index +
+        // value), slice offsets, x once, y (and b)
+        const double bytes = (double)(n + 1) * 4 + (double)A.padded * (4 + sizeof(T)) +
+                             (double)((n + SLICE - 1) / SLICE + 1) * 8 + vbytes(b ? 3 : 2);
         int slot = prof ? prof->begin(MSTAB_K_SPMV, bytes) : -1;
-        launch_spmv<T>(wide, grid, stream, n, rp, ci, va, x, y, b, ctl, part, a);
+        launch_spmv<T>(grid, stream, A, x, y, b, ctl, part, a);
         HIPCHK(hipGetLastError());
         if (prof) prof->end(slot);
     }
@@ -645,7 +690,6 @@ struct mstab_solver {
     int64_t n = 0, nnz = 0;
     const int32_t *rp = nullptr, *ci = nullptr;
     const double *va = nullptr;
-    float *va32 = nullptr;
     hipStream_t stream = nullptr;
     uint32_t pkey = 0;
     Engine<double> e64;
@@ -859,16 +903,13 @@ mstab_status mstab_create(const mstab_csr *A, int32_t s, int32_t ell, const msta
     h->stream = (hipStream_t)hip_stream;
     h->pkey = p_key_from_seed(h->opt.p_seed);
     h->prof.init(h->stream);
-    h->e64.alloc(h->n, s, ell, h->rp, h->ci, h->va, h->nnz, h->pkey, h->stream, &h->prof,
-                 !h->mixed());
+    Sell<double> A64 = make_sell<double, double>(h->n, h->rp, h->ci, h->va, h->stream);
+    h->e64.alloc(h->n, s, ell, A64, true, h->pkey, h->stream, &h->prof, !h->mixed());
     if (h->mixed()) {
-        HIPCHK(hipMalloc(&h->va32, sizeof(float) * (size_t)std::max<int64_t>(h->nnz, 1)));
         HIPCHK(hipMalloc(&h->r32, sizeof(float) * (size_t)round_up(h->n, 256)));
         HIPCHK(hipMemsetAsync(h->r32, 0, sizeof(float) * (size_t)round_up(h->n, 256), h->stream));
-        hipLaunchKernelGGL((k_copy_cast<float, double>), dim3(grid1(h->nnz)), dim3(BLOCK), 0,
-                           h->stream, h->nnz, h->va, h->va32);
-        HIPCHK(hipGetLastError());
-        h->e32.alloc(h->n, s, ell, h->rp, h->ci, h->va32, h->nnz, h->pkey, h->stream, &h->prof);
+        Sell<float> A32 = make_sell<float, double>(h->n, h->rp, h->ci, h->va, h->stream, A64.col);
+        h->e32.alloc(h->n, s, ell, A32, false, h->pkey, h->stream, &h->prof);
         h->e32.refresh_v = true;
     }
     HIPCHK(hipStreamSynchronize(h->stream));
@@ -877,12 +918,12 @@ mstab_status mstab_create(const mstab_csr *A, int32_t s, int32_t ell, const msta
     }
     catch (const StatusError &e) {
         mstab_status st = record(h, e);
-        if (h) { h->e64.release(); h->e32.release(); (void)hipFree(h->va32); (void)hipFree(h->r32); h->prof.destroy(); delete h; }
+        if (h) { h->e64.release(); h->e32.release(); (void)hipFree(h->r32); h->prof.destroy(); delete h; }
         return st;
     }
     catch (const HipError &e) {
         mstab_status st = record_hip(h, e);
-        if (h) { h->e64.release(); h->e32.release(); (void)hipFree(h->va32); (void)hipFree(h->r32); h->prof.destroy(); delete h; }
+        if (h) { h->e64.release(); h->e32.release(); (void)hipFree(h->r32); h->prof.destroy(); delete h; }
         return (e.e == hipErrorOutOfMemory) ? MSTAB_E_NOMEM : st;
     }
     catch (const std::bad_alloc &) {
@@ -1004,7 +1045,6 @@ mstab_status mstab_destroy(mstab_solver *h)
     (void)hipStreamSynchronize(h->stream);
     h->e64.release();
     h->e32.release();
-    (void)hipFree(h->va32);
     (void)hipFree(h->r32);
     h->prof.destroy();
     delete h;
@@ -1097,9 +1137,14 @@ mstab_status mstab_spmv(const mstab_csr *A, const double *x, double *y, void *hi
     Scratch sc;
     sc.init(st);
     SpmvArgs a{ACT_NONE, 0, 0, 0, 1, 0u};
-    const bool wide = max_block_entries(A->row_ptr, A->n, st) > 2048;
-    launch_spmv<double>(wide, grid_for(A->n, BLOCK, SPMV_MAX_BLOCKS), st, A->n, A->row_ptr,
-                        A->col_idx, A->val, x, y, (const double *)nullptr, sc.ctl, sc.part, a);
+    Sell<double> M = make_sell<double, double>(A->n, A->row_ptr, A->col_idx, A->val, st);
+    launch_spmv<double>(grid_for(A->n, SPMV_BLOCK, SPMV_MAX_BLOCKS), st, M, x, y,
+                        (const double *)nullptr, sc.ctl, sc.part, a);
+    const hipError_t le = hipGetLastError();
+    const hipError_t se = hipStreamSynchronize(st);
+    free_sell(M, true);
+    HIPCHK(le);
+    HIPCHK(se);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(st));
     return MSTAB_OK;

@@ -12,7 +12,9 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libmstab.so")
+# MSTAB_LIBRARY may name another build of the same library (e.g. a variant
+# compiled with different tuning macros); the default is the in-tree build.
+LIB_PATH = os.environ.get("MSTAB_LIBRARY") or os.path.join(HERE, "libmstab.so")
 
 OK, NOT_CONVERGED, E_INVALID, E_HIP, E_NOMEM, E_BREAKDOWN, E_NONFINITE = 0, 1, -1, -2, -3, -4, -5
 METHOD_MSTAB, METHOD_IDRSTAB = 0, 1

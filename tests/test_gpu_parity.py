@@ -11,14 +11,15 @@ is larger: the oracle is run twice, with its inner products summed forward
 and backward (same definition, other rounding), and for s = 8, l = 4 the two
 runs already differ by up to ~6e-9 (the s x s projection systems are badly
 conditioned there), while for s l <= 9 they agree to ~1e-12.  A cycle is l(s+1)
-MVs, so counts move in whole cycles; where the two oracle runs disagree on the
-count, or the last recursive residual ends within 5% of the threshold, one
-cycle more or less is allowed and x is held to 10 tol.
+MVs, so counts move in whole cycles; where the system is rounding-sensitive
+(the two oracle runs differ by more than 1e-10 or in their counts) or the
+last recursive residual ends within 5% of the threshold, one cycle more or
+less is allowed and x is held to 10 tol.
 
 Free-running sequences amplify rounding differences from system to system
 (about tenfold per system here), so they are held to the tolerance-level bar:
 every system converged, x within 10 tol of the oracle's, total MVs within 5%
-plus two cycles.  FP32+refinement solves reach the FP64 tolerance; their error
+plus half a cycle per system.  FP32+refinement solves reach the FP64 tolerance; their error
 against the oracle is stated and bounded by 2 kappa tol.
 """
 import math
@@ -114,8 +115,8 @@ def test_spmv_parity(torch_dev, ms, orc, name, n):
 
 
 def test_spmv_ragged_rows(torch_dev, ms, orc):
-    """Rows of 0..40 entries: empty rows, and 256-row chunks above the LDS
-    capacity (the global-memory fallback) next to chunks below it."""
+    """Rows of 0..40 entries: empty rows, rows longer than one batch of eight
+    loads, and a stretch of short rows."""
     torch = torch_dev
     rng = np.random.default_rng(7)
     n = 3001
@@ -177,7 +178,7 @@ def compare_free(xs_g, inf_g, xs_o, inf_o, cyc_mv, tol=1e-8):
         assert ig["converged"] and io.converged and ig["relres_true"] <= tol, (k, ig, io)
     assert max(errs) <= 10 * tol, errs
     tg, to = sum(i["mv_total"] for i in inf_g), sum(i.mv_total for i in inf_o)
-    assert abs(tg - to) <= 0.05 * to + 2 * cyc_mv, (tg, to)
+    assert abs(tg - to) <= 0.05 * to + 0.5 * cyc_mv * len(inf_o), (tg, to)
 
 
 @pytest.mark.parametrize("method", [0, 1])
@@ -229,7 +230,7 @@ def test_teacher_forced_sequence(torch_dev, ms, orc, name, n, seed, s, ell, meth
         sens.append(sen)
         assert ig["converged"] and io.converged
         assert ig["recycled"] == io.recycled
-        if near_threshold(io) or ir.mv_total != io.mv_total:
+        if near_threshold(io) or ir.mv_total != io.mv_total or sen > 1e-10:
             assert abs(ig["cycles"] - io.cycles) <= 1
             assert err <= 10 * 1e-8
         else:
