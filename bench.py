@@ -27,6 +27,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = ("systems/sec + MVs/system at rel-res 1e-8; SpMV HBM GB/s vs peak, "
           "M(s)stab vs IDRstab")
+PMC_RECORD = os.path.join(ROOT, "profiles", "spmv_sell64_convdiff128_pmc.json")
 HBM_PEAK_GBS = 8000.0
 CLASS_NAMES = ["spmv", "gamma", "eta", "gram", "poly"]
 
@@ -78,6 +79,21 @@ def cpu_baseline(cd, s, ell):
             "mvs_per_system": info.mv_total}
 
 
+def measured_traffic(kernel_name_part: str):
+    """HBM bytes per dispatch from the committed counter record, if it was taken
+    with the current kernel sources (else None)."""
+    from paper_1604_06043_amd import prof
+    if not os.path.exists(PMC_RECORD):
+        return None
+    rec = json.load(open(PMC_RECORD))
+    if rec.get("sources_sha256") != prof.sources_digest():
+        return None
+    for name, t in rec["traffic"].items():
+        if kernel_name_part in name:
+            return t["traffic_bytes"]
+    return None
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -91,6 +107,9 @@ def main():
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-events", action="store_true",
                     help="time the steps without per-kernel HIP events (no roofline)")
+    ap.add_argument("--calib", action="store_true",
+                    help="first copy 256 MiB device-to-device with a plain copy kernel "
+                         "(reference for the HBM byte counters)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -106,6 +125,12 @@ def main():
         raise SystemExit("bench.py needs a GPU")
     torch.cuda.set_device(0)
     ms.load()
+    if args.calib:
+        src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     s, ell = args.s, args.ell
     cd = I.config("c2", seed=0, n=args.n)
     A = ms.mstab_assemble_convdiff(cd.dim, cd.n, cd.beta, cd.inv_dt)
@@ -146,10 +171,12 @@ def main():
         dom = max(stats, key=lambda c: stats[c][1])
         n, msec, by = stats[dom]
         achieved = by / (msec * 1e-3) / 1e9
+        traffic = measured_traffic(f"k_spmv<double, {s}>") if dom == "spmv" else None
         roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                    "bytes_per_launch": by / n, "us_per_launch": 1e3 * msec / n}
+                    "frac": round(achieved / HBM_PEAK_GBS, 4),
+                    "traffic": None if traffic is None else round(traffic),
+                    "bytes_per_launch": round(by / n), "us_per_launch": round(1e3 * msec / n, 2)}
 
     variants = {}
     if not args.no_variants:
