@@ -1,0 +1,73 @@
+"""Pins of the FP64 network reference: single-channel convolutions against
+SciPy's correlate2d, every gradient against central finite differences, and
+the closed form of Adam's first step."""
+import numpy as np
+import pytest
+from scipy.signal import correlate2d
+
+from oracle import cnn
+
+
+def test_conv_matches_scipy_correlate2d():
+    rng = np.random.default_rng(0)
+    x = rng.standard_normal((3, 7, 5))
+    w = rng.standard_normal((2, 3, 3, 3))
+    b = rng.standard_normal(2)
+    y = cnn.conv3x3(x, w, b)
+    for co in range(2):
+        ref = b[co] + sum(correlate2d(x[ci], w[co, ci], mode="same", boundary="fill") for ci in range(3))
+        assert np.allclose(y[co], ref, rtol=1e-13, atol=1e-13)
+
+
+def _num_grad(f, a, h=1e-6):
+    g = np.zeros_like(a)
+    it = np.nditer(a, flags=["multi_index"])
+    for _ in it:
+        i = it.multi_index
+        old = a[i]
+        a[i] = old + h
+        fp = f()
+        a[i] = old - h
+        fm = f()
+        a[i] = old
+        g[i] = (fp - fm) / (2 * h)
+    return g
+
+
+@pytest.mark.parametrize("channels,H,W", [([2, 3, 3, 1], 5, 4), ([2, 4, 1], 3, 6)])
+def test_gradients_match_finite_differences(channels, H, W):
+    rng = np.random.default_rng(1)
+    params = [(w.copy(), rng.standard_normal(w.shape[0]) * 0.1) for w, _ in cnn.init_params(channels, 2)]
+    x = rng.standard_normal((channels[0], H, W))
+    t = rng.standard_normal((channels[-1], H, W))
+
+    def loss():
+        return cnn.mse(cnn.forward(params, x)[-1], t)
+
+    _, grads, dx = cnn.backward(params, cnn.forward(params, x), t)
+    for (w, b), (gw, gb) in zip(params, grads):
+        assert np.allclose(gw, _num_grad(loss, w), rtol=1e-6, atol=1e-9)
+        assert np.allclose(gb, _num_grad(loss, b), rtol=1e-6, atol=1e-9)
+    assert np.allclose(dx, _num_grad(loss, x), rtol=1e-6, atol=1e-9)
+
+
+def test_batch_gradient_is_mean_of_samples():
+    rng = np.random.default_rng(3)
+    params = cnn.init_params([2, 3, 1], 4)
+    xs = [rng.standard_normal((2, 4, 4)) for _ in range(3)]
+    ts = [rng.standard_normal((1, 4, 4)) for _ in range(3)]
+    loss, g = cnn.loss_and_grads_batch(params, xs, ts)
+    singles = [cnn.backward(params, cnn.forward(params, x), t) for x, t in zip(xs, ts)]
+    assert np.isclose(loss, np.mean([s[0] for s in singles]))
+    assert np.allclose(g[0][0], np.mean([s[1][0][0] for s in singles], axis=0))
+
+
+def test_adam_first_step_is_lr_times_sign():
+    rng = np.random.default_rng(5)
+    params = cnn.init_params([2, 3, 1], 6)
+    grads = [(rng.standard_normal(w.shape), rng.standard_normal(b.shape)) for w, b in params]
+    new, state = cnn.adam_step(params, grads, cnn.adam_init(params), lr=1e-3, eps=0.0)
+    for (w, b), (nw, nb), (gw, gb) in zip(params, new, grads):
+        assert np.allclose(nw - w, -1e-3 * np.sign(gw), rtol=1e-12, atol=1e-15)
+        assert np.allclose(nb - b, -1e-3 * np.sign(gb), rtol=1e-12, atol=1e-15)
+    assert state[0] == 1
