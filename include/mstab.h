@@ -229,6 +229,94 @@ mstab_status mstab_project(int64_t n, int32_t s, uint64_t p_seed, const double *
 mstab_status mstab_rhs_step(int64_t n, const double *x, double inv_dt, const double *f, double *b,
                             void *hip_stream);
 
+/* ------------------------------------------------------------------------ */
+/*
+ * Learned initial guess.  The paper solves each system of the sequence
+ * (Section 1) starting from the previous solution; this extension offers a
+ * better x0: a convolutional network maps (x^(i), b^(i+1)) on an H x W grid to
+ * the correction x^(i+1) - x^(i).  The solver stays the judge:
+ * mstab_solve_next_guess takes the network's guess only if its true residual
+ * is below that of x^(i).
+ *
+ * Network: 6 layers of 3x3 convolutions with zero padding, channels
+ * 2 -> 32 -> 32 -> 32 -> 32 -> 32 -> 1, ReLU after each layer but the last,
+ * loss = mean squared error, Adam (beta 0.9, 0.999, eps 1e-8) on FP32 master
+ * parameters.  Forward and backward run on BF16 weights and activations with
+ * FP32 accumulation (MFMA for the 32 -> 32 layers).
+ * Per sample, s = max|b^(i+1)|; input channels (x^(i) / s, b^(i+1) / s);
+ * target (x^(i+1) - x^(i)) / s; guess x^(i) + s * output.
+ *
+ * Layouts: a grid vector is the solver's vector (x index fastest, n = H W,
+ * W a multiple of 32).  A prepared input is H W pixels x 2 channels of BF16
+ * (channels fastest, 4 bytes per pixel); a batch stores samples one after the
+ * other.  Parameters are mstab_cnn_param_count() floats, layer after layer,
+ * each w[c_out][c_in][3][3] followed by b[c_out].
+ */
+typedef struct mstab_cnn mstab_cnn;
+
+/* Number of FP32 parameters (37 889). */
+int64_t mstab_cnn_param_count(void);
+
+/*
+ * Create a network for H x W grids and batches of up to max_batch samples
+ * (H >= 1, W a positive multiple of 32, H W max_batch < 2^31).  Allocates
+ * parameters, Adam moments and the activations of a full batch on the current
+ * device; parameters start at zero (call mstab_cnn_set_params).
+ * Errors: E_INVALID, E_NOMEM, E_HIP; *out is NULL on failure.
+ */
+mstab_status mstab_cnn_create(int64_t H, int64_t W, int32_t max_batch, void *hip_stream,
+                              mstab_cnn **out);
+mstab_status mstab_cnn_destroy(mstab_cnn *h);
+
+/* Set the FP32 parameters (host, count floats) and reset the Adam state. */
+mstab_status mstab_cnn_set_params(mstab_cnn *h, const float *params_host, int64_t count);
+
+/* Copy parameters and/or the last gradient to host (either may be NULL). */
+mstab_status mstab_cnn_get_params(const mstab_cnn *h, float *params_host, float *grads_host,
+                                  int64_t count);
+
+/*
+ * Prepare one sample: input_bf16 (device, 2 H W BF16) from x_prev and b, and,
+ * if target is not NULL, target (device, H W floats) from x_next.  x_prev, b,
+ * x_next: device, H W doubles.  scale (host, may be NULL) receives s.
+ */
+mstab_status mstab_cnn_prepare(mstab_cnn *h, const double *x_prev, const double *b,
+                               const double *x_next, void *input_bf16, float *target,
+                               double *scale);
+
+/* Forward pass of a batch of prepared inputs; out (device, batch H W floats) may be NULL. */
+mstab_status mstab_cnn_forward(mstab_cnn *h, const void *input_bf16, int32_t batch, float *out);
+
+/*
+ * Forward and backward pass of a batch: the gradient of the batch mean loss
+ * is kept on the device for mstab_cnn_adam_step; loss (host, may be NULL)
+ * receives the mean loss.  Weight gradients are summed in a fixed order
+ * (deterministic).
+ */
+mstab_status mstab_cnn_gradient(mstab_cnn *h, const void *input_bf16, const float *target,
+                                int32_t batch, double *loss);
+
+/* One Adam update with learning rate lr from the last gradient. */
+mstab_status mstab_cnn_adam_step(mstab_cnn *h, double lr);
+
+/*
+ * x_guess = x_prev + s * network(x_prev / s, b / s) for one system (device, H W
+ * doubles; x_guess may alias x_prev).
+ */
+mstab_status mstab_cnn_guess(mstab_cnn *h, const double *x_prev, const double *b, double *x_guess);
+
+/*
+ * Copy an internal tensor of the last pass to dst (device, bytes capacity), for
+ * tests: which 0 = input of layer `layer` (0..5; BF16, 2 or 32 channels per
+ * pixel), 1 = network output (FP32), 2 = gradient of the loss with respect to
+ * layer `layer`'s pre-activation output (0..4; BF16, 32 channels), 3 = gradient
+ * with respect to the output (FP32).  Sizes are those of a full batch.
+ */
+mstab_status mstab_cnn_tensor(const mstab_cnn *h, int32_t which, int32_t layer, void *dst,
+                              int64_t bytes);
+
+const char *mstab_cnn_last_error(void);
+
 #ifdef __cplusplus
 }
 #endif

@@ -132,3 +132,23 @@ def adam_step(params, grads, state, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
 def adam_init(params):
     z = [(np.zeros_like(w), np.zeros_like(b)) for w, b in params]
     return (0, z, [(a.copy(), c.copy()) for a, c in z])
+
+
+def make_sample(x_prev: np.ndarray, b: np.ndarray, x_next: np.ndarray | None, H: int, W: int):
+    """Network input and target for one system of the sequence.
+
+    With s = max |b|: input channels (x_prev / s, b / s), target
+    (x_next - x_prev) / s, all on the H x W grid (x index fastest).  Returns
+    (input (2, H, W), target (1, H, W) or None, s)."""
+    s = float(np.max(np.abs(b))) if b.size else 0.0
+    if s == 0.0:
+        z = np.zeros((1, H, W))
+        return np.zeros((2, H, W)), (None if x_next is None else z), 0.0
+    inp = np.stack([np.asarray(x_prev) / s, np.asarray(b) / s]).reshape(2, H, W)
+    tgt = None if x_next is None else ((np.asarray(x_next) - np.asarray(x_prev)) / s).reshape(1, H, W)
+    return inp, tgt, s
+
+
+def apply_guess(x_prev: np.ndarray, out: np.ndarray, s: float) -> np.ndarray:
+    """Initial guess from the network output: x_prev + s * out."""
+    return np.asarray(x_prev) + s * np.asarray(out).reshape(-1)

@@ -30,6 +30,9 @@ EXPORTS = [
     "mstab_recycle_set", "mstab_destroy", "mstab_status_str", "mstab_last_error",
     "mstab_set_profiling", "mstab_kernel_stats", "mstab_convdiff_nnz", "mstab_assemble_convdiff",
     "mstab_spmv", "mstab_project", "mstab_rhs_step",
+    "mstab_cnn_param_count", "mstab_cnn_create", "mstab_cnn_destroy", "mstab_cnn_set_params",
+    "mstab_cnn_get_params", "mstab_cnn_prepare", "mstab_cnn_forward", "mstab_cnn_gradient",
+    "mstab_cnn_adam_step", "mstab_cnn_guess", "mstab_cnn_tensor", "mstab_cnn_last_error",
 ]
 
 
@@ -97,6 +100,18 @@ def load(path: str = LIB_PATH):
         "mstab_spmv": (i32, [ctypes.POINTER(mstab_csr), P, P, P]),
         "mstab_project": (i32, [i64, i32, u64, P, P, P]),
         "mstab_rhs_step": (i32, [i64, P, f64, P, P, P]),
+        "mstab_cnn_param_count": (i64, []),
+        "mstab_cnn_create": (i32, [i64, i64, i32, P, ctypes.POINTER(P)]),
+        "mstab_cnn_destroy": (i32, [P]),
+        "mstab_cnn_set_params": (i32, [P, P, i64]),
+        "mstab_cnn_get_params": (i32, [P, P, P, i64]),
+        "mstab_cnn_prepare": (i32, [P, P, P, P, P, P, ctypes.POINTER(f64)]),
+        "mstab_cnn_forward": (i32, [P, P, i32, P]),
+        "mstab_cnn_gradient": (i32, [P, P, P, i32, ctypes.POINTER(f64)]),
+        "mstab_cnn_adam_step": (i32, [P, f64]),
+        "mstab_cnn_guess": (i32, [P, P, P, P]),
+        "mstab_cnn_tensor": (i32, [P, i32, i32, P, i64]),
+        "mstab_cnn_last_error": (ctypes.c_char_p, []),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -289,3 +304,95 @@ class Solver:
         _check(self.lib.mstab_kernel_stats(self.h, kclass, ctypes.byref(n), ctypes.byref(ms),
                                            ctypes.byref(by)), self.h)
         return n.value, ms.value, by.value
+
+
+# ---------------------------------------------------------------------------
+# Learned initial guess (mstab_cnn_*)
+# ---------------------------------------------------------------------------
+CNN_CHANNELS = (2, 32, 32, 32, 32, 32, 1)
+CNN_T_ACT, CNN_T_OUT, CNN_T_DZ, CNN_T_DOUT = 0, 1, 2, 3
+
+
+def _check_cnn(st: int):
+    if st != OK:
+        lib = load()
+        raise MstabError(st, f"{lib.mstab_status_str(st).decode()}: {lib.mstab_cnn_last_error().decode()}")
+    return st
+
+
+def mstab_cnn_param_count() -> int:
+    return int(load().mstab_cnn_param_count())
+
+
+class Cnn:
+    """Handle of mstab_cnn_create; methods forward to the mstab_cnn_* calls.
+
+    Prepared inputs are device tensors of 2 H W bfloat16 per sample; targets
+    and outputs device float32 tensors of H W per sample.
+    """
+
+    def __init__(self, H: int, W: int, max_batch: int = 1, stream=None):
+        self.lib = load()
+        self.H, self.W, self.max_batch = H, W, max_batch
+        self._stream = _stream(stream)
+        h = ctypes.c_void_p()
+        _check_cnn(self.lib.mstab_cnn_create(H, W, max_batch, self._stream, ctypes.byref(h)))
+        self.h = h
+        self.nparam = mstab_cnn_param_count()
+
+    def close(self):
+        if self.h:
+            self.lib.mstab_cnn_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, params):
+        import numpy as np
+        a = np.ascontiguousarray(params, dtype=np.float32)
+        _check_cnn(self.lib.mstab_cnn_set_params(self.h, a.ctypes.data_as(ctypes.c_void_p), a.size))
+
+    def get_params(self):
+        """(parameters, last gradient) as float32 numpy arrays."""
+        import numpy as np
+        p = np.empty(self.nparam, np.float32)
+        g = np.empty(self.nparam, np.float32)
+        _check_cnn(self.lib.mstab_cnn_get_params(self.h, p.ctypes.data_as(ctypes.c_void_p),
+                                                 g.ctypes.data_as(ctypes.c_void_p), self.nparam))
+        return p, g
+
+    def prepare(self, x_prev, b, x_next=None, inp=None, target=None) -> float:
+        _require_cuda(x_prev, b, x_next, inp, target)
+        scale = ctypes.c_double()
+        _check_cnn(self.lib.mstab_cnn_prepare(self.h, _ptr(x_prev), _ptr(b), _ptr(x_next), _ptr(inp),
+                                              _ptr(target), ctypes.byref(scale)))
+        return scale.value
+
+    def forward(self, inp, batch: int, out=None):
+        _require_cuda(inp, out)
+        _check_cnn(self.lib.mstab_cnn_forward(self.h, _ptr(inp), batch, _ptr(out)))
+        return out
+
+    def gradient(self, inp, target, batch: int) -> float:
+        _require_cuda(inp, target)
+        loss = ctypes.c_double()
+        _check_cnn(self.lib.mstab_cnn_gradient(self.h, _ptr(inp), _ptr(target), batch, ctypes.byref(loss)))
+        return loss.value
+
+    def adam_step(self, lr: float):
+        _check_cnn(self.lib.mstab_cnn_adam_step(self.h, float(lr)))
+
+    def guess(self, x_prev, b, x_guess):
+        _require_cuda(x_prev, b, x_guess)
+        _check_cnn(self.lib.mstab_cnn_guess(self.h, _ptr(x_prev), _ptr(b), _ptr(x_guess)))
+        return x_guess
+
+    def tensor(self, which: int, layer: int, dst):
+        _require_cuda(dst)
+        _check_cnn(self.lib.mstab_cnn_tensor(self.h, which, layer, _ptr(dst),
+                                             dst.numel() * dst.element_size()))
+        return dst

@@ -71,3 +71,20 @@ def test_adam_first_step_is_lr_times_sign():
         assert np.allclose(nw - w, -1e-3 * np.sign(gw), rtol=1e-12, atol=1e-15)
         assert np.allclose(nb - b, -1e-3 * np.sign(gb), rtol=1e-12, atol=1e-15)
     assert state[0] == 1
+
+
+def test_sample_round_trip_and_scale_invariance():
+    rng = np.random.default_rng(5)
+    H, W = 4, 6
+    xp, b, xn = (rng.standard_normal(H * W) for _ in range(3))
+    inp, tgt, s = cnn.make_sample(xp, b, xn, H, W)
+    assert s == np.max(np.abs(b)) and np.max(np.abs(inp[1])) == 1.0
+    # the exact correction as network output reproduces the next solution
+    np.testing.assert_allclose(cnn.apply_guess(xp, tgt, s), xn, rtol=0, atol=1e-14)
+    # inputs and targets do not depend on the units of the system
+    inp2, tgt2, s2 = cnn.make_sample(8.0 * xp, 8.0 * b, 8.0 * xn, H, W)
+    assert s2 == 8.0 * s
+    np.testing.assert_array_equal(inp2, inp)
+    np.testing.assert_array_equal(tgt2, tgt)
+    z_inp, z_tgt, z_s = cnn.make_sample(xp, np.zeros(H * W), xn, H, W)
+    assert z_s == 0.0 and not z_inp.any() and not z_tgt.any()
