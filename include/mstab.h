@@ -142,6 +142,15 @@ mstab_status mstab_solve_next(mstab_solver *h, const double *b, double *x, mstab
 mstab_status mstab_solve_next_guess(mstab_solver *h, const double *b, const double *x_prev,
                                     const double *x_guess, double *x, mstab_info *info);
 
+/*
+ * r = b - A x with the handle's matrix and product kernel (device, n doubles
+ * each; r must not alias b or x); norm2 (host, may be NULL) receives ||r||^2.
+ * One product with A, counted in the handle's total (mstab_mv_count) but not
+ * in any solve's info.
+ */
+mstab_status mstab_residual(mstab_solver *h, const double *b, const double *x, double *r,
+                            double *norm2);
+
 /* Products with A: over the handle's lifetime and in the last solve. */
 mstab_status mstab_mv_count(const mstab_solver *h, int64_t *total, int64_t *last_system);
 
@@ -233,18 +242,24 @@ mstab_status mstab_rhs_step(int64_t n, const double *x, double inv_dt, const dou
 /*
  * Learned initial guess.  The paper solves each system of the sequence
  * (Section 1) starting from the previous solution; this extension offers a
- * better x0: a convolutional network maps (x^(i), b^(i+1)) on an H x W grid to
- * the correction x^(i+1) - x^(i).  The solver stays the judge:
- * mstab_solve_next_guess takes the network's guess only if its true residual
- * is below that of x^(i).
+ * better x0: a convolutional network maps the system (x^(i), b^(i+1)) on an
+ * H x W grid to the correction d = x^(i+1) - x^(i).  Its features are the
+ * residual r0 = b^(i+1) - A x^(i) (mstab_residual) and x^(i): d solves
+ * A d = r0, so the map is linear in r0 and, for a matrix with constant
+ * coefficients, translation invariant, which a convolution can approximate
+ * locally.  The solver stays the judge: mstab_solve_next_guess takes the
+ * network's guess only if its true residual is below that of x^(i).
  *
  * Network: 6 layers of 3x3 convolutions with zero padding, channels
  * 2 -> 32 -> 32 -> 32 -> 32 -> 32 -> 1, ReLU after each layer but the last,
  * loss = mean squared error, Adam (beta 0.9, 0.999, eps 1e-8) on FP32 master
  * parameters.  Forward and backward run on BF16 weights and activations with
  * FP32 accumulation (MFMA for the 32 -> 32 layers).
- * Per sample, s = max|b^(i+1)|; input channels (x^(i) / s, b^(i+1) / s);
- * target (x^(i+1) - x^(i)) / s; guess x^(i) + s * output.
+ * Per sample, s = max|r0| and sx = max|x^(i)|; input channels (r0 / s,
+ * x^(i) / sx); target (x^(i+1) - x^(i)) unit / s; guess x^(i) + (s / unit)
+ * output.  unit (fixed per network, e.g. the largest diagonal entry of A)
+ * makes the target of order one.  Quotients are divisions rounded to FP32,
+ * then to BF16 (nearest even); a zero scale gives a zero channel.
  *
  * Layouts: a grid vector is the solver's vector (x index fastest, n = H W,
  * W a multiple of 32).  A prepared input is H W pixels x 2 channels of BF16
@@ -259,13 +274,15 @@ int64_t mstab_cnn_param_count(void);
 
 /*
  * Create a network for H x W grids and batches of up to max_batch samples
- * (H >= 1, W a positive multiple of 32, H W max_batch < 2^31).  Allocates
- * parameters, Adam moments and the activations of a full batch on the current
- * device; parameters start at zero (call mstab_cnn_set_params).
+ * (H >= 1, W a positive multiple of 32, H W max_batch < 2^31, unit > 0).
+ * dilation (host, 6 values in 1..32, NULL = all 1) spaces the taps of layer
+ * l dilation[l] cells apart: y(i, j) takes x(i + (di - 1) d, j + (dj - 1) d).
+ * Allocates parameters, Adam moments and the activations of a full batch on
+ * the current device; parameters start at zero (call mstab_cnn_set_params).
  * Errors: E_INVALID, E_NOMEM, E_HIP; *out is NULL on failure.
  */
-mstab_status mstab_cnn_create(int64_t H, int64_t W, int32_t max_batch, void *hip_stream,
-                              mstab_cnn **out);
+mstab_status mstab_cnn_create(int64_t H, int64_t W, int32_t max_batch, double unit,
+                              const int32_t *dilation, void *hip_stream, mstab_cnn **out);
 mstab_status mstab_cnn_destroy(mstab_cnn *h);
 
 /* Set the FP32 parameters (host, count floats) and reset the Adam state. */
@@ -276,11 +293,11 @@ mstab_status mstab_cnn_get_params(const mstab_cnn *h, float *params_host, float 
                                   int64_t count);
 
 /*
- * Prepare one sample: input_bf16 (device, 2 H W BF16) from x_prev and b, and,
- * if target is not NULL, target (device, H W floats) from x_next.  x_prev, b,
+ * Prepare one sample: input_bf16 (device, 2 H W BF16) from x_prev and r0, and,
+ * if target is not NULL, target (device, H W floats) from x_next.  x_prev, r0,
  * x_next: device, H W doubles.  scale (host, may be NULL) receives s.
  */
-mstab_status mstab_cnn_prepare(mstab_cnn *h, const double *x_prev, const double *b,
+mstab_status mstab_cnn_prepare(mstab_cnn *h, const double *x_prev, const double *r0,
                                const double *x_next, void *input_bf16, float *target,
                                double *scale);
 
@@ -300,10 +317,11 @@ mstab_status mstab_cnn_gradient(mstab_cnn *h, const void *input_bf16, const floa
 mstab_status mstab_cnn_adam_step(mstab_cnn *h, double lr);
 
 /*
- * x_guess = x_prev + s * network(x_prev / s, b / s) for one system (device, H W
- * doubles; x_guess may alias x_prev).
+ * x_guess = x_prev + (s / unit) network(r0 / s, x_prev / sx) for one system
+ * (device, H W doubles; x_guess may alias x_prev).
  */
-mstab_status mstab_cnn_guess(mstab_cnn *h, const double *x_prev, const double *b, double *x_guess);
+mstab_status mstab_cnn_guess(mstab_cnn *h, const double *x_prev, const double *r0,
+                             double *x_guess);
 
 /*
  * Copy an internal tensor of the last pass to dst (device, bytes capacity), for

@@ -38,6 +38,7 @@ constexpr int TAPS = 9;
 constexpr int CIN[NL] = {2, 32, 32, 32, 32, 32};
 constexpr int COUT[NL] = {32, 32, 32, 32, 32, 1};
 constexpr int DW_BLOCKS = 256;   // split-K workgroups of a weight gradient
+constexpr int MAX_DIL = 32;      // largest dilation of a layer
 
 constexpr int param_count_layer(int l) { return COUT[l] * CIN[l] * TAPS + COUT[l]; }
 constexpr int param_offset(int l)
@@ -50,7 +51,7 @@ constexpr int NPARAM = param_offset(NL);
 
 struct CnnCtl {
     double loss_sum;
-    unsigned long long absmax_bits;
+    unsigned long long absmax_bits[2];   // max |r0|, max |x_prev| (bit patterns)
 };
 
 // ---------------------------------------------------------------------------
@@ -87,52 +88,67 @@ __global__ void k_prep_weights(const float *__restrict__ p, bf16 *__restrict__ w
 }
 
 // ---------------------------------------------------------------------------
-// Sample preparation: s = max |b|; input (x_prev / s, b / s); target (x_next - x_prev) / s
+// Sample preparation.  With s = max |r0| and sx = max |x_prev|: input channels
+// (r0 / s, x_prev / sx), target ((x_next - x_prev) unit) / s.  Quotients are
+// divisions (not products with a reciprocal), rounded to FP32, then to BF16
+// (round to nearest even); a zero scale gives a zero channel.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(BLOCK) void k_absmax(int64_t n, const double *__restrict__ b,
-                                                  CnnCtl *ctl)
+__global__ __launch_bounds__(BLOCK) void k_absmax(int64_t n, const double *__restrict__ r0,
+                                                  const double *__restrict__ xp, CnnCtl *ctl)
 {
-    double m = 0.0;
-    for (int64_t e = (int64_t)blockIdx.x * BLOCK + threadIdx.x; e < n;
-         e += (int64_t)gridDim.x * BLOCK)
-        m = fmax(m, fabs(b[e]));
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o));
-    // max of non-negative doubles = max of their bit patterns: order-independent
-    if ((threadIdx.x & 63) == 0)
-        atomicMax(&ctl->absmax_bits, (unsigned long long)__double_as_longlong(m));
-}
-
-__global__ __launch_bounds__(BLOCK) void k_prep_sample(int64_t n, const double *__restrict__ xp,
-                                                       const double *__restrict__ b,
-                                                       const double *__restrict__ xn,
-                                                       const CnnCtl *ctl, bf16 *__restrict__ in,
-                                                       float *__restrict__ target)
-{
-    // values are divided by s (not multiplied by 1/s), rounded to FP32, then
-    // to BF16 (round to nearest even)
-    const double s = __longlong_as_double((long long)ctl->absmax_bits);
+    double m0 = 0.0, m1 = 0.0;
     for (int64_t e = (int64_t)blockIdx.x * BLOCK + threadIdx.x; e < n;
          e += (int64_t)gridDim.x * BLOCK) {
-        const double xs = s > 0.0 ? xp[e] / s : 0.0;
-        const double bs = s > 0.0 ? b[e] / s : 0.0;
-        in[2 * e] = (bf16)(float)xs;
-        in[2 * e + 1] = (bf16)(float)bs;
-        if (target) target[e] = (float)(s > 0.0 ? (xn[e] - xp[e]) / s : 0.0);
+        m0 = fmax(m0, fabs(r0[e]));
+        m1 = fmax(m1, fabs(xp[e]));
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        m0 = fmax(m0, __shfl_xor(m0, o));
+        m1 = fmax(m1, __shfl_xor(m1, o));
+    }
+    // the maximum of non-negative doubles is the maximum of their bit
+    // patterns, so the result does not depend on the order of the updates
+    if ((threadIdx.x & 63) == 0) {
+        atomicMax(&ctl->absmax_bits[0], (unsigned long long)__double_as_longlong(m0));
+        atomicMax(&ctl->absmax_bits[1], (unsigned long long)__double_as_longlong(m1));
     }
 }
 
-// x_guess = x_prev + s * out, two roundings (no contraction).  x_prev and
-// x_guess may be the same array (each element is read, then written).
-__global__ __launch_bounds__(BLOCK) void k_guess(int64_t n, const double *xp,
-                                                 const float *__restrict__ out, const CnnCtl *ctl,
-                                                 double *xg)
+__device__ __forceinline__ double scale_of(const CnnCtl *ctl, int i)
+{
+    return __longlong_as_double((long long)ctl->absmax_bits[i]);
+}
+
+__global__ __launch_bounds__(BLOCK) void k_prep_sample(int64_t n, const double *__restrict__ r0,
+                                                       const double *__restrict__ xp,
+                                                       const double *__restrict__ xn, double unit,
+                                                       const CnnCtl *ctl, bf16 *__restrict__ in,
+                                                       float *__restrict__ target)
 {
 #pragma clang fp contract(off)
-    const double s = __longlong_as_double((long long)ctl->absmax_bits);
+    const double s = scale_of(ctl, 0), sx = scale_of(ctl, 1);
+    for (int64_t e = (int64_t)blockIdx.x * BLOCK + threadIdx.x; e < n;
+         e += (int64_t)gridDim.x * BLOCK) {
+        const double c0 = s > 0.0 ? r0[e] / s : 0.0;
+        const double c1 = sx > 0.0 ? xp[e] / sx : 0.0;
+        in[2 * e] = (bf16)(float)c0;
+        in[2 * e + 1] = (bf16)(float)c1;
+        if (target) target[e] = (float)(s > 0.0 ? ((xn[e] - xp[e]) * unit) / s : 0.0);
+    }
+}
+
+// x_guess = x_prev + (s / unit) out, each operation rounded (no contraction).
+// x_prev and x_guess may be the same array (each element is read, then written).
+__global__ __launch_bounds__(BLOCK) void k_guess(int64_t n, const double *xp,
+                                                 const float *__restrict__ out, double unit,
+                                                 const CnnCtl *ctl, double *xg)
+{
+#pragma clang fp contract(off)
+    const double q = scale_of(ctl, 0) / unit;
     for (int64_t e = (int64_t)blockIdx.x * BLOCK + threadIdx.x; e < n;
          e += (int64_t)gridDim.x * BLOCK)
-        xg[e] = xp[e] + s * (double)out[e];
+        xg[e] = xp[e] + q * (double)out[e];
 }
 
 // ---------------------------------------------------------------------------
@@ -143,7 +159,8 @@ __device__ __forceinline__ bool inside(int y, int x, int H, int W)
     return y >= 0 && y < H && x >= 0 && x < W;
 }
 
-__global__ __launch_bounds__(BLOCK) void k_conv_first(int B, int H, int W, const bf16 *__restrict__ in,
+__global__ __launch_bounds__(BLOCK) void k_conv_first(int B, int H, int W, int d,
+                                                      const bf16 *__restrict__ in,
                                                       const float *__restrict__ w0,
                                                       const float *__restrict__ bias,
                                                       bf16 *__restrict__ out)
@@ -163,7 +180,7 @@ __global__ __launch_bounds__(BLOCK) void k_conv_first(int B, int H, int W, const
         for (int co = 0; co < CH; ++co) acc[co] = sb[co];
 #pragma unroll 1
         for (int tap = 0; tap < TAPS; ++tap) {
-            const int yy = y + tap / 3 - 1, xx = x + tap % 3 - 1;
+            const int yy = y + (tap / 3 - 1) * d, xx = x + (tap % 3 - 1) * d;
             if (!inside(yy, xx, H, W)) continue;
             const int64_t q = (img * H + yy) * W + xx;
             const float a0 = (float)in[2 * q], a1 = (float)in[2 * q + 1];
@@ -180,7 +197,8 @@ __global__ __launch_bounds__(BLOCK) void k_conv_first(int B, int H, int W, const
     }
 }
 
-__global__ __launch_bounds__(BLOCK) void k_conv_last(int B, int H, int W, const bf16 *__restrict__ in,
+__global__ __launch_bounds__(BLOCK) void k_conv_last(int B, int H, int W, int d,
+                                                     const bf16 *__restrict__ in,
                                                      const float *__restrict__ w5,
                                                      const float *__restrict__ bias5,
                                                      float *__restrict__ out)
@@ -196,7 +214,7 @@ __global__ __launch_bounds__(BLOCK) void k_conv_last(int B, int H, int W, const 
         const int y = (int)((g / W) % H), x = (int)(g % W);
         float acc = b5;
         for (int tap = 0; tap < TAPS; ++tap) {
-            const int yy = y + tap / 3 - 1, xx = x + tap % 3 - 1;
+            const int yy = y + (tap / 3 - 1) * d, xx = x + (tap % 3 - 1) * d;
             if (!inside(yy, xx, H, W)) continue;
             const bf16x8 *src = reinterpret_cast<const bf16x8 *>(in + ((img * H + yy) * W + xx) * CH);
 #pragma unroll
@@ -217,7 +235,8 @@ __global__ __launch_bounds__(BLOCK) void k_conv_last(int B, int H, int W, const 
 // One wavefront computes a 32 (channels) x 32 (pixels) tile per step.
 // ---------------------------------------------------------------------------
 template <int MODE>
-__global__ __launch_bounds__(BLOCK) void k_conv_mid(int B, int H, int W, const bf16 *__restrict__ in,
+__global__ __launch_bounds__(BLOCK) void k_conv_mid(int B, int H, int W, int d,
+                                                    const bf16 *__restrict__ in,
                                                     const bf16 *__restrict__ wt,
                                                     const float *__restrict__ bias,
                                                     const bf16 *__restrict__ mask,
@@ -247,7 +266,7 @@ __global__ __launch_bounds__(BLOCK) void k_conv_mid(int B, int H, int W, const b
 #pragma unroll
         for (int m = 0; m < 18; ++m) {
             const int tap = m >> 1, c0 = (m & 1) * 16 + 8 * half;
-            const int yy = y + tap / 3 - 1, xx = x + tap % 3 - 1;
+            const int yy = y + (tap / 3 - 1) * d, xx = x + (tap % 3 - 1) * d;
             bf16x8 b;
             if (inside(yy, xx, H, W))
                 b = *reinterpret_cast<const bf16x8 *>(in + ((img * H + yy) * W + xx) * CH + c0);
@@ -317,7 +336,7 @@ __global__ __launch_bounds__(64) void k_loss_final(int nblocks, const double *__
 // dout[p - off(tap)].  Weights: per-workgroup partials of
 // dW5[ci][tap] = sum_p A5[p + off(tap)][ci] dout[p] and db5 = sum_p dout[p].
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(BLOCK) void k_last_bwd_data(int B, int H, int W,
+__global__ __launch_bounds__(BLOCK) void k_last_bwd_data(int B, int H, int W, int d,
                                                          const float *__restrict__ dout,
                                                          const float *__restrict__ w5,
                                                          const bf16 *__restrict__ a5,
@@ -337,7 +356,7 @@ __global__ __launch_bounds__(BLOCK) void k_last_bwd_data(int B, int H, int W,
 #pragma unroll 1
         for (int tap = 0; tap < TAPS; ++tap) {
             // p meets dout[p - off(tap)]
-            const int yy = y - (tap / 3 - 1), xx = x - (tap % 3 - 1);
+            const int yy = y - (tap / 3 - 1) * d, xx = x - (tap % 3 - 1) * d;
             if (!inside(yy, xx, H, W)) continue;
             const float d = dout[(img * H + yy) * W + xx];
 #pragma unroll
@@ -358,14 +377,14 @@ __global__ __launch_bounds__(BLOCK) void k_last_bwd_data(int B, int H, int W,
 
 // threads 0..287: (ci, tap) = (t / 9, t % 9); thread 288: the bias.  Partials
 // part[block][289].
-__global__ __launch_bounds__(320) void k_last_bwd_weight(int B, int H, int W,
+__global__ __launch_bounds__(320) void k_last_bwd_weight(int B, int H, int W, int d,
                                                          const float *__restrict__ dout,
                                                          const bf16 *__restrict__ a5,
                                                          float *__restrict__ part)
 {
     const int t = threadIdx.x;
     const int ci = t / TAPS, tap = t % TAPS;
-    const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+    const int dy = (tap / 3 - 1) * d, dx = (tap % 3 - 1) * d;
     const int64_t npix = (int64_t)B * H * W;
     float acc = 0.f;
     for (int64_t g = blockIdx.x; g < npix; g += gridDim.x) {
@@ -389,14 +408,14 @@ __global__ __launch_bounds__(320) void k_last_bwd_weight(int B, int H, int W,
 // X in LDS per step; wavefront w accumulates the taps w, w+4, w+8.
 // Partials part[block][tap][co][ci] and part_b[block][co].
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(BLOCK) void k_mid_bwd_weight(int B, int H, int W,
+__global__ __launch_bounds__(BLOCK) void k_mid_bwd_weight(int B, int H, int W, int d,
                                                           const bf16 *__restrict__ dz,
                                                           const bf16 *__restrict__ x,
                                                           float *__restrict__ part,
                                                           float *__restrict__ part_b)
 {
     __shared__ bf16 s_dz[32][CH];
-    __shared__ bf16 s_x[3][34][CH];
+    __shared__ bf16 s_x[3][32 + 2 * MAX_DIL][CH];   // rows y - d, y, y + d; columns x0 - d ..
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, half = lane >> 5, col = lane & 31;
     f32x16 acc[3];
 #pragma unroll
@@ -415,10 +434,11 @@ __global__ __launch_bounds__(BLOCK) void k_mid_bwd_weight(int B, int H, int W,
             *reinterpret_cast<bf16x8 *>(&s_dz[p][c]) =
                 *reinterpret_cast<const bf16x8 *>(dz + ((img * H + y) * W + x0 + p) * CH + c);
         }
-        // stage X halo: rows y-1..y+1, columns x0-1..x0+32 (zeros outside)
-        for (int v = threadIdx.x; v < 3 * 34 * 4; v += BLOCK) {
-            const int r = v / (34 * 4), pc = (v / 4) % 34, c = (v % 4) * 8;
-            const int yy = y + r - 1, xx = x0 + pc - 1;
+        // stage X halo: rows y - d, y, y + d, columns x0 - d .. x0 + 31 + d (zeros outside)
+        const int cols = 32 + 2 * d;
+        for (int v = threadIdx.x; v < 3 * cols * 4; v += BLOCK) {
+            const int r = v / (cols * 4), pc = (v / 4) % cols, c = (v % 4) * 8;
+            const int yy = y + (r - 1) * d, xx = x0 + pc - d;
             bf16x8 val = bf16x8{};
             if (inside(yy, xx, H, W))
                 val = *reinterpret_cast<const bf16x8 *>(x + ((img * H + yy) * W + xx) * CH + c);
@@ -440,10 +460,10 @@ __global__ __launch_bounds__(BLOCK) void k_mid_bwd_weight(int B, int H, int W,
                 const int tap = wave + 4 * i;
                 if (tap >= TAPS) break;
                 const int dy = tap / 3 - 1, dx = tap % 3 - 1;
-                // B: pixels k, column ci = col: X[y + dy][x0 + k + dx]
+                // B: pixels k, column ci = col: X[y + dy d][x0 + k + dx d]
                 bf16x8 b;
 #pragma unroll
-                for (int j = 0; j < 8; ++j) b[j] = s_x[1 + dy][1 + 16 * ks + 8 * half + j + dx][col];
+                for (int j = 0; j < 8; ++j) b[j] = s_x[1 + dy][d + 16 * ks + 8 * half + j + dx * d][col];
                 acc[i] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc[i], 0, 0, 0);
             }
         }
@@ -469,7 +489,7 @@ __global__ __launch_bounds__(BLOCK) void k_mid_bwd_weight(int B, int H, int W,
 
 // Layer 0 weight gradient: threads 0..575 = (tap, ci, co), 576..607 bias.
 // dW0[co][ci][tap] = sum_p in[p + off(tap)][ci] dz0[p][co]; partials part[block][608].
-__global__ __launch_bounds__(640) void k_first_bwd_weight(int B, int H, int W,
+__global__ __launch_bounds__(640) void k_first_bwd_weight(int B, int H, int W, int d,
                                                           const bf16 *__restrict__ dz0,
                                                           const bf16 *__restrict__ in,
                                                           float *__restrict__ part)
@@ -477,7 +497,7 @@ __global__ __launch_bounds__(640) void k_first_bwd_weight(int B, int H, int W,
     const int t = threadIdx.x;
     const int nw = TAPS * 2 * CH;
     const int tap = t / (2 * CH), ci = (t / CH) % 2, co = t % CH;
-    const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+    const int dy = (tap / 3 - 1) * d, dx = (tap % 3 - 1) * d;
     const int64_t npix = (int64_t)B * H * W;
     float acc = 0.f;
     for (int64_t g = blockIdx.x; g < npix; g += gridDim.x) {
@@ -565,6 +585,8 @@ __global__ __launch_bounds__(BLOCK) void k_adam(int n, float *__restrict__ p,
 struct mstab_cnn {
     int64_t H = 0, W = 0;
     int32_t max_batch = 0;
+    double unit = 1.0;       // target = unit (x_next - x_prev) / s
+    int dil[NL] = {1, 1, 1, 1, 1, 1};
     hipStream_t stream = nullptr;
     float *p = nullptr, *g = nullptr, *m = nullptr, *v = nullptr;   // FP32 parameters, grads, Adam
     bf16 *wf = nullptr, *wb = nullptr;
@@ -614,15 +636,15 @@ mstab_status run_forward(mstab_cnn *h, const bf16 *in, int B)
     const int H = (int)h->H, W = (int)h->W;
     const int64_t npix = (int64_t)B * H * W;
     hipLaunchKernelGGL(k_conv_first, dim3(grid_of(npix, 8192)), dim3(BLOCK), 0, h->stream, B, H, W,
-                       in, h->w0, h->bias, h->act[1]);
+                       h->dil[0], in, h->w0, h->bias, h->act[1]);
     const int64_t tiles = npix / 32;
     const int mid_grid = (int)std::min<int64_t>((tiles + 3) / 4, 4096);
     for (int l = 1; l <= 4; ++l)
         hipLaunchKernelGGL(k_conv_mid<0>, dim3(mid_grid), dim3(BLOCK), 0, h->stream, B, H, W,
-                           h->act[l], h->wf + (size_t)(l - 1) * TAPS * CH * CH, h->bias + l * CH,
+                           h->dil[l], h->act[l], h->wf + (size_t)(l - 1) * TAPS * CH * CH, h->bias + l * CH,
                            (const bf16 *)nullptr, h->act[l + 1]);
     hipLaunchKernelGGL(k_conv_last, dim3(grid_of(npix, 8192)), dim3(BLOCK), 0, h->stream, B, H, W,
-                       h->act[5], h->w5, h->bias + 5 * CH, h->out);
+                       h->dil[5], h->act[5], h->w5, h->bias + 5 * CH, h->out);
     CNNCHK(hipGetLastError());
     return MSTAB_OK;
 }
@@ -633,17 +655,30 @@ extern "C" {
 
 int64_t mstab_cnn_param_count(void) { return NPARAM; }
 
-mstab_status mstab_cnn_create(int64_t H, int64_t W, int32_t max_batch, void *hip_stream,
-                              mstab_cnn **out)
+mstab_status mstab_cnn_create(int64_t H, int64_t W, int32_t max_batch, double unit,
+                              const int32_t *dilation, void *hip_stream, mstab_cnn **out)
 {
     if (!out) return MSTAB_E_INVALID;
     *out = nullptr;
+    if (dilation) {
+        for (int l = 0; l < NL; ++l)
+            if (dilation[l] < 1 || dilation[l] > MAX_DIL) {
+                g_cnn_error = "dilations must lie in 1..32";
+                return MSTAB_E_INVALID;
+            }
+    }
+    if (!(unit > 0.0) || !std::isfinite(unit)) {
+        g_cnn_error = "unit must be positive and finite";
+        return MSTAB_E_INVALID;
+    }
     if (H < 1 || W < 32 || W % 32 != 0 || max_batch < 1 || H * W * (int64_t)max_batch > ((int64_t)1 << 31)) {
         g_cnn_error = "H >= 1, W a positive multiple of 32 and H*W*max_batch < 2^31 are required";
         return MSTAB_E_INVALID;
     }
     mstab_cnn *h = new mstab_cnn();
-    h->H = H; h->W = W; h->max_batch = max_batch;
+    h->H = H; h->W = W; h->max_batch = max_batch; h->unit = unit;
+    if (dilation)
+        for (int l = 0; l < NL; ++l) h->dil[l] = dilation[l];
     h->stream = (hipStream_t)hip_stream;
     const int64_t npix = H * W * max_batch;
     auto fail = [&](mstab_status st) { mstab_cnn_destroy(h); return st; };
@@ -727,23 +762,24 @@ mstab_status mstab_cnn_get_params(const mstab_cnn *h, float *params_host, float 
     return MSTAB_OK;
 }
 
-mstab_status mstab_cnn_prepare(mstab_cnn *h, const double *x_prev, const double *b,
+mstab_status mstab_cnn_prepare(mstab_cnn *h, const double *x_prev, const double *r0,
                                const double *x_next, void *input_bf16, float *target,
                                double *scale)
 {
-    if (!h || !x_prev || !b || !input_bf16 || (target && !x_next)) return MSTAB_E_INVALID;
+    if (!h || !x_prev || !r0 || !input_bf16 || (target && !x_next)) return MSTAB_E_INVALID;
     const int64_t n = h->H * h->W;
-    CNNCHK(hipMemsetAsync(&h->ctl->absmax_bits, 0, sizeof(unsigned long long), h->stream));
-    hipLaunchKernelGGL(k_absmax, dim3(grid_of(n, 1024)), dim3(BLOCK), 0, h->stream, n, b, h->ctl);
-    hipLaunchKernelGGL(k_prep_sample, dim3(grid_of(n, 8192)), dim3(BLOCK), 0, h->stream, n, x_prev,
-                       b, x_next, h->ctl, (bf16 *)input_bf16, target);
+    CNNCHK(hipMemsetAsync(h->ctl->absmax_bits, 0, sizeof(h->ctl->absmax_bits), h->stream));
+    hipLaunchKernelGGL(k_absmax, dim3(grid_of(n, 1024)), dim3(BLOCK), 0, h->stream, n, r0, x_prev,
+                       h->ctl);
+    hipLaunchKernelGGL(k_prep_sample, dim3(grid_of(n, 8192)), dim3(BLOCK), 0, h->stream, n, r0,
+                       x_prev, x_next, h->unit, h->ctl, (bf16 *)input_bf16, target);
     CNNCHK(hipGetLastError());
     if (scale) {
         CNNCHK(hipMemcpyAsync(h->ctl_host, h->ctl, sizeof(CnnCtl), hipMemcpyDeviceToHost, h->stream));
         CNNCHK(hipStreamSynchronize(h->stream));
-        double s;
-        memcpy(&s, &h->ctl_host->absmax_bits, sizeof s);
-        *scale = s;
+        double sv;
+        memcpy(&sv, &h->ctl_host->absmax_bits[0], sizeof sv);
+        *scale = sv;
     }
     return MSTAB_OK;
 }
@@ -773,27 +809,27 @@ mstab_status mstab_cnn_gradient(mstab_cnn *h, const void *input_bf16, const floa
                        h->dout, h->rpart);
     hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(64), 0, h->stream, loss_grid, h->rpart, h->ctl);
     // layer 5
-    hipLaunchKernelGGL(k_last_bwd_weight, dim3(DW_BLOCKS), dim3(320), 0, h->stream, B, H, W, h->dout,
-                       h->act[5], h->part);
+    hipLaunchKernelGGL(k_last_bwd_weight, dim3(DW_BLOCKS), dim3(320), 0, h->stream, B, H, W,
+                       h->dil[5], h->dout, h->act[5], h->part);
     hipLaunchKernelGGL(k_grad_reduce, dim3(2), dim3(BLOCK), 0, h->stream, 2, 5, DW_BLOCKS, h->part,
                        (const float *)nullptr, h->g);
     hipLaunchKernelGGL(k_last_bwd_data, dim3(grid_of(npix, 8192)), dim3(BLOCK), 0, h->stream, B, H, W,
-                       h->dout, h->w5, h->act[5], h->dz[4]);
+                       h->dil[5], h->dout, h->w5, h->act[5], h->dz[4]);
     // layers 4..1: weight gradient from dz[l], then dz[l - 1]
     const int64_t tiles = npix / 32;
     const int mid_grid = (int)std::min<int64_t>((tiles + 3) / 4, 4096);
     for (int l = 4; l >= 1; --l) {
         hipLaunchKernelGGL(k_mid_bwd_weight, dim3(DW_BLOCKS), dim3(BLOCK), 0, h->stream, B, H, W,
-                           h->dz[l], h->act[l], h->part, h->part_b);
+                           h->dil[l], h->dz[l], h->act[l], h->part, h->part_b);
         hipLaunchKernelGGL(k_grad_reduce, dim3((TAPS * CH * CH + CH + BLOCK - 1) / BLOCK), dim3(BLOCK),
                            0, h->stream, 0, l, DW_BLOCKS, h->part, h->part_b, h->g);
         hipLaunchKernelGGL(k_conv_mid<1>, dim3(mid_grid), dim3(BLOCK), 0, h->stream, B, H, W,
-                           h->dz[l], h->wb + (size_t)(l - 1) * TAPS * CH * CH, (const float *)nullptr,
+                           h->dil[l], h->dz[l], h->wb + (size_t)(l - 1) * TAPS * CH * CH, (const float *)nullptr,
                            h->act[l], h->dz[l - 1]);
     }
     // layer 0 (no input gradient needed)
     hipLaunchKernelGGL(k_first_bwd_weight, dim3(DW_BLOCKS), dim3(640), 0, h->stream, B, H, W,
-                       h->dz[0], (const bf16 *)input_bf16, h->part);
+                       h->dil[0], h->dz[0], (const bf16 *)input_bf16, h->part);
     hipLaunchKernelGGL(k_grad_reduce, dim3(3), dim3(BLOCK), 0, h->stream, 1, 0, DW_BLOCKS, h->part,
                        (const float *)nullptr, h->g);
     CNNCHK(hipGetLastError());
@@ -819,16 +855,17 @@ mstab_status mstab_cnn_adam_step(mstab_cnn *h, double lr)
     return prep_weights(h);
 }
 
-mstab_status mstab_cnn_guess(mstab_cnn *h, const double *x_prev, const double *b, double *x_guess)
+mstab_status mstab_cnn_guess(mstab_cnn *h, const double *x_prev, const double *r0,
+                             double *x_guess)
 {
-    if (!h || !x_prev || !b || !x_guess) return MSTAB_E_INVALID;
-    mstab_status st = mstab_cnn_prepare(h, x_prev, b, nullptr, h->act[0], nullptr, nullptr);
+    if (!h || !x_prev || !r0 || !x_guess) return MSTAB_E_INVALID;
+    mstab_status st = mstab_cnn_prepare(h, x_prev, r0, nullptr, h->act[0], nullptr, nullptr);
     if (st != MSTAB_OK) return st;
     st = run_forward(h, h->act[0], 1);
     if (st != MSTAB_OK) return st;
     const int64_t n = h->H * h->W;
     hipLaunchKernelGGL(k_guess, dim3(grid_of(n, 8192)), dim3(BLOCK), 0, h->stream, n, x_prev, h->out,
-                       h->ctl, x_guess);
+                       h->unit, h->ctl, x_guess);
     CNNCHK(hipGetLastError());
     CNNCHK(hipStreamSynchronize(h->stream));
     return MSTAB_OK;

@@ -965,6 +965,23 @@ mstab_status mstab_solve_next_guess(mstab_solver *h, const double *b, const doub
     API_END(h)
 }
 
+mstab_status mstab_residual(mstab_solver *h, const double *b, const double *x, double *r,
+                            double *norm2)
+{
+    if (!h) { g_tls_error = "handle is NULL"; return MSTAB_E_INVALID; }
+    API_BEGIN
+    if (!b || !x || !r) fail(MSTAB_E_INVALID, "NULL vector");
+    if (r == b || r == x) fail(MSTAB_E_INVALID, "r must not alias b or x");
+    Engine<double> &E = h->e64;
+    E.small(SMALL_CLEAR);
+    E.spmv(x, r, b, ACT_TRUE, 0, 0);
+    E.sync_status();
+    if (norm2) *norm2 = E.st_host->tt;
+    h->mv_total += 1;
+    return MSTAB_OK;
+    API_END(h)
+}
+
 mstab_status mstab_mv_count(const mstab_solver *h, int64_t *total, int64_t *last_system)
 {
     if (!h) return MSTAB_E_INVALID;

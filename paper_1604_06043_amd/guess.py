@@ -1,0 +1,281 @@
+"""Learned initial guess along time-stepping sequences.
+
+Workload: the 2-D upwind convection-diffusion operator on an n x n grid
+(Pe = 100, implicit Euler with dt = 1e-3, flow direction of matrix seed 0),
+b^(k) = x^(k-1) / dt + f^(k) with f^(k) eight drifting Gaussian bumps whose
+paths depend on the sequence seed.  One matrix A serves every sequence, as in
+the paper's setting of one A and many right-hand sides.
+
+    generate()  runs the GPU solver along sequences and keeps network samples
+                (prepared inputs and targets) in device memory;
+    train()     Adam on the mstab_cnn_* kernels;
+    evaluate()  the same held-out sequence with and without the guess: MVs
+                and seconds per system, guesses accepted by the solver's
+                true-residual gate.
+
+``python -m paper_1604_06043_amd.guess --n 512`` runs all three and prints one
+JSON line.  Everything numeric runs in the library's kernels; this module
+only orders the calls and moves tensors.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import time
+
+import numpy as np
+
+from . import inputs as I
+from . import mstab as M
+
+CHANNELS = M.CNN_CHANNELS
+MATRIX_SEED = 0
+# dilations of the six layers: taps 1, 3, 9, 27 cells apart cover every offset
+# up to 40 (balanced ternary), then 3 and 1; receptive field radius 44 cells
+DILATION = (1, 3, 9, 27, 3, 1)
+
+
+def diag_unit(cd) -> float:
+    """Diagonal entry of the constant-coefficient operator (the target unit)."""
+    h = 1.0 / (cd.n + 1)
+    return cd.inv_dt + 2.0 * cd.dim / (h * h) + sum(abs(b) for b in cd.beta[:cd.dim]) / h
+
+
+def init_params(seed: int, last_scale: float = 0.1) -> np.ndarray:
+    """He-normal weights (std sqrt(2 / fan_in)), zero biases; the last layer
+    scaled down so that the first guesses stay close to x_prev."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for l, (cin, cout) in enumerate(zip(CHANNELS[:-1], CHANNELS[1:])):
+        w = rng.standard_normal(cout * cin * 9) * math.sqrt(2.0 / (9 * cin))
+        if l == len(CHANNELS) - 2:
+            w *= last_scale
+        parts += [w, np.zeros(cout)]
+    p = np.concatenate(parts).astype(np.float32)
+    assert p.size == M.mstab_cnn_param_count()
+    return p
+
+
+class Problem:
+    """The matrix (on the device) and the forcing of any sequence seed."""
+
+    def __init__(self, n: int):
+        self.n, self.N = n, n * n
+        self.cd = I.config("c4", seed=MATRIX_SEED, n=n)
+        self.A = M.mstab_assemble_convdiff(2, n, self.cd.beta, self.cd.inv_dt)
+        self.unit = diag_unit(self.cd)
+
+    def forcing(self, seed: int, steps: int):
+        """Device tensor (steps, N): f^(1..steps) of sequence ``seed``."""
+        import torch
+        bumps = I.Bumps(seed)
+        return torch.tensor(np.stack([bumps.at(k, self.n) for k in range(1, steps + 1)]),
+                            device="cuda")
+
+
+def generate(prob: Problem, cnn: M.Cnn, seeds, steps: int, s: int = 4, ell: int = 2,
+             tol: float = 1e-8):
+    """Samples of every step of every sequence: (inputs, targets, stats)."""
+    import torch
+    total = len(seeds) * steps
+    inp = torch.empty((total, 2 * prob.N), dtype=torch.bfloat16, device="cuda")
+    tgt = torch.empty((total, prob.N), dtype=torch.float32, device="cuda")
+    mv = []
+    k = 0
+    for seed in seeds:
+        F = prob.forcing(seed, steps)
+        solver = M.Solver(prob.A, s, ell, tol=tol, p_seed=seed)
+        x = torch.zeros(prob.N, dtype=torch.float64, device="cuda")
+        xn = torch.empty_like(x)
+        b = torch.empty_like(x)
+        r0 = torch.empty_like(x)
+        for j in range(steps):
+            M.mstab_rhs_step(x, prob.cd.inv_dt, F[j], b)
+            solver.residual(b, x, r0)
+            xn.copy_(x)
+            info = solver.solve_next(b, xn)
+            if not info["converged"]:
+                raise RuntimeError(f"sequence {seed} step {j}: not converged")
+            mv.append(info["mv_total"])
+            cnn.prepare(x, r0, xn, inp[k], tgt[k])
+            x.copy_(xn)
+            k += 1
+        solver.close()
+        del F
+    return inp, tgt, {"samples": total, "mv_per_system": float(np.mean(mv))}
+
+
+def train(cnn: M.Cnn, inp, tgt, epochs: int, batch: int, lr: float, seed: int = 0,
+          lr_final: float = 0.05, log=None):
+    """Adam with a cosine-decayed learning rate over shuffled batches."""
+    import torch
+    n = inp.shape[0]
+    steps_per_epoch = n // batch
+    total = max(1, epochs * steps_per_epoch)
+    rng = np.random.default_rng(seed)
+    bi = torch.empty((batch, inp.shape[1]), dtype=inp.dtype, device="cuda")
+    bt = torch.empty((batch, tgt.shape[1]), dtype=tgt.dtype, device="cuda")
+    hist = []
+    t = 0
+    for ep in range(epochs):
+        perm = torch.as_tensor(rng.permutation(n)[:steps_per_epoch * batch], device="cuda")
+        losses = []
+        for k in range(steps_per_epoch):
+            idx = perm[k * batch:(k + 1) * batch]
+            torch.index_select(inp, 0, idx, out=bi)
+            torch.index_select(tgt, 0, idx, out=bt)
+            losses.append(cnn.gradient(bi, bt, batch))
+            frac = t / total
+            cnn.adam_step(lr * (lr_final + (1 - lr_final) * 0.5 * (1 + math.cos(math.pi * frac))))
+            t += 1
+        hist.append(float(np.mean(losses)))
+        if log:
+            log(f"epoch {ep + 1}/{epochs}: mean loss {hist[-1]:.4e}")
+    return hist
+
+
+def network_guess(solver: M.Solver, cnn: M.Cnn, b, x, r, xg, rounds: int = 1):
+    """x_guess after ``rounds`` corrections x <- x + N(b - A x) starting from x
+    (the network N as an approximate inverse of A); one product with A per
+    round.  Returns the number of products."""
+    solver.residual(b, x, r)
+    cnn.guess(x, r, xg)
+    for _ in range(rounds - 1):
+        solver.residual(b, xg, r)
+        cnn.guess(xg, r, xg)
+    return rounds
+
+
+def evaluate(prob: Problem, cnn: M.Cnn | None, seed: int, steps: int, s: int = 4, ell: int = 2,
+             tol: float = 1e-8, method: int = M.METHOD_MSTAB, rounds: int = 1):
+    """Solve a sequence with (cnn given) or without the learned guess.
+
+    Returns per-system MVs (all products with A, the guess's residuals and the
+    gate's two checks included), seconds per system over the whole loop, and
+    the accepted guesses."""
+    import torch
+    F = prob.forcing(seed, steps)
+    solver = M.Solver(prob.A, s, ell, tol=tol, p_seed=seed, method=method)
+    x = torch.zeros(prob.N, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(x)
+    r0 = torch.empty_like(x)
+    xg = torch.empty_like(x)
+    mv, acc, res = [], [], []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for j in range(steps):
+        M.mstab_rhs_step(x, prob.cd.inv_dt, F[j], b)
+        if cnn is None:
+            info = solver.solve_next(b, x)
+            mv.append(info["mv_total"])
+        else:
+            extra = network_guess(solver, cnn, b, x, r0, xg, rounds)
+            info = solver.solve_next_guess(b, x, xg, x)
+            mv.append(info["mv_total"] + extra)
+            acc.append(info["guess_accepted"])
+        res.append(info["relres_true"])
+        if not info["converged"]:
+            raise RuntimeError(f"sequence {seed} step {j}: not converged")
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    solver.close()
+    return {"mv": mv, "accepted": acc, "relres_true": res, "seconds": sec,
+            "mv_per_system": float(np.mean(mv)), "seconds_per_system": sec / steps}
+
+
+def guess_quality(prob: Problem, cnn: M.Cnn, seed: int, steps: int, s: int = 4, ell: int = 2,
+                  tol: float = 1e-8, rounds: int = 1):
+    """Along a sequence solved without the guess (every system starts from the
+    same x_prev): per round of corrections, the residual ratio
+    ||b - A x_guess|| / ||b - A x_prev|| and the error ratio
+    ||x - x_guess|| / ||x - x_prev|| against the converged x.
+    Returns two arrays of shape (steps, rounds)."""
+    import torch
+    F = prob.forcing(seed, steps)
+    solver = M.Solver(prob.A, s, ell, tol=tol, p_seed=seed)
+    x = torch.zeros(prob.N, dtype=torch.float64, device="cuda")
+    b, r, xg, xp = (torch.empty_like(x) for _ in range(4))
+    res = np.zeros((steps, rounds))
+    err = np.zeros((steps, rounds))
+    guesses = [torch.empty_like(x) for _ in range(rounds)]
+    for j in range(steps):
+        M.mstab_rhs_step(x, prob.cd.inv_dt, F[j], b)
+        n0 = solver.residual(b, x, r)
+        cur = x
+        for k in range(rounds):
+            if k:
+                solver.residual(b, cur, r)
+            cnn.guess(cur, r, guesses[k])
+            cur = guesses[k]
+            nk = solver.residual(b, cur, xg)           # xg: scratch for the residual
+            res[j, k] = math.sqrt(nk / n0) if n0 > 0 else 0.0
+        xp.copy_(x)
+        solver.solve_next(b, x)
+        e0 = torch.linalg.vector_norm(x - xp).item()
+        for k in range(rounds):
+            ek = torch.linalg.vector_norm(x - guesses[k]).item()
+            err[j, k] = ek / e0 if e0 > 0 else 0.0
+    solver.close()
+    return res, err
+
+
+def run(n=512, train_seeds=10, steps=200, eval_steps=200, epochs=20, batch=8, lr=1e-3, s=4, ell=2,
+        seed=0, dilation=DILATION, rounds=1, log=print):
+    import torch
+    torch.cuda.set_device(0)
+    prob = Problem(n)
+    cnn = M.Cnn(n, n, batch, prob.unit, dilation)
+    cnn.set_params(init_params(seed))
+    t0 = time.perf_counter()
+    inp, tgt, gen = generate(prob, cnn, range(1, train_seeds + 1), steps, s, ell)
+    torch.cuda.synchronize()
+    t_gen = time.perf_counter() - t0
+    log(f"generated {gen['samples']} samples in {t_gen:.1f} s ({gen['mv_per_system']:.1f} MVs/system)")
+    t0 = time.perf_counter()
+    hist = train(cnn, inp, tgt, epochs, batch, lr, seed, log=log)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    del inp, tgt
+    held = 1000 + seed
+    plain = evaluate(prob, None, held, eval_steps, s, ell)
+    learned = evaluate(prob, cnn, held, eval_steps, s, ell, rounds=rounds)
+    q, qe = guess_quality(prob, cnn, held, eval_steps, s, ell, rounds=max(rounds, 1))
+    return {
+        "workload": f"convdiff2d_{n}x{n}_pe100_bumps", "n": n * n, "s": s, "ell": ell,
+        "dilation": list(dilation), "rounds": rounds,
+        "train_samples": gen["samples"], "epochs": epochs, "batch": batch,
+        "seconds_generate": t_gen, "seconds_train": t_train,
+        "loss_first_epoch": hist[0], "loss_last_epoch": hist[-1],
+        "eval_steps": eval_steps,
+        "plain": {"mv_per_system": plain["mv_per_system"],
+                  "seconds_per_system": plain["seconds_per_system"]},
+        "learned": {"mv_per_system": learned["mv_per_system"],
+                    "seconds_per_system": learned["seconds_per_system"],
+                    "accepted": int(np.sum(learned["accepted"]))},
+        "guess_residual_ratio_median": [float(v) for v in np.median(q, axis=0)],
+        "guess_error_ratio_median": [float(v) for v in np.median(qe, axis=0)],
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--n", type=int, default=512)
+    ap.add_argument("--train-seeds", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--eval-steps", type=int, default=200)
+    ap.add_argument("--epochs", type=int, default=20)
+    ap.add_argument("--batch", type=int, default=8)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--s", type=int, default=4)
+    ap.add_argument("--ell", type=int, default=2)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--rounds", type=int, default=1)
+    a = ap.parse_args()
+    r = run(a.n, a.train_seeds, a.steps, a.eval_steps, a.epochs, a.batch, a.lr, a.s, a.ell, a.seed,
+            rounds=a.rounds, log=lambda m: print(m, flush=True))
+    print(json.dumps(r), flush=True)
+
+
+if __name__ == "__main__":
+    main()

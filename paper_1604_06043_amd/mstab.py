@@ -26,7 +26,7 @@ KERNEL_CLASSES = {"spmv": K_SPMV, "gamma": K_GAMMA, "eta": K_ETA, "gram": K_GRAM
 # functions declared in include/mstab.h
 EXPORTS = [
     "mstab_options_default", "mstab_create", "mstab_solve_next", "mstab_solve_next_guess",
-    "mstab_mv_count", "mstab_residual_history", "mstab_recycle_reset", "mstab_recycle_get",
+    "mstab_mv_count", "mstab_residual", "mstab_residual_history", "mstab_recycle_reset", "mstab_recycle_get",
     "mstab_recycle_set", "mstab_destroy", "mstab_status_str", "mstab_last_error",
     "mstab_set_profiling", "mstab_kernel_stats", "mstab_convdiff_nnz", "mstab_assemble_convdiff",
     "mstab_spmv", "mstab_project", "mstab_rhs_step",
@@ -85,6 +85,7 @@ def load(path: str = LIB_PATH):
         "mstab_solve_next": (i32, [P, P, P, ctypes.POINTER(mstab_info)]),
         "mstab_solve_next_guess": (i32, [P, P, P, P, P, ctypes.POINTER(mstab_info)]),
         "mstab_mv_count": (i32, [P, ctypes.POINTER(i64), ctypes.POINTER(i64)]),
+        "mstab_residual": (i32, [P, P, P, P, ctypes.POINTER(f64)]),
         "mstab_residual_history": (i32, [P, P, P, i64, ctypes.POINTER(i64)]),
         "mstab_recycle_reset": (i32, [P]),
         "mstab_recycle_get": (i32, [P, P, P, ctypes.POINTER(i64), ctypes.POINTER(i32)]),
@@ -101,7 +102,7 @@ def load(path: str = LIB_PATH):
         "mstab_project": (i32, [i64, i32, u64, P, P, P]),
         "mstab_rhs_step": (i32, [i64, P, f64, P, P, P]),
         "mstab_cnn_param_count": (i64, []),
-        "mstab_cnn_create": (i32, [i64, i64, i32, P, ctypes.POINTER(P)]),
+        "mstab_cnn_create": (i32, [i64, i64, i32, f64, P, P, ctypes.POINTER(P)]),
         "mstab_cnn_destroy": (i32, [P]),
         "mstab_cnn_set_params": (i32, [P, P, i64]),
         "mstab_cnn_get_params": (i32, [P, P, P, i64]),
@@ -268,6 +269,13 @@ class Solver:
         _check(self.lib.mstab_mv_count(self.h, ctypes.byref(t), ctypes.byref(l)))
         return t.value, l.value
 
+    def residual(self, b, x, r) -> float:
+        """r = b - A x; returns ||r||^2 (one product with A)."""
+        _require_cuda(b, x, r)
+        n2 = ctypes.c_double()
+        _check(self.lib.mstab_residual(self.h, _ptr(b), _ptr(x), _ptr(r), ctypes.byref(n2)), self.h)
+        return n2.value
+
     def residual_history(self):
         n = ctypes.c_int64()
         _check(self.lib.mstab_residual_history(self.h, None, None, 0, ctypes.byref(n)))
@@ -331,12 +339,16 @@ class Cnn:
     and outputs device float32 tensors of H W per sample.
     """
 
-    def __init__(self, H: int, W: int, max_batch: int = 1, stream=None):
+    def __init__(self, H: int, W: int, max_batch: int = 1, unit: float = 1.0, dilation=None,
+                 stream=None):
         self.lib = load()
-        self.H, self.W, self.max_batch = H, W, max_batch
+        self.H, self.W, self.max_batch, self.unit = H, W, max_batch, unit
+        self.dilation = tuple(dilation) if dilation is not None else (1,) * 6
         self._stream = _stream(stream)
+        dil = (ctypes.c_int32 * 6)(*self.dilation)
         h = ctypes.c_void_p()
-        _check_cnn(self.lib.mstab_cnn_create(H, W, max_batch, self._stream, ctypes.byref(h)))
+        _check_cnn(self.lib.mstab_cnn_create(H, W, max_batch, float(unit), ctypes.cast(dil, ctypes.c_void_p),
+                                             self._stream, ctypes.byref(h)))
         self.h = h
         self.nparam = mstab_cnn_param_count()
 
@@ -365,10 +377,10 @@ class Cnn:
                                                  g.ctypes.data_as(ctypes.c_void_p), self.nparam))
         return p, g
 
-    def prepare(self, x_prev, b, x_next=None, inp=None, target=None) -> float:
-        _require_cuda(x_prev, b, x_next, inp, target)
+    def prepare(self, x_prev, r0, x_next=None, inp=None, target=None) -> float:
+        _require_cuda(x_prev, r0, x_next, inp, target)
         scale = ctypes.c_double()
-        _check_cnn(self.lib.mstab_cnn_prepare(self.h, _ptr(x_prev), _ptr(b), _ptr(x_next), _ptr(inp),
+        _check_cnn(self.lib.mstab_cnn_prepare(self.h, _ptr(x_prev), _ptr(r0), _ptr(x_next), _ptr(inp),
                                               _ptr(target), ctypes.byref(scale)))
         return scale.value
 
@@ -386,9 +398,9 @@ class Cnn:
     def adam_step(self, lr: float):
         _check_cnn(self.lib.mstab_cnn_adam_step(self.h, float(lr)))
 
-    def guess(self, x_prev, b, x_guess):
-        _require_cuda(x_prev, b, x_guess)
-        _check_cnn(self.lib.mstab_cnn_guess(self.h, _ptr(x_prev), _ptr(b), _ptr(x_guess)))
+    def guess(self, x_prev, r0, x_guess):
+        _require_cuda(x_prev, r0, x_guess)
+        _check_cnn(self.lib.mstab_cnn_guess(self.h, _ptr(x_prev), _ptr(r0), _ptr(x_guess)))
         return x_guess
 
     def tensor(self, which: int, layer: int, dst):
