@@ -23,7 +23,11 @@ module only fixes the parameters):
 * forcing ``f`` i.i.d. U(0,1), drawn once and kept fixed over time;
 * variable diffusion ``kappa = exp(z)``, ``z`` standard normal per node;
 * the cut-space basis P: uniform entries on [-1, 1) from a counter-based
-  hash (a random choice of P, which the method allows), see :func:`p_dense`.
+  hash (a random choice of P, which the method allows), see :func:`p_dense`;
+* an unstructured matrix from a random geometric graph on the periodic unit
+  3-torus (:func:`rgg`): identity plus graph Laplacian plus an antisymmetric
+  convection term, rows relabelled by a random permutation.  Its CSR arrays
+  are built here (the graph is the random input), identically for both sides.
 """
 from __future__ import annotations
 
@@ -245,3 +249,60 @@ def sin_rhs(n: int = 40) -> np.ndarray:
 def white_noise(seed: int, step: int, N: int) -> np.ndarray:
     """xi ~ N(0,1) for step ``step`` (distinct block of the XI stream)."""
     return normal(seed, S_XI, N, offset=step * ((N + 1) // 2))
+
+
+@dataclass
+class Graph:
+    """CSR of A = I + L + S on a random geometric graph (see :func:`rgg`)."""
+    N: int
+    radius: float
+    beta: tuple
+    row_ptr: np.ndarray
+    col: np.ndarray
+    val: np.ndarray
+    seed: int = 0
+
+    @property
+    def nnz(self) -> int:
+        return int(self.col.shape[0])
+
+
+def rgg(N: int, seed: int, degree: float = 14.0) -> Graph:
+    """Random geometric graph matrix on the periodic unit 3-torus.
+
+    N points uniform on [0,1)^3 (stream RGG); an edge joins two points closer
+    than r = (3 degree / (4 pi N))^(1/3) in the periodic metric (expected
+    degree ``degree``).  With W the 0/1 adjacency, D its degrees and
+    p_j - p_i the shortest periodic displacement,
+        A = I + (D - W) + S,   S_ij = beta . (p_j - p_i) / (2 r)
+    (S antisymmetric; beta a unit vector, a normalized standard normal triple
+    of stream DIR).  Rows and columns are relabelled by one random
+    permutation (the argsort of uniform keys that follow the points in the
+    RGG stream); columns are sorted within each row.
+    """
+    from scipy.spatial import cKDTree
+    pts = uniform(seed, S_RGG, 3 * N).reshape(N, 3)
+    r = (3.0 * degree / (4.0 * math.pi * N)) ** (1.0 / 3.0)
+    pairs = cKDTree(pts, boxsize=1.0).query_pairs(r, output_type="ndarray")
+    i, j = pairs[:, 0].astype(np.int64), pairs[:, 1].astype(np.int64)
+    del pairs
+    g = normal(seed, S_DIR, 3)
+    beta = g / math.sqrt(float(g @ g))
+    disp = pts[j] - pts[i]
+    disp -= np.round(disp)
+    sij = (disp @ beta) / (2.0 * r)
+    del disp
+    deg = np.bincount(i, minlength=N) + np.bincount(j, minlength=N)
+    perm = np.argsort(uniform(seed, S_RGG, N, offset=3 * N), kind="stable")
+    new = np.empty(N, dtype=np.int64)
+    new[perm] = np.arange(N, dtype=np.int64)          # old index -> new index
+    rows = np.concatenate([new[i], new[j], new])
+    cols = np.concatenate([new[j], new[i], new])
+    vals = np.concatenate([-1.0 + sij, -1.0 - sij, 1.0 + deg.astype(np.float64)])
+    del i, j, sij
+    order = np.argsort(rows * N + cols, kind="stable")
+    rows, cols, vals = rows[order], cols[order], vals[order]
+    row_ptr = np.zeros(N + 1, dtype=np.int64)
+    np.cumsum(np.bincount(rows, minlength=N), out=row_ptr[1:])
+    return Graph(N, r, tuple(float(b) for b in beta), row_ptr.astype(np.int32),
+                 cols.astype(np.int32), vals, seed)
