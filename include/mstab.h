@@ -84,8 +84,10 @@ typedef struct {
     int64_t fetch_level;       /* AT_LEVEL: level j of the fetched U, V */
     uint64_t p_seed;           /* seed of the cut-space basis P (counter-based uniform entries) */
     int32_t max_replacements;  /* true-residual replacements at the end of a solve; default 3 */
-    double inner_tol;          /* F32_REFINE: relative tolerance of each inner solve (recursive
-                                  residual; the FP64 true residual judges the result); default 1e-4 */
+    double inner_tol;          /* F32_REFINE: tightest relative tolerance of an inner solve
+                                  (recursive residual; the FP64 true residual judges the result);
+                                  an inner solve asks for max(inner_tol, 0.3 tol ||b|| / ||r||),
+                                  the reduction still missing; default 1e-4 */
     int32_t max_refinements;   /* F32_REFINE: outer correction steps; default 20 */
 } mstab_options;
 

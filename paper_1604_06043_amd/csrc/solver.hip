@@ -817,7 +817,12 @@ mstab_status solve_mixed(mstab_solver *h, const double *b, double *x, mstab_info
                            E.Tv, 1.0 / sigma, h->r32);
         HIPCHK(hipGetLastError());
         F.fill(F.X, F.ld, 0.0f);
-        SolveResult in = F.solve(h->r32, h->opt.inner_tol, h->opt.max_mv - (mv32 + mv64 + mvchk),
+        // ask the inner solve only for the reduction still missing (with a
+        // margin for the gap between FP32 recursive and FP64 true residuals),
+        // never for less than inner_tol
+        const double need = h->opt.tol * std::sqrt(bb) / sigma;
+        const double inner = std::max(h->opt.inner_tol, std::min(0.5, 0.3 * need));
+        SolveResult in = F.solve(h->r32, inner, h->opt.max_mv - (mv32 + mv64 + mvchk),
                                  h->opt.method, h->opt.fetch, std::sqrt(h->opt.inner_tol),
                                  h->opt.fetch_level, 0, false);
         ++refinements;

@@ -376,6 +376,35 @@ def test_recycled_zero_data_restarts(torch_dev, ms, orc):
     assert info["mv_total"] == io.mv_total
 
 
+def test_recycled_start_absorbs_shifts_in_span_u(torch_dev, ms, orc):
+    """Starts in x0 + span(U) give the same iteration on the GPU too: the
+    first recycled gamma step removes the shift exactly."""
+    torch = torch_dev
+    print("[span(U) invariance]", flush=True)
+    cd = I.config("c1", seed=0, n=32)
+    Ag = gpu_assemble(ms, cd)
+    solver = ms.Solver(Ag, 4, 2, p_seed=0)
+    f = dev(torch, cd.f)
+    x = torch.zeros(cd.N, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(x)
+    for _ in range(3):
+        ms.mstab_rhs_step(x, cd.inv_dt, f, b)
+        solver.solve_next(b, x)
+    U, V, level = solver.recycle_get()
+    ms.mstab_rhs_step(x, cd.inv_dt, f, b)
+    xr = x.clone()
+    iref = solver.solve_next(b, xr)
+    rng = np.random.default_rng(1)
+    for scale in (1e-3, 1.0, 1e3):
+        solver.recycle_set(U, V, level)
+        alpha = torch.tensor(scale * rng.standard_normal(4), device="cuda")
+        xa = x + U.T @ alpha
+        ia = solver.solve_next(b, xa)
+        assert ia["mv"] == iref["mv"] and ia["converged"]
+        assert (xa - xr).abs().max().item() <= 1e-10 * xr.abs().max().item()
+    solver.close()
+
+
 def test_guess_gate(torch_dev, ms, orc):
     torch = torch_dev
     cd, Ao, Ag = small_problem(torch, ms, orc, n=20)
@@ -432,3 +461,89 @@ def test_mixed_precision_sequence(torch_dev, ms, orc):
         err = np.linalg.norm(xg - xo) / np.linalg.norm(xo)
         print(f"  system {k}: mixed vs FP64 oracle rel err {err:.2e}, refinements {ig['refinements']}")
         assert err <= 2 * kappa * 1e-8
+
+
+# ---------------------------------------------------------------------------
+# Unstructured matrix: random geometric graph, rows relabelled at random
+# ---------------------------------------------------------------------------
+def rgg_problem(torch, ms, orc, N, seed):
+    g = I.rgg(N, seed)
+    Ao = orc.CSR(g.row_ptr, g.col, g.val)
+    Ag = ms.CSR(dev(torch, g.row_ptr), dev(torch, g.col), dev(torch, g.val))
+    forcing = [0.1 * I.white_noise(seed, k, N) for k in range(12)]
+    return g, Ao, Ag, forcing
+
+
+def test_rgg_spmv_bit_exact(torch_dev, ms, orc):
+    torch = torch_dev
+    g, Ao, Ag, _ = rgg_problem(torch, ms, orc, 30000, 4)
+    x = np.random.default_rng(0).standard_normal(g.N)
+    y = torch.empty(g.N, dtype=torch.float64, device="cuda")
+    ms.mstab_spmv(Ag, dev(torch, x), y)
+    np.testing.assert_array_equal(y.cpu().numpy(), orc.spmv(Ao, x))
+
+
+@pytest.mark.parametrize("s,ell,method", [(4, 2, 0), (4, 2, 1), (2, 4, 0)])
+def test_rgg_teacher_forced(torch_dev, ms, orc, s, ell, method):
+    """b^(i+1) = x^(i) + 0.1 xi^(i) on the graph matrix, system by system."""
+    torch = torch_dev
+    print(f"[rgg teacher-forced s={s} l={ell} method={method}]", flush=True)
+    seed = 5
+    g, Ao, Ag, forcing = rgg_problem(torch, ms, orc, 20000, seed)
+    P = I.p_dense(seed, g.N, s)
+    solver = ms.Solver(Ag, s, ell, p_seed=seed, method=method)
+    xo = np.zeros(g.N)
+    rec = orc.Recycle.empty(g.N, s)
+    errs = []
+    for k in range(6):
+        b = orc.rhs_step(xo, 1.0, forcing[k])
+        if method == 0 and rec.have:
+            solver.recycle_set(dev(torch, rec.U.T), dev(torch, rec.V.T), rec.level)
+        else:
+            solver.recycle_reset()
+        x = dev(torch, xo)
+        ig = solver.solve_next(dev(torch, b), x)
+        with orc.reversed_sums():
+            xr, ir, _, _ = orc.solve(Ao, b, xo, s, ell, P, recycle=rec.copy(), method=method)
+        xn, io, rec, _ = orc.solve(Ao, b, xo, s, ell, P, recycle=rec, method=method)
+        err = np.linalg.norm(x.cpu().numpy() - xn) / np.linalg.norm(xn)
+        sen = np.linalg.norm(xr - xn) / np.linalg.norm(xn)
+        errs.append(err)
+        assert ig["converged"] and io.converged and ig["recycled"] == io.recycled
+        if near_threshold(io) or ir.mv_total != io.mv_total or sen > 1e-10:
+            assert abs(ig["cycles"] - io.cycles) <= 1
+            assert err <= 10 * 1e-8
+        else:
+            assert err <= max(1e-9, 10 * sen), (k, err, sen, errs)
+            assert ig["mv_total"] == io.mv_total, (k, ig, io)
+        xo = xn
+    print("  rel err per system", ["%.1e" % e for e in errs])
+
+
+def test_rgg_mixed_precision(torch_dev, ms, orc):
+    """FP32 inner solves with FP64 refinement on the graph matrix: every
+    system reaches the FP64 tolerance; error against the FP64 oracle stated."""
+    torch = torch_dev
+    print("[rgg mixed precision]", flush=True)
+    seed = 6
+    s, ell = 4, 2
+    g, Ao, Ag, forcing = rgg_problem(torch, ms, orc, 20000, seed)
+    solver = ms.Solver(Ag, s, ell, p_seed=seed, precision=ms.PREC_F32_REFINE)
+    P = I.p_dense(seed, g.N, s)
+    x = torch.zeros(g.N, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(x)
+    rec = orc.Recycle.empty(g.N, s)
+    for k in range(6):
+        xprev = x.cpu().numpy()
+        ms.mstab_rhs_step(x, 1.0, dev(torch, forcing[k]), b)
+        bo = orc.rhs_step(xprev, 1.0, forcing[k])
+        ig = solver.solve_next(b, x)
+        # the FP64 oracle from the same start and right-hand side
+        xn, io, rec, _ = orc.solve(Ao, bo, xprev, s, ell, P, recycle=rec)
+        xg = x.cpu().numpy()
+        true = np.linalg.norm(bo - orc.spmv(Ao, xg)) / np.linalg.norm(bo)
+        err = np.linalg.norm(xg - xn) / np.linalg.norm(xn)
+        print(f"  system {k}: true relres {true:.2e}, vs FP64 oracle {err:.2e}, "
+              f"refinements {ig['refinements']}, MVs {ig['mv_total']} (FP64 {ig['mv_f64']})")
+        assert ig["converged"] and true <= 1e-8
+        assert err <= 1e-6

@@ -272,6 +272,34 @@ def test_recycled_start_keeps_v_equal_au_and_helps(orc):
     assert sum(i.mv_total for i in inf_m[1:]) < sum(i.mv_total for i in inf_i[1:])
 
 
+def test_recycled_start_absorbs_shifts_in_span_u(orc):
+    """With recycled U, V (V = A U), the first gamma step at level 0 solves
+    P^T V gamma = P^T r0 and sets x += U gamma, r -= V gamma.  Starting from
+    x0 + U alpha instead gives gamma - alpha and the same x, r: every start
+    in x0 + span(U) yields the same iteration (so a guess made of recycled
+    coefficients cannot change what M(s)stab does)."""
+    cd, A = small_convdiff(orc, 2, 24, seed=0)
+    s, ell = 4, 2
+    P = I.p_dense(0, A.n, s)
+    rec = orc.Recycle.empty(A.n, s)
+    x = np.zeros(A.n)
+    for _ in range(3):
+        b = orc.rhs_step(x, cd.inv_dt, cd.f)
+        x, _, rec, _ = orc.solve(A, b, x, s, ell, P, recycle=rec)
+    assert rec.have
+    b = orc.rhs_step(x, cd.inv_dt, cd.f)
+    ref, iref, _, _ = orc.solve(A, b, x, s, ell, P, recycle=rec.copy())
+    rng = np.random.default_rng(0)
+    for scale in (1e-3, 1.0, 1e3):
+        alpha = scale * rng.standard_normal(s)
+        xa, ia, _, _ = orc.solve(A, b, x + rec.U @ alpha, s, ell, P, recycle=rec.copy())
+        assert ia.mv == iref.mv and ia.cycles == iref.cycles and ia.converged
+        assert np.abs(xa - ref).max() <= 1e-10 * np.abs(ref).max()
+    # a shift outside span(U) does change the iteration
+    xo, io, _, _ = orc.solve(A, b, x + 1e-3 * rng.standard_normal(A.n), s, ell, P, recycle=rec.copy())
+    assert np.abs(xo - ref).max() > 1e-9 * np.abs(ref).max()
+
+
 def test_true_residual_finish(orc):
     cd, A = small_convdiff(orc, 3, 6, seed=4)
     P = I.p_dense(2, A.n, 4)
