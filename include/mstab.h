@@ -53,7 +53,10 @@ typedef enum {
 
 typedef enum {
     MSTAB_PREC_F64 = 0,        /* every vector operation in FP64 */
-    MSTAB_PREC_F32_REFINE = 1  /* FP32 inner M(s)stab(l), FP64 true residual and correction */
+    MSTAB_PREC_F32_REFINE = 1  /* FP32 M(s)stab(l) whose residual is replaced after every cycle
+                                  by the FP64 true residual b - A x, x accumulated in FP64
+                                  (the paper's residual replacement, Section 6, in mixed
+                                  precision); FP64 small solves */
 } mstab_precision;
 
 typedef enum {
@@ -84,10 +87,8 @@ typedef struct {
     int64_t fetch_level;       /* AT_LEVEL: level j of the fetched U, V */
     uint64_t p_seed;           /* seed of the cut-space basis P (counter-based uniform entries) */
     int32_t max_replacements;  /* true-residual replacements at the end of a solve; default 3 */
-    double inner_tol;          /* F32_REFINE: tightest relative tolerance of an inner solve
-                                  (recursive residual; the FP64 true residual judges the result);
-                                  an inner solve asks for max(inner_tol, 0.3 tol ||b|| / ||r||),
-                                  the reduction still missing; default 1e-4 */
+    double inner_tol;          /* reserved (F32_REFINE replaces the FP32 residual by the FP64
+                                  true residual after every cycle and stops on it); default 1e-4 */
     int32_t max_refinements;   /* F32_REFINE: outer correction steps; default 20 */
 } mstab_options;
 
@@ -95,11 +96,12 @@ typedef struct {
     int32_t status;            /* the mstab_status of the solve */
     int32_t converged;         /* true relative residual <= tol */
     int32_t recycled;          /* the solve started from recycled U, V */
-    int32_t restarts;          /* breakdown restarts (fresh Arnoldi basis) */
+    int32_t restarts;          /* breakdown restarts (fresh Arnoldi basis); F32_REFINE: also FP32
+                                  processes abandoned for loss of accuracy */
     int32_t replacements;      /* true-residual replacements */
-    int32_t refinements;       /* F32_REFINE: outer correction steps */
+    int32_t refinements;       /* F32_REFINE: FP32 processes started (1 unless one was abandoned) */
     int32_t guess_accepted;    /* mstab_solve_next_guess: the guess passed the residual gate */
-    int32_t pad_;
+    int32_t f64_fallback;      /* F32_REFINE: the FP32 processes stalled and FP64 iterations finished */
     int64_t mv;                /* products with A in the iteration (initial residual, Arnoldi, cycles) */
     int64_t mv_check;          /* products with A for true-residual checks and guess gates */
     int64_t mv_f64;            /* F32_REFINE: products with the FP64 matrix (all in mv/mv_check) */

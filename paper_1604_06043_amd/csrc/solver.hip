@@ -17,6 +17,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <new>
 #include <string>
 #include <vector>
@@ -403,6 +404,17 @@ struct Engine {
     }
 
     // P^T y (and ||y||^2): dst 0 -> ptv[0][q]; dst 1 -> ptt, tt
+    // Called after every completed cycle with ||r||^2 when set (the FP32
+    // solve of the mixed form replaces its recursive residual there).
+    // HOOK_REPLACED: it has enqueued a replacement, which must leave the new
+    // residual in Rc(0) and its P^T r, ||r||^2 and gamma in ctl;
+    // HOOK_STOP: end the solve (not converged).
+    enum { HOOK_NONE = 0, HOOK_REPLACED = 1, HOOK_STOP = 2 };
+    std::function<int(double)> after_cycle;
+    // After a replacement, with the new ||r||^2: false ends the solve (not
+    // converged).
+    std::function<bool(double)> after_replace;
+
     void project(const T *y, int dst, int q)
     {
         const int grid = grid_for(n, BLOCK, GRAM_MAX_BLOCKS);
@@ -620,6 +632,23 @@ struct Engine {
                 ++res.cycles;
                 level += ell;
                 r_is_true = false;
+                const int hook = after_cycle ? after_cycle(st_host->rr) : HOOK_NONE;
+                if (hook == HOOK_STOP) {
+                    res.status = MSTAB_NOT_CONVERGED;
+                    rr = st_host->rr;
+                    goto out;
+                }
+                if (hook == HOOK_REPLACED) {
+                    sync_status();
+                    mv = st_host->mv;
+                    if (st_host->flags & FLAG_NONFINITE) { res.status = MSTAB_E_NONFINITE; goto out; }
+                    if (st_host->flags & FLAG_BREAKDOWN) { res.status = MSTAB_E_BREAKDOWN; goto out; }
+                    if (after_replace && !after_replace(st_host->rr)) {
+                        res.status = MSTAB_NOT_CONVERGED;
+                        rr = st_host->rr;
+                        goto out;
+                    }
+                }
                 rr = st_host->rr;
                 hist_mv.push_back(mv + res.mv_check);
                 hist_res.push_back(std::sqrt(rr / bb));
@@ -695,6 +724,7 @@ struct mstab_solver {
     Engine<double> e64;
     Engine<float> e32;
     float *r32 = nullptr;   // F32_REFINE: scaled residual (right-hand side of the inner solve)
+    double *xbak = nullptr; // F32_REFINE: x before the last fold of the FP32 iterate
     Profiler prof;
     int64_t mv_total = 0, mv_last = 0;
     std::vector<int64_t> hist_mv;
@@ -774,11 +804,31 @@ mstab_status solve_f64(mstab_solver *h, const double *b, double *x, mstab_info *
 
 // Defect correction: FP64 true residual, FP32 M(s)stab(l) on the correction
 // equation A d = r / ||r|| to inner_tol, x += ||r|| d; until ||b - A x|| <= tol ||b||.
+// factor by which the FP32 residual must fall between two replacements
+// (1: after every cycle, the paper's practice)
+#ifndef MSTAB_REPLACE_DROP
+#define MSTAB_REPLACE_DROP 1.0
+#endif
+constexpr double REPLACE_DROP = MSTAB_REPLACE_DROP;
+// an FP32 process whose recursive residual grows by DIVERGED_GROWTH, or whose
+// true residual grows by FOLD_GROWTH, over the smallest true residual it has
+// reached has lost its accuracy and is ended (x returns to that point)
+constexpr double DIVERGED_GROWTH = 1e3;
+constexpr double FOLD_GROWTH = 1e2;
+
 mstab_status solve_mixed(mstab_solver *h, const double *b, double *x, mstab_info *info,
                          int extra_checks, int accepted)
 {
+    // One FP32 Krylov process per refinement.  At the end of a cycle where
+    // its residual has fallen far enough (reliable updating), its iterate is
+    // folded into the FP64 x and its recursive residual is replaced by the
+    // FP64 true residual b - A x (scaled by the fixed sigma, rounded to
+    // FP32).  U, V and the Sonneveld space carry on across the replacement.
+    // A refinement ends when the replaced residual meets the tolerance or the
+    // FP32 process stops; the FP64 true residual then decides, and a further
+    // refinement (fresh process) starts only if it is still too large.
     auto t0 = std::chrono::steady_clock::now();
-    Engine<double> &E = h->e64;   // only its X, Tv, ctl, spmv are used
+    Engine<double> &E = h->e64;   // x64, true residuals; FP64 iterations on a stall
     Engine<float> &F = h->e32;
     const double tol2 = h->opt.tol * h->opt.tol;
     SolveResult tot;
@@ -786,8 +836,12 @@ mstab_status solve_mixed(mstab_solver *h, const double *b, double *x, mstab_info
     h->hist_mv.clear();
     h->hist_res.clear();
     int64_t mv32 = 0, mvchk = extra_checks, mv64 = 0;
-    int refinements = 0;
+    int refinements = 0, abandoned = 0, stalls = 0, fallback = 0;
     double bb = 0.0;
+    struct HookGuard {
+        Engine<float> &F;
+        ~HookGuard() { F.after_cycle = nullptr; F.after_replace = nullptr; }
+    } guard{F};
     for (;;) {
         E.small(SMALL_CLEAR);
         E.spmv(E.X, E.Tv, b, ACT_TRUE, 0, 0);
@@ -804,29 +858,87 @@ mstab_status solve_mixed(mstab_solver *h, const double *b, double *x, mstab_info
         }
         tot.relres_true = std::sqrt(tt / bb);
         tot.relres_rec = tot.relres_true;
-        h->hist_mv.push_back(mv32 + mv64 + mvchk);
-        h->hist_res.push_back(tot.relres_true);
+        if (h->hist_mv.empty()) {
+            h->hist_mv.push_back(mv32 + mv64 + mvchk);
+            h->hist_res.push_back(tot.relres_true);
+        }
         if (tt <= tol2 * bb) { tot.converged = true; break; }
+        if (stalls >= 2) break;   // FP64 iterations finish below
         if (refinements >= h->opt.max_refinements ||
             mv32 + mv64 + mvchk >= h->opt.max_mv) {
             tot.status = MSTAB_NOT_CONVERGED;
             break;
         }
         const double sigma = std::sqrt(tt);
+        const double inv_sigma = 1.0 / sigma;
         hipLaunchKernelGGL(k_scale_to_f32, dim3(grid1(h->n)), dim3(BLOCK), 0, h->stream, h->n,
-                           E.Tv, 1.0 / sigma, h->r32);
+                           E.Tv, inv_sigma, h->r32);
         HIPCHK(hipGetLastError());
         F.fill(F.X, F.ld, 0.0f);
-        // ask the inner solve only for the reduction still missing (with a
-        // margin for the gap between FP32 recursive and FP64 true residuals),
-        // never for less than inner_tol
-        const double need = h->opt.tol * std::sqrt(bb) / sigma;
-        const double inner = std::max(h->opt.inner_tol, std::min(0.5, 0.3 * need));
-        SolveResult in = F.solve(h->r32, inner, h->opt.max_mv - (mv32 + mv64 + mvchk),
-                                 h->opt.method, h->opt.fetch, std::sqrt(h->opt.inner_tol),
+        // in units of sigma the FP64 tolerance is tol ||b|| / sigma (a
+        // replaced residual is the true one, so the process may aim there)
+        const double scale = std::sqrt(bb) / sigma;
+        const double thr2_inner = tol2 * scale * scale;
+        // Replace once the recursive residual has dropped by REPLACE_DROP
+        // below the last true one, and whenever the process would stop on
+        // it.  x at the smallest true residual so far is kept in xbak; a
+        // process whose residual grows well past that is ended, and x returns
+        // to the best point before the next refinement.
+        double last_rr = 1.0, best_rr = 1.0;
+        bool stopped = false, pending_fold = false;
+        int64_t hook_mv = 0;
+        HIPCHK(hipMemcpyAsync(h->xbak, E.X, sizeof(double) * h->n, hipMemcpyDeviceToDevice,
+                              h->stream));
+        F.after_cycle = [&, sigma, inv_sigma](double rr_now) -> int {
+            if (!std::isfinite(rr_now) || rr_now > DIVERGED_GROWTH * DIVERGED_GROWTH * best_rr) {
+                stopped = true;
+                return Engine<float>::HOOK_STOP;
+            }
+            if (!(rr_now <= REPLACE_DROP * REPLACE_DROP * last_rr || rr_now <= thr2_inner))
+                return Engine<float>::HOOK_NONE;
+            pending_fold = true;
+            hipLaunchKernelGGL(k_correct, dim3(grid1(h->n)), dim3(BLOCK), 0, h->stream, h->n, F.X,
+                               sigma, E.X);
+            F.fill(F.X, F.ld, 0.0f);
+            E.spmv(E.X, E.Tv, b, ACT_TRUE, 0, 0);
+            ++hook_mv;
+            hipLaunchKernelGGL(k_scale_to_f32, dim3(grid1(h->n)), dim3(BLOCK), 0, h->stream, h->n,
+                               E.Tv, inv_sigma, F.Rc(0));
+            F.project(F.Rc(0), 1, 0);
+            F.small(SMALL_REPLACE);
+            return Engine<float>::HOOK_REPLACED;
+        };
+        F.after_replace = [&](double rr_true) -> bool {
+            if (!std::isfinite(rr_true)) {
+                stopped = true;
+                return false;   // pending: x returns to the best point below
+            }
+            pending_fold = false;
+            last_rr = rr_true;
+            if (rr_true < best_rr) {
+                best_rr = rr_true;
+                HIPCHK(hipMemcpyAsync(h->xbak, E.X, sizeof(double) * h->n,
+                                      hipMemcpyDeviceToDevice, h->stream));
+            } else if (rr_true > FOLD_GROWTH * FOLD_GROWTH * best_rr) {
+                stopped = true;
+                return false;
+            }
+            return true;
+        };
+        SolveResult in = F.solve(h->r32, h->opt.tol * scale, h->opt.max_mv - (mv32 + mv64 + mvchk),
+                                 h->opt.method, h->opt.fetch, h->opt.fetch_rel * scale,
                                  h->opt.fetch_level, 0, false);
+        F.after_cycle = nullptr;
+        F.after_replace = nullptr;
+        if (pending_fold || last_rr > best_rr) {
+            // x is not at the best true residual of this process: go back there
+            HIPCHK(hipMemcpyAsync(E.X, h->xbak, sizeof(double) * h->n, hipMemcpyDeviceToDevice,
+                                  h->stream));
+            stopped = true;
+        }
         ++refinements;
         mv32 += in.mv;
+        mv64 += hook_mv;
         mvchk += in.mv_check;
         tot.cycles += in.cycles;
         tot.restarts += in.restarts;
@@ -834,10 +946,42 @@ mstab_status solve_mixed(mstab_solver *h, const double *b, double *x, mstab_info
         tot.recycled = tot.recycled || in.recycled;
         tot.level = in.level;
         if (in.fetched >= 0) tot.fetched = in.fetched;
-        if (in.status < 0 && in.status != MSTAB_E_BREAKDOWN) { tot.status = in.status; break; }
-        hipLaunchKernelGGL(k_correct, dim3(grid1(h->n)), dim3(BLOCK), 0, h->stream, h->n, F.X,
-                           sigma, E.X);
-        HIPCHK(hipGetLastError());
+        // progress after the last confirmed replacement (at most one cycle
+        // that did not lower the residual) is not folded: x stays at the
+        // best confirmed point
+        if (stopped) ++abandoned;
+        // a process that ended without lowering the true residual tenfold
+        // is a stall; after two, FP64 iterations finish the system from the
+        // best x (FP32 cannot carry this (s, l) on this matrix)
+        stalls = (best_rr > 1e-2) ? stalls + 1 : 0;
+        const int64_t base = h->hist_mv.back();
+        for (size_t i = 1; i < F.hist_mv.size(); ++i) {
+            h->hist_mv.push_back(base + F.hist_mv[i] + (int64_t)i);
+            h->hist_res.push_back(F.hist_res[i] / scale);
+        }
+        if (in.status < 0 && in.status != MSTAB_E_BREAKDOWN && in.status != MSTAB_E_NONFINITE) {
+            tot.status = in.status;
+            break;
+        }
+    }
+    if (!tot.converged && tot.status != MSTAB_E_NONFINITE && stalls >= 2 &&
+        mv32 + mv64 + mvchk < h->opt.max_mv) {
+        fallback = 1;
+        SolveResult in = E.solve(b, h->opt.tol, h->opt.max_mv - (mv32 + mv64 + mvchk),
+                                 h->opt.method, h->opt.fetch, h->opt.fetch_rel, h->opt.fetch_level,
+                                 h->opt.max_replacements);
+        mv64 += in.mv + in.mv_check;
+        tot.cycles += in.cycles;
+        tot.restarts += in.restarts;
+        tot.replacements += in.replacements;
+        tot.converged = in.converged;
+        tot.status = in.status;
+        tot.relres_true = in.relres_true;
+        tot.relres_rec = in.relres_rec;
+        for (size_t i = 0; i < E.hist_mv.size(); ++i) {
+            h->hist_mv.push_back(mv32 + mvchk + (mv64 - in.mv - in.mv_check) + E.hist_mv[i]);
+            h->hist_res.push_back(E.hist_res[i]);
+        }
     }
     if (tot.status == MSTAB_OK && !tot.converged) tot.status = MSTAB_NOT_CONVERGED;
     HIPCHK(hipMemcpyAsync(x, E.X, sizeof(double) * h->n, hipMemcpyDeviceToDevice, h->stream));
@@ -852,6 +996,8 @@ mstab_status solve_mixed(mstab_solver *h, const double *b, double *x, mstab_info
         info->refinements = refinements;
         info->mv_f64 = mv64;
         info->guess_accepted = accepted;
+        info->restarts += abandoned;
+        info->f64_fallback = fallback;
     }
     return (mstab_status)tot.status;
 }
@@ -909,10 +1055,12 @@ mstab_status mstab_create(const mstab_csr *A, int32_t s, int32_t ell, const msta
     h->pkey = p_key_from_seed(h->opt.p_seed);
     h->prof.init(h->stream);
     Sell<double> A64 = make_sell<double, double>(h->n, h->rp, h->ci, h->va, h->stream);
-    h->e64.alloc(h->n, s, ell, A64, true, h->pkey, h->stream, &h->prof, !h->mixed());
+    // the mixed form keeps a full FP64 engine for the FP64 fallback
+    h->e64.alloc(h->n, s, ell, A64, true, h->pkey, h->stream, &h->prof);
     if (h->mixed()) {
         HIPCHK(hipMalloc(&h->r32, sizeof(float) * (size_t)round_up(h->n, 256)));
         HIPCHK(hipMemsetAsync(h->r32, 0, sizeof(float) * (size_t)round_up(h->n, 256), h->stream));
+        HIPCHK(hipMalloc(&h->xbak, sizeof(double) * (size_t)round_up(h->n, 256)));
         Sell<float> A32 = make_sell<float, double>(h->n, h->rp, h->ci, h->va, h->stream, A64.col);
         h->e32.alloc(h->n, s, ell, A32, false, h->pkey, h->stream, &h->prof);
         h->e32.refresh_v = true;
@@ -923,12 +1071,12 @@ mstab_status mstab_create(const mstab_csr *A, int32_t s, int32_t ell, const msta
     }
     catch (const StatusError &e) {
         mstab_status st = record(h, e);
-        if (h) { h->e64.release(); h->e32.release(); (void)hipFree(h->r32); h->prof.destroy(); delete h; }
+        if (h) { h->e64.release(); h->e32.release(); (void)hipFree(h->r32); (void)hipFree(h->xbak); h->prof.destroy(); delete h; }
         return st;
     }
     catch (const HipError &e) {
         mstab_status st = record_hip(h, e);
-        if (h) { h->e64.release(); h->e32.release(); (void)hipFree(h->r32); h->prof.destroy(); delete h; }
+        if (h) { h->e64.release(); h->e32.release(); (void)hipFree(h->r32); (void)hipFree(h->xbak); h->prof.destroy(); delete h; }
         return (e.e == hipErrorOutOfMemory) ? MSTAB_E_NOMEM : st;
     }
     catch (const std::bad_alloc &) {
@@ -1068,6 +1216,7 @@ mstab_status mstab_destroy(mstab_solver *h)
     h->e64.release();
     h->e32.release();
     (void)hipFree(h->r32);
+    (void)hipFree(h->xbak);
     h->prof.destroy();
     delete h;
     return MSTAB_OK;

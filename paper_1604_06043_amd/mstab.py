@@ -54,14 +54,14 @@ class mstab_info(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("converged", ctypes.c_int32),
                 ("recycled", ctypes.c_int32), ("restarts", ctypes.c_int32),
                 ("replacements", ctypes.c_int32), ("refinements", ctypes.c_int32),
-                ("guess_accepted", ctypes.c_int32), ("pad_", ctypes.c_int32),
+                ("guess_accepted", ctypes.c_int32), ("f64_fallback", ctypes.c_int32),
                 ("mv", ctypes.c_int64), ("mv_check", ctypes.c_int64), ("mv_f64", ctypes.c_int64),
                 ("cycles", ctypes.c_int64), ("level", ctypes.c_int64),
                 ("fetched_level", ctypes.c_int64), ("relres_recursive", ctypes.c_double),
                 ("relres_true", ctypes.c_double), ("seconds", ctypes.c_double)]
 
     def as_dict(self) -> dict:
-        d = {f: getattr(self, f) for f, _ in self._fields_ if f != "pad_"}
+        d = {f: getattr(self, f) for f, _ in self._fields_}
         d["mv_total"] = self.mv + self.mv_check
         return d
 

@@ -1,0 +1,150 @@
+"""Measurements of the solver on the sequence workloads beside the main bench.
+
+    python -m paper_1604_06043_amd.workloads sweep   # 128^3, s in {2,4,8}, l in {1,2,4}
+    python -m paper_1604_06043_amd.workloads c3      # 256^3, lognormal kappa, s=8, l=4, 20 RHS
+    python -m paper_1604_06043_amd.workloads c5      # 4M-row random geometric graph, 100 RHS
+
+Each prints one JSON line per measurement (systems/s and MVs/system of
+M(s)stab(l) and IDR(s)stab(l), FP64 and FP32 + FP64 refinement, and the
+error of the mixed form against the FP64 path).  Inputs come from
+:mod:`inputs`; every arithmetic step runs in the library's kernels.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import sys
+import time
+
+import numpy as np
+
+from . import inputs as I
+from . import mstab as M
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+class Sequence:
+    """A matrix on the device and the forcing of b^(k+1) = x^(k) inv_dt + f^(k)."""
+
+    def __init__(self, A: M.CSR, inv_dt: float, forcing, name: str):
+        self.A, self.inv_dt, self.forcing, self.name = A, inv_dt, forcing, name
+        self.N = A.n
+
+    def f(self, k):
+        return self.forcing(k)
+
+
+def run(seq: Sequence, systems: int, s: int, ell: int, method: int = M.METHOD_MSTAB,
+        precision: int = M.PREC_F64, seed: int = 0, keep_x: bool = False, **opt):
+    """Solve the sequence once; returns (seconds, MVs per system, infos, xs)."""
+    import torch
+    solver = M.Solver(seq.A, s, ell, p_seed=seed, method=method, precision=precision, **opt)
+    x = torch.zeros(seq.N, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(x)
+    infos, xs = [], []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(systems):
+        M.mstab_rhs_step(x, seq.inv_dt, seq.f(k), b)
+        info = solver.solve_next(b, x)
+        if not info["converged"]:
+            raise RuntimeError(f"{seq.name}: system {k} did not converge: {info}")
+        infos.append(info)
+        if keep_x:
+            xs.append(x.clone())
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    solver.close()
+    mv = sum(i["mv_total"] for i in infos) / systems
+    return sec, mv, infos, xs
+
+
+def compare(seq: Sequence, systems: int, s: int, ell: int, seed: int = 0, idr: bool = True,
+            mixed: bool = True, **opt):
+    """M(s)stab FP64 (and IDR(s)stab, FP32+refinement) on one sequence."""
+    import torch
+    out = {"workload": seq.name, "N": seq.N, "nnz": seq.A.nnz, "s": s, "ell": ell,
+           "systems": systems, "tol": 1e-8}
+    # warm-up: first launches and allocator
+    run(seq, 1, s, ell, seed=seed)
+    t, mv, infos, xs = run(seq, systems, s, ell, seed=seed, keep_x=mixed, **opt)
+    out["mstab_f64"] = {"systems_per_s": systems / t, "mvs_per_system": mv}
+    log(f"[{seq.name}] M({s})stab({ell}) FP64: {systems / t:.2f} systems/s, {mv:.1f} MVs/system")
+    if idr:
+        t, mv, _, _ = run(seq, systems, s, ell, method=M.METHOD_IDRSTAB, seed=seed, **opt)
+        out["idrstab_f64"] = {"systems_per_s": systems / t, "mvs_per_system": mv}
+        log(f"[{seq.name}] IDR({s})stab({ell}) FP64: {systems / t:.2f} systems/s, {mv:.1f} MVs/system")
+    if mixed:
+        tm, mvm, im, xm = run(seq, systems, s, ell, precision=M.PREC_F32_REFINE, seed=seed,
+                              keep_x=True, **opt)
+        errs = [float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b))
+                for a, b in zip(xm, xs)]
+        out["mstab_f32_refine"] = {
+            "systems_per_s": systems / tm, "mvs_per_system": mvm,
+            "f64_mvs_per_system": sum(i["mv_f64"] for i in im) / systems,
+            "refinements_per_system": sum(i["refinements"] for i in im) / systems,
+            "max_true_relres": max(i["relres_true"] for i in im),
+            "rel_err_vs_f64_path_max": max(errs), "rel_err_vs_f64_path_last": errs[-1]}
+        log(f"[{seq.name}] M({s})stab({ell}) FP32+refinement: {systems / tm:.2f} systems/s, "
+            f"{mvm:.1f} MVs/system, max err vs FP64 path {max(errs):.2e}")
+    return out
+
+
+def convdiff_sequence(name: str, n: int | None = None, seed: int = 0) -> Sequence:
+    import torch
+    cd = I.config(name, seed=seed, n=n)
+    kappa = None if cd.kappa is None else torch.tensor(cd.kappa, device="cuda")
+    A = M.mstab_assemble_convdiff(cd.dim, cd.n, cd.beta, cd.inv_dt, kappa)
+    f = torch.tensor(cd.f, device="cuda")
+    del kappa
+    return Sequence(A, cd.inv_dt, lambda k: f, f"{name}_n{cd.n}")
+
+
+def rgg_sequence(N: int, seed: int = 0, systems: int = 100) -> Sequence:
+    """b^(k+1) = x^(k) + 0.1 xi^(k) on the graph matrix (inv_dt = 1, f = 0.1 xi)."""
+    import torch
+    t0 = time.perf_counter()
+    g = I.rgg(N, seed)
+    log(f"[rgg] N={N} nnz={g.nnz} generated in {time.perf_counter() - t0:.1f} s")
+    A = M.CSR(torch.tensor(g.row_ptr, device="cuda"), torch.tensor(g.col, device="cuda"),
+              torch.tensor(g.val, device="cuda"))
+    del g
+    F = torch.empty((systems, N), dtype=torch.float64, device="cuda")
+    for k in range(systems):
+        F[k] = torch.tensor(0.1 * I.white_noise(seed, k, N), device="cuda")
+    return Sequence(A, 1.0, lambda k: F[k], f"rgg_N{N}")
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("which", choices=["sweep", "c3", "c5", "c2"])
+    ap.add_argument("--n", type=int, default=None)
+    ap.add_argument("--N", type=int, default=1 << 22)
+    ap.add_argument("--systems", type=int, default=None)
+    a = ap.parse_args()
+    import torch
+    torch.cuda.set_device(0)
+    M.load()
+    if a.which == "sweep":
+        seq = convdiff_sequence("c2", a.n)
+        systems = a.systems or 50
+        for s in (2, 4, 8):
+            for ell in (1, 2, 4):
+                print(json.dumps(compare(seq, systems, s, ell, mixed=False)), flush=True)
+    elif a.which == "c2":
+        seq = convdiff_sequence("c2", a.n)
+        print(json.dumps(compare(seq, a.systems or 50, 4, 2)), flush=True)
+    elif a.which == "c3":
+        seq = convdiff_sequence("c3", a.n)
+        print(json.dumps(compare(seq, a.systems or 20, 8, 4)), flush=True)
+    elif a.which == "c5":
+        systems = a.systems or 100
+        seq = rgg_sequence(a.N, 0, systems)
+        print(json.dumps(compare(seq, systems, 4, 2)), flush=True)
+
+
+if __name__ == "__main__":
+    main()
