@@ -55,7 +55,7 @@ typedef enum {
     MSTAB_PREC_F64 = 0,        /* every vector operation in FP64 */
     MSTAB_PREC_F32_REFINE = 1  /* FP32 M(s)stab(l) whose residual is replaced after every cycle
                                   by the FP64 true residual b - A x, x accumulated in FP64
-                                  (the paper's residual replacement, Section 6, in mixed
+                                  (the paper's residual replacement of Section 5.1, in mixed
                                   precision); FP64 small solves */
 } mstab_precision;
 

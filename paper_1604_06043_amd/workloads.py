@@ -3,6 +3,7 @@
     python -m paper_1604_06043_amd.workloads sweep   # 128^3, s in {2,4,8}, l in {1,2,4}
     python -m paper_1604_06043_amd.workloads c3      # 256^3, lognormal kappa, s=8, l=4, 20 RHS
     python -m paper_1604_06043_amd.workloads c5      # 4M-row random geometric graph, 100 RHS
+    python -m paper_1604_06043_amd.workloads fetch   # fetch policies of M(s)stab on 128^3 and 64^2
 
 Each prints one JSON line per measurement (systems/s and MVs/system of
 M(s)stab(l) and IDR(s)stab(l), FP64 and FP32 + FP64 refinement, and the
@@ -120,7 +121,7 @@ def rgg_sequence(N: int, seed: int = 0, systems: int = 100) -> Sequence:
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
-    ap.add_argument("which", choices=["sweep", "c3", "c5", "c2"])
+    ap.add_argument("which", choices=["sweep", "c3", "c5", "c2", "fetch"])
     ap.add_argument("--n", type=int, default=None)
     ap.add_argument("--N", type=int, default=1 << 22)
     ap.add_argument("--systems", type=int, default=None)
@@ -140,6 +141,20 @@ def main():
     elif a.which == "c3":
         seq = convdiff_sequence("c3", a.n)
         print(json.dumps(compare(seq, a.systems or 20, 8, 4)), flush=True)
+    elif a.which == "fetch":
+        policies = {"threshold": M.FETCH_THRESHOLD, "once": M.FETCH_ONCE, "at_end": M.FETCH_AT_END}
+        for name, n, systems in (("c1", 64, 10), ("c2", 64, 30), ("c2", 128, 50)):
+            seq = convdiff_sequence(name, n)
+            row = {"workload": seq.name, "systems": systems, "s": 4, "ell": 2}
+            t, mv, infos, _ = run(seq, systems, 4, 2, method=M.METHOD_IDRSTAB)
+            row["idrstab"] = {"systems_per_s": systems / t, "mvs_per_system": mv,
+                              "mvs": [i["mv_total"] for i in infos]}
+            for pname, pol in policies.items():
+                t, mv, infos, _ = run(seq, systems, 4, 2, fetch=pol)
+                row[f"mstab_{pname}"] = {"systems_per_s": systems / t, "mvs_per_system": mv,
+                                         "mvs": [i["mv_total"] for i in infos]}
+                log(f"[{seq.name}] fetch {pname}: {mv:.1f} MVs/system (IDR {row['idrstab']['mvs_per_system']:.1f})")
+            print(json.dumps(row), flush=True)
     elif a.which == "c5":
         systems = a.systems or 100
         seq = rgg_sequence(a.N, 0, systems)
