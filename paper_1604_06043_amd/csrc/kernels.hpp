@@ -46,6 +46,7 @@ struct Ctl {
     double ptt[MAXS];                   // P^T of the last true residual
     double gamma[MAXS];
     double eta[MAXS];
+    double eta_all[MAXS][MAXS];         // [q][p]: eta of step q of the current level
     double tau[MAXL];
     double h[MAXS + 1];                 // Gram-Schmidt coefficients
     double prec[MAXS][MAXS];            // [q][a] = p_a . v_q of refreshed fetched data
@@ -582,28 +583,75 @@ __global__ __launch_bounds__(BLOCK) void k_gamma(int64_t ld, T *__restrict__ W, 
 // ---------------------------------------------------------------------------
 template <typename T, int S>
 __global__ __launch_bounds__(BLOCK) void k_eta(int64_t ld, T *__restrict__ W,
-                                               const T *__restrict__ R, int k, int q,
-                                               const Ctl *ctl)
+                                               const T *__restrict__ R, int k, int q, Ctl *ctl)
 {
+    // step q of level k, top level only:
+    //   v_q^(k) := r^(k+1) - sum_{p<q} eta_p v_p^(k+1) - sum_{p>=q} eta_p v_p^(k)
+    // (the levels below k are not read again before the level ends; k_eta_low
+    // updates them all at once).  eta is kept for k_eta_low.
     if (ctl->st.flags) return;
     constexpr int VW = Vec16<T>::W;
     T h[S];
 #pragma unroll
     for (int p = 0; p < S; ++p) h[p] = (T)ctl->eta[p];
+    if (blockIdx.x == 0 && threadIdx.x < S) ctl->eta_all[q][threadIdx.x] = ctl->eta[threadIdx.x];
+    const T *Wi = W + (int64_t)(k + 1) * S * ld;   // level k
+    const T *Wn = Wi + (int64_t)S * ld;            // level k + 1
     for (int64_t e = ((int64_t)blockIdx.x * BLOCK + threadIdx.x) * VW; e < ld;
          e += (int64_t)gridDim.x * BLOCK * VW) {
-        for (int i = -1; i <= k; ++i) {
-            T acc[VW], w[VW];
-            ld16(R + (int64_t)(i + 1) * ld + e, acc);
-            const T *Wi = W + (int64_t)(i + 1) * S * ld;   // level i
-            const T *Wn = Wi + (int64_t)S * ld;            // level i + 1
+        T acc[VW], w[S][VW];
+        ld16(R + (int64_t)(k + 1) * ld + e, acc);
 #pragma unroll
-            for (int p = 0; p < S; ++p) {
-                ld16(((p < q) ? Wn : Wi) + p * ld + e, w);
+        for (int p = 0; p < S; ++p) ld16(((p < q) ? Wn : Wi) + p * ld + e, w[p]);
 #pragma unroll
-                for (int c = 0; c < VW; ++c) acc[c] = fmaT(-h[p], w[c], acc[c]);
+        for (int p = 0; p < S; ++p)
+#pragma unroll
+            for (int c = 0; c < VW; ++c) acc[c] = fmaT(-h[p], w[p][c], acc[c]);
+        st16(W + (int64_t)((k + 1) * S + q) * ld + e, acc);
+    }
+}
+
+// The levels -1..k-1 of all s steps of level k, top down in one pass:
+//   v_q^(i) := r^(i+1) - sum_{p<q} eta_{q,p} v_p^(i+1) - sum_{p>=q} eta_{q,p} v_p^(i)
+// with v^(i+1) already updated (level k by k_eta, lower ones earlier in this
+// pass, carried in registers) and v_p^(i), p >= q, still the old values.
+// Same operations in the same order as s per-step passes over all levels.
+template <typename T, int S>
+__global__ __launch_bounds__(BLOCK) void k_eta_low(int64_t ld, T *__restrict__ W,
+                                                   const T *__restrict__ R, int k, const Ctl *ctl)
+{
+    if (ctl->st.flags) return;
+    constexpr int VW = Vec16<T>::W;
+    for (int64_t e = ((int64_t)blockIdx.x * BLOCK + threadIdx.x) * VW; e < ld;
+         e += (int64_t)gridDim.x * BLOCK * VW) {
+        T up[S][VW];   // updated level i + 1
+#pragma unroll
+        for (int p = 0; p < S; ++p) ld16(W + (int64_t)((k + 1) * S + p) * ld + e, up[p]);
+        for (int i = k - 1; i >= -1; --i) {
+            T old[S][VW], r[VW];
+            ld16(R + (int64_t)(i + 1) * ld + e, r);
+#pragma unroll
+            for (int p = 0; p < S; ++p) ld16(W + (int64_t)((i + 1) * S + p) * ld + e, old[p]);
+#pragma unroll
+            for (int q = 0; q < S; ++q) {
+                T acc[VW];
+#pragma unroll
+                for (int c = 0; c < VW; ++c) acc[c] = r[c];
+#pragma unroll
+                for (int p = 0; p < S; ++p) {
+                    const T hp = (T)ctl->eta_all[q][p];
+#pragma unroll
+                    for (int c = 0; c < VW; ++c)
+                        acc[c] = fmaT(-hp, (p < q) ? up[p][c] : old[p][c], acc[c]);
+                }
+                st16(W + (int64_t)((i + 1) * S + q) * ld + e, acc);
+#pragma unroll
+                for (int c = 0; c < VW; ++c) old[q][c] = acc[c];   // old[q] is not read again
             }
-            st16(W + (int64_t)((i + 1) * S + q) * ld + e, acc);
+#pragma unroll
+            for (int p = 0; p < S; ++p)
+#pragma unroll
+                for (int c = 0; c < VW; ++c) up[p][c] = old[p][c];
         }
     }
 }

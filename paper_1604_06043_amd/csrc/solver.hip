@@ -335,12 +335,32 @@ struct Engine {
     void eta(int k, int q)
     {
         const int grid = grid_for(ld / Vec16<T>::W, BLOCK, VEC_MAX_BLOCKS);
-        int slot = prof ? prof->begin(MSTAB_K_ETA, vbytes((k + 2) * (s + 2))) : -1;
+        // r^(k+1) and s vectors read, v_q^(k) written
+        int slot = prof ? prof->begin(MSTAB_K_ETA, vbytes(s + 2)) : -1;
         switch (s) {
 #define CASE(S)                                                                               \
     case S:                                                                                   \
         hipLaunchKernelGGL((k_eta<T, S>), dim3(grid), dim3(BLOCK), 0, stream, ld, W, R, k, q, \
                            ctl);                                                              \
+        break;
+            CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
+#undef CASE
+        }
+        HIPCHK(hipGetLastError());
+        if (prof) prof->end(slot);
+    }
+
+    // levels -1..k-1 of all s steps of level k (after its last step)
+    void eta_low(int k)
+    {
+        const int grid = grid_for(ld / Vec16<T>::W, BLOCK, VEC_MAX_BLOCKS);
+        // level k (s), then per lower level r^(i+1) and s vectors read, s written
+        int slot = prof ? prof->begin(MSTAB_K_ETA, vbytes(s + (k + 1) * (2 * s + 1))) : -1;
+        switch (s) {
+#define CASE(S)                                                                                \
+    case S:                                                                                    \
+        hipLaunchKernelGGL((k_eta_low<T, S>), dim3(grid), dim3(BLOCK), 0, stream, ld, W, R, k, \
+                           ctl);                                                               \
         break;
             CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
 #undef CASE
@@ -500,6 +520,7 @@ struct Engine {
                 eta(k, q);
                 spmv(Wc(k, q), Wc(k + 1, q), nullptr, ACT_V, k, q);
             }
+            eta_low(k);
         }
         gram();
         poly();
