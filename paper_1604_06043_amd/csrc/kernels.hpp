@@ -319,6 +319,12 @@ struct SpmvArgs {
 constexpr int SPMV_BLOCK = MSTAB_SPMV_BLOCK;
 constexpr int SLICE = 64;
 
+constexpr int MAX_DIAG = 16;
+struct DiaOffsets {
+    int64_t off[MAX_DIAG];   // column - row of each stored diagonal, ascending
+};
+constexpr unsigned long long DIA_EMPTY = 0x8000000000000000ull;   // unused table slot
+
 // Sliced ELLPACK copy of a CSR matrix (device arrays).
 template <typename T>
 struct Sell {
@@ -327,6 +333,14 @@ struct Sell {
     int64_t *slice_ptr = nullptr;    // n_slices + 1
     int32_t *col = nullptr;          // padded
     T *val = nullptr;                // padded
+    // Diagonal storage, used instead when every entry lies on one of nd <= 16
+    // diagonals (stencil matrices): offsets ascending, values diagonal-major
+    // (dval[d n + r], zero where row r has no entry d), and a presence mask
+    // per row (bit d).
+    int nd = 0;
+    DiaOffsets doff{};
+    uint16_t *dmask = nullptr;
+    T *dval = nullptr;
 };
 
 // Scatter CSR rows into the sliced layout (one thread per row).
@@ -349,6 +363,52 @@ __global__ __launch_bounds__(BLOCK) void k_to_sell(int64_t n, const int32_t *__r
     }
 }
 
+// The distinct diagonals (column - row) of a CSR matrix, collected into a
+// table of MAX_DIAG slots.  Every thread probes the slots in the same order
+// and claims an empty one by compare-and-swap, so a value enters once; a
+// value that finds no slot sets *overflow.
+__global__ __launch_bounds__(BLOCK) void k_dia_offsets(int64_t n, const int32_t *__restrict__ rp,
+                                                       const int32_t *__restrict__ ci,
+                                                       unsigned long long *table, int *overflow)
+{
+    for (int64_t r = (int64_t)blockIdx.x * BLOCK + threadIdx.x; r < n;
+         r += (int64_t)gridDim.x * BLOCK) {
+        for (int32_t j = rp[r]; j < rp[r + 1]; ++j) {
+            const unsigned long long off = (unsigned long long)((int64_t)ci[j] - r);
+            bool placed = false;
+            for (int t = 0; t < MAX_DIAG && !placed; ++t) {
+                unsigned long long cur =
+                    __hip_atomic_load(&table[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (cur == DIA_EMPTY) cur = atomicCAS(&table[t], DIA_EMPTY, off);
+                placed = (cur == DIA_EMPTY || cur == off);
+            }
+            if (!placed) __hip_atomic_store(overflow, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+}
+
+// Scatter CSR rows into diagonal storage (dval zeroed beforehand).
+template <typename TD, typename TS>
+__global__ __launch_bounds__(BLOCK) void k_to_dia(int64_t n, const int32_t *__restrict__ rp,
+                                                  const int32_t *__restrict__ ci,
+                                                  const TS *__restrict__ va, int nd,
+                                                  DiaOffsets doff, uint16_t *__restrict__ mask,
+                                                  TD *__restrict__ dval)
+{
+    for (int64_t r = (int64_t)blockIdx.x * BLOCK + threadIdx.x; r < n;
+         r += (int64_t)gridDim.x * BLOCK) {
+        uint32_t m = 0;
+        for (int32_t j = rp[r]; j < rp[r + 1]; ++j) {
+            const int64_t off = (int64_t)ci[j] - r;
+            int d = 0;
+            while (d < nd - 1 && doff.off[d] != off) ++d;
+            dval[(int64_t)d * n + r] = (TD)va[j];
+            m |= 1u << d;
+        }
+        if (mask) mask[r] = (uint16_t)m;
+    }
+}
+
 // S = number of projection columns (a.s must equal S; 0 for a plain product).
 // Each wavefront takes 64 consecutive rows = one slice, so the slice offset and
 // width are wavefront-uniform (scalar registers) and the loop over the width
@@ -356,72 +416,34 @@ __global__ __launch_bounds__(BLOCK) void k_to_sell(int64_t n, const int32_t *__r
 // is allocated in full, so the index and value loads run to the slice width
 // for all 64 lanes; the row lengths only select which products are added.
 // Adding nothing for a padding entry keeps the CSR-order sum exact.
+// y[r] (and the residual form b[r] - sum) plus the row's share of the partials.
 template <typename T, int S>
-__global__ __launch_bounds__(SPMV_BLOCK) void k_spmv(int64_t n, const int32_t *__restrict__ rp,
-                                                     const int64_t *__restrict__ slice_ptr,
-                                                     const int32_t *__restrict__ scol,
-                                                     const T *__restrict__ sval,
-                                                     const T *__restrict__ x,
-                                                     T *__restrict__ y,
-                                                     const T *__restrict__ b, Ctl *ctl,
-                                                     double *part, int stride, SpmvArgs a)
+__device__ __forceinline__ void spmv_row_out(int64_t r, T sum, bool resid, const T *__restrict__ b,
+                                             T *__restrict__ y, uint32_t pkey,
+                                             double (&vals)[S + 2])
 {
 #pragma clang fp contract(off)
-    if (ctl->st.flags) return;
-    const int lane = threadIdx.x & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const bool resid = (a.act == ACT_RESID || a.act == ACT_TRUE);
-
-    double vals[S + 2];
-#pragma unroll
-    for (int v = 0; v < S + 2; ++v) vals[v] = 0.0;
-
-    const int64_t nslices = (n + SLICE - 1) / SLICE;
-    for (int64_t t = (int64_t)blockIdx.x * (SPMV_BLOCK / SLICE) + wave; t < nslices;
-         t += (int64_t)gridDim.x * (SPMV_BLOCK / SLICE)) {
-        const int64_t sp0 = slice_ptr[t];
-        const int32_t w = (int32_t)((slice_ptr[t + 1] - sp0) / SLICE);
-        const int64_t r = t * SLICE + lane;
-        const bool valid = r < n;
-        const int32_t len = valid ? rp[r + 1] - rp[r] : 0;
-        const T *vp = sval + sp0 + lane;
-        const int32_t *cp = scol + sp0 + lane;
-        T sum = (T)0;
-        for (int32_t j0 = 0; j0 < w; j0 += 8) {
-            int32_t c[8];
-            T v[8], xv[8];
-#pragma unroll
-            for (int j = 0; j < 8; ++j)
-                if (j0 + j < w) {
-                    // the matrix is streamed once per product: keep it out of the caches
-                    c[j] = __builtin_nontemporal_load(cp + (int64_t)(j0 + j) * SLICE);
-                    v[j] = __builtin_nontemporal_load(vp + (int64_t)(j0 + j) * SLICE);
-                }
-#pragma unroll
-            for (int j = 0; j < 8; ++j)
-                if (j0 + j < w) xv[j] = x[c[j]];
-#pragma unroll
-            for (int j = 0; j < 8; ++j)
-                if (j0 + j < w) {
-                    const T prod = v[j] * xv[j];
-                    const T nsum = sum + prod;
-                    sum = (j0 + j < len) ? nsum : sum;
-                }
-        }
-        if (valid) {
-            T yv = sum;
-            if (resid) {
-                const T bv = b[r];
-                yv = bv - sum;
-                vals[S + 1] += (double)bv * (double)bv;
-            }
-            y[r] = yv;
-            const double yd = (double)yv;
-            vals[S] += yd * yd;
-#pragma unroll
-            for (int j = 0; j < S; ++j) vals[j] += pval(a.pkey, (uint32_t)r, j) * yd;
-        }
+    T yv = sum;
+    if (resid) {
+        const T bv = b[r];
+        yv = bv - sum;
+        vals[S + 1] += (double)bv * (double)bv;
     }
+    y[r] = yv;
+    const double yd = (double)yv;
+    vals[S] += yd * yd;
+#pragma unroll
+    for (int j = 0; j < S; ++j) vals[j] += pval(pkey, (uint32_t)r, j) * yd;
+}
+
+// The end of every product kernel: workgroup partials of P^T y, ||y||^2 and
+// ||b||^2, the last workgroup's fixed-order totals, and (wavefront 0) the
+// bookkeeping and small solve that the product's role calls for.
+template <int S>
+__device__ void spmv_finalize(double (&vals)[S + 2], Ctl *ctl, double *part, int stride,
+                              const SpmvArgs &a)
+{
+    const int lane = threadIdx.x & 63;
     const int nv = S + 2;
     block_partials<S + 2, SPMV_BLOCK>(vals, nv, part, stride);
     __shared__ double tot[MAXS + 2];
@@ -512,6 +534,112 @@ __global__ __launch_bounds__(SPMV_BLOCK) void k_spmv(int64_t n, const int32_t *_
         ctl->st.flags |= flags;
         if (where) ctl->st.where = where;
     }
+}
+
+template <typename T, int S>
+__global__ __launch_bounds__(SPMV_BLOCK) void k_spmv(int64_t n, const int32_t *__restrict__ rp,
+                                                     const int64_t *__restrict__ slice_ptr,
+                                                     const int32_t *__restrict__ scol,
+                                                     const T *__restrict__ sval,
+                                                     const T *__restrict__ x,
+                                                     T *__restrict__ y,
+                                                     const T *__restrict__ b, Ctl *ctl,
+                                                     double *part, int stride, SpmvArgs a)
+{
+#pragma clang fp contract(off)
+    if (ctl->st.flags) return;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const bool resid = (a.act == ACT_RESID || a.act == ACT_TRUE);
+
+    double vals[S + 2];
+#pragma unroll
+    for (int v = 0; v < S + 2; ++v) vals[v] = 0.0;
+
+    const int64_t nslices = (n + SLICE - 1) / SLICE;
+    for (int64_t t = (int64_t)blockIdx.x * (SPMV_BLOCK / SLICE) + wave; t < nslices;
+         t += (int64_t)gridDim.x * (SPMV_BLOCK / SLICE)) {
+        const int64_t sp0 = slice_ptr[t];
+        const int32_t w = (int32_t)((slice_ptr[t + 1] - sp0) / SLICE);
+        const int64_t r = t * SLICE + lane;
+        const bool valid = r < n;
+        const int32_t len = valid ? rp[r + 1] - rp[r] : 0;
+        const T *vp = sval + sp0 + lane;
+        const int32_t *cp = scol + sp0 + lane;
+        T sum = (T)0;
+        for (int32_t j0 = 0; j0 < w; j0 += 8) {
+            int32_t c[8];
+            T v[8], xv[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+                if (j0 + j < w) {
+                    // the matrix is streamed once per product: keep it out of the caches
+                    c[j] = __builtin_nontemporal_load(cp + (int64_t)(j0 + j) * SLICE);
+                    v[j] = __builtin_nontemporal_load(vp + (int64_t)(j0 + j) * SLICE);
+                }
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+                if (j0 + j < w) xv[j] = x[c[j]];
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+                if (j0 + j < w) {
+                    const T prod = v[j] * xv[j];
+                    const T nsum = sum + prod;
+                    sum = (j0 + j < len) ? nsum : sum;
+                }
+        }
+        if (valid) spmv_row_out<T, S>(r, sum, resid, b, y, a.pkey, vals);
+    }
+    spmv_finalize<S>(vals, ctl, part, stride, a);
+}
+
+// The same product for a matrix in diagonal storage (stencil matrices): one
+// thread per row, the diagonals' values of 64 consecutive rows one 512-byte
+// read each, no column indices.  Present entries are multiplied, rounded and
+// added in ascending column order (the CSR order), so the result equals the
+// sliced product bit for bit.
+template <typename T, int S>
+__global__ __launch_bounds__(SPMV_BLOCK) void k_spmv_dia(int64_t n, int nd, DiaOffsets doff,
+                                                         const uint16_t *__restrict__ mask,
+                                                         const T *__restrict__ dval,
+                                                         const T *__restrict__ x,
+                                                         T *__restrict__ y,
+                                                         const T *__restrict__ b, Ctl *ctl,
+                                                         double *part, int stride, SpmvArgs a)
+{
+#pragma clang fp contract(off)
+    if (ctl->st.flags) return;
+    const bool resid = (a.act == ACT_RESID || a.act == ACT_TRUE);
+    double vals[S + 2];
+#pragma unroll
+    for (int v = 0; v < S + 2; ++v) vals[v] = 0.0;
+    // x is gathered wherever the column lies in [0, n) (the presence bits only
+    // select the sum), so the gathers do not wait for the mask
+    for (int64_t r = (int64_t)blockIdx.x * SPMV_BLOCK + threadIdx.x; r < n;
+         r += (int64_t)gridDim.x * SPMV_BLOCK) {
+        const uint32_t m = mask[r];
+        T sum = (T)0;
+        for (int d0 = 0; d0 < nd; d0 += 8) {
+            T v[8], xv[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+                if (d0 + j < nd) {
+                    const int64_t c = r + doff.off[d0 + j];
+                    // the matrix is streamed once per product: keep it out of the caches
+                    v[j] = __builtin_nontemporal_load(dval + (int64_t)(d0 + j) * n + r);
+                    xv[j] = (c >= 0 && c < n) ? x[c] : (T)0;
+                }
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+                if (d0 + j < nd) {
+                    const T prod = v[j] * xv[j];
+                    const T nsum = sum + prod;
+                    sum = ((m >> (d0 + j)) & 1u) ? nsum : sum;
+                }
+        }
+        spmv_row_out<T, S>(r, sum, resid, b, y, a.pkey, vals);
+    }
+    spmv_finalize<S>(vals, ctl, part, stride, a);
 }
 
 // 16-byte vectors of T (2 doubles or 4 floats) for the streaming kernels.

@@ -153,9 +153,50 @@ struct Profiler {
 // Build the sliced ELLPACK copy of a device CSR matrix (setup only): slice
 // widths from a host copy of the row pointer, then one scatter kernel.
 // With share_col, the column array of `other` is reused.
+// Diagonals of a CSR matrix (GPU table of MAX_DIAG slots): returns their
+// number, ascending in *out, or 0 if there are more than MAX_DIAG or the
+// diagonal storage would pad more than a quarter of the entries.
+inline int detect_diagonals(int64_t n, int64_t nnz, const int32_t *rp, const int32_t *ci,
+                            hipStream_t st, DiaOffsets *out)
+{
+    if (n < 1 || nnz < 1) return 0;
+    unsigned long long *table = nullptr;
+    int *overflow = nullptr;
+    HIPCHK(hipMalloc(&table, sizeof(unsigned long long) * MAX_DIAG));
+    HIPCHK(hipMalloc(&overflow, sizeof(int)));
+    std::vector<unsigned long long> h(MAX_DIAG, DIA_EMPTY);
+    int hov = 0;
+    HIPCHK(hipMemcpyAsync(table, h.data(), sizeof(unsigned long long) * MAX_DIAG,
+                          hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemsetAsync(overflow, 0, sizeof(int), st));
+    hipLaunchKernelGGL(k_dia_offsets, dim3(grid_for(n, BLOCK, VEC_MAX_BLOCKS)), dim3(BLOCK), 0, st,
+                       n, rp, ci, table, overflow);
+    const hipError_t le = hipGetLastError();
+    HIPCHK(hipMemcpyAsync(h.data(), table, sizeof(unsigned long long) * MAX_DIAG,
+                          hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(&hov, overflow, sizeof(int), hipMemcpyDeviceToHost, st));
+    const hipError_t se = hipStreamSynchronize(st);
+    (void)hipFree(table);
+    (void)hipFree(overflow);
+    HIPCHK(le);
+    HIPCHK(se);
+    if (hov) return 0;
+    std::vector<int64_t> offs;
+    for (unsigned long long v : h)
+        if (v != DIA_EMPTY) offs.push_back((int64_t)v);
+    std::sort(offs.begin(), offs.end());
+    const int nd = (int)offs.size();
+    if (nd == 0 || (double)nd * (double)n > 1.25 * (double)nnz) return 0;
+    for (int d = 0; d < MAX_DIAG; ++d) out->off[d] = d < nd ? offs[d] : 0;
+    return nd;
+}
+
+// The device copy of A used by the product kernels: diagonal storage when A
+// is a stencil matrix (at most 16 diagonals), else sliced ELLPACK.  like: the
+// FP64 copy whose column array (or diagonal mask) this copy shares.
 template <typename T, typename TS>
 Sell<T> make_sell(int64_t n, const int32_t *rp, const int32_t *ci, const TS *va, hipStream_t st,
-                  const int32_t *share_col = nullptr)
+                  const Sell<double> *like = nullptr)
 {
     Sell<T> m;
     m.n = n;
@@ -164,6 +205,24 @@ Sell<T> make_sell(int64_t n, const int32_t *rp, const int32_t *ci, const TS *va,
     HIPCHK(hipMemcpyAsync(h.data(), rp, sizeof(int32_t) * (n + 1), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     m.nnz = h[n];
+    const int grid = grid_for(n, BLOCK, VEC_MAX_BLOCKS);
+    m.nd = like ? like->nd : detect_diagonals(n, m.nnz, rp, ci, st, &m.doff);
+    if (m.nd > 0) {
+        if (like) m.doff = like->doff;
+        const size_t cnt = (size_t)m.nd * (size_t)n;
+        HIPCHK(hipMalloc(&m.dval, sizeof(T) * cnt));
+        HIPCHK(hipMemsetAsync(m.dval, 0, sizeof(T) * cnt, st));
+        if (like) {
+            m.dmask = like->dmask;
+        } else {
+            HIPCHK(hipMalloc(&m.dmask, sizeof(uint16_t) * (size_t)n));
+        }
+        hipLaunchKernelGGL((k_to_dia<T, TS>), dim3(grid), dim3(BLOCK), 0, st, n, rp, ci, va, m.nd,
+                           m.doff, like ? nullptr : m.dmask, m.dval);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipStreamSynchronize(st));
+        return m;
+    }
     const int64_t ns = (n + SLICE - 1) / SLICE;
     std::vector<int64_t> sp((size_t)ns + 1);
     sp[0] = 0;
@@ -180,13 +239,13 @@ Sell<T> make_sell(int64_t n, const int32_t *rp, const int32_t *ci, const TS *va,
                           hipMemcpyHostToDevice, st));
     HIPCHK(hipMalloc(&m.val, sizeof(T) * cnt));
     HIPCHK(hipMemsetAsync(m.val, 0, sizeof(T) * cnt, st));        // padding: value 0
+    const int32_t *share_col = like ? like->col : nullptr;
     if (share_col) {
         m.col = const_cast<int32_t *>(share_col);
     } else {
         HIPCHK(hipMalloc(&m.col, sizeof(int32_t) * cnt));
         HIPCHK(hipMemsetAsync(m.col, 0, sizeof(int32_t) * cnt, st)); // padding: column 0
     }
-    const int grid = grid_for(n, BLOCK, VEC_MAX_BLOCKS);
     hipLaunchKernelGGL((k_to_sell<T, TS>), dim3(grid), dim3(BLOCK), 0, st, n, rp, ci, va,
                        m.slice_ptr, share_col ? nullptr : m.col, m.val);
     HIPCHK(hipGetLastError());
@@ -199,14 +258,41 @@ void free_sell(Sell<T> &m, bool own_col)
 {
     (void)hipFree(m.slice_ptr);
     (void)hipFree(m.val);
-    if (own_col) (void)hipFree(m.col);
+    (void)hipFree(m.dval);
+    if (own_col) {
+        (void)hipFree(m.col);
+        (void)hipFree(m.dmask);
+    }
     m = Sell<T>();
+}
+
+// bytes a product must move: the matrix copy, x once, y (and b)
+template <typename T>
+double spmv_bytes(const Sell<T> &A, bool with_b)
+{
+    const double n = (double)A.n;
+    const double vecs = (with_b ? 3.0 : 2.0) * n * sizeof(T);
+    if (A.nd > 0) return (double)A.nd * n * sizeof(T) + 2.0 * n + vecs;
+    return (n + 1) * 4 + (double)A.padded * (4 + sizeof(T)) + (double)((A.n + SLICE - 1) / SLICE + 1) * 8 +
+           vecs;
 }
 
 template <typename T>
 void launch_spmv(int grid, hipStream_t stream, const Sell<T> &A, const T *x, T *y, const T *b,
                  Ctl *ctl, double *part, SpmvArgs a)
 {
+    if (A.nd > 0) {
+        switch (a.s) {
+#define CASE(S)                                                                                   \
+    case S:                                                                                       \
+        hipLaunchKernelGGL((k_spmv_dia<T, S>), dim3(grid), dim3(SPMV_BLOCK), 0, stream, A.n, A.nd, \
+                           A.doff, A.dmask, A.dval, x, y, b, ctl, part, PART_STRIDE, a);          \
+        break;
+            CASE(0) CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
+#undef CASE
+        }
+        return;
+    }
     switch (a.s) {
 #define CASE(S)                                                                                \
     case S:                                                                                    \
@@ -305,10 +391,7 @@ struct Engine {
     {
         SpmvArgs a{act, k, q, s, ell, pkey};
         const int grid = grid_for(n, SPMV_BLOCK, SPMV_MAX_BLOCKS);
-        // bytes the kernel must move: row pointer, the padded slices (index +
-        // value), slice offsets, x once, y (and b)
-        const double bytes = (double)(n + 1) * 4 + (double)A.padded * (4 + sizeof(T)) +
-                             (double)((n + SLICE - 1) / SLICE + 1) * 8 + vbytes(b ? 3 : 2);
+        const double bytes = spmv_bytes(A, b != nullptr);
         int slot = prof ? prof->begin(MSTAB_K_SPMV, bytes) : -1;
         launch_spmv<T>(grid, stream, A, x, y, b, ctl, part, a);
         HIPCHK(hipGetLastError());
@@ -1082,7 +1165,7 @@ mstab_status mstab_create(const mstab_csr *A, int32_t s, int32_t ell, const msta
         HIPCHK(hipMalloc(&h->r32, sizeof(float) * (size_t)round_up(h->n, 256)));
         HIPCHK(hipMemsetAsync(h->r32, 0, sizeof(float) * (size_t)round_up(h->n, 256), h->stream));
         HIPCHK(hipMalloc(&h->xbak, sizeof(double) * (size_t)round_up(h->n, 256)));
-        Sell<float> A32 = make_sell<float, double>(h->n, h->rp, h->ci, h->va, h->stream, A64.col);
+        Sell<float> A32 = make_sell<float, double>(h->n, h->rp, h->ci, h->va, h->stream, &A64);
         h->e32.alloc(h->n, s, ell, A32, false, h->pkey, h->stream, &h->prof);
         h->e32.refresh_v = true;
     }

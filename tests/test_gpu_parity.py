@@ -438,6 +438,27 @@ def test_kernel_profiling_counts(torch_dev, ms, orc):
     n_eta, _, _ = solver.kernel_stats(ms.K_ETA)
     # per level: s top-level steps and one pass over the lower levels
     assert n_eta == info["cycles"] * ell * (s + 1)
+    # the 5-point matrix runs in diagonal storage: 5 diagonals of values, a
+    # 2-byte mask, x and y (b in the residual products) per row
+    N = cd.N
+    n_res = 1 + info["mv_check"]   # initial residual and true-residual checks read b
+    expect = n_spmv * (5 * 8 * N + 2 * N + 2 * 8 * N) + n_res * 8 * N
+    assert abs(by - expect) <= 1e-9 * expect
+
+
+def test_graph_matrix_uses_sliced_storage(torch_dev, ms, orc):
+    """More than 16 diagonals: the sliced ELLPACK copy (4-byte index + value
+    per padded entry, the row pointer, slice offsets)."""
+    torch = torch_dev
+    g, Ao, Ag, forcing = rgg_problem(torch, ms, orc, 5000, 2)
+    solver = ms.Solver(Ag, 2, 1, p_seed=2)
+    solver.set_profiling(True)
+    x = torch.zeros(g.N, dtype=torch.float64, device="cuda")
+    solver.solve_next(dev(torch, forcing[0]), x)
+    n_spmv, _, by = solver.kernel_stats(ms.K_SPMV)
+    per = by / n_spmv
+    # at least every entry's index and value, the row pointer, x and y
+    assert per >= 12 * g.nnz + 4 * (g.N + 1) + 16 * g.N
 
 
 # ---------------------------------------------------------------------------
