@@ -27,7 +27,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = ("systems/sec + MVs/system at rel-res 1e-8; SpMV HBM GB/s vs peak, "
           "M(s)stab vs IDRstab")
-PMC_RECORD = os.path.join(ROOT, "profiles", "spmv_sell64_convdiff128_pmc.json")
+PMC_RECORD = os.path.join(ROOT, "profiles", "spmv_dia_convdiff128_pmc.json")
 HBM_PEAK_GBS = 8000.0
 CLASS_NAMES = ["spmv", "gamma", "eta", "gram", "poly"]
 
@@ -171,7 +171,7 @@ def main():
         dom = max(stats, key=lambda c: stats[c][1])
         n, msec, by = stats[dom]
         achieved = by / (msec * 1e-3) / 1e9
-        traffic = measured_traffic(f"k_spmv<double, {s}>") if dom == "spmv" else None
+        traffic = measured_traffic(f"k_spmv_dia<double, {s}>") if dom == "spmv" else None
         roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(achieved / HBM_PEAK_GBS, 4),
