@@ -37,7 +37,8 @@ constexpr int CH = 32;
 constexpr int TAPS = 9;
 constexpr int CIN[NL] = {2, 32, 32, 32, 32, 32};
 constexpr int COUT[NL] = {32, 32, 32, 32, 32, 1};
-constexpr int DW_BLOCKS = 256;   // split-K workgroups of a weight gradient
+constexpr int DW_BLOCKS = 1024;  // split-K workgroups of a weight gradient
+constexpr int DW_GROUPS = 8;     // pixel groups of a first/last-layer gradient workgroup
 constexpr int MAX_DIL = 32;      // largest dilation of a layer
 
 constexpr int param_count_layer(int l) { return COUT[l] * CIN[l] * TAPS + COUT[l]; }
@@ -375,29 +376,50 @@ __global__ __launch_bounds__(BLOCK) void k_last_bwd_data(int B, int H, int W, in
     }
 }
 
-// threads 0..287: (ci, tap) = (t / 9, t % 9); thread 288: the bias.  Partials
-// part[block][289].
-__global__ __launch_bounds__(320) void k_last_bwd_weight(int B, int H, int W, int d,
+// Workgroup b takes a contiguous share of the pixels; thread (g, ci) sums
+// A5[p + off(tap)][ci] dout[p] over every DW_GROUPS-th pixel of it for all
+// taps, then the groups are added in order.  Partials part[block][289]:
+// index ci * 9 + tap, and 288 the bias.
+__global__ __launch_bounds__(256) void k_last_bwd_weight(int B, int H, int W, int d,
                                                          const float *__restrict__ dout,
                                                          const bf16 *__restrict__ a5,
                                                          float *__restrict__ part)
 {
-    const int t = threadIdx.x;
-    const int ci = t / TAPS, tap = t % TAPS;
-    const int dy = (tap / 3 - 1) * d, dx = (tap % 3 - 1) * d;
+    __shared__ float s_acc[DW_GROUPS][CH][TAPS];
+    __shared__ float s_b[DW_GROUPS];
+    const int t = threadIdx.x, ci = t % CH, g = t / CH;
     const int64_t npix = (int64_t)B * H * W;
-    float acc = 0.f;
-    for (int64_t g = blockIdx.x; g < npix; g += gridDim.x) {
-        const float d = dout[g];
-        if (t < CH * TAPS) {
-            const int64_t img = g / ((int64_t)H * W);
-            const int y = (int)((g / W) % H) + dy, x = (int)(g % W) + dx;
-            if (inside(y, x, H, W)) acc = fmaf((float)a5[((img * H + y) * W + x) * CH + ci], d, acc);
-        } else if (t == CH * TAPS) {
-            acc += d;
+    const int64_t chunk = (npix + gridDim.x - 1) / gridDim.x;
+    const int64_t p0 = (int64_t)blockIdx.x * chunk, p1 = min(npix, p0 + chunk);
+    float acc[TAPS];
+#pragma unroll
+    for (int k = 0; k < TAPS; ++k) acc[k] = 0.f;
+    float bacc = 0.f;
+    for (int64_t p = p0 + g; p < p1; p += DW_GROUPS) {
+        const float dv = dout[p];
+        const int64_t img = p / ((int64_t)H * W);
+        const int y = (int)((p / W) % H), x = (int)(p % W);
+#pragma unroll
+        for (int tap = 0; tap < TAPS; ++tap) {
+            const int yy = y + (tap / 3 - 1) * d, xx = x + (tap % 3 - 1) * d;
+            if (inside(yy, xx, H, W))
+                acc[tap] = fmaf((float)a5[((img * H + yy) * W + xx) * CH + ci], dv, acc[tap]);
         }
+        bacc += dv;
     }
-    if (t <= CH * TAPS) part[(size_t)blockIdx.x * (CH * TAPS + 1) + t] = acc;
+#pragma unroll
+    for (int tap = 0; tap < TAPS; ++tap) s_acc[g][ci][tap] = acc[tap];
+    if (ci == 0) s_b[g] = bacc;
+    __syncthreads();
+    for (int v = t; v <= CH * TAPS; v += 256) {
+        float sum = 0.f;
+        if (v < CH * TAPS) {
+            for (int k = 0; k < DW_GROUPS; ++k) sum += s_acc[k][v / TAPS][v % TAPS];
+        } else {
+            for (int k = 0; k < DW_GROUPS; ++k) sum += s_b[k];
+        }
+        part[(size_t)blockIdx.x * (CH * TAPS + 1) + v] = sum;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -487,79 +509,126 @@ __global__ __launch_bounds__(BLOCK) void k_mid_bwd_weight(int B, int H, int W, i
     }
 }
 
-// Layer 0 weight gradient: threads 0..575 = (tap, ci, co), 576..607 bias.
-// dW0[co][ci][tap] = sum_p in[p + off(tap)][ci] dz0[p][co]; partials part[block][608].
-__global__ __launch_bounds__(640) void k_first_bwd_weight(int B, int H, int W, int d,
+// Layer 0 weight gradient, like the last layer's: thread (g, co) sums
+// in[p + off(tap)][ci] dz0[p][co] for both input channels and all taps over
+// every DW_GROUPS-th pixel of the workgroup's share.  Partials
+// part[block][608]: index (tap * 2 + ci) * 32 + co, then 576 + co the bias.
+__global__ __launch_bounds__(256) void k_first_bwd_weight(int B, int H, int W, int d,
                                                           const bf16 *__restrict__ dz0,
                                                           const bf16 *__restrict__ in,
                                                           float *__restrict__ part)
 {
-    const int t = threadIdx.x;
-    const int nw = TAPS * 2 * CH;
-    const int tap = t / (2 * CH), ci = (t / CH) % 2, co = t % CH;
-    const int dy = (tap / 3 - 1) * d, dx = (tap % 3 - 1) * d;
+    constexpr int NW = TAPS * 2 * CH;
+    __shared__ float s_acc[DW_GROUPS][2 * TAPS + 1][CH];
+    const int t = threadIdx.x, co = t % CH, g = t / CH;
     const int64_t npix = (int64_t)B * H * W;
-    float acc = 0.f;
-    for (int64_t g = blockIdx.x; g < npix; g += gridDim.x) {
-        const int64_t img = g / ((int64_t)H * W);
-        if (t < nw) {
-            const int y = (int)((g / W) % H) + dy, x = (int)(g % W) + dx;
-            if (inside(y, x, H, W))
-                acc = fmaf((float)in[((img * H + y) * W + x) * 2 + ci], (float)dz0[g * CH + co], acc);
-        } else if (t < nw + CH) {
-            acc += (float)dz0[g * CH + (t - nw)];
+    const int64_t chunk = (npix + gridDim.x - 1) / gridDim.x;
+    const int64_t p0 = (int64_t)blockIdx.x * chunk, p1 = min(npix, p0 + chunk);
+    float acc[2 * TAPS];
+#pragma unroll
+    for (int k = 0; k < 2 * TAPS; ++k) acc[k] = 0.f;
+    float bacc = 0.f;
+    for (int64_t p = p0 + g; p < p1; p += DW_GROUPS) {
+        const float dv = (float)dz0[p * CH + co];
+        const int64_t img = p / ((int64_t)H * W);
+        const int y = (int)((p / W) % H), x = (int)(p % W);
+#pragma unroll
+        for (int tap = 0; tap < TAPS; ++tap) {
+            const int yy = y + (tap / 3 - 1) * d, xx = x + (tap % 3 - 1) * d;
+            if (inside(yy, xx, H, W)) {
+                const int64_t q = (img * H + yy) * W + xx;
+                acc[tap * 2] = fmaf((float)in[2 * q], dv, acc[tap * 2]);
+                acc[tap * 2 + 1] = fmaf((float)in[2 * q + 1], dv, acc[tap * 2 + 1]);
+            }
         }
+        bacc += dv;
     }
-    if (t < nw + CH) part[(size_t)blockIdx.x * (nw + CH) + t] = acc;
+#pragma unroll
+    for (int k = 0; k < 2 * TAPS; ++k) s_acc[g][k][co] = acc[k];
+    s_acc[g][2 * TAPS][co] = bacc;
+    __syncthreads();
+    for (int v = t; v < NW + CH; v += 256) {
+        const int k = v < NW ? v / CH : 2 * TAPS, c = v % CH;
+        float sum = 0.f;
+        for (int gg = 0; gg < DW_GROUPS; ++gg) sum += s_acc[gg][k][c];
+        part[(size_t)blockIdx.x * (NW + CH) + v] = sum;
+    }
 }
 
-// Sum per-workgroup partials in block order into the FP32 gradient array.
+// Sum per-workgroup partials into the FP32 gradient array in a fixed order:
+// runs of RED_RUN blocks in sequence, then the run sums pairwise (a rounding
+// chain of RED_RUN + log2(DW_BLOCKS / RED_RUN) additions).
 // kind 0: middle layer (part[b][tap][co][ci], part_b[b][co]); 1: layer 0; 2: layer 5.
+constexpr int RED_RUN = 32;
+constexpr int RED_RUNS = DW_BLOCKS / RED_RUN;   // 32
+constexpr int RED_VALS = BLOCK / RED_RUNS;      // values per reduce workgroup (8)
+static_assert(RED_RUNS * RED_VALS == BLOCK && DW_BLOCKS % RED_RUN == 0, "reduce shape");
+
+// Workgroup: RED_VALS values x RED_RUNS runs; thread (k, v) adds run k of
+// value v, then one thread per value adds the runs pairwise.
 __global__ __launch_bounds__(BLOCK) void k_grad_reduce(int kind, int layer, int nblocks,
                                                        const float *__restrict__ part,
                                                        const float *__restrict__ part_b,
                                                        float *__restrict__ grad)
 {
-    const int t = blockIdx.x * BLOCK + threadIdx.x;
+    __shared__ float s_run[RED_RUNS][RED_VALS];
+    const int vi = threadIdx.x % RED_VALS, k = threadIdx.x / RED_VALS;
+    const int t = blockIdx.x * RED_VALS + vi;   // value index of this layer
+    int nvals, stride;
+    const float *src;
+    int idx = t;
+    if (kind == 0) {
+        nvals = TAPS * CH * CH + CH;
+        if (t < TAPS * CH * CH) { src = part; stride = TAPS * CH * CH; }
+        else { src = part_b; stride = CH; idx = t - TAPS * CH * CH; }
+    } else if (kind == 1) {
+        nvals = TAPS * 2 * CH + CH; src = part; stride = nvals;
+    } else {
+        nvals = CH * TAPS + 1; src = part; stride = nvals;
+    }
+    float sacc = 0.f;
+    if (t < nvals)
+        for (int b = k * RED_RUN; b < min(nblocks, (k + 1) * RED_RUN); ++b)
+            sacc += src[(size_t)b * stride + idx];
+    s_run[k][vi] = sacc;
+    __syncthreads();
+    if (k != 0 || t >= nvals) return;
+    float run[RED_RUNS];
+#pragma unroll
+    for (int j = 0; j < RED_RUNS; ++j) run[j] = s_run[j][vi];
+#pragma unroll
+    for (int h = RED_RUNS / 2; h > 0; h >>= 1)
+#pragma unroll
+        for (int j = 0; j < h; ++j) run[j] += run[j + h];
+    const float sv = run[0];
     float *g = grad + param_offset(layer);
     if (kind == 0) {
-        const int nw = TAPS * CH * CH;
-        if (t < nw) {
+        if (t < TAPS * CH * CH) {
             const int tap = t / (CH * CH), co = (t / CH) % CH, ci = t % CH;
-            float s = 0.f;
-            for (int b = 0; b < nblocks; ++b) s += part[(size_t)b * nw + t];
-            g[(co * CH + ci) * TAPS + tap] = s;
-        } else if (t < nw + CH) {
-            float s = 0.f;
-            for (int b = 0; b < nblocks; ++b) s += part_b[(size_t)b * CH + (t - nw)];
-            g[CH * CH * TAPS + (t - nw)] = s;
+            g[(co * CH + ci) * TAPS + tap] = sv;
+        } else {
+            g[CH * CH * TAPS + (t - TAPS * CH * CH)] = sv;
         }
     } else if (kind == 1) {
         const int nw = TAPS * 2 * CH;
-        if (t < nw + CH) {
-            float s = 0.f;
-            for (int b = 0; b < nblocks; ++b) s += part[(size_t)b * (nw + CH) + t];
-            if (t < nw) {
-                const int tap = t / (2 * CH), ci = (t / CH) % 2, co = t % CH;
-                g[(co * 2 + ci) * TAPS + tap] = s;
-            } else {
-                g[CH * 2 * TAPS + (t - nw)] = s;
-            }
+        if (t < nw) {
+            const int tap = t / (2 * CH), ci = (t / CH) % 2, co = t % CH;
+            g[(co * 2 + ci) * TAPS + tap] = sv;
+        } else {
+            g[CH * 2 * TAPS + (t - nw)] = sv;
         }
     } else {
         const int nw = CH * TAPS;
-        if (t < nw + 1) {
-            float s = 0.f;
-            for (int b = 0; b < nblocks; ++b) s += part[(size_t)b * (nw + 1) + t];
-            if (t < nw) {
-                const int ci = t / TAPS, tap = t % TAPS;
-                g[ci * TAPS + tap] = s;
-            } else {
-                g[nw] = s;
-            }
+        if (t < nw) {
+            const int ci = t / TAPS, tap = t % TAPS;
+            g[ci * TAPS + tap] = sv;
+        } else {
+            g[nw] = sv;
         }
     }
 }
+
+int reduce_grid(int nvals) { return (nvals + RED_VALS - 1) / RED_VALS; }
 
 // Adam (Kingma and Ba) on the FP32 parameters.
 __global__ __launch_bounds__(BLOCK) void k_adam(int n, float *__restrict__ p,
@@ -809,9 +878,10 @@ mstab_status mstab_cnn_gradient(mstab_cnn *h, const void *input_bf16, const floa
                        h->dout, h->rpart);
     hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(64), 0, h->stream, loss_grid, h->rpart, h->ctl);
     // layer 5
-    hipLaunchKernelGGL(k_last_bwd_weight, dim3(DW_BLOCKS), dim3(320), 0, h->stream, B, H, W,
+    hipLaunchKernelGGL(k_last_bwd_weight, dim3(DW_BLOCKS), dim3(256), 0, h->stream, B, H, W,
                        h->dil[5], h->dout, h->act[5], h->part);
-    hipLaunchKernelGGL(k_grad_reduce, dim3(2), dim3(BLOCK), 0, h->stream, 2, 5, DW_BLOCKS, h->part,
+    hipLaunchKernelGGL(k_grad_reduce, dim3(reduce_grid(CH * TAPS + 1)), dim3(BLOCK), 0, h->stream, 2,
+                       5, DW_BLOCKS, h->part,
                        (const float *)nullptr, h->g);
     hipLaunchKernelGGL(k_last_bwd_data, dim3(grid_of(npix, 8192)), dim3(BLOCK), 0, h->stream, B, H, W,
                        h->dil[5], h->dout, h->w5, h->act[5], h->dz[4]);
@@ -821,16 +891,17 @@ mstab_status mstab_cnn_gradient(mstab_cnn *h, const void *input_bf16, const floa
     for (int l = 4; l >= 1; --l) {
         hipLaunchKernelGGL(k_mid_bwd_weight, dim3(DW_BLOCKS), dim3(BLOCK), 0, h->stream, B, H, W,
                            h->dil[l], h->dz[l], h->act[l], h->part, h->part_b);
-        hipLaunchKernelGGL(k_grad_reduce, dim3((TAPS * CH * CH + CH + BLOCK - 1) / BLOCK), dim3(BLOCK),
+        hipLaunchKernelGGL(k_grad_reduce, dim3(reduce_grid(TAPS * CH * CH + CH)), dim3(BLOCK),
                            0, h->stream, 0, l, DW_BLOCKS, h->part, h->part_b, h->g);
         hipLaunchKernelGGL(k_conv_mid<1>, dim3(mid_grid), dim3(BLOCK), 0, h->stream, B, H, W,
                            h->dil[l], h->dz[l], h->wb + (size_t)(l - 1) * TAPS * CH * CH, (const float *)nullptr,
                            h->act[l], h->dz[l - 1]);
     }
     // layer 0 (no input gradient needed)
-    hipLaunchKernelGGL(k_first_bwd_weight, dim3(DW_BLOCKS), dim3(640), 0, h->stream, B, H, W,
+    hipLaunchKernelGGL(k_first_bwd_weight, dim3(DW_BLOCKS), dim3(256), 0, h->stream, B, H, W,
                        h->dil[0], h->dz[0], (const bf16 *)input_bf16, h->part);
-    hipLaunchKernelGGL(k_grad_reduce, dim3(3), dim3(BLOCK), 0, h->stream, 1, 0, DW_BLOCKS, h->part,
+    hipLaunchKernelGGL(k_grad_reduce, dim3(reduce_grid(TAPS * 2 * CH + CH)), dim3(BLOCK), 0, h->stream,
+                       1, 0, DW_BLOCKS, h->part,
                        (const float *)nullptr, h->g);
     CNNCHK(hipGetLastError());
     if (loss) {
