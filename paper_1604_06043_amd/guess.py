@@ -258,6 +258,43 @@ def run(n=512, train_seeds=10, steps=200, eval_steps=200, epochs=20, batch=8, lr
     }
 
 
+def train_bench(n: int = 512, batch: int = 8, steps: int = 10, warmup: int = 3, calib: bool = False):
+    """Time the network alone: forward + backward + Adam on a synthetic batch
+    of n x n samples, and the forward pass of a batch."""
+    import torch
+    torch.cuda.set_device(0)
+    if calib:   # a plain 256 MiB device copy, the reference for the byte counters
+        src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda")
+        torch.empty_like(src).copy_(src)
+        del src
+    net = M.Cnn(n, n, batch, 1.0, DILATION)
+    net.set_params(init_params(0))
+    rng = np.random.default_rng(0)
+    inp = torch.tensor(rng.standard_normal((batch, 2 * n * n)), device="cuda").to(torch.bfloat16)
+    tgt = torch.tensor(rng.standard_normal((batch, n * n)), device="cuda", dtype=torch.float32)
+    out = torch.empty((batch, n * n), device="cuda", dtype=torch.float32)
+    for _ in range(warmup):
+        net.gradient(inp, tgt, batch)
+        net.adam_step(1e-3)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        net.gradient(inp, tgt, batch)
+        net.adam_step(1e-3)
+    torch.cuda.synchronize()
+    t_train = (time.perf_counter() - t0) / steps
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        net.forward(inp, batch, out)
+    torch.cuda.synchronize()
+    t_fwd = (time.perf_counter() - t0) / steps
+    net.close()
+    flop_fwd = 2.0 * n * n * batch * sum(9 * a * b for a, b in zip(CHANNELS[:-1], CHANNELS[1:]))
+    return {"workload": f"guess_network_{n}x{n}_batch{batch}", "ms_train_step": 1e3 * t_train,
+            "ms_forward": 1e3 * t_fwd, "gflop_forward": flop_fwd / 1e9,
+            "tflops_forward": flop_fwd / t_fwd / 1e12, "tflops_train": 3 * flop_fwd / t_train / 1e12}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--n", type=int, default=512)
@@ -271,7 +308,13 @@ def main():
     ap.add_argument("--ell", type=int, default=2)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--rounds", type=int, default=1)
+    ap.add_argument("--train-bench", action="store_true",
+                    help="time the network alone on synthetic batches")
+    ap.add_argument("--calib", action="store_true")
     a = ap.parse_args()
+    if a.train_bench:
+        print(json.dumps(train_bench(a.n, a.batch, calib=a.calib)), flush=True)
+        return
     r = run(a.n, a.train_seeds, a.steps, a.eval_steps, a.epochs, a.batch, a.lr, a.s, a.ell, a.seed,
             rounds=a.rounds, log=lambda m: print(m, flush=True))
     print(json.dumps(r), flush=True)

@@ -26,9 +26,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 KERNEL_SOURCES = [os.path.join(HERE, "csrc", f) for f in ("kernels.hpp", "solver.hip")]
 
 
-def sources_digest() -> str:
+def sources_digest(files=None) -> str:
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in (files or KERNEL_SOURCES):
         with open(f, "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
@@ -70,7 +70,7 @@ def calibration(per: dict, copy_bytes: int) -> float:
     return copy_bytes / best
 
 
-def summarize(kt_dir, fetch_dir, write_dir, kernel, command, copy_bytes=256 << 20):
+def summarize(kt_dir, fetch_dir, write_dir, kernel, command, copy_bytes=256 << 20, sources=None):
     stats = kernel_stats(kt_dir)
     fetch, write = counters(fetch_dir), counters(write_dir)
     fs, ws = calibration(fetch, copy_bytes), calibration(write, copy_bytes)
@@ -83,7 +83,7 @@ def summarize(kt_dir, fetch_dir, write_dir, kernel, command, copy_bytes=256 << 2
                          "dispatches": len(fetch.get(name, []))}
     return {"command": command, "kernel": kernel, "stats": stats, "selected": sel,
             "fetch_scale": fs, "write_scale": ws, "traffic": traffic,
-            "sources_sha256": sources_digest()}
+            "sources_sha256": sources_digest(sources)}
 
 
 def write_md(summary: dict, path: str, title: str):
@@ -116,8 +116,10 @@ def main():
     ap.add_argument("--command", required=True)
     ap.add_argument("--title", default="Kernel profile")
     ap.add_argument("--json")
+    ap.add_argument("--sources", nargs="*", help="kernel source files (under csrc/) of the digest")
     a = ap.parse_args()
-    s = summarize(a.kt_dir, a.fetch_dir, a.write_dir, a.kernel, a.command)
+    srcs = [os.path.join(HERE, "csrc", f) for f in a.sources] if a.sources else None
+    s = summarize(a.kt_dir, a.fetch_dir, a.write_dir, a.kernel, a.command, sources=srcs)
     write_md(s, a.out_md, a.title)
     if a.json:
         rec = {"kernel": a.kernel, "sources_sha256": s["sources_sha256"], "command": a.command,
