@@ -191,11 +191,13 @@ const char *mstab_status_str(mstab_status s);
 const char *mstab_last_error(const mstab_solver *h);
 
 /*
- * Kernel timing of the iteration (for roofline measurement): while enabled,
- * every launch of the kernel classes below is bracketed by HIP events on the
- * handle's stream; mstab_kernel_stats returns launch count, summed duration in
- * ms and summed algorithmic bytes (reads + writes the kernel must make) for a
- * class since the last enable.
+ * Kernel timing of the iteration (for roofline measurement): with enable = N
+ * > 0, the first of every N launches of each kernel class below is bracketed
+ * by HIP events on the handle's stream (N = 1: every launch; a larger N keeps
+ * the events' own cost out of the timed work); enable = 0 stops.
+ * mstab_kernel_stats returns, for a class since the last enable, the number of
+ * timed launches, their summed duration in ms and their summed algorithmic
+ * bytes (reads + writes the kernel must make).
  */
 typedef enum {
     MSTAB_K_SPMV = 0,          /* y = A x with the P-projection epilogue */

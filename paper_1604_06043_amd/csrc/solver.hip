@@ -93,6 +93,8 @@ constexpr int PART_VALUES = MAXS + MAXS * MAXS + 1;
 // ---------------------------------------------------------------------------
 struct Profiler {
     bool on = false;
+    int period = 1;                 // time one launch in `period` of each class
+    int64_t seen[MSTAB_K_COUNT] = {};
     hipStream_t stream = nullptr;
     std::vector<hipEvent_t> ev;     // 2 per slot
     std::vector<int> cls;
@@ -118,12 +120,13 @@ struct Profiler {
     void reset()
     {
         used = 0;
-        for (int c = 0; c < MSTAB_K_COUNT; ++c) { launches[c] = 0; ms[c] = 0; nbytes[c] = 0; }
+        for (int c = 0; c < MSTAB_K_COUNT; ++c) { launches[c] = 0; ms[c] = 0; nbytes[c] = 0; seen[c] = 0; }
     }
     // returns slot or -1
     int begin(int c, double b)
     {
         if (!on) return -1;
+        if (seen[c]++ % period != 0) return -1;
         if (used == (int)cls.size()) harvest();
         int i = used++;
         cls[i] = c;
@@ -1353,7 +1356,8 @@ mstab_status mstab_set_profiling(mstab_solver *h, int32_t enable)
     HIPCHK(hipStreamSynchronize(h->stream));
     h->prof.harvest();
     h->prof.reset();
-    h->prof.on = enable != 0;
+    h->prof.on = enable > 0;
+    h->prof.period = enable > 0 ? enable : 1;
     return MSTAB_OK;
     API_END(h)
 }

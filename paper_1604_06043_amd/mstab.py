@@ -304,8 +304,9 @@ class Solver:
         _require_cuda(U, V)
         _check(self.lib.mstab_recycle_set(self.h, _ptr(U), _ptr(V), int(level)), self.h)
 
-    def set_profiling(self, enable: bool):
-        _check(self.lib.mstab_set_profiling(self.h, 1 if enable else 0), self.h)
+    def set_profiling(self, enable, every: int = 1):
+        """Time one launch in `every` of each kernel class (False: stop)."""
+        _check(self.lib.mstab_set_profiling(self.h, int(every) if enable else 0), self.h)
 
     def kernel_stats(self, kclass: int):
         n, ms, by = ctypes.c_int64(), ctypes.c_double(), ctypes.c_double()
