@@ -325,6 +325,14 @@ struct DiaOffsets {
 };
 constexpr unsigned long long DIA_EMPTY = 0x8000000000000000ull;   // unused table slot
 
+// Diagonal storage is sliced like the rows: the nd values of 64 consecutive
+// rows lie together, diagonal by diagonal, so a wavefront's loads of a slice
+// are one contiguous block of nd * 64 entries.
+__host__ __device__ __forceinline__ int64_t dia_index(int64_t r, int d, int nd)
+{
+    return (r / 64) * (int64_t)nd * 64 + (int64_t)d * 64 + (r % 64);
+}
+
 // Sliced ELLPACK copy of a CSR matrix (device arrays).
 template <typename T>
 struct Sell {
@@ -334,9 +342,9 @@ struct Sell {
     int32_t *col = nullptr;          // padded
     T *val = nullptr;                // padded
     // Diagonal storage, used instead when every entry lies on one of nd <= 16
-    // diagonals (stencil matrices): offsets ascending, values diagonal-major
-    // (dval[d n + r], zero where row r has no entry d), and a presence mask
-    // per row (bit d).
+    // diagonals (stencil matrices): offsets ascending, values at
+    // dval[dia_index(r, d, nd)] (zero where row r has no entry d), and a
+    // presence mask per row (bit d).
     int nd = 0;
     DiaOffsets doff{};
     uint16_t *dmask = nullptr;
@@ -402,7 +410,7 @@ __global__ __launch_bounds__(BLOCK) void k_to_dia(int64_t n, const int32_t *__re
             const int64_t off = (int64_t)ci[j] - r;
             int d = 0;
             while (d < nd - 1 && doff.off[d] != off) ++d;
-            dval[(int64_t)d * n + r] = (TD)va[j];
+            dval[dia_index(r, d, nd)] = (TD)va[j];
             m |= 1u << d;
         }
         if (mask) mask[r] = (uint16_t)m;
@@ -626,7 +634,7 @@ __global__ __launch_bounds__(SPMV_BLOCK) void k_spmv_dia(int64_t n, int nd, DiaO
                 if (d0 + j < nd) {
                     const int64_t c = r + doff.off[d0 + j];
                     // the matrix is streamed once per product: keep it out of the caches
-                    v[j] = __builtin_nontemporal_load(dval + (int64_t)(d0 + j) * n + r);
+                    v[j] = __builtin_nontemporal_load(dval + dia_index(r, d0 + j, nd));
                     xv[j] = (c >= 0 && c < n) ? x[c] : (T)0;
                 }
 #pragma unroll

@@ -212,7 +212,7 @@ Sell<T> make_sell(int64_t n, const int32_t *rp, const int32_t *ci, const TS *va,
     m.nd = like ? like->nd : detect_diagonals(n, m.nnz, rp, ci, st, &m.doff);
     if (m.nd > 0) {
         if (like) m.doff = like->doff;
-        const size_t cnt = (size_t)m.nd * (size_t)n;
+        const size_t cnt = (size_t)m.nd * (size_t)round_up(n, 64);   // whole slices
         HIPCHK(hipMalloc(&m.dval, sizeof(T) * cnt));
         HIPCHK(hipMemsetAsync(m.dval, 0, sizeof(T) * cnt, st));
         if (like) {
