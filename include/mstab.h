@@ -53,10 +53,14 @@ typedef enum {
 
 typedef enum {
     MSTAB_PREC_F64 = 0,        /* every vector operation in FP64 */
-    MSTAB_PREC_F32_REFINE = 1  /* FP32 M(s)stab(l) whose residual is replaced after every cycle
+    MSTAB_PREC_F32_REFINE = 1, /* FP32 M(s)stab(l) whose residual is replaced after every cycle
                                   by the FP64 true residual b - A x, x accumulated in FP64
                                   (the paper's residual replacement of Section 5.1, in mixed
                                   precision); FP64 small solves */
+    MSTAB_PREC_F32_MATRIX = 2  /* FP64 M(s)stab(l) whose products use an FP32 copy of A's values
+                                  (FP64 vectors and sums); the initial and true residuals use A
+                                  itself, and true-residual replacement (up to
+                                  max(max_replacements, 10)) corrects the O(eps32) difference */
 } mstab_precision;
 
 typedef enum {
@@ -104,7 +108,7 @@ typedef struct {
     int32_t f64_fallback;      /* F32_REFINE: the FP32 processes stalled and FP64 iterations finished */
     int64_t mv;                /* products with A in the iteration (initial residual, Arnoldi, cycles) */
     int64_t mv_check;          /* products with A for true-residual checks and guess gates */
-    int64_t mv_f64;            /* F32_REFINE: products with the FP64 matrix (all in mv/mv_check) */
+    int64_t mv_f64;            /* F32_REFINE, F32_MATRIX: products with the FP64 matrix (all in mv/mv_check) */
     int64_t cycles;            /* cycles of Algorithm 1 */
     int64_t level;             /* level j of the final U, V */
     int64_t fetched_level;     /* level of the data fetched by this solve, -1 if none */

@@ -544,11 +544,13 @@ __device__ void spmv_finalize(double (&vals)[S + 2], Ctl *ctl, double *part, int
     }
 }
 
-template <typename T, int S>
+// TM: type of the stored matrix values (T, or float for FP64 vectors with an
+// FP32 copy of the matrix); each value is converted to T before its product.
+template <typename T, int S, typename TM = T>
 __global__ __launch_bounds__(SPMV_BLOCK) void k_spmv(int64_t n, const int32_t *__restrict__ rp,
                                                      const int64_t *__restrict__ slice_ptr,
                                                      const int32_t *__restrict__ scol,
-                                                     const T *__restrict__ sval,
+                                                     const TM *__restrict__ sval,
                                                      const T *__restrict__ x,
                                                      T *__restrict__ y,
                                                      const T *__restrict__ b, Ctl *ctl,
@@ -572,7 +574,7 @@ __global__ __launch_bounds__(SPMV_BLOCK) void k_spmv(int64_t n, const int32_t *_
         const int64_t r = t * SLICE + lane;
         const bool valid = r < n;
         const int32_t len = valid ? rp[r + 1] - rp[r] : 0;
-        const T *vp = sval + sp0 + lane;
+        const TM *vp = sval + sp0 + lane;
         const int32_t *cp = scol + sp0 + lane;
         T sum = (T)0;
         for (int32_t j0 = 0; j0 < w; j0 += 8) {
@@ -583,7 +585,7 @@ __global__ __launch_bounds__(SPMV_BLOCK) void k_spmv(int64_t n, const int32_t *_
                 if (j0 + j < w) {
                     // the matrix is streamed once per product: keep it out of the caches
                     c[j] = __builtin_nontemporal_load(cp + (int64_t)(j0 + j) * SLICE);
-                    v[j] = __builtin_nontemporal_load(vp + (int64_t)(j0 + j) * SLICE);
+                    v[j] = (T)__builtin_nontemporal_load(vp + (int64_t)(j0 + j) * SLICE);
                 }
 #pragma unroll
             for (int j = 0; j < 8; ++j)
@@ -606,10 +608,10 @@ __global__ __launch_bounds__(SPMV_BLOCK) void k_spmv(int64_t n, const int32_t *_
 // read each, no column indices.  Present entries are multiplied, rounded and
 // added in ascending column order (the CSR order), so the result equals the
 // sliced product bit for bit.
-template <typename T, int S>
+template <typename T, int S, typename TM = T>
 __global__ __launch_bounds__(SPMV_BLOCK) void k_spmv_dia(int64_t n, int nd, DiaOffsets doff,
                                                          const uint16_t *__restrict__ mask,
-                                                         const T *__restrict__ dval,
+                                                         const TM *__restrict__ dval,
                                                          const T *__restrict__ x,
                                                          T *__restrict__ y,
                                                          const T *__restrict__ b, Ctl *ctl,
@@ -634,7 +636,7 @@ __global__ __launch_bounds__(SPMV_BLOCK) void k_spmv_dia(int64_t n, int nd, DiaO
                 if (d0 + j < nd) {
                     const int64_t c = r + doff.off[d0 + j];
                     // the matrix is streamed once per product: keep it out of the caches
-                    v[j] = __builtin_nontemporal_load(dval + dia_index(r, d0 + j, nd));
+                    v[j] = (T)__builtin_nontemporal_load(dval + dia_index(r, d0 + j, nd));
                     xv[j] = (c >= 0 && c < n) ? x[c] : (T)0;
                 }
 #pragma unroll

@@ -269,26 +269,29 @@ void free_sell(Sell<T> &m, bool own_col)
     m = Sell<T>();
 }
 
-// bytes a product must move: the matrix copy, x once, y (and b)
-template <typename T>
-double spmv_bytes(const Sell<T> &A, bool with_b)
+// bytes a product must move: the matrix copy, x once, y (and b); vectors of
+// vsize-byte elements
+template <typename TM>
+double spmv_bytes(const Sell<TM> &A, bool with_b, double vsize)
 {
     const double n = (double)A.n;
-    const double vecs = (with_b ? 3.0 : 2.0) * n * sizeof(T);
-    if (A.nd > 0) return (double)A.nd * n * sizeof(T) + 2.0 * n + vecs;
-    return (n + 1) * 4 + (double)A.padded * (4 + sizeof(T)) + (double)((A.n + SLICE - 1) / SLICE + 1) * 8 +
+    const double vecs = (with_b ? 3.0 : 2.0) * n * vsize;
+    if (A.nd > 0) return (double)A.nd * n * sizeof(TM) + 2.0 * n + vecs;
+    return (n + 1) * 4 + (double)A.padded * (4 + sizeof(TM)) + (double)((A.n + SLICE - 1) / SLICE + 1) * 8 +
            vecs;
 }
 
-template <typename T>
-void launch_spmv(int grid, hipStream_t stream, const Sell<T> &A, const T *x, T *y, const T *b,
+// TM: value type of the stored matrix (T, or float for an FP32 copy used with
+// FP64 vectors)
+template <typename T, typename TM = T>
+void launch_spmv(int grid, hipStream_t stream, const Sell<TM> &A, const T *x, T *y, const T *b,
                  Ctl *ctl, double *part, SpmvArgs a)
 {
     if (A.nd > 0) {
         switch (a.s) {
 #define CASE(S)                                                                                   \
     case S:                                                                                       \
-        hipLaunchKernelGGL((k_spmv_dia<T, S>), dim3(grid), dim3(SPMV_BLOCK), 0, stream, A.n, A.nd, \
+        hipLaunchKernelGGL((k_spmv_dia<T, S, TM>), dim3(grid), dim3(SPMV_BLOCK), 0, stream, A.n, A.nd, \
                            A.doff, A.dmask, A.dval, x, y, b, ctl, part, PART_STRIDE, a);          \
         break;
             CASE(0) CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
@@ -299,7 +302,7 @@ void launch_spmv(int grid, hipStream_t stream, const Sell<T> &A, const T *x, T *
     switch (a.s) {
 #define CASE(S)                                                                                \
     case S:                                                                                    \
-        hipLaunchKernelGGL((k_spmv<T, S>), dim3(grid), dim3(SPMV_BLOCK), 0, stream, A.n, A.rp, \
+        hipLaunchKernelGGL((k_spmv<T, S, TM>), dim3(grid), dim3(SPMV_BLOCK), 0, stream, A.n, A.rp, \
                            A.slice_ptr, A.col, A.val, x, y, b, ctl, part, PART_STRIDE, a);     \
         break;
         CASE(0) CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
@@ -379,6 +382,8 @@ struct Engine {
     void release()
     {
         free_sell(A, own_col);
+        if (use_low) free_sell(A_low, false);
+        use_low = false;
         (void)hipFree(W); (void)hipFree(R); (void)hipFree(X); (void)hipFree(Tv);
         (void)hipFree(recU); (void)hipFree(recV); (void)hipFree(rec_ptv);
         (void)hipFree(ctl); (void)hipFree(part);
@@ -390,13 +395,28 @@ struct Engine {
     // ---- launches ---------------------------------------------------------
     double vbytes(double vectors) const { return vectors * (double)n * sizeof(T); }
 
+    // FP32 copy of the matrix for the iteration's products (FP64 vectors; the
+    // initial and true residuals keep the FP64 matrix), if set
+    Sell<float> A_low{};
+    bool use_low = false;
+    // with A_low: replace the recursive residual by the true one whenever it
+    // has fallen by this factor since the last true residual (the gap between
+    // the two grows with the correction made since then)
+    double low_drop = 1e-3;
+
     void spmv(const T *x, T *y, const T *b, int act, int k, int q)
     {
         SpmvArgs a{act, k, q, s, ell, pkey};
         const int grid = grid_for(n, SPMV_BLOCK, SPMV_MAX_BLOCKS);
-        const double bytes = spmv_bytes(A, b != nullptr);
+        // the FP64 matrix for true residuals and the initial residual
+        const bool low = use_low && act != ACT_TRUE && act != ACT_RESID;
+        const double bytes = low ? spmv_bytes(A_low, b != nullptr, sizeof(T))
+                                 : spmv_bytes(A, b != nullptr, sizeof(T));
         int slot = prof ? prof->begin(MSTAB_K_SPMV, bytes) : -1;
-        launch_spmv<T>(grid, stream, A, x, y, b, ctl, part, a);
+        if (low)
+            launch_spmv<T, float>(grid, stream, A_low, x, y, b, ctl, part, a);
+        else
+            launch_spmv<T>(grid, stream, A, x, y, b, ctl, part, a);
         HIPCHK(hipGetLastError());
         if (prof) prof->end(slot);
     }
@@ -675,6 +695,7 @@ struct Engine {
         const double thr2 = tol2 * bb;
         set_thr2(thr2);
         double rr = st_host->rr;
+        double rr_true_mark = rr;   // ||r||^2 at the last true residual
         int64_t mv = st_host->mv;
         bool r_is_true = true;
         hist_mv.push_back(mv);
@@ -726,6 +747,7 @@ struct Engine {
                         sync_status();
                         mv = st_host->mv;
                         rr = st_host->rr;
+                        rr_true_mark = rr;
                         r_is_true = true;
                         if (st_host->flags & FLAG_NONFINITE || !std::isfinite(rr)) {
                             res.status = MSTAB_E_NONFINITE;
@@ -757,6 +779,19 @@ struct Engine {
                     }
                 }
                 rr = st_host->rr;
+                if (use_low && rr > thr2 && rr <= low_drop * low_drop * rr_true_mark && mv < max_mv) {
+                    spmv(X, Tv, b, ACT_TRUE, 0, 0);
+                    copy_vecs(Rc(0), Tv, 1);
+                    small(SMALL_REPLACE);
+                    sync_status();
+                    ++res.mv_check;
+                    ++res.replacements;
+                    if (st_host->flags & FLAG_NONFINITE) { res.status = MSTAB_E_NONFINITE; goto out; }
+                    if (st_host->flags & FLAG_BREAKDOWN) { res.status = MSTAB_E_BREAKDOWN; goto out; }
+                    rr = st_host->rr;
+                    rr_true_mark = rr;
+                    r_is_true = true;
+                }
                 hist_mv.push_back(mv + res.mv_check);
                 hist_res.push_back(std::sqrt(rr / bb));
                 const double rel = std::sqrt(rr / bb);
@@ -888,14 +923,24 @@ void fill_info(mstab_info *info, const SolveResult &r, double secs)
 
 int grid1(int64_t n) { return grid_for(n, BLOCK, VEC_MAX_BLOCKS); }
 
+// true-residual replacements allowed with the FP32 matrix copy (each one a
+// defect-correction step; two or three suffice in practice)
+constexpr int LOW_MATRIX_REPLACEMENTS = 10;
+
 mstab_status solve_f64(mstab_solver *h, const double *b, double *x, mstab_info *info,
                        int extra_checks, int accepted)
 {
     auto t0 = std::chrono::steady_clock::now();
     Engine<double> &E = h->e64;
     HIPCHK(hipMemcpyAsync(E.X, x, sizeof(double) * h->n, hipMemcpyDeviceToDevice, h->stream));
+    // with the FP32 matrix copy the iteration solves a system O(eps32) away from
+    // A: its recursive residual meets tol before the true one does, and each
+    // true-residual replacement is a step of defect correction
+    const bool low = h->opt.precision == MSTAB_PREC_F32_MATRIX;
+    const int max_repl = low ? std::max(h->opt.max_replacements, LOW_MATRIX_REPLACEMENTS)
+                             : h->opt.max_replacements;
     SolveResult r = E.solve(b, h->opt.tol, h->opt.max_mv, h->opt.method, h->opt.fetch,
-                            h->opt.fetch_rel, h->opt.fetch_level, h->opt.max_replacements);
+                            h->opt.fetch_rel, h->opt.fetch_level, max_repl);
     HIPCHK(hipMemcpyAsync(x, E.X, sizeof(double) * h->n, hipMemcpyDeviceToDevice, h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));
     r.mv_check += extra_checks;
@@ -905,7 +950,12 @@ mstab_status solve_f64(mstab_solver *h, const double *b, double *x, mstab_info *
     h->hist_res = E.hist_res;
     double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     fill_info(info, r, secs);
-    if (info) info->guess_accepted = accepted;
+    if (info) {
+        info->guess_accepted = accepted;
+        // products with the FP64 matrix: the initial residual (and one per
+        // restart) and the true-residual checks
+        if (low) info->mv_f64 = 1 + r.restarts + r.mv_check;
+    }
     return (mstab_status)r.status;
 }
 
@@ -1154,7 +1204,8 @@ mstab_status mstab_create(const mstab_csr *A, int32_t s, int32_t ell, const msta
     if (o) h->opt = *o;
     else mstab_options_default(&h->opt);
     if (!(h->opt.tol > 0.0) || h->opt.max_mv < 1) fail(MSTAB_E_INVALID, "tol/max_mv invalid");
-    if (h->opt.precision != MSTAB_PREC_F64 && h->opt.precision != MSTAB_PREC_F32_REFINE)
+    if (h->opt.precision != MSTAB_PREC_F64 && h->opt.precision != MSTAB_PREC_F32_REFINE &&
+        h->opt.precision != MSTAB_PREC_F32_MATRIX)
         fail(MSTAB_E_INVALID, "unknown precision");
     h->s = s; h->ell = ell; h->n = A->n; h->nnz = A->nnz;
     h->rp = A->row_ptr; h->ci = A->col_idx; h->va = A->val;
@@ -1164,6 +1215,10 @@ mstab_status mstab_create(const mstab_csr *A, int32_t s, int32_t ell, const msta
     Sell<double> A64 = make_sell<double, double>(h->n, h->rp, h->ci, h->va, h->stream);
     // the mixed form keeps a full FP64 engine for the FP64 fallback
     h->e64.alloc(h->n, s, ell, A64, true, h->pkey, h->stream, &h->prof);
+    if (h->opt.precision == MSTAB_PREC_F32_MATRIX) {
+        h->e64.A_low = make_sell<float, double>(h->n, h->rp, h->ci, h->va, h->stream, &A64);
+        h->e64.use_low = true;
+    }
     if (h->mixed()) {
         HIPCHK(hipMalloc(&h->r32, sizeof(float) * (size_t)round_up(h->n, 256)));
         HIPCHK(hipMemsetAsync(h->r32, 0, sizeof(float) * (size_t)round_up(h->n, 256), h->stream));

@@ -79,6 +79,18 @@ def compare(seq: Sequence, systems: int, s: int, ell: int, seed: int = 0, idr: b
         out["idrstab_f64"] = {"systems_per_s": systems / t, "mvs_per_system": mv}
         log(f"[{seq.name}] IDR({s})stab({ell}) FP64: {systems / t:.2f} systems/s, {mv:.1f} MVs/system")
     if mixed:
+        for name, method in (("mstab_f32_matrix", M.METHOD_MSTAB), ("idrstab_f32_matrix", M.METHOD_IDRSTAB)):
+            tl, mvl, il, xl = run(seq, systems, s, ell, method=method, precision=M.PREC_F32_MATRIX,
+                                  seed=seed, keep_x=True, **opt)
+            errs = [float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b))
+                    for a, b in zip(xl, xs)]
+            out[name] = {"systems_per_s": systems / tl, "mvs_per_system": mvl,
+                         "f64_mvs_per_system": sum(i["mv_f64"] for i in il) / systems,
+                         "max_true_relres": max(i["relres_true"] for i in il),
+                         "rel_err_vs_f64_path_max": max(errs)}
+            log(f"[{seq.name}] {name}: {systems / tl:.2f} systems/s, {mvl:.1f} MVs/system, "
+                f"max err vs FP64 path {max(errs):.2e}")
+            del xl
         tm, mvm, im, xm = run(seq, systems, s, ell, precision=M.PREC_F32_REFINE, seed=seed,
                               keep_x=True, **opt)
         errs = [float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b))

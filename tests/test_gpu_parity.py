@@ -595,3 +595,31 @@ def test_mixed_precision_large_s_ell(torch_dev, ms, orc, n, s, ell):
         assert ig["converged"] and true <= 1e-8
         assert err <= 1e-6
         assert all(math.isfinite(r) for r in hres)
+
+
+
+@pytest.mark.parametrize("name,n,s,ell,method", [("c1", 64, 4, 2, 0), ("c1", 64, 4, 2, 1), ("c3", 24, 8, 4, 0)])
+def test_fp32_matrix_copy(torch_dev, ms, orc, name, n, s, ell, method):
+    """FP64 iterations on an FP32 copy of A's values: every system reaches the
+    FP64 tolerance with A itself (true-residual replacements correct the
+    O(eps32) gap), and the error against the FP64 oracle is within 2 kappa tol."""
+    torch = torch_dev
+    print(f"[fp32 matrix copy {name} n={n} s={s} l={ell} method={method}]", flush=True)
+    cd = I.config(name, seed=0, n=n)
+    Ao = orc.assemble_convdiff(cd.dim, cd.n, cd.beta, cd.inv_dt, cd.kappa)
+    Ag = gpu_assemble(ms, cd)
+    systems = 5
+    xs_g, inf_g, _ = run_sequence_gpu(torch, ms, Ag, cd, s, ell, systems, method,
+                                      precision=ms.PREC_F32_MATRIX)
+    P = I.p_dense(0, cd.N, s)
+    xs_o, inf_o = orc.solve_sequence(Ao, cd.f, cd.inv_dt, s, ell, P, systems, method=method)
+    kappa = np.linalg.cond(Ao.dense()) if cd.N <= 5000 else 1e4
+    for k, (xg, ig, xo) in enumerate(zip(xs_g, inf_g, xs_o)):
+        b = xs_g[k - 1] * cd.inv_dt + cd.f if k else cd.f
+        true = np.linalg.norm(b - orc.spmv(Ao, xg)) / np.linalg.norm(b)
+        err = np.linalg.norm(xg - xo) / np.linalg.norm(xo)
+        print(f"  system {k}: true relres {true:.2e}, vs FP64 oracle {err:.2e}, MVs {ig['mv_total']} "
+              f"(oracle {inf_o[k].mv_total}), FP64-matrix products {ig['mv_f64']}")
+        assert ig["converged"] and true <= 1e-8
+        assert ig["mv_f64"] >= 1
+        assert err <= 2 * kappa * 1e-8
