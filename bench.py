@@ -8,7 +8,8 @@ Every step starts from x = 0 with the recycle data dropped, so each step does
 the same work.  value = systems per second over the timed steps.
 
 Also reported on the same line: MVs per system; IDR(s)stab(l) on the same
-sequence (no recycling); the FP32+FP64-refinement form; the kernel roofline of
+sequence (no recycling); the FP32+FP64-replacement form and the form with an
+FP32 copy of the matrix; the kernel roofline of
 the dominant kernel class (HIP events on the solver's stream over the timed
 steps); and the CPU oracle on a bounded sample.
 
@@ -214,6 +215,19 @@ def main():
                                   "mvs_per_system": mvm / args.systems,
                                   "rel_err_vs_f64_path_last_system": err}
         log(f"[bench] FP32+refinement: {args.systems / tm:.2f} systems/s, err {err:.2e}")
+        low = ms.Solver(A, s, ell, p_seed=0, method=ms.METHOD_MSTAB, precision=ms.PREC_F32_MATRIX)
+
+        def low_step():
+            x, mv, infos = run_sequence(torch, ms, low, cd, f, args.systems)
+            holder["x"] = x
+            return mv
+        tl, (mvl,) = timed(torch, low_step, 1, 0)
+        errl = float(torch.linalg.norm(holder["x"] - x64) / torch.linalg.norm(x64))
+        low.close()
+        variants["f32_matrix"] = {"systems_per_s": args.systems / tl,
+                                  "mvs_per_system": mvl / args.systems,
+                                  "rel_err_vs_f64_path_last_system": errl}
+        log(f"[bench] FP32 matrix copy: {args.systems / tl:.2f} systems/s, err {errl:.2e}")
 
     cpu = None
     if not args.no_cpu_baseline:
