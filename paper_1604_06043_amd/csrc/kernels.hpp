@@ -290,12 +290,13 @@ __device__ void block_partials(double (&vals)[NV], int nv, double *part, int str
 // Storage: sliced ELLPACK with 64-row slices (built from the caller's CSR at
 // create time).  Entry j of row r = 64 t + l sits at slice_ptr[t] + 64 j + l,
 // so the j-th entries of a wavefront's 64 rows are one contiguous 64-element
-// load; row lengths come from the CSR row pointer, padding is never read.
-// One thread per row; indices and values are loaded eight at a time before
-// their gathers from x.  Products are rounded, then added in CSR order
-// (contraction off): the textbook order, so the result equals a sequential CSR
-// product bit for bit.  Workgroups of 1024 threads keep the number of
-// partials, and with it the final reduction, small.
+// load, run to the slice's longest row; padded entries (column 0, value 0)
+// are loaded with the rest but never added (row lengths come from the CSR row
+// pointer).  One thread per row; indices and values are loaded eight at a
+// time before their gathers from x.  Products are rounded, then added in CSR
+// order (contraction off): the textbook order, so the result equals a
+// sequential CSR product bit for bit.  At most 1024 workgroups keep the
+// number of partials, and with it the final reduction, small.
 // ---------------------------------------------------------------------------
 enum : int32_t {
     ACT_NONE = 0,
