@@ -3,9 +3,11 @@
 // One Engine<T> runs Algorithm 1 of arXiv 1604.06043 in precision T with all
 // state on the device; the host only enqueues kernels and reads a 56-byte
 // status block once per cycle.  The FP64 mode runs Engine<double> on the
-// system itself; the mixed mode runs Engine<float> on FP64 residual-correction
-// equations (defect correction with the FP64 true residual), keeping the FP32
-// recycle data across correction steps and systems.
+// system itself (with an FP32 copy of the matrix for the iteration's products
+// in the F32_MATRIX mode); the F32_REFINE mode runs Engine<float> on the
+// residual scaled by its FP64 norm, replacing the FP32 residual by the FP64
+// true residual after its cycles and keeping the FP32 recycle data across
+// systems.
 #include "kernels.hpp"
 #include "mstab.h"
 
@@ -959,9 +961,8 @@ mstab_status solve_f64(mstab_solver *h, const double *b, double *x, mstab_info *
     return (mstab_status)r.status;
 }
 
-// Defect correction: FP64 true residual, FP32 M(s)stab(l) on the correction
-// equation A d = r / ||r|| to inner_tol, x += ||r|| d; until ||b - A x|| <= tol ||b||.
-// factor by which the FP32 residual must fall between two replacements
+// The F32_REFINE mode.
+// Factor by which the FP32 residual must fall between two replacements
 // (1: after every cycle, the paper's practice)
 #ifndef MSTAB_REPLACE_DROP
 #define MSTAB_REPLACE_DROP 1.0
