@@ -623,3 +623,23 @@ def test_fp32_matrix_copy(torch_dev, ms, orc, name, n, s, ell, method):
         assert ig["converged"] and true <= 1e-8
         assert ig["mv_f64"] >= 1
         assert err <= 2 * kappa * 1e-8
+
+
+
+def test_fresh_mstab_handle_is_idrstab(torch_dev, ms, orc):
+    """With no recycle data yet, M(s)stab(l) is IDR(s)stab(l): the first system
+    gives the same x bit for bit and the same MV count and history."""
+    torch = torch_dev
+    cd = I.config("c1", seed=1, n=48)
+    Ag = gpu_assemble(ms, cd)
+    out = []
+    for method in (ms.METHOD_MSTAB, ms.METHOD_IDRSTAB):
+        solver = ms.Solver(Ag, 4, 2, p_seed=1, method=method)
+        x = torch.zeros(cd.N, dtype=torch.float64, device="cuda")
+        info = solver.solve_next(dev(torch, cd.f), x)
+        out.append((x.cpu().numpy(), info, solver.residual_history()))
+        solver.close()
+    (xa, ia, ha), (xb, ib, hb) = out
+    assert not ia["recycled"] and not ib["recycled"]
+    np.testing.assert_array_equal(xa, xb)
+    assert ia["mv_total"] == ib["mv_total"] and ha == hb

@@ -251,6 +251,22 @@ def test_finite_termination_worked_example(orc, seed):
 # --------------------------------------------------------------------------
 # Recycling semantics
 # --------------------------------------------------------------------------
+def test_graph_matrix_solution_matches_dense_lu(orc):
+    """The unstructured workload's matrix (random geometric graph, relabelled):
+    the solve agrees with LAPACK within 10 kappa tol."""
+    g = I.rgg(200, 4)
+    A = orc.CSR(g.row_ptr, g.col, g.val)
+    D = A.dense()
+    b = 0.1 * I.white_noise(4, 0, g.N)
+    P = I.p_dense(4, g.N, 4)
+    x, info, _, _ = orc.solve(A, b, np.zeros(g.N), 4, 2, P)
+    ref = np.linalg.solve(D, b)
+    kappa = np.linalg.cond(D)
+    assert info.converged
+    assert np.linalg.norm(x - ref) <= 10 * kappa * 1e-8 * np.linalg.norm(ref)
+    assert np.linalg.norm(b - D @ x) <= 1e-8 * np.linalg.norm(b)
+
+
 def test_mstab_on_a_single_system_is_idrstab(orc):
     cd, A = small_convdiff(orc, 2, 12, seed=2)
     P = I.p_dense(5, A.n, 4)
