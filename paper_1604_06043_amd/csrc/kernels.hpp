@@ -380,10 +380,21 @@ __global__ __launch_bounds__(BLOCK) void k_dia_offsets(int64_t n, const int32_t 
                                                        const int32_t *__restrict__ ci,
                                                        unsigned long long *table, int *overflow)
 {
+    // offsets this workgroup has already placed (a cache in front of the
+    // global table; duplicates in it are harmless)
+    __shared__ unsigned long long s_seen[MAX_DIAG];
+    __shared__ int s_count;
+    if (threadIdx.x < MAX_DIAG) s_seen[threadIdx.x] = DIA_EMPTY;
+    if (threadIdx.x == 0) s_count = 0;
+    __syncthreads();
     for (int64_t r = (int64_t)blockIdx.x * BLOCK + threadIdx.x; r < n;
          r += (int64_t)gridDim.x * BLOCK) {
         for (int32_t j = rp[r]; j < rp[r + 1]; ++j) {
             const unsigned long long off = (unsigned long long)((int64_t)ci[j] - r);
+            bool known = false;
+            for (int t = 0; t < MAX_DIAG && !known; ++t)
+                known = __hip_atomic_load(&s_seen[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) == off;
+            if (known) continue;
             bool placed = false;
             for (int t = 0; t < MAX_DIAG && !placed; ++t) {
                 unsigned long long cur =
@@ -391,7 +402,13 @@ __global__ __launch_bounds__(BLOCK) void k_dia_offsets(int64_t n, const int32_t 
                 if (cur == DIA_EMPTY) cur = atomicCAS(&table[t], DIA_EMPTY, off);
                 placed = (cur == DIA_EMPTY || cur == off);
             }
-            if (!placed) __hip_atomic_store(overflow, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (!placed) {
+                __hip_atomic_store(overflow, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            } else {
+                const int k = atomicAdd(&s_count, 1);
+                if (k < MAX_DIAG)
+                    __hip_atomic_store(&s_seen[k], off, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            }
         }
     }
 }
