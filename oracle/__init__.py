@@ -14,7 +14,10 @@ Functions follow the paper (Neuenhofen, arXiv 1604.06043):
 * :func:`bicgstab` -- textbook BiCGStab, which the IDR cycle of Section 2.3
   reproduces for s = l = 1;
 * :func:`assemble_convdiff`, :func:`spmv` -- the upwind finite-difference
-  matrices of the synthetic workloads and the plain CSR product.
+  matrices of the synthetic workloads and the plain CSR product;
+* :func:`jacobi_split`, :func:`solve_jacobi` -- the split preconditioned
+  system of Section 5.1, L^{-1} A R^{-1} y = L^{-1} b with x = R^{-1} y, for
+  the diagonal splitting L = R = |D|^{1/2}.
 """
 from __future__ import annotations
 
@@ -250,21 +253,65 @@ def bicgstab(A: CSR, b, x0, rhat, iters: int) -> np.ndarray:
     return x
 
 
+def jacobi_split(A: CSR):
+    """Split diagonal preconditioning (Section 5.1's form with L = R = |D|^{1/2}).
+
+    Returns (Ahat, d, e) with e_i = sqrt(|a_ii|), d_i = 1 / e_i and
+    Ahat_ij = (a_ij d_i) d_j, i.e. Ahat = L^{-1} A R^{-1}.  A row without a
+    stored, finite, nonzero diagonal entry is an error.
+    """
+    n = A.n
+    rows = np.repeat(np.arange(n), np.diff(A.row_ptr))
+    on_diag = A.col == rows
+    diag = np.full(n, np.nan)
+    diag[rows[on_diag]] = A.val[on_diag]
+    if not np.all(np.isfinite(diag)) or np.any(diag == 0.0):
+        raise ValueError("jacobi_split: missing, zero or non-finite diagonal entry")
+    e = np.sqrt(np.abs(diag))
+    d = 1.0 / e
+    val = (A.val * d[rows]) * d[A.col]
+    return CSR(A.row_ptr.copy(), A.col.copy(), val), d, e
+
+
+def solve_jacobi(A: CSR, b, x0, s: int, ell: int, P: np.ndarray, split=None, **kw):
+    """:func:`solve` on the split system: y0 = R x0, solve Ahat y = L^{-1} b, x = R^{-1} y.
+
+    The tolerance and the residual replacement act on the preconditioned
+    residual L^{-1} (b - A R^{-1} y), as in the ocean run of Section 5.1.
+    ``split`` may pass a precomputed :func:`jacobi_split` result.  Returns
+    (x, info, recycle, dump) as :func:`solve`; recycled U, V live in the
+    split system's space.
+    """
+    Ah, d, e = split if split is not None else jacobi_split(A)
+    b = np.asarray(b, dtype=np.float64)
+    y0 = np.asarray(x0, dtype=np.float64) * e
+    y, info, rec, dd = solve(Ah, b * d, y0, s, ell, P, **kw)
+    return y * d, info, rec, dd
+
+
 def rhs_step(x: np.ndarray, inv_dt: float, f: np.ndarray) -> np.ndarray:
     """Implicit Euler right-hand side b = x inv_dt + f (multiply, then add)."""
     return x * inv_dt + f
 
 
 def solve_sequence(A: CSR, f, inv_dt: float, s: int, ell: int, P, systems: int,
-                   method: int = MSTAB, tol: float = 1e-8, fetch: int = FETCH_THRESHOLD, **kw):
-    """Time-stepping sequence: b^(k+1) = x^(k) inv_dt + f, x0 = x^(k), x^(0) = 0."""
+                   method: int = MSTAB, tol: float = 1e-8, fetch: int = FETCH_THRESHOLD,
+                   jacobi: bool = False, **kw):
+    """Time-stepping sequence: b^(k+1) = x^(k) inv_dt + f, x0 = x^(k), x^(0) = 0.
+
+    ``jacobi`` solves every system in the split diagonally preconditioned form."""
     x = np.zeros(A.n)
     rec = Recycle.empty(A.n, s)
     xs, infos = [], []
+    split = jacobi_split(A) if jacobi else None
     for _ in range(systems):
         b = rhs_step(x, inv_dt, f)
-        x, info, rec, _ = solve(A, b, x, s, ell, P, tol=tol, method=method, fetch=fetch,
-                                recycle=rec, **kw)
+        if jacobi:
+            x, info, rec, _ = solve_jacobi(A, b, x, s, ell, P, split=split, tol=tol, method=method,
+                                           fetch=fetch, recycle=rec, **kw)
+        else:
+            x, info, rec, _ = solve(A, b, x, s, ell, P, tol=tol, method=method, fetch=fetch,
+                                    recycle=rec, **kw)
         xs.append(x.copy())
         infos.append(info)
     return xs, infos
