@@ -64,7 +64,7 @@ def _load():
         _lib.orc_spmv.argtypes = [i64, P, P, P, P, P]
         _lib.orc_solve.restype = i32
         _lib.orc_solve.argtypes = [i64, P, P, P, i32, i32, P, f64, i64, i32, i32, f64, i64, i32,
-                                   P, P, P, P, P, P, P, P, P, P, i64, P, i64, P]
+                                   i32, P, P, P, P, P, P, P, P, P, P, i64, P, i64, P]
         _lib.orc_set_sum_order.restype = None
         _lib.orc_set_sum_order.argtypes = [i32]
         _lib.orc_bicgstab.restype = i32
@@ -165,8 +165,11 @@ class Info:
 def solve(A: CSR, b, x0, s: int, ell: int, P: np.ndarray, tol: float = 1e-8,
           max_mv: int = 10 ** 9, method: int = MSTAB, fetch: int = FETCH_THRESHOLD,
           fetch_rel: float | None = None, fetch_level: int = -1, max_repl: int = 3,
-          recycle: Recycle | None = None, dump_cycle: int = -1):
+          recycle: Recycle | None = None, dump_cycle: int = -1, replace_every: int = 0):
     """Run Algorithm 1 on A x = b from x0.  Returns (x, info, recycle, dump).
+
+    ``replace_every`` = k > 0 replaces the recursive residual by b - A x after
+    every k-th cycle (Section 5.1's ocean run: k = 1).
 
     ``recycle`` is updated in place (fetched data) and also returned.
     ``dump`` (if dump_cycle >= 0) is a dict with the state after the level
@@ -196,7 +199,7 @@ def solve(A: CSR, b, x0, s: int, ell: int, P: np.ndarray, tol: float = 1e-8,
         dump = np.zeros(n * (2 + ell + s * (ell + 2)) + ell + n * (2 + 2 * s))
     st = lib.orc_solve(n, _ptr(A.row_ptr), _ptr(A.col), _ptr(A.val), s, ell, _ptr(P),
                        float(tol), int(max_mv), int(method), int(fetch), float(fetch_rel),
-                       int(fetch_level), int(max_repl), _ptr(b), _ptr(x),
+                       int(fetch_level), int(max_repl), int(replace_every), _ptr(b), _ptr(x),
                        _ptr(recycle.U), _ptr(recycle.V), _ptr(lvl), _ptr(have),
                        _ptr(oi), _ptr(of), _ptr(hmv), _ptr(hres), cap, _ptr(hl),
                        int(dump_cycle), _ptr(dump))

@@ -14,7 +14,12 @@
  *     the true residual b - A x is formed (one counted check MV) and, while it
  *     still exceeds tol, it replaces r and the loop continues (at most
  *     max_repl times), as the ocean experiment of Section 5.1 replaces the
- *     residual after the solution update.
+ *     residual after the solution update.  With replace_every = k > 0 the
+ *     recursive residual is also replaced by b - A x at the end of every k-th
+ *     cycle while it is above the tolerance (one counted check MV each): the
+ *     ocean run of Section 5.1 does so after every cycle (k = 1), on the
+ *     split-preconditioned system.  These periodic replacements are counted
+ *     with the others but do not use up max_repl.
  *   - The solution update of Algorithm 1 sums over i = 1..l (the printed
  *     lower index is a typo).  x and u_q use the level vectors from before
  *     r and v_q are overwritten.
@@ -434,7 +439,7 @@ static int cycle(Work *w, double *x, double *dump)
 int orc_solve(int64_t n, const int32_t *rp, const int32_t *ci, const double *va,
               int s, int ell, const double *P,
               double tol, int64_t max_mv, int method, int fetch, double fetch_rel,
-              int64_t fetch_level, int max_repl,
+              int64_t fetch_level, int max_repl, int replace_every,
               const double *b, double *x,
               double *U, double *V, int64_t *rec_level, int *rec_have,
               int64_t *out_i64, double *out_f64,
@@ -451,7 +456,8 @@ int orc_solve(int64_t n, const int32_t *rp, const int32_t *ci, const double *va,
     if (!w.W || !w.R || !t) { free(w.W); free(w.R); free(t); return ORC_E_NOMEM; }
 
     int64_t mv_check = 0, cycles = 0, hl = 0, fetched = -1, level = 0;
-    int converged = 0, recycled = 0, restarts = 0, repl = 0, status = ORC_OK;
+    int converged = 0, recycled = 0, restarts = 0, repl = 0, repl_end = 0, status = ORC_OK;
+    int64_t since_true = 0;   /* cycles since r was last the true residual */
     double rr = 0.0, relres_true = -1.0;
     const double tol2 = tol * tol;
 
@@ -518,6 +524,20 @@ int orc_solve(int64_t n, const int32_t *rp, const int32_t *ci, const double *va,
                 memcpy(d, r, (size_t)n * sizeof(double)); d += n;
                 memcpy(d, WCOL(&w, -1, 0), (size_t)n * 2 * s * sizeof(double));
             }
+            ++since_true;
+            if (replace_every > 0 && since_true >= replace_every && rr > tol2 * nb2 &&
+                w.A.mv < max_mv) {
+                /* periodic replacement after the solution update */
+                Mat Ap = w.A;
+                matvec(&Ap, x, r);
+                ++mv_check;
+                for (int64_t e = 0; e < n; ++e) r[e] = b[e] - r[e];
+                rr = dot(n, r, r);
+                if (!isfinite(rr)) { status = ORC_E_NONFINITE; goto done; }
+                r_is_true = 1;
+                since_true = 0;
+                ++repl;
+            }
             HIST(sqrt(rr / nb2));
             double rel = sqrt(rr / nb2);
             int fire = 0;
@@ -547,11 +567,13 @@ int orc_solve(int64_t n, const int32_t *rp, const int32_t *ci, const double *va,
         relres_true = sqrt(tt / nb2);
         if (!isfinite(tt)) { status = ORC_E_NONFINITE; goto done; }
         if (tt <= tol2 * nb2) { converged = 1; break; }
-        if (rr <= tol2 * nb2 && repl < max_repl && w.A.mv < max_mv) {
+        if (rr <= tol2 * nb2 && repl_end < max_repl && w.A.mv < max_mv) {
             memcpy(r, t, (size_t)n * sizeof(double));
             rr = tt;
             r_is_true = 1;
+            since_true = 0;
             ++repl;
+            ++repl_end;
             continue;
         }
         break;

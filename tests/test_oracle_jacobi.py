@@ -135,3 +135,55 @@ def test_split_rejects_missing_or_zero_diagonal(orc):
     D[2, 3] = 1.0
     with pytest.raises(ValueError):
         orc.jacobi_split(csr_from_dense(orc, D))
+
+
+def test_periodic_replacement_tracks_true_residual(orc):
+    """Section 5.1's ocean run replaces the residual by the true one after the
+    solution update of every cycle.  With replace_every = 1 each recorded
+    residual (but the last, below the tolerance) is the true residual of that
+    cycle's x, computed here independently; each replacement costs one check
+    product.  The recycled start of this split system has a recursive/true gap
+    of ~1e-10 relative without it."""
+    cd = I.config("c3", seed=4, n=14)
+    A = orc.assemble_convdiff(cd.dim, cd.n, cd.beta, cd.inv_dt, cd.kappa)
+    split = orc.jacobi_split(A)
+    Ah, d, _ = split
+    S = Ah.scipy()
+    P = I.p_dense(4, cd.N, 8)
+    x1, _, rec, _ = orc.solve_jacobi(A, cd.f, np.zeros(cd.N), 8, 4, P, split=split)
+    b1 = orc.rhs_step(x1, cd.inv_dt, cd.f)
+    bh = b1 * d
+    gaps, ratio = {}, {}
+    for every in (0, 1):
+        _, info, _, _ = orc.solve_jacobi(A, b1, x1, 8, 4, P, split=split, recycle=rec.copy(),
+                                         replace_every=every)
+        assert info.converged
+        gaps[every], ratio[every] = [], []
+        for c in range(info.cycles):
+            _, _, _, dd = orc.solve_jacobi(A, b1, x1, 8, 4, P, split=split, recycle=rec.copy(),
+                                           replace_every=every, dump_cycle=c)
+            true = np.linalg.norm(bh - S @ dd["x_after"]) / np.linalg.norm(bh)
+            gaps[every].append(abs(info.hist_res[c + 1] - true) / true)
+            ratio[every].append(true / info.hist_res[c + 1])
+        if every == 1:
+            assert max(gaps[1][:-1]) <= 1e-8, gaps[1]
+            # one check product per replaced cycle, plus the final true residual
+            assert info.replacements == info.cycles - 1
+            assert info.mv_check == info.cycles
+    assert max(ratio[0]) > 1e3   # the gap the replacement removes
+
+
+def test_periodic_replacement_every_second_cycle(orc):
+    """replace_every = 2 replaces after cycles 2, 4, ...: on an unpreconditioned
+    system that needs several cycles, the count of check products is fixed by
+    the number of cycles."""
+    cd = I.config("c1", seed=0, n=32)
+    A = orc.assemble_convdiff(cd.dim, cd.n, cd.beta, cd.inv_dt)
+    P = I.p_dense(0, cd.N, 2)
+    _, info, _, _ = orc.solve(A, cd.f, np.zeros(cd.N), 2, 1, P, method=orc.IDRSTAB,
+                              replace_every=2)
+    assert info.converged and info.cycles >= 5
+    # cycles 2, 4, ... below the last replace; the last ends below tol
+    periodic = (info.cycles - 1) // 2
+    assert info.mv_check == periodic + 1 + (info.replacements - periodic)
+    assert info.replacements >= periodic
