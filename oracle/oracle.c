@@ -506,6 +506,7 @@ int orc_solve(int64_t n, const int32_t *rp, const int32_t *ci, const double *va,
                     matvec(&w.A, x, r);
                     for (int64_t e = 0; e < n; ++e) r[e] = b[e] - r[e];
                     r_is_true = 1;
+                    since_true = 0;
                     rr = dot(n, r, r);
                     if (!isfinite(rr)) { status = ORC_E_NONFINITE; goto done; }
                     continue;
