@@ -71,6 +71,18 @@ typedef enum {
     MSTAB_FETCH_NEVER = 4      /* never replace the held data */
 } mstab_fetch;
 
+typedef enum {
+    MSTAB_PRECOND_NONE = 0,    /* solve A x = b as given */
+    MSTAB_PRECOND_JACOBI = 1   /* split diagonal preconditioning, Section 5.1's split form
+                                  L^-1 A R^-1 y = L^-1 b, x = R^-1 y, with L = R = |D|^(1/2)
+                                  (D = diag(A)).  The handle iterates on the split system:
+                                  tol, relres_recursive, relres_true, the residual history and
+                                  the true-residual replacement refer to the preconditioned
+                                  residual L^-1 (b - A x), and recycled U, V (recycle_get/set)
+                                  live in the split system's space.  Every row needs a stored,
+                                  finite, nonzero diagonal entry (else E_INVALID at create). */
+} mstab_precond;
+
 /* CSR matrix; all arrays are device pointers, n rows, nnz entries. */
 typedef struct {
     int64_t n;
@@ -94,6 +106,13 @@ typedef struct {
     double inner_tol;          /* reserved (F32_REFINE replaces the FP32 residual by the FP64
                                   true residual after every cycle and stops on it); default 1e-4 */
     int32_t max_refinements;   /* F32_REFINE: outer correction steps; default 20 */
+    int32_t precond;           /* mstab_precond; default NONE */
+    int32_t replace_every;     /* F64, F32_MATRIX: k > 0 replaces the recursive residual by the
+                                  true one after every k-th cycle while it is above tol (one
+                                  check MV each; the ocean run of Section 5.1 uses k = 1); these
+                                  do not count against max_replacements.  Default 0 (only the
+                                  final replacements).  F32_REFINE replaces after every cycle
+                                  by construction and ignores it. */
 } mstab_options;
 
 typedef struct {
@@ -137,7 +156,9 @@ mstab_status mstab_create(const mstab_csr *A, int32_t s, int32_t ell, const msta
  * x holds the initial guess on entry (normally the previous solution) and the
  * solution on return.  With method MSTAB and held recycle data the solve starts
  * from it; the fetch policy may replace the held data.  info may be NULL.
- * On failure x holds the last consistent iterate.
+ * On failure x holds the last consistent iterate.  With MSTAB_PRECOND_JACOBI,
+ * b and x stay in the original system's terms: the call forms L^-1 b and
+ * y0 = R x0, iterates on the split system and returns x = R^-1 y.
  */
 mstab_status mstab_solve_next(mstab_solver *h, const double *b, double *x, mstab_info *info);
 
@@ -146,6 +167,7 @@ mstab_status mstab_solve_next(mstab_solver *h, const double *b, double *x, mstab
  * only if ||b - A x_guess|| < ||b - A x_prev|| (two counted check MVs),
  * otherwise x_prev is.  (b, x_prev, x_guess, x: device, n doubles; x may alias
  * x_prev or x_guess.)  info->guess_accepted reports the decision.
+ * E_INVALID on a handle created with a preconditioner.
  */
 mstab_status mstab_solve_next_guess(mstab_solver *h, const double *b, const double *x_prev,
                                     const double *x_guess, double *x, mstab_info *info);
@@ -154,7 +176,7 @@ mstab_status mstab_solve_next_guess(mstab_solver *h, const double *b, const doub
  * r = b - A x with the handle's matrix and product kernel (device, n doubles
  * each; r must not alias b or x); norm2 (host, may be NULL) receives ||r||^2.
  * One product with A, counted in the handle's total (mstab_mv_count) but not
- * in any solve's info.
+ * in any solve's info.  E_INVALID on a handle created with a preconditioner.
  */
 mstab_status mstab_residual(mstab_solver *h, const double *b, const double *x, double *r,
                             double *norm2);
@@ -233,6 +255,17 @@ int64_t mstab_convdiff_nnz(int32_t dim, int64_t n);
 mstab_status mstab_assemble_convdiff(int32_t dim, int64_t n, const double *beta, double inv_dt,
                                      const double *kappa, int32_t *row_ptr, int32_t *col_idx,
                                      double *val, void *hip_stream);
+
+/*
+ * The split diagonal preconditioning of MSTAB_PRECOND_JACOBI (Section 5.1's
+ * split form, L = R = |D|^(1/2)): e_i = sqrt(|a_ii|), d_i = 1 / e_i and
+ * val_out[k] = (val[k] d_i) d_j for entry k = (i, j), i.e. the values of
+ * L^-1 A R^-1 in A's sparsity pattern.  val_out (nnz), d and e (n each):
+ * device doubles; d or e may be NULL.  E_INVALID if a row has no stored,
+ * finite, nonzero diagonal entry.
+ */
+mstab_status mstab_jacobi_split(const mstab_csr *A, double *val_out, double *d, double *e,
+                                void *hip_stream);
 
 /* y = A x (device, FP64), the plain sparse product used by the iteration. */
 mstab_status mstab_spmv(const mstab_csr *A, const double *x, double *y, void *hip_stream);

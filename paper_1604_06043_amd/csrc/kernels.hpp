@@ -380,36 +380,43 @@ __global__ __launch_bounds__(BLOCK) void k_dia_offsets(int64_t n, const int32_t 
                                                        const int32_t *__restrict__ ci,
                                                        unsigned long long *table, int *overflow)
 {
-    // offsets this workgroup has already placed (a cache in front of the
-    // global table; duplicates in it are harmless)
-    __shared__ unsigned long long s_seen[MAX_DIAG];
-    __shared__ int s_count;
-    if (threadIdx.x < MAX_DIAG) s_seen[threadIdx.x] = DIA_EMPTY;
-    if (threadIdx.x == 0) s_count = 0;
+    // Each workgroup first collects the offsets of its rows in an LDS table,
+    // then merges that table into the global one: the global table then sees
+    // at most MAX_DIAG probes per workgroup instead of one per entry.  More
+    // than MAX_DIAG distinct offsets in one workgroup means more in the matrix.
+    __shared__ unsigned long long s_tab[MAX_DIAG];
+    __shared__ int s_over;
+    if (threadIdx.x < MAX_DIAG) s_tab[threadIdx.x] = DIA_EMPTY;
+    if (threadIdx.x == 0) s_over = 0;
     __syncthreads();
+    bool over = false;
     for (int64_t r = (int64_t)blockIdx.x * BLOCK + threadIdx.x; r < n;
          r += (int64_t)gridDim.x * BLOCK) {
         for (int32_t j = rp[r]; j < rp[r + 1]; ++j) {
             const unsigned long long off = (unsigned long long)((int64_t)ci[j] - r);
-            bool known = false;
-            for (int t = 0; t < MAX_DIAG && !known; ++t)
-                known = __hip_atomic_load(&s_seen[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) == off;
-            if (known) continue;
             bool placed = false;
             for (int t = 0; t < MAX_DIAG && !placed; ++t) {
                 unsigned long long cur =
-                    __hip_atomic_load(&table[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                if (cur == DIA_EMPTY) cur = atomicCAS(&table[t], DIA_EMPTY, off);
+                    __hip_atomic_load(&s_tab[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                if (cur == DIA_EMPTY) cur = atomicCAS(&s_tab[t], DIA_EMPTY, off);
                 placed = (cur == DIA_EMPTY || cur == off);
             }
-            if (!placed) {
-                __hip_atomic_store(overflow, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            } else {
-                const int k = atomicAdd(&s_count, 1);
-                if (k < MAX_DIAG)
-                    __hip_atomic_store(&s_seen[k], off, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-            }
+            over |= !placed;
         }
+    }
+    if (over) s_over = 1;
+    __syncthreads();
+    if (threadIdx.x < MAX_DIAG) {
+        const unsigned long long off = s_tab[threadIdx.x];
+        bool placed = (off == DIA_EMPTY);
+        for (int t = 0; t < MAX_DIAG && !placed; ++t) {
+            unsigned long long cur =
+                __hip_atomic_load(&table[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (cur == DIA_EMPTY) cur = atomicCAS(&table[t], DIA_EMPTY, off);
+            placed = (cur == DIA_EMPTY || cur == off);
+        }
+        if (!placed || (threadIdx.x == 0 && s_over))
+            __hip_atomic_store(overflow, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 
@@ -1232,6 +1239,55 @@ __global__ __launch_bounds__(BLOCK) void k_rhs_step(int64_t n, const double *__r
         const double t = x[e] * inv_dt;
         b[e] = t + f[e];
     }
+}
+
+// Split diagonal preconditioning (Section 5.1's split form, L = R = |D|^(1/2)):
+// e_i = sqrt(|a_ii|) and d_i = 1 / e_i, both correctly rounded.  A row whose
+// diagonal entry is not stored, zero or not finite sets *bad (and gets 1).
+__global__ __launch_bounds__(BLOCK) void k_jacobi_diag(int64_t n, const int32_t *__restrict__ rp,
+                                                       const int32_t *__restrict__ ci,
+                                                       const double *__restrict__ va,
+                                                       double *__restrict__ d,
+                                                       double *__restrict__ e, int *bad)
+{
+    for (int64_t r = (int64_t)blockIdx.x * BLOCK + threadIdx.x; r < n;
+         r += (int64_t)gridDim.x * BLOCK) {
+        double a = 0.0;
+        for (int32_t j = rp[r]; j < rp[r + 1]; ++j)
+            if (ci[j] == r) a = va[j];
+        double ev = 1.0;
+        if (a != 0.0 && isfinite(a)) ev = sqrt(fabs(a));
+        else __hip_atomic_store(bad, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        e[r] = ev;
+        d[r] = 1.0 / ev;
+    }
+}
+
+// Values of L^-1 A R^-1: out_k = (a_ij d_i) d_j, two roundings, no contraction.
+__global__ __launch_bounds__(BLOCK) void k_jacobi_scale(int64_t n, const int32_t *__restrict__ rp,
+                                                        const int32_t *__restrict__ ci,
+                                                        const double *__restrict__ va,
+                                                        const double *__restrict__ d,
+                                                        double *__restrict__ out)
+{
+#pragma clang fp contract(off)
+    for (int64_t r = (int64_t)blockIdx.x * BLOCK + threadIdx.x; r < n;
+         r += (int64_t)gridDim.x * BLOCK) {
+        const double di = d[r];
+        for (int32_t j = rp[r]; j < rp[r + 1]; ++j) {
+            const double t = va[j] * di;
+            out[j] = t * d[ci[j]];
+        }
+    }
+}
+
+// y = x * w elementwise (y may alias x).
+__global__ __launch_bounds__(BLOCK) void k_mul(int64_t n, const double *x,
+                                               const double *__restrict__ w, double *y)
+{
+    for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * BLOCK)
+        y[i] = x[i] * w[i];
 }
 
 }  // namespace mstab

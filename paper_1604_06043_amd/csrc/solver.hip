@@ -196,6 +196,32 @@ inline int detect_diagonals(int64_t n, int64_t nnz, const int32_t *rp, const int
     return nd;
 }
 
+// Split diagonal preconditioning: d, e (n doubles each) and the values of
+// L^-1 A R^-1 in A's pattern (val_out, nnz doubles).  E_INVALID if a row has
+// no stored, finite, nonzero diagonal entry.
+inline void jacobi_split_dev(int64_t n, const int32_t *rp, const int32_t *ci, const double *va,
+                             double *val_out, double *d, double *e, hipStream_t st)
+{
+    if (n < 1) return;
+    int *bad = nullptr;
+    int hbad = 0;
+    HIPCHK(hipMalloc(&bad, sizeof(int)));
+    hipError_t ce = hipMemsetAsync(bad, 0, sizeof(int), st);
+    const int grid = grid_for(n, BLOCK, VEC_MAX_BLOCKS);
+    if (ce == hipSuccess) {
+        hipLaunchKernelGGL(k_jacobi_diag, dim3(grid), dim3(BLOCK), 0, st, n, rp, ci, va, d, e, bad);
+        ce = hipGetLastError();
+    }
+    if (ce == hipSuccess) ce = hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, st);
+    const hipError_t se = hipStreamSynchronize(st);
+    (void)hipFree(bad);
+    HIPCHK(ce);
+    HIPCHK(se);
+    if (hbad) fail(MSTAB_E_INVALID, "Jacobi splitting: a diagonal entry is missing, zero or not finite");
+    hipLaunchKernelGGL(k_jacobi_scale, dim3(grid), dim3(BLOCK), 0, st, n, rp, ci, va, d, val_out);
+    HIPCHK(hipGetLastError());
+}
+
 // The device copy of A used by the product kernels: diagonal storage when A
 // is a stencil matrix (at most 16 diagonals), else sliced ELLPACK.  like: the
 // FP64 copy whose column array (or diagonal mask) this copy shares.
@@ -401,6 +427,10 @@ struct Engine {
     // initial and true residuals keep the FP64 matrix), if set
     Sell<float> A_low{};
     bool use_low = false;
+    // k > 0: replace the recursive residual by the true one after every k-th
+    // cycle while it is above the tolerance (Section 5.1's ocean run, k = 1);
+    // these replacements do not use up the budget of the final ones
+    int replace_every = 0;
     // with A_low: replace the recursive residual by the true one whenever it
     // has fallen by this factor since the last true residual (the gap between
     // the two grows with the correction made since then)
@@ -698,6 +728,8 @@ struct Engine {
         set_thr2(thr2);
         double rr = st_host->rr;
         double rr_true_mark = rr;   // ||r||^2 at the last true residual
+        int64_t since_true = 0;     // cycles since r was last the true residual
+        int periodic_repl = 0;
         int64_t mv = st_host->mv;
         bool r_is_true = true;
         hist_mv.push_back(mv);
@@ -751,6 +783,7 @@ struct Engine {
                         rr = st_host->rr;
                         rr_true_mark = rr;
                         r_is_true = true;
+                        since_true = 0;
                         if (st_host->flags & FLAG_NONFINITE || !std::isfinite(rr)) {
                             res.status = MSTAB_E_NONFINITE;
                             goto out;
@@ -781,7 +814,12 @@ struct Engine {
                     }
                 }
                 rr = st_host->rr;
-                if (use_low && rr > thr2 && rr <= low_drop * low_drop * rr_true_mark && mv < max_mv) {
+                ++since_true;
+                const bool periodic = replace_every > 0 && since_true >= replace_every;
+                const bool low_gap = use_low && rr <= low_drop * low_drop * rr_true_mark;
+                if ((periodic || low_gap) && rr > thr2 && mv < max_mv) {
+                    if (periodic) ++periodic_repl;
+                    since_true = 0;
                     spmv(X, Tv, b, ACT_TRUE, 0, 0);
                     copy_vecs(Rc(0), Tv, 1);
                     small(SMALL_REPLACE);
@@ -823,11 +861,12 @@ struct Engine {
                 res.relres_true = std::sqrt(tt / bb);
                 if (!std::isfinite(tt)) { res.status = MSTAB_E_NONFINITE; goto out; }
                 if (tt <= thr2) { res.converged = true; break; }
-                if (rr <= thr2 && res.replacements < max_repl && mv < max_mv) {
+                if (rr <= thr2 && res.replacements - periodic_repl < max_repl && mv < max_mv) {
                     copy_vecs(Rc(0), Tv, 1);
                     small(SMALL_REPLACE);
                     rr = tt;
                     r_is_true = true;
+                    since_true = 0;
                     ++res.replacements;
                     continue;
                 }
@@ -869,6 +908,9 @@ struct mstab_solver {
     Engine<float> e32;
     float *r32 = nullptr;   // F32_REFINE: scaled residual (right-hand side of the inner solve)
     double *xbak = nullptr; // F32_REFINE: x before the last fold of the FP32 iterate
+    // PRECOND_JACOBI: d = |diag A|^-1/2, e = |diag A|^1/2, and L^-1 b
+    double *pd = nullptr, *pe = nullptr, *bhat = nullptr;
+    double *split_tmp = nullptr;  // create only: the split values while the copies are built
     Profiler prof;
     int64_t mv_total = 0, mv_last = 0;
     std::vector<int64_t> hist_mv;
@@ -893,6 +935,22 @@ mstab_status record_hip(mstab_solver *h, const HipError &e)
     if (h) h->err = buf;
     g_tls_error = buf;
     return MSTAB_E_HIP;
+}
+
+void release_handle(mstab_solver *h)
+{
+    if (!h) return;
+    (void)hipStreamSynchronize(h->stream);
+    h->e64.release();
+    h->e32.release();
+    (void)hipFree(h->r32);
+    (void)hipFree(h->xbak);
+    (void)hipFree(h->pd);
+    (void)hipFree(h->pe);
+    (void)hipFree(h->bhat);
+    (void)hipFree(h->split_tmp);
+    h->prof.destroy();
+    delete h;
 }
 
 #define API_BEGIN try {
@@ -1208,14 +1266,29 @@ mstab_status mstab_create(const mstab_csr *A, int32_t s, int32_t ell, const msta
     if (h->opt.precision != MSTAB_PREC_F64 && h->opt.precision != MSTAB_PREC_F32_REFINE &&
         h->opt.precision != MSTAB_PREC_F32_MATRIX)
         fail(MSTAB_E_INVALID, "unknown precision");
+    if (h->opt.precond != MSTAB_PRECOND_NONE && h->opt.precond != MSTAB_PRECOND_JACOBI)
+        fail(MSTAB_E_INVALID, "unknown preconditioner");
+    if (h->opt.replace_every < 0) fail(MSTAB_E_INVALID, "replace_every < 0");
     h->s = s; h->ell = ell; h->n = A->n; h->nnz = A->nnz;
     h->rp = A->row_ptr; h->ci = A->col_idx; h->va = A->val;
     h->stream = (hipStream_t)hip_stream;
     h->pkey = p_key_from_seed(h->opt.p_seed);
     h->prof.init(h->stream);
+    double *split_val = nullptr;   // L^-1 A R^-1, needed only while the device copies are built
+    if (h->opt.precond == MSTAB_PRECOND_JACOBI) {
+        const size_t vb = sizeof(double) * (size_t)round_up(h->n, 256);
+        HIPCHK(hipMalloc(&h->pd, vb));
+        HIPCHK(hipMalloc(&h->pe, vb));
+        HIPCHK(hipMalloc(&h->bhat, vb));
+        HIPCHK(hipMalloc(&split_val, sizeof(double) * (size_t)std::max<int64_t>(h->nnz, 1)));
+        h->split_tmp = split_val;
+        jacobi_split_dev(h->n, h->rp, h->ci, h->va, split_val, h->pd, h->pe, h->stream);
+        h->va = split_val;
+    }
     Sell<double> A64 = make_sell<double, double>(h->n, h->rp, h->ci, h->va, h->stream);
     // the mixed form keeps a full FP64 engine for the FP64 fallback
     h->e64.alloc(h->n, s, ell, A64, true, h->pkey, h->stream, &h->prof);
+    h->e64.replace_every = h->opt.replace_every;
     if (h->opt.precision == MSTAB_PREC_F32_MATRIX) {
         h->e64.A_low = make_sell<float, double>(h->n, h->rp, h->ci, h->va, h->stream, &A64);
         h->e64.use_low = true;
@@ -1229,17 +1302,21 @@ mstab_status mstab_create(const mstab_csr *A, int32_t s, int32_t ell, const msta
         h->e32.refresh_v = true;
     }
     HIPCHK(hipStreamSynchronize(h->stream));
+    // the device copies hold the split values; the handle keeps the caller's arrays
+    (void)hipFree(h->split_tmp);
+    h->split_tmp = nullptr;
+    h->va = A->val;
     *out = h;
     return MSTAB_OK;
     }
     catch (const StatusError &e) {
         mstab_status st = record(h, e);
-        if (h) { h->e64.release(); h->e32.release(); (void)hipFree(h->r32); (void)hipFree(h->xbak); h->prof.destroy(); delete h; }
+        release_handle(h);
         return st;
     }
     catch (const HipError &e) {
         mstab_status st = record_hip(h, e);
-        if (h) { h->e64.release(); h->e32.release(); (void)hipFree(h->r32); (void)hipFree(h->xbak); h->prof.destroy(); delete h; }
+        release_handle(h);
         return (e.e == hipErrorOutOfMemory) ? MSTAB_E_NOMEM : st;
     }
     catch (const std::bad_alloc &) {
@@ -1253,7 +1330,26 @@ mstab_status mstab_solve_next(mstab_solver *h, const double *b, double *x, mstab
     if (!h) { g_tls_error = "handle is NULL"; return MSTAB_E_INVALID; }
     API_BEGIN
     if (!b || !x) fail(MSTAB_E_INVALID, "b or x is NULL");
-    return h->mixed() ? solve_mixed(h, b, x, info, 0, 0) : solve_f64(h, b, x, info, 0, 0);
+    if (!h->pd)
+        return h->mixed() ? solve_mixed(h, b, x, info, 0, 0) : solve_f64(h, b, x, info, 0, 0);
+    // split system: L^-1 b, y0 = R x0; afterwards x = R^-1 y (also after a failure)
+    const int grid = grid1(h->n);
+    hipLaunchKernelGGL(k_mul, dim3(grid), dim3(BLOCK), 0, h->stream, h->n, b, h->pd, h->bhat);
+    HIPCHK(hipGetLastError());
+    hipLaunchKernelGGL(k_mul, dim3(grid), dim3(BLOCK), 0, h->stream, h->n, x, h->pe, x);
+    HIPCHK(hipGetLastError());
+    mstab_status st;
+    try {
+        st = h->mixed() ? solve_mixed(h, h->bhat, x, info, 0, 0)
+                        : solve_f64(h, h->bhat, x, info, 0, 0);
+    } catch (...) {
+        hipLaunchKernelGGL(k_mul, dim3(grid), dim3(BLOCK), 0, h->stream, h->n, x, h->pd, x);
+        throw;
+    }
+    hipLaunchKernelGGL(k_mul, dim3(grid), dim3(BLOCK), 0, h->stream, h->n, x, h->pd, x);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return st;
     API_END(h)
 }
 
@@ -1263,6 +1359,7 @@ mstab_status mstab_solve_next_guess(mstab_solver *h, const double *b, const doub
     if (!h) { g_tls_error = "handle is NULL"; return MSTAB_E_INVALID; }
     API_BEGIN
     if (!b || !x_prev || !x_guess || !x) fail(MSTAB_E_INVALID, "NULL vector");
+    if (h->pd) fail(MSTAB_E_INVALID, "guess gate on a preconditioned handle");
     Engine<double> &E = h->e64;
     E.small(SMALL_CLEAR);
     HIPCHK(hipMemcpyAsync(E.X, x_guess, sizeof(double) * h->n, hipMemcpyDeviceToDevice, h->stream));
@@ -1288,6 +1385,7 @@ mstab_status mstab_residual(mstab_solver *h, const double *b, const double *x, d
     API_BEGIN
     if (!b || !x || !r) fail(MSTAB_E_INVALID, "NULL vector");
     if (r == b || r == x) fail(MSTAB_E_INVALID, "r must not alias b or x");
+    if (h->pd) fail(MSTAB_E_INVALID, "residual on a preconditioned handle");
     Engine<double> &E = h->e64;
     E.small(SMALL_CLEAR);
     E.spmv(x, r, b, ACT_TRUE, 0, 0);
@@ -1374,14 +1472,7 @@ mstab_status mstab_recycle_set(mstab_solver *h, const double *U, const double *V
 
 mstab_status mstab_destroy(mstab_solver *h)
 {
-    if (!h) return MSTAB_OK;
-    (void)hipStreamSynchronize(h->stream);
-    h->e64.release();
-    h->e32.release();
-    (void)hipFree(h->r32);
-    (void)hipFree(h->xbak);
-    h->prof.destroy();
-    delete h;
+    release_handle(h);
     return MSTAB_OK;
 }
 
@@ -1460,6 +1551,38 @@ struct Scratch {
 }  // namespace
 
 extern "C" {
+
+mstab_status mstab_jacobi_split(const mstab_csr *A, double *val_out, double *d, double *e,
+                                void *hip_stream)
+{
+    double *td = nullptr, *te = nullptr;
+    API_BEGIN
+    if (!A || !A->row_ptr || !A->col_idx || !A->val || !val_out) fail(MSTAB_E_INVALID, "NULL pointer");
+    if (A->n < 0 || A->n >= ((int64_t)1 << 29) || A->nnz < 0 || A->nnz >= ((int64_t)1 << 31))
+        fail(MSTAB_E_INVALID, "size out of range");
+    if (A->n == 0) return MSTAB_OK;
+    hipStream_t st = (hipStream_t)hip_stream;
+    if (!d) HIPCHK(hipMalloc(&td, sizeof(double) * (size_t)A->n));
+    if (!e) HIPCHK(hipMalloc(&te, sizeof(double) * (size_t)A->n));
+    jacobi_split_dev(A->n, A->row_ptr, A->col_idx, A->val, val_out, d ? d : td, e ? e : te, st);
+    HIPCHK(hipStreamSynchronize(st));
+    (void)hipFree(td);
+    (void)hipFree(te);
+    return MSTAB_OK;
+    }
+    catch (const StatusError &ex) {
+        (void)hipFree(td);
+        (void)hipFree(te);
+        g_tls_error = ex.msg;
+        return ex.st;
+    }
+    catch (const HipError &ex) {
+        (void)hipFree(td);
+        (void)hipFree(te);
+        mstab_status stt = record_hip(nullptr, ex);
+        return (ex.e == hipErrorOutOfMemory) ? MSTAB_E_NOMEM : stt;
+    }
+}
 
 mstab_status mstab_spmv(const mstab_csr *A, const double *x, double *y, void *hip_stream)
 {

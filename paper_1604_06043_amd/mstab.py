@@ -19,6 +19,7 @@ LIB_PATH = os.environ.get("MSTAB_LIBRARY") or os.path.join(HERE, "libmstab.so")
 OK, NOT_CONVERGED, E_INVALID, E_HIP, E_NOMEM, E_BREAKDOWN, E_NONFINITE = 0, 1, -1, -2, -3, -4, -5
 METHOD_MSTAB, METHOD_IDRSTAB = 0, 1
 PREC_F64, PREC_F32_REFINE, PREC_F32_MATRIX = 0, 1, 2
+PRECOND_NONE, PRECOND_JACOBI = 0, 1
 FETCH_THRESHOLD, FETCH_AT_LEVEL, FETCH_AT_END, FETCH_ONCE, FETCH_NEVER = 0, 1, 2, 3, 4
 K_SPMV, K_GAMMA, K_ETA, K_GRAM, K_POLY = 0, 1, 2, 3, 4
 KERNEL_CLASSES = {"spmv": K_SPMV, "gamma": K_GAMMA, "eta": K_ETA, "gram": K_GRAM, "poly": K_POLY}
@@ -29,7 +30,7 @@ EXPORTS = [
     "mstab_mv_count", "mstab_residual", "mstab_residual_history", "mstab_recycle_reset", "mstab_recycle_get",
     "mstab_recycle_set", "mstab_destroy", "mstab_status_str", "mstab_last_error",
     "mstab_set_profiling", "mstab_kernel_stats", "mstab_convdiff_nnz", "mstab_assemble_convdiff",
-    "mstab_spmv", "mstab_project", "mstab_rhs_step",
+    "mstab_jacobi_split", "mstab_spmv", "mstab_project", "mstab_rhs_step",
     "mstab_cnn_param_count", "mstab_cnn_create", "mstab_cnn_destroy", "mstab_cnn_set_params",
     "mstab_cnn_get_params", "mstab_cnn_prepare", "mstab_cnn_forward", "mstab_cnn_gradient",
     "mstab_cnn_adam_step", "mstab_cnn_guess", "mstab_cnn_tensor", "mstab_cnn_last_error",
@@ -47,7 +48,8 @@ class mstab_options(ctypes.Structure):
                 ("precision", ctypes.c_int32), ("fetch", ctypes.c_int32),
                 ("fetch_rel", ctypes.c_double), ("fetch_level", ctypes.c_int64),
                 ("p_seed", ctypes.c_uint64), ("max_replacements", ctypes.c_int32),
-                ("inner_tol", ctypes.c_double), ("max_refinements", ctypes.c_int32)]
+                ("inner_tol", ctypes.c_double), ("max_refinements", ctypes.c_int32),
+                ("precond", ctypes.c_int32), ("replace_every", ctypes.c_int32)]
 
 
 class mstab_info(ctypes.Structure):
@@ -98,6 +100,7 @@ def load(path: str = LIB_PATH):
                                      ctypes.POINTER(f64)]),
         "mstab_convdiff_nnz": (i64, [i32, i64]),
         "mstab_assemble_convdiff": (i32, [i32, i64, P, f64, P, P, P, P, P]),
+        "mstab_jacobi_split": (i32, [ctypes.POINTER(mstab_csr), P, P, P, P]),
         "mstab_spmv": (i32, [ctypes.POINTER(mstab_csr), P, P, P]),
         "mstab_project": (i32, [i64, i32, u64, P, P, P]),
         "mstab_rhs_step": (i32, [i64, P, f64, P, P, P]),
@@ -197,6 +200,15 @@ def mstab_assemble_convdiff(dim: int, n: int, beta, inv_dt: float, kappa=None, s
     _check(load().mstab_assemble_convdiff(dim, n, ctypes.cast(b3, ctypes.c_void_p), float(inv_dt),
                                           _ptr(kappa), _ptr(rp), _ptr(ci), _ptr(va), _stream(stream)))
     return CSR(rp, ci, va)
+
+
+def mstab_jacobi_split(A: CSR, val_out, d=None, e=None, stream=None):
+    """Values of L^-1 A R^-1 (L = R = |diag A|^1/2) into val_out; d, e optional."""
+    _require_cuda(val_out, *(t for t in (d, e) if t is not None))
+    st = A.struct()
+    _check(load().mstab_jacobi_split(ctypes.byref(st), _ptr(val_out), _ptr(d), _ptr(e),
+                                     _stream(stream)))
+    return val_out
 
 
 def mstab_spmv(A: CSR, x, y, stream=None):

@@ -4,6 +4,7 @@
     python -m paper_1604_06043_amd.workloads c3      # 256^3, lognormal kappa, s=8, l=4, 20 RHS
     python -m paper_1604_06043_amd.workloads c5      # 4M-row random geometric graph, 100 RHS
     python -m paper_1604_06043_amd.workloads fetch   # fetch policies of M(s)stab on 128^3 and 64^2
+    python -m paper_1604_06043_amd.workloads jacobi  # split diagonal preconditioning on c3 and c5
 
 Each prints one JSON line per measurement (systems/s and MVs/system of
 M(s)stab(l) and IDR(s)stab(l), FP64 and FP32 + FP64 refinement, and the
@@ -106,6 +107,27 @@ def compare(seq: Sequence, systems: int, s: int, ell: int, seed: int = 0, idr: b
     return out
 
 
+def jacobi_compare(seq: Sequence, systems: int, s: int, ell: int, seed: int = 0):
+    """M(s)stab and IDR(s)stab with and without the split diagonal preconditioning."""
+    out = {"workload": seq.name, "N": seq.N, "nnz": seq.A.nnz, "s": s, "ell": ell,
+           "systems": systems, "tol": 1e-8}
+    run(seq, 1, s, ell, seed=seed)
+    runs = [("mstab", M.METHOD_MSTAB, M.PREC_F64), ("idrstab", M.METHOD_IDRSTAB, M.PREC_F64),
+            ("mstab_f32_matrix", M.METHOD_MSTAB, M.PREC_F32_MATRIX),
+            ("idrstab_f32_matrix", M.METHOD_IDRSTAB, M.PREC_F32_MATRIX)]
+    for name, method, prec in runs:
+        variants = [(M.PRECOND_NONE, 0, "plain"), (M.PRECOND_JACOBI, 0, "jacobi")]
+        if prec == M.PREC_F64:
+            variants.append((M.PRECOND_JACOBI, 1, "jacobi_replace1"))
+        for pc, every, tag in variants:
+            t, mv, infos, _ = run(seq, systems, s, ell, method=method, precision=prec, seed=seed,
+                                  precond=pc, replace_every=every)
+            out[f"{name}_{tag}"] = {"systems_per_s": systems / t, "mvs_per_system": mv,
+                                    "max_relres_true": max(i["relres_true"] for i in infos)}
+            log(f"[{seq.name}] {name} {tag}: {systems / t:.2f} systems/s, {mv:.1f} MVs/system")
+    return out
+
+
 def convdiff_sequence(name: str, n: int | None = None, seed: int = 0) -> Sequence:
     import torch
     cd = I.config(name, seed=seed, n=n)
@@ -133,7 +155,7 @@ def rgg_sequence(N: int, seed: int = 0, systems: int = 100) -> Sequence:
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
-    ap.add_argument("which", choices=["sweep", "c3", "c5", "c2", "fetch"])
+    ap.add_argument("which", choices=["sweep", "c3", "c5", "c2", "fetch", "jacobi"])
     ap.add_argument("--n", type=int, default=None)
     ap.add_argument("--N", type=int, default=1 << 22)
     ap.add_argument("--systems", type=int, default=None)
@@ -171,6 +193,11 @@ def main():
         systems = a.systems or 100
         seq = rgg_sequence(a.N, 0, systems)
         print(json.dumps(compare(seq, systems, 4, 2)), flush=True)
+    elif a.which == "jacobi":
+        for seq, systems, s, ell in ((convdiff_sequence("c3", a.n), a.systems or 20, 8, 4),
+                                     (rgg_sequence(a.N, 0, a.systems or 100), a.systems or 100, 4, 2)):
+            print(json.dumps(jacobi_compare(seq, systems, s, ell)), flush=True)
+            del seq
 
 
 if __name__ == "__main__":

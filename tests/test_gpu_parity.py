@@ -643,3 +643,169 @@ def test_fresh_mstab_handle_is_idrstab(torch_dev, ms, orc):
     assert not ia["recycled"] and not ib["recycled"]
     np.testing.assert_array_equal(xa, xb)
     assert ia["mv_total"] == ib["mv_total"] and ha == hb
+
+
+# ---------------------------------------------------------------------------
+# Split diagonal preconditioning (Section 5.1's split form, L = R = |D|^1/2)
+# ---------------------------------------------------------------------------
+def jacobi_case(orc, kind, seed):
+    if kind == "c3":
+        cd = I.config("c3", seed=seed, n=20)
+        return orc.assemble_convdiff(cd.dim, cd.n, cd.beta, cd.inv_dt, cd.kappa)
+    g = I.rgg(20000, seed)
+    return orc.CSR(g.row_ptr, g.col, g.val)
+
+
+@pytest.mark.parametrize("kind,seed", [("c3", 2), ("graph", 3)])
+def test_jacobi_split_bit_exact(torch_dev, ms, orc, kind, seed):
+    """d = 1/sqrt|a_ii|, e = sqrt|a_ii| and (a_ij d_i) d_j: each correctly
+    rounded on both sides, so bit for bit."""
+    torch = torch_dev
+    Ao = jacobi_case(orc, kind, seed)
+    Ag = upload_csr(torch, ms, Ao)
+    val = torch.empty(Ao.nnz, dtype=torch.float64, device="cuda")
+    d = torch.empty(Ao.n, dtype=torch.float64, device="cuda")
+    e = torch.empty_like(d)
+    ms.mstab_jacobi_split(Ag, val, d, e)
+    Ah, do, eo = orc.jacobi_split(Ao)
+    np.testing.assert_array_equal(val.cpu().numpy(), Ah.val)
+    np.testing.assert_array_equal(d.cpu().numpy(), do)
+    np.testing.assert_array_equal(e.cpu().numpy(), eo)
+
+
+def test_jacobi_split_rejects_zero_diagonal(torch_dev, ms, orc):
+    torch = torch_dev
+    # 5 x 5: row 2 stores (2, 3) but no diagonal entry
+    rp = np.array([0, 1, 2, 3, 4, 5], dtype=np.int32)
+    ci = np.array([0, 1, 3, 3, 4], dtype=np.int32)
+    va = np.array([1.0, 2.0, 1.0, 4.0, 5.0])
+    Ag = upload_csr(torch, ms, orc.CSR(rp, ci, va))
+    out = torch.empty(5, dtype=torch.float64, device="cuda")
+    with pytest.raises(ms.MstabError, match="diagonal"):
+        ms.mstab_jacobi_split(Ag, out)
+    with pytest.raises(ms.MstabError, match="diagonal"):
+        ms.Solver(Ag, 2, 1, precond=ms.PRECOND_JACOBI)
+
+
+@pytest.mark.parametrize("name,n,seed,s,ell,method,every", [
+    ("c3", 14, 4, 8, 4, 0, 1), ("c3", 16, 1, 4, 2, 0, 0), ("c3", 16, 1, 4, 2, 1, 0),
+    ("c3", 16, 1, 4, 2, 0, 1), ("c1", 48, 2, 4, 2, 0, 0), ("c1", 48, 2, 2, 1, 0, 2)])
+def test_jacobi_teacher_forced(torch_dev, ms, orc, name, n, seed, s, ell, method, every):
+    """The split system system by system from the oracle's x^(i) and recycled
+    U, V (in the split space): the bar of the unpreconditioned solves.
+    every = k > 0: the residual is also replaced after every k-th cycle.  (At
+    s = 8, l = 4 the recycled starts of this matrix leave the recursive
+    residual 1e4 below the true one; the per-cycle replacement that the paper
+    pairs with the split system removes that gap.)"""
+    torch = torch_dev
+    print(f"[jacobi teacher-forced {name} n={n} s={s} l={ell} method={method} every={every}]",
+          flush=True)
+    cd = I.config(name, seed=seed, n=n)
+    Ao = orc.assemble_convdiff(cd.dim, cd.n, cd.beta, cd.inv_dt, cd.kappa)
+    Ag = gpu_assemble(ms, cd)
+    split = orc.jacobi_split(Ao)
+    P = I.p_dense(seed, cd.N, s)
+    solver = ms.Solver(Ag, s, ell, p_seed=seed, method=method, precond=ms.PRECOND_JACOBI,
+                       replace_every=every)
+    xo = np.zeros(cd.N)
+    rec = orc.Recycle.empty(cd.N, s)
+    errs, mvs = [], []
+    for k in range(6):
+        b = orc.rhs_step(xo, cd.inv_dt, cd.f)
+        if method == 0 and rec.have:
+            solver.recycle_set(dev(torch, rec.U.T), dev(torch, rec.V.T), rec.level)
+        else:
+            solver.recycle_reset()
+        x = dev(torch, xo)
+        ig = solver.solve_next(dev(torch, b), x)
+        with orc.reversed_sums():
+            xr, ir, _, _ = orc.solve_jacobi(Ao, b, xo, s, ell, P, split=split, recycle=rec.copy(),
+                                            method=method, replace_every=every)
+        xn, io, rec, _ = orc.solve_jacobi(Ao, b, xo, s, ell, P, split=split, recycle=rec,
+                                          method=method, replace_every=every)
+        err = np.linalg.norm(x.cpu().numpy() - xn) / np.linalg.norm(xn)
+        sen = np.linalg.norm(xr - xn) / np.linalg.norm(xn)
+        errs.append(err)
+        mvs.append((ig["mv_total"], io.mv_total))
+        print(f"  system {k}: gpu status {ig['status']} mv {ig['mv_total']} cycles {ig['cycles']} "
+              f"repl {ig['replacements']} relres rec {ig['relres_recursive']:.2e} true "
+              f"{ig['relres_true']:.2e}; oracle mv {io.mv_total} cycles {io.cycles} "
+              f"true {io.relres_true:.2e}; err {err:.2e}", flush=True)
+        assert ig["converged"] and io.converged
+        assert ig["recycled"] == io.recycled
+        if near_threshold(io) or ir.mv_total != io.mv_total or sen > 1e-10:
+            assert abs(ig["cycles"] - io.cycles) <= 1
+            assert err <= 10 * 1e-8
+        else:
+            assert err <= max(1e-9, 10 * sen), (k, err, sen, errs)
+            assert ig["mv_total"] == io.mv_total, (k, ig, io)
+            assert ig["replacements"] == io.replacements, (k, ig, io)
+        xo = xn
+    print("  rel err per system", ["%.1e" % e for e in errs], "MVs (gpu, oracle)", mvs)
+
+
+def test_jacobi_free_running_c3(torch_dev, ms, orc):
+    """Variable diffusion, each side on its own: the free-running bar, and x
+    meets the tolerance on the preconditioned residual L^-1 (b - A x) of the
+    original systems."""
+    torch = torch_dev
+    cd = I.config("c3", seed=0, n=24)
+    s, ell, systems = 4, 2, 6
+    Ao = orc.assemble_convdiff(cd.dim, cd.n, cd.beta, cd.inv_dt, cd.kappa)
+    Ag = gpu_assemble(ms, cd)
+    xs_g, inf_g, _ = run_sequence_gpu(torch, ms, Ag, cd, s, ell, systems, 0,
+                                      precond=ms.PRECOND_JACOBI)
+    P = I.p_dense(0, cd.N, s)
+    xs_o, inf_o = orc.solve_sequence(Ao, cd.f, cd.inv_dt, s, ell, P, systems, jacobi=True)
+    compare_free(xs_g, inf_g, xs_o, inf_o, ell * (s + 1))
+    _, inf_p, _ = run_sequence_gpu(torch, ms, Ag, cd, s, ell, systems, 0)
+    d = orc.jacobi_split(Ao)[1]
+    for k, xg in enumerate(xs_g):
+        b = xs_g[k - 1] * cd.inv_dt + cd.f if k else cd.f
+        rp = np.linalg.norm(d * (b - orc.spmv(Ao, xg))) / np.linalg.norm(d * b)
+        assert rp <= 1e-8 * (1 + 1e-6)
+    mj = sum(i["mv_total"] for i in inf_g)
+    mp = sum(i["mv_total"] for i in inf_p)
+    # a measurement, not a bar: the two stop on different residuals
+    print(f"  MVs over {systems} systems: split {mj}, plain {mp}")
+
+
+@pytest.mark.parametrize("precision", ["F32_MATRIX", "F32_REFINE"])
+def test_jacobi_mixed_precision(torch_dev, ms, orc, precision):
+    torch = torch_dev
+    cd = I.config("c3", seed=0, n=24)
+    s, ell, systems = 8, 4, 4
+    Ao = orc.assemble_convdiff(cd.dim, cd.n, cd.beta, cd.inv_dt, cd.kappa)
+    Ag = gpu_assemble(ms, cd)
+    prec = getattr(ms, "PREC_" + precision)
+    xs_g, inf_g, _ = run_sequence_gpu(torch, ms, Ag, cd, s, ell, systems, 0, precision=prec,
+                                      precond=ms.PRECOND_JACOBI)
+    P = I.p_dense(0, cd.N, s)
+    xs_o, _ = orc.solve_sequence(Ao, cd.f, cd.inv_dt, s, ell, P, systems, jacobi=True)
+    Ah, d, _ = orc.jacobi_split(Ao)
+    kappa = np.linalg.cond(Ah.dense())
+    for k, (xg, ig, xo) in enumerate(zip(xs_g, inf_g, xs_o)):
+        b = xs_g[k - 1] * cd.inv_dt + cd.f if k else cd.f
+        rp = np.linalg.norm(d * (b - orc.spmv(Ao, xg))) / np.linalg.norm(d * b)
+        err = np.linalg.norm(xg - xo) / np.linalg.norm(xo)
+        print(f"  system {k}: preconditioned true relres {rp:.2e}, vs FP64 oracle {err:.2e}, "
+              f"MVs {ig['mv_total']}, FP64-matrix products {ig['mv_f64']}")
+        assert ig["converged"] and rp <= 1e-8 * (1 + 1e-6)
+        assert err <= 2 * kappa * 1e-8
+
+
+def test_jacobi_handle_rejects_guess_and_residual(torch_dev, ms, orc):
+    torch = torch_dev
+    cd = I.config("c1", seed=0, n=24)
+    Ag = gpu_assemble(ms, cd)
+    solver = ms.Solver(Ag, 2, 1, precond=ms.PRECOND_JACOBI)
+    b = dev(torch, cd.f)
+    x = torch.zeros_like(b)
+    r = torch.empty_like(b)
+    with pytest.raises(ms.MstabError, match="preconditioned"):
+        solver.residual(b, x, r)
+    with pytest.raises(ms.MstabError, match="preconditioned"):
+        solver.solve_next_guess(b, x, x.clone(), x)
+    # the handle still solves
+    assert solver.solve_next(b, x)["converged"]
+    solver.close()
