@@ -184,7 +184,7 @@ def main():
         dom = max(stats, key=lambda c: stats[c][1])
         n, msec, by = stats[dom]
         achieved = by / (msec * 1e-3) / 1e9
-        traffic = measured_traffic(f"k_spmv_dia<double, {s}>") if dom == "spmv" else None
+        traffic = measured_traffic(f"k_spmv_dia<double, {s}, double>") if dom == "spmv" else None
         roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
                     "timed": f"1 launch in {EVENT_PERIOD} of each kernel class, HIP events on the solver stream",
                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
