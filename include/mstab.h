@@ -138,6 +138,8 @@ typedef struct {
 
 typedef struct mstab_solver mstab_solver;
 
+#define MSTAB_MAX_BATCH 256   /* handles per mstab_solve_batch call */
+
 /* Fill o with defaults.  Errors: E_INVALID if o is NULL. */
 mstab_status mstab_options_default(mstab_options *o);
 
@@ -161,6 +163,21 @@ mstab_status mstab_create(const mstab_csr *A, int32_t s, int32_t ell, const msta
  * y0 = R x0, iterates on the split system and returns x = R^-1 y.
  */
 mstab_status mstab_solve_next(mstab_solver *h, const double *b, double *x, mstab_info *info);
+
+/*
+ * mstab_solve_next on count independent handles at once (count <= 256): one
+ * host thread per handle, each enqueueing on its handle's stream, so that
+ * the small kernels of several latency-bound sequences share the GPU (the
+ * sequences stay independent; handles on distinct streams run concurrently,
+ * handles on one stream in turn).  h, b, x: host arrays of count entries
+ * (b[i], x[i]: device, n_i doubles each, as for mstab_solve_next); info:
+ * NULL or count entries.  Handles must be distinct.  Returns the first
+ * negative status of any handle (mstab_last_error(NULL) names it), else
+ * NOT_CONVERGED if any did not converge, else OK; each handle's own status
+ * is in info[i].status and its error text in mstab_last_error(h[i]).
+ */
+mstab_status mstab_solve_batch(mstab_solver *const *h, int32_t count, const double *const *b,
+                               double *const *x, mstab_info *info);
 
 /*
  * As mstab_solve_next with an external initial guess: x_guess is used as x0

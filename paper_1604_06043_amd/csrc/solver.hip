@@ -22,6 +22,7 @@
 #include <functional>
 #include <new>
 #include <string>
+#include <thread>
 #include <vector>
 
 using namespace mstab;
@@ -903,6 +904,7 @@ struct mstab_solver {
     const int32_t *rp = nullptr, *ci = nullptr;
     const double *va = nullptr;
     hipStream_t stream = nullptr;
+    int device = 0;         // the HIP device current at create
     uint32_t pkey = 0;
     Engine<double> e64;
     Engine<float> e32;
@@ -1272,6 +1274,7 @@ mstab_status mstab_create(const mstab_csr *A, int32_t s, int32_t ell, const msta
     h->s = s; h->ell = ell; h->n = A->n; h->nnz = A->nnz;
     h->rp = A->row_ptr; h->ci = A->col_idx; h->va = A->val;
     h->stream = (hipStream_t)hip_stream;
+    HIPCHK(hipGetDevice(&h->device));
     h->pkey = p_key_from_seed(h->opt.p_seed);
     h->prof.init(h->stream);
     double *split_val = nullptr;   // L^-1 A R^-1, needed only while the device copies are built
@@ -1351,6 +1354,53 @@ mstab_status mstab_solve_next(mstab_solver *h, const double *b, double *x, mstab
     HIPCHK(hipStreamSynchronize(h->stream));
     return st;
     API_END(h)
+}
+
+mstab_status mstab_solve_batch(mstab_solver *const *h, int32_t count, const double *const *b,
+                               double *const *x, mstab_info *info)
+{
+    API_BEGIN
+    if (count < 0 || count > MSTAB_MAX_BATCH) fail(MSTAB_E_INVALID, "count=%d outside 0..%d", count, MSTAB_MAX_BATCH);
+    if (count == 0) return MSTAB_OK;
+    if (!h || !b || !x) fail(MSTAB_E_INVALID, "NULL array");
+    for (int i = 0; i < count; ++i) {
+        if (!h[i] || !b[i] || !x[i]) fail(MSTAB_E_INVALID, "NULL entry %d", i);
+        for (int j = 0; j < i; ++j)
+            if (h[j] == h[i]) fail(MSTAB_E_INVALID, "handle %d repeated", i);
+    }
+    std::vector<mstab_status> st((size_t)count, MSTAB_OK);
+    std::vector<std::thread> pool;
+    pool.reserve((size_t)count);
+    auto work = [&](int i) {
+        // each handle's calls run on its own host thread and stream
+        if (hipSetDevice(h[i]->device) != hipSuccess) {
+            h[i]->err = "hipSetDevice failed in a batch worker";
+            st[i] = MSTAB_E_HIP;
+            return;
+        }
+        st[i] = mstab_solve_next(h[i], b[i], x[i], info ? &info[i] : nullptr);
+    };
+    try {
+        for (int i = 1; i < count; ++i) pool.emplace_back(work, i);
+    } catch (...) {
+        for (auto &t : pool) t.join();
+        fail(MSTAB_E_NOMEM, "could not start %d host threads", count - 1);
+    }
+    work(0);
+    for (auto &t : pool) t.join();
+    mstab_status worst = MSTAB_OK;
+    for (int i = 0; i < count; ++i) {
+        if (st[i] < 0) {
+            if (worst >= 0) {
+                worst = st[i];
+                g_tls_error = "handle " + std::to_string(i) + ": " + h[i]->err;
+            }
+        } else if (st[i] == MSTAB_NOT_CONVERGED && worst == MSTAB_OK) {
+            worst = MSTAB_NOT_CONVERGED;
+        }
+    }
+    return worst;
+    API_END(nullptr)
 }
 
 mstab_status mstab_solve_next_guess(mstab_solver *h, const double *b, const double *x_prev,

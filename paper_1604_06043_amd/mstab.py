@@ -26,7 +26,8 @@ KERNEL_CLASSES = {"spmv": K_SPMV, "gamma": K_GAMMA, "eta": K_ETA, "gram": K_GRAM
 
 # functions declared in include/mstab.h
 EXPORTS = [
-    "mstab_options_default", "mstab_create", "mstab_solve_next", "mstab_solve_next_guess",
+    "mstab_options_default", "mstab_create", "mstab_solve_next", "mstab_solve_batch",
+    "mstab_solve_next_guess",
     "mstab_mv_count", "mstab_residual", "mstab_residual_history", "mstab_recycle_reset", "mstab_recycle_get",
     "mstab_recycle_set", "mstab_destroy", "mstab_status_str", "mstab_last_error",
     "mstab_set_profiling", "mstab_kernel_stats", "mstab_convdiff_nnz", "mstab_assemble_convdiff",
@@ -85,6 +86,8 @@ def load(path: str = LIB_PATH):
         "mstab_create": (i32, [ctypes.POINTER(mstab_csr), i32, i32, ctypes.POINTER(mstab_options), P,
                                ctypes.POINTER(P)]),
         "mstab_solve_next": (i32, [P, P, P, ctypes.POINTER(mstab_info)]),
+        "mstab_solve_batch": (i32, [ctypes.POINTER(P), i32, ctypes.POINTER(P), ctypes.POINTER(P),
+                                    ctypes.POINTER(mstab_info)]),
         "mstab_solve_next_guess": (i32, [P, P, P, P, P, ctypes.POINTER(mstab_info)]),
         "mstab_mv_count": (i32, [P, ctypes.POINTER(i64), ctypes.POINTER(i64)]),
         "mstab_residual": (i32, [P, P, P, P, ctypes.POINTER(f64)]),
@@ -200,6 +203,25 @@ def mstab_assemble_convdiff(dim: int, n: int, beta, inv_dt: float, kappa=None, s
     _check(load().mstab_assemble_convdiff(dim, n, ctypes.cast(b3, ctypes.c_void_p), float(inv_dt),
                                           _ptr(kappa), _ptr(rp), _ptr(ci), _ptr(va), _stream(stream)))
     return CSR(rp, ci, va)
+
+
+def solve_batch(solvers, bs, xs) -> list:
+    """mstab_solve_batch: the next system of each solver at once (one host
+    thread per solver); returns the info dicts.  Give each solver its own
+    stream for the solves to overlap."""
+    n = len(solvers)
+    if not (len(bs) == len(xs) == n):
+        raise ValueError("solvers, bs and xs differ in length")
+    _require_cuda(*bs, *xs)
+    P = ctypes.c_void_p
+    hs = (P * n)(*[sv.h for sv in solvers])
+    bp = (P * n)(*[b.data_ptr() for b in bs])
+    xp = (P * n)(*[x.data_ptr() for x in xs])
+    infos = (mstab_info * n)()
+    lib = load()
+    st = lib.mstab_solve_batch(hs, n, bp, xp, infos)
+    _check(st, None, allow=(OK, NOT_CONVERGED))
+    return [i.as_dict() for i in infos]
 
 
 def mstab_jacobi_split(A: CSR, val_out, d=None, e=None, stream=None):

@@ -1,10 +1,12 @@
 """Measurements of the solver on the sequence workloads beside the main bench.
 
     python -m paper_1604_06043_amd.workloads sweep   # 128^3, s in {2,4,8}, l in {1,2,4}
+    python -m paper_1604_06043_amd.workloads c1      # 64^2 (latency-bound), s=4, l=2, 10 RHS
     python -m paper_1604_06043_amd.workloads c3      # 256^3, lognormal kappa, s=8, l=4, 20 RHS
     python -m paper_1604_06043_amd.workloads c5      # 4M-row random geometric graph, 100 RHS
     python -m paper_1604_06043_amd.workloads fetch   # fetch policies of M(s)stab on 128^3 and 64^2
     python -m paper_1604_06043_amd.workloads jacobi  # split diagonal preconditioning on c3 and c5
+    python -m paper_1604_06043_amd.workloads batch   # B independent 64^2 sequences solved together
 
 Each prints one JSON line per measurement (systems/s and MVs/system of
 M(s)stab(l) and IDR(s)stab(l), FP64 and FP32 + FP64 refinement, and the
@@ -128,6 +130,36 @@ def jacobi_compare(seq: Sequence, systems: int, s: int, ell: int, seed: int = 0)
     return out
 
 
+def batch_throughput(B: int, systems: int = 10, n: int = 64, s: int = 4, ell: int = 2):
+    """B independent c1-type sequences (seeds 0..B-1), each on its own handle
+    and stream, advanced together by mstab_solve_batch; aggregate systems/s."""
+    import torch
+    cds = [I.config("c1", seed=k, n=n) for k in range(B)]
+    mats = []
+    for cd in cds:
+        mats.append(M.mstab_assemble_convdiff(cd.dim, cd.n, cd.beta, cd.inv_dt, None))
+    streams = [torch.cuda.Stream() for _ in range(B)]
+    solvers = [M.Solver(A, s, ell, p_seed=0, stream=st) for A, st in zip(mats, streams)]
+    fs = [torch.tensor(cd.f, device="cuda") for cd in cds]
+    xs = [torch.zeros(cd.N, dtype=torch.float64, device="cuda") for cd in cds]
+    bs = [torch.empty_like(x) for x in xs]
+    torch.cuda.synchronize()
+    mv, t0 = 0, time.perf_counter()
+    for _ in range(systems):
+        for i in range(B):
+            M.mstab_rhs_step(xs[i], cds[i].inv_dt, fs[i], bs[i])
+        infos = M.solve_batch(solvers, bs, xs)
+        if not all(i["converged"] for i in infos):
+            raise RuntimeError("a batched system did not converge")
+        mv += sum(i["mv_total"] for i in infos)
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    for sv in solvers:
+        sv.close()
+    return {"workload": f"c1_n{n}", "sequences": B, "systems_each": systems, "s": s, "ell": ell,
+            "systems_per_s": B * systems / sec, "mvs_per_system": mv / (B * systems)}
+
+
 def convdiff_sequence(name: str, n: int | None = None, seed: int = 0) -> Sequence:
     import torch
     cd = I.config(name, seed=seed, n=n)
@@ -155,7 +187,7 @@ def rgg_sequence(N: int, seed: int = 0, systems: int = 100) -> Sequence:
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
-    ap.add_argument("which", choices=["sweep", "c3", "c5", "c2", "fetch", "jacobi"])
+    ap.add_argument("which", choices=["sweep", "c1", "c3", "c5", "c2", "fetch", "jacobi", "batch"])
     ap.add_argument("--n", type=int, default=None)
     ap.add_argument("--N", type=int, default=1 << 22)
     ap.add_argument("--systems", type=int, default=None)
@@ -169,6 +201,17 @@ def main():
         for s in (2, 4, 8):
             for ell in (1, 2, 4):
                 print(json.dumps(compare(seq, systems, s, ell, mixed=False)), flush=True)
+    elif a.which == "batch":
+        import os
+        for B in (1, 2, 4, 8, 16, 32):
+            batch_throughput(B, 2)   # warm-up
+            r = batch_throughput(B, a.systems or 10)
+            r["gpu_max_hw_queues"] = os.environ.get("GPU_MAX_HW_QUEUES", "default")
+            log(f"[batch] {B} sequences: {r['systems_per_s']:.0f} systems/s, {r['mvs_per_system']:.1f} MVs/system")
+            print(json.dumps(r), flush=True)
+    elif a.which == "c1":
+        seq = convdiff_sequence("c1", a.n)
+        print(json.dumps(compare(seq, a.systems or 10, 4, 2, mixed=False)), flush=True)
     elif a.which == "c2":
         seq = convdiff_sequence("c2", a.n)
         print(json.dumps(compare(seq, a.systems or 50, 4, 2)), flush=True)

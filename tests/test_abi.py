@@ -89,3 +89,14 @@ def test_struct_layouts_match_header(tmp_path):
         assert int(out[name]) == ctypes.sizeof(cls), name
         for f, _ in cls._fields_:
             assert int(out[f"{name}.{f}"]) == getattr(cls, f).offset, (name, f)
+
+
+def test_solve_batch_rejects_bad_arguments_without_a_device(lib):
+    P = ctypes.c_void_p
+    assert lib.mstab_solve_batch(None, 0, None, None, None) == mstab.OK
+    assert lib.mstab_solve_batch(None, -1, None, None, None) == mstab.E_INVALID
+    assert lib.mstab_solve_batch(None, 257, None, None, None) == mstab.E_INVALID
+    assert lib.mstab_solve_batch(None, 2, None, None, None) == mstab.E_INVALID
+    nulls = (P * 2)(None, None)
+    assert lib.mstab_solve_batch(nulls, 2, nulls, nulls, None) == mstab.E_INVALID
+    assert b"NULL entry" in lib.mstab_last_error(None)

@@ -809,3 +809,35 @@ def test_jacobi_handle_rejects_guess_and_residual(torch_dev, ms, orc):
     # the handle still solves
     assert solver.solve_next(b, x)["converged"]
     solver.close()
+
+
+def test_batch_matches_sequential(torch_dev, ms, orc):
+    """Independent sequences solved together (one host thread and stream per
+    handle) give the same x bit for bit, and the same MV counts, as the same
+    sequences solved one after another."""
+    torch = torch_dev
+    B, systems, s, ell = 6, 4, 4, 2
+    cds = [I.config("c1", seed=k, n=48) for k in range(B)]
+    mats = [gpu_assemble(ms, cd) for cd in cds]
+    ref = [run_sequence_gpu(torch, ms, A, cd, s, ell, systems, 0) for cd, A in zip(cds, mats)]
+    streams = [torch.cuda.Stream() for _ in range(B)]
+    solvers = [ms.Solver(A, s, ell, p_seed=0, method=0, stream=st) for A, st in zip(mats, streams)]
+    xs = [torch.zeros(cd.N, dtype=torch.float64, device="cuda") for cd in cds]
+    bs = [torch.empty_like(x) for x in xs]
+    fs = [dev(torch, cd.f) for cd in cds]
+    torch.cuda.synchronize()
+    for k in range(systems):
+        for i in range(B):
+            ms.mstab_rhs_step(xs[i], cds[i].inv_dt, fs[i], bs[i])
+        infos = ms.solve_batch(solvers, bs, xs)
+        for i in range(B):
+            np.testing.assert_array_equal(xs[i].cpu().numpy(), ref[i][0][k])
+            assert infos[i]["mv_total"] == ref[i][1][k]["mv_total"]
+            assert infos[i]["converged"] and infos[i]["status"] == 0
+    for sv in solvers:
+        sv.close()
+    # a repeated handle is rejected before any work
+    sv = ms.Solver(mats[0], s, ell)
+    with pytest.raises(ms.MstabError, match="repeated"):
+        ms.solve_batch([sv, sv], bs[:2], xs[:2])
+    sv.close()
