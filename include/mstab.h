@@ -83,6 +83,18 @@ typedef enum {
                                   finite, nonzero diagonal entry (else E_INVALID at create). */
 } mstab_precond;
 
+typedef enum {
+    MSTAB_REORDER_NONE = 0,    /* iterate in the caller's row order */
+    MSTAB_REORDER_RCM = 1      /* iterate on P A P^T with P the reverse Cuthill-McKee order of A's
+                                  symmetrized pattern (mstab_rcm_order, computed on the host at
+                                  create): neighbouring unknowns get nearby indices, so the
+                                  product's gathers of x stay in cache.  b and x keep the caller's
+                                  order; the cut-space basis, the residual history and recycled
+                                  U, V (recycle_get/set) refer to the reordered rows
+                                  (mstab_permutation gives the order).  Applied before
+                                  PRECOND_JACOBI. */
+} mstab_reorder;
+
 /* CSR matrix; all arrays are device pointers, n rows, nnz entries. */
 typedef struct {
     int64_t n;
@@ -113,6 +125,7 @@ typedef struct {
                                   do not count against max_replacements.  Default 0 (only the
                                   final replacements).  F32_REFINE replaces after every cycle
                                   by construction and ignores it. */
+    int32_t reorder;           /* mstab_reorder; default NONE */
 } mstab_options;
 
 typedef struct {
@@ -184,7 +197,7 @@ mstab_status mstab_solve_batch(mstab_solver *const *h, int32_t count, const doub
  * only if ||b - A x_guess|| < ||b - A x_prev|| (two counted check MVs),
  * otherwise x_prev is.  (b, x_prev, x_guess, x: device, n doubles; x may alias
  * x_prev or x_guess.)  info->guess_accepted reports the decision.
- * E_INVALID on a handle created with a preconditioner.
+ * E_INVALID on a handle created with a preconditioner or a reordering.
  */
 mstab_status mstab_solve_next_guess(mstab_solver *h, const double *b, const double *x_prev,
                                     const double *x_guess, double *x, mstab_info *info);
@@ -193,7 +206,8 @@ mstab_status mstab_solve_next_guess(mstab_solver *h, const double *b, const doub
  * r = b - A x with the handle's matrix and product kernel (device, n doubles
  * each; r must not alias b or x); norm2 (host, may be NULL) receives ||r||^2.
  * One product with A, counted in the handle's total (mstab_mv_count) but not
- * in any solve's info.  E_INVALID on a handle created with a preconditioner.
+ * in any solve's info.  E_INVALID on a handle created with a preconditioner or a
+ * reordering.
  */
 mstab_status mstab_residual(mstab_solver *h, const double *b, const double *x, double *r,
                             double *norm2);
@@ -272,6 +286,26 @@ int64_t mstab_convdiff_nnz(int32_t dim, int64_t n);
 mstab_status mstab_assemble_convdiff(int32_t dim, int64_t n, const double *beta, double inv_dt,
                                      const double *kappa, int32_t *row_ptr, int32_t *col_idx,
                                      double *val, void *hip_stream);
+
+/*
+ * perm (host, n int32) receives the handle's row order: perm[new] = old, the
+ * identity without MSTAB_REORDER_RCM.  Errors: E_INVALID, E_HIP.
+ */
+mstab_status mstab_permutation(const mstab_solver *h, int32_t *perm);
+
+/*
+ * Reverse Cuthill-McKee order of the symmetrized pattern (A + A^T, diagonal
+ * ignored) of an n-row CSR matrix given in host memory: perm (host, n int32)
+ * receives perm[new] = old.  Each connected component (taken in order of its
+ * lowest-degree node) is searched breadth-first from a pseudo-peripheral node
+ * (a minimum-degree node of the last level of a search from that node), each
+ * node's unvisited neighbours appended by increasing degree, then index; the
+ * order is then reversed.  Host only (no device work).  Errors: E_INVALID
+ * (n out of range, NULL, row_ptr not starting at 0 or decreasing, a column
+ * outside [0, n)).
+ */
+mstab_status mstab_rcm_order(int64_t n, const int32_t *row_ptr, const int32_t *col_idx,
+                             int32_t *perm);
 
 /*
  * The split diagonal preconditioning of MSTAB_PRECOND_JACOBI (Section 5.1's

@@ -197,6 +197,109 @@ inline int detect_diagonals(int64_t n, int64_t nnz, const int32_t *rp, const int
     return nd;
 }
 
+// Reverse Cuthill-McKee order of the symmetrized pattern of a CSR matrix
+// (host arrays): perm[new] = old.  Components are taken in order of their
+// lowest-degree unvisited node; each is searched breadth-first from a
+// minimum-degree node of the last level of a first search from that node (a
+// pseudo-peripheral start), neighbours appended in order of degree, then
+// index; the whole order is reversed at the end.
+std::vector<int32_t> rcm_order(int64_t n, const int32_t *rp, const int32_t *ci)
+{
+    std::vector<int64_t> start((size_t)n + 1, 0);
+    for (int64_t i = 0; i < n; ++i)
+        for (int32_t k = rp[i]; k < rp[i + 1]; ++k)
+            if (ci[k] != i) { ++start[i + 1]; ++start[(size_t)ci[k] + 1]; }
+    for (int64_t i = 0; i < n; ++i) start[i + 1] += start[i];
+    std::vector<int32_t> adj((size_t)start[n]);
+    {
+        std::vector<int64_t> fill(start.begin(), start.end() - 1);
+        for (int64_t i = 0; i < n; ++i)
+            for (int32_t k = rp[i]; k < rp[i + 1]; ++k)
+                if (ci[k] != i) {
+                    adj[(size_t)fill[i]++] = ci[k];
+                    adj[(size_t)fill[ci[k]]++] = (int32_t)i;
+                }
+    }
+    std::vector<int32_t> deg((size_t)n);
+    std::vector<int64_t> end((size_t)n);
+    for (int64_t i = 0; i < n; ++i) {
+        auto b = adj.begin() + start[i], e = adj.begin() + start[i + 1];
+        std::sort(b, e);
+        end[i] = start[i] + (std::unique(b, e) - b);
+        deg[i] = (int32_t)(end[i] - start[i]);
+    }
+    std::vector<int32_t> by_deg((size_t)n);
+    for (int64_t i = 0; i < n; ++i) by_deg[i] = (int32_t)i;
+    std::stable_sort(by_deg.begin(), by_deg.end(), [&](int32_t a, int32_t b) { return deg[a] < deg[b]; });
+    std::vector<int32_t> order;
+    order.reserve((size_t)n);
+    std::vector<int32_t> mark((size_t)n, -1);   // component of the first search
+    std::vector<char> seen((size_t)n, 0);
+    std::vector<int32_t> q, nb;
+    int32_t comp = 0;
+    for (int32_t s0 : by_deg) {
+        if (seen[s0]) continue;
+        // first search: its last level holds the pseudo-peripheral start
+        q.assign(1, s0);
+        mark[s0] = comp;
+        size_t head = 0, level_begin = 0;
+        while (head < q.size()) {
+            const size_t level_end = q.size();
+            level_begin = head;
+            for (; head < level_end; ++head) {
+                const int32_t v = q[head];
+                for (int64_t k = start[v]; k < end[v]; ++k)
+                    if (mark[adj[k]] != comp) { mark[adj[k]] = comp; q.push_back(adj[k]); }
+            }
+        }
+        int32_t root = q[level_begin];
+        for (size_t k = level_begin; k < q.size(); ++k)
+            if (deg[q[k]] < deg[root] || (deg[q[k]] == deg[root] && q[k] < root)) root = q[k];
+        ++comp;
+        // Cuthill-McKee search from the root
+        const size_t first = order.size();
+        order.push_back(root);
+        seen[root] = 1;
+        for (size_t h = first; h < order.size(); ++h) {
+            const int32_t v = order[h];
+            nb.clear();
+            for (int64_t k = start[v]; k < end[v]; ++k)
+                if (!seen[adj[k]]) { seen[adj[k]] = 1; nb.push_back(adj[k]); }
+            std::sort(nb.begin(), nb.end(), [&](int32_t a, int32_t b) {
+                return deg[a] != deg[b] ? deg[a] < deg[b] : a < b;
+            });
+            order.insert(order.end(), nb.begin(), nb.end());
+        }
+    }
+    std::reverse(order.begin(), order.end());
+    return order;
+}
+
+// dst[i] = src[perm[i]] (times w[i] if w), and its inverse dst[perm[i]] = src[i] (times w[i]).
+__global__ __launch_bounds__(BLOCK) void k_gather(int64_t n, const int32_t *__restrict__ perm,
+                                                  const double *__restrict__ src,
+                                                  const double *__restrict__ w,
+                                                  double *__restrict__ dst)
+{
+    for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * BLOCK) {
+        const double v = src[perm[i]];
+        dst[i] = w ? v * w[i] : v;
+    }
+}
+
+__global__ __launch_bounds__(BLOCK) void k_scatter(int64_t n, const int32_t *__restrict__ perm,
+                                                   const double *__restrict__ src,
+                                                   const double *__restrict__ w,
+                                                   double *__restrict__ dst)
+{
+    for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * BLOCK) {
+        const double v = src[i];
+        dst[perm[i]] = w ? v * w[i] : v;
+    }
+}
+
 // Split diagonal preconditioning: d, e (n doubles each) and the values of
 // L^-1 A R^-1 in A's pattern (val_out, nnz doubles).  E_INVALID if a row has
 // no stored, finite, nonzero diagonal entry.
@@ -913,6 +1016,11 @@ struct mstab_solver {
     // PRECOND_JACOBI: d = |diag A|^-1/2, e = |diag A|^1/2, and L^-1 b
     double *pd = nullptr, *pe = nullptr, *bhat = nullptr;
     double *split_tmp = nullptr;  // create only: the split values while the copies are built
+    // REORDER_RCM: perm[new] = old, the reordered CSR (its row pointer stays in
+    // use by the sliced product), and the reordered iterate
+    int32_t *perm = nullptr, *rp_perm = nullptr, *ci_perm = nullptr;
+    double *va_perm = nullptr, *xwork = nullptr;
+    bool transformed() const { return pd || perm; }
     Profiler prof;
     int64_t mv_total = 0, mv_last = 0;
     std::vector<int64_t> hist_mv;
@@ -951,6 +1059,11 @@ void release_handle(mstab_solver *h)
     (void)hipFree(h->pe);
     (void)hipFree(h->bhat);
     (void)hipFree(h->split_tmp);
+    (void)hipFree(h->perm);
+    (void)hipFree(h->rp_perm);
+    (void)hipFree(h->ci_perm);
+    (void)hipFree(h->va_perm);
+    (void)hipFree(h->xwork);
     h->prof.destroy();
     delete h;
 }
@@ -1271,18 +1384,69 @@ mstab_status mstab_create(const mstab_csr *A, int32_t s, int32_t ell, const msta
     if (h->opt.precond != MSTAB_PRECOND_NONE && h->opt.precond != MSTAB_PRECOND_JACOBI)
         fail(MSTAB_E_INVALID, "unknown preconditioner");
     if (h->opt.replace_every < 0) fail(MSTAB_E_INVALID, "replace_every < 0");
+    if (h->opt.reorder != MSTAB_REORDER_NONE && h->opt.reorder != MSTAB_REORDER_RCM)
+        fail(MSTAB_E_INVALID, "unknown reordering");
     h->s = s; h->ell = ell; h->n = A->n; h->nnz = A->nnz;
     h->rp = A->row_ptr; h->ci = A->col_idx; h->va = A->val;
     h->stream = (hipStream_t)hip_stream;
     HIPCHK(hipGetDevice(&h->device));
     h->pkey = p_key_from_seed(h->opt.p_seed);
     h->prof.init(h->stream);
+    if (h->opt.reorder == MSTAB_REORDER_RCM) {
+        // host: the order and the symmetrically permuted CSR (columns re-sorted)
+        const int64_t n = h->n;
+        std::vector<int32_t> rp((size_t)n + 1), ci((size_t)h->nnz);
+        std::vector<double> va((size_t)h->nnz);
+        HIPCHK(hipMemcpyAsync(rp.data(), h->rp, sizeof(int32_t) * (n + 1), hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(hipMemcpyAsync(ci.data(), h->ci, sizeof(int32_t) * h->nnz, hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(hipMemcpyAsync(va.data(), h->va, sizeof(double) * h->nnz, hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(hipStreamSynchronize(h->stream));
+        if (rp[0] != 0 || rp[n] != h->nnz) fail(MSTAB_E_INVALID, "row_ptr does not span nnz");
+        for (int64_t i = 0; i < n; ++i)
+            if (rp[i + 1] < rp[i]) fail(MSTAB_E_INVALID, "row_ptr decreases at row %lld", (long long)i);
+        for (int64_t k = 0; k < h->nnz; ++k)
+            if (ci[k] < 0 || ci[k] >= n) fail(MSTAB_E_INVALID, "column index out of range");
+        const std::vector<int32_t> perm = rcm_order(n, rp.data(), ci.data());
+        if ((int64_t)perm.size() != n) fail(MSTAB_E_INVALID, "reordering lost rows");
+        std::vector<int32_t> iperm((size_t)n);
+        for (int64_t i = 0; i < n; ++i) iperm[perm[i]] = (int32_t)i;
+        std::vector<int32_t> prp((size_t)n + 1), pci((size_t)h->nnz);
+        std::vector<double> pva((size_t)h->nnz);
+        std::vector<std::pair<int32_t, double>> row;
+        prp[0] = 0;
+        for (int64_t i = 0; i < n; ++i) {
+            const int32_t o = perm[i];
+            row.clear();
+            for (int32_t k = rp[o]; k < rp[o + 1]; ++k) row.emplace_back(iperm[ci[k]], va[k]);
+            std::sort(row.begin(), row.end(),
+                      [](const std::pair<int32_t, double> &a, const std::pair<int32_t, double> &b) {
+                          return a.first < b.first;
+                      });
+            int64_t w = prp[i];
+            for (const auto &e : row) { pci[w] = e.first; pva[w] = e.second; ++w; }
+            prp[i + 1] = (int32_t)w;
+        }
+        HIPCHK(hipMalloc(&h->perm, sizeof(int32_t) * (size_t)n));
+        HIPCHK(hipMalloc(&h->rp_perm, sizeof(int32_t) * (size_t)(n + 1)));
+        HIPCHK(hipMalloc(&h->ci_perm, sizeof(int32_t) * (size_t)std::max<int64_t>(h->nnz, 1)));
+        HIPCHK(hipMalloc(&h->va_perm, sizeof(double) * (size_t)std::max<int64_t>(h->nnz, 1)));
+        HIPCHK(hipMalloc(&h->xwork, sizeof(double) * (size_t)round_up(n, 256)));
+        if (!h->bhat) HIPCHK(hipMalloc(&h->bhat, sizeof(double) * (size_t)round_up(n, 256)));
+        HIPCHK(hipMemcpyAsync(h->perm, perm.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, h->stream));
+        HIPCHK(hipMemcpyAsync(h->rp_perm, prp.data(), sizeof(int32_t) * (n + 1), hipMemcpyHostToDevice, h->stream));
+        HIPCHK(hipMemcpyAsync(h->ci_perm, pci.data(), sizeof(int32_t) * h->nnz, hipMemcpyHostToDevice, h->stream));
+        HIPCHK(hipMemcpyAsync(h->va_perm, pva.data(), sizeof(double) * h->nnz, hipMemcpyHostToDevice, h->stream));
+        HIPCHK(hipStreamSynchronize(h->stream));   // the host vectors go out of scope
+        h->rp = h->rp_perm;
+        h->ci = h->ci_perm;
+        h->va = h->va_perm;
+    }
     double *split_val = nullptr;   // L^-1 A R^-1, needed only while the device copies are built
     if (h->opt.precond == MSTAB_PRECOND_JACOBI) {
         const size_t vb = sizeof(double) * (size_t)round_up(h->n, 256);
         HIPCHK(hipMalloc(&h->pd, vb));
         HIPCHK(hipMalloc(&h->pe, vb));
-        HIPCHK(hipMalloc(&h->bhat, vb));
+        if (!h->bhat) HIPCHK(hipMalloc(&h->bhat, vb));
         HIPCHK(hipMalloc(&split_val, sizeof(double) * (size_t)std::max<int64_t>(h->nnz, 1)));
         h->split_tmp = split_val;
         jacobi_split_dev(h->n, h->rp, h->ci, h->va, split_val, h->pd, h->pe, h->stream);
@@ -1305,10 +1469,16 @@ mstab_status mstab_create(const mstab_csr *A, int32_t s, int32_t ell, const msta
         h->e32.refresh_v = true;
     }
     HIPCHK(hipStreamSynchronize(h->stream));
-    // the device copies hold the split values; the handle keeps the caller's arrays
+    // the device copies hold the split (and reordered) values; the reordered
+    // row pointer stays (the sliced product reads it); the rest is released
     (void)hipFree(h->split_tmp);
     h->split_tmp = nullptr;
-    h->va = A->val;
+    (void)hipFree(h->ci_perm);
+    (void)hipFree(h->va_perm);
+    h->ci_perm = nullptr;
+    h->va_perm = nullptr;
+    h->va = h->perm ? nullptr : A->val;
+    h->ci = h->perm ? nullptr : A->col_idx;
     *out = h;
     return MSTAB_OK;
     }
@@ -1333,10 +1503,34 @@ mstab_status mstab_solve_next(mstab_solver *h, const double *b, double *x, mstab
     if (!h) { g_tls_error = "handle is NULL"; return MSTAB_E_INVALID; }
     API_BEGIN
     if (!b || !x) fail(MSTAB_E_INVALID, "b or x is NULL");
-    if (!h->pd)
+    if (!h->transformed())
         return h->mixed() ? solve_mixed(h, b, x, info, 0, 0) : solve_f64(h, b, x, info, 0, 0);
-    // split system: L^-1 b, y0 = R x0; afterwards x = R^-1 y (also after a failure)
     const int grid = grid1(h->n);
+    if (h->perm) {
+        // reordered (and possibly split) system: b' = L^-1 b[perm], y0 = R x0[perm];
+        // afterwards x[perm] = R^-1 y (also after a failure)
+        hipLaunchKernelGGL(k_gather, dim3(grid), dim3(BLOCK), 0, h->stream, h->n, h->perm, b,
+                           (const double *)h->pd, h->bhat);
+        HIPCHK(hipGetLastError());
+        hipLaunchKernelGGL(k_gather, dim3(grid), dim3(BLOCK), 0, h->stream, h->n, h->perm, x,
+                           (const double *)h->pe, h->xwork);
+        HIPCHK(hipGetLastError());
+        mstab_status st;
+        try {
+            st = h->mixed() ? solve_mixed(h, h->bhat, h->xwork, info, 0, 0)
+                            : solve_f64(h, h->bhat, h->xwork, info, 0, 0);
+        } catch (...) {
+            hipLaunchKernelGGL(k_scatter, dim3(grid), dim3(BLOCK), 0, h->stream, h->n, h->perm,
+                               (const double *)h->xwork, (const double *)h->pd, x);
+            throw;
+        }
+        hipLaunchKernelGGL(k_scatter, dim3(grid), dim3(BLOCK), 0, h->stream, h->n, h->perm,
+                           (const double *)h->xwork, (const double *)h->pd, x);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipStreamSynchronize(h->stream));
+        return st;
+    }
+    // split system: L^-1 b, y0 = R x0; afterwards x = R^-1 y (also after a failure)
     hipLaunchKernelGGL(k_mul, dim3(grid), dim3(BLOCK), 0, h->stream, h->n, b, h->pd, h->bhat);
     HIPCHK(hipGetLastError());
     hipLaunchKernelGGL(k_mul, dim3(grid), dim3(BLOCK), 0, h->stream, h->n, x, h->pe, x);
@@ -1409,7 +1603,7 @@ mstab_status mstab_solve_next_guess(mstab_solver *h, const double *b, const doub
     if (!h) { g_tls_error = "handle is NULL"; return MSTAB_E_INVALID; }
     API_BEGIN
     if (!b || !x_prev || !x_guess || !x) fail(MSTAB_E_INVALID, "NULL vector");
-    if (h->pd) fail(MSTAB_E_INVALID, "guess gate on a preconditioned handle");
+    if (h->transformed()) fail(MSTAB_E_INVALID, "guess gate on a preconditioned or reordered handle");
     Engine<double> &E = h->e64;
     E.small(SMALL_CLEAR);
     HIPCHK(hipMemcpyAsync(E.X, x_guess, sizeof(double) * h->n, hipMemcpyDeviceToDevice, h->stream));
@@ -1435,7 +1629,7 @@ mstab_status mstab_residual(mstab_solver *h, const double *b, const double *x, d
     API_BEGIN
     if (!b || !x || !r) fail(MSTAB_E_INVALID, "NULL vector");
     if (r == b || r == x) fail(MSTAB_E_INVALID, "r must not alias b or x");
-    if (h->pd) fail(MSTAB_E_INVALID, "residual on a preconditioned handle");
+    if (h->transformed()) fail(MSTAB_E_INVALID, "residual on a preconditioned or reordered handle");
     Engine<double> &E = h->e64;
     E.small(SMALL_CLEAR);
     E.spmv(x, r, b, ACT_TRUE, 0, 0);
@@ -1601,6 +1795,38 @@ struct Scratch {
 }  // namespace
 
 extern "C" {
+
+mstab_status mstab_rcm_order(int64_t n, const int32_t *row_ptr, const int32_t *col_idx,
+                             int32_t *perm)
+{
+    API_BEGIN
+    if (n < 0 || n >= ((int64_t)1 << 29)) fail(MSTAB_E_INVALID, "n out of range");
+    if (n == 0) return MSTAB_OK;
+    if (!row_ptr || !col_idx || !perm) fail(MSTAB_E_INVALID, "NULL pointer");
+    if (row_ptr[0] != 0) fail(MSTAB_E_INVALID, "row_ptr[0] != 0");
+    for (int64_t i = 0; i < n; ++i)
+        if (row_ptr[i + 1] < row_ptr[i]) fail(MSTAB_E_INVALID, "row_ptr decreases at row %lld", (long long)i);
+    for (int64_t k = 0; k < row_ptr[n]; ++k)
+        if (col_idx[k] < 0 || col_idx[k] >= n) fail(MSTAB_E_INVALID, "column index out of range");
+    const std::vector<int32_t> p = rcm_order(n, row_ptr, col_idx);
+    std::copy(p.begin(), p.end(), perm);
+    return MSTAB_OK;
+    API_END(nullptr)
+}
+
+mstab_status mstab_permutation(const mstab_solver *h, int32_t *perm)
+{
+    if (!h) { g_tls_error = "handle is NULL"; return MSTAB_E_INVALID; }
+    if (!perm) return MSTAB_E_INVALID;
+    API_BEGIN
+    if (!h->perm) {
+        for (int64_t i = 0; i < h->n; ++i) perm[i] = (int32_t)i;
+        return MSTAB_OK;
+    }
+    HIPCHK(hipMemcpy(perm, h->perm, sizeof(int32_t) * (size_t)h->n, hipMemcpyDeviceToHost));
+    return MSTAB_OK;
+    API_END(const_cast<mstab_solver *>(h))
+}
 
 mstab_status mstab_jacobi_split(const mstab_csr *A, double *val_out, double *d, double *e,
                                 void *hip_stream)

@@ -20,6 +20,7 @@ OK, NOT_CONVERGED, E_INVALID, E_HIP, E_NOMEM, E_BREAKDOWN, E_NONFINITE = 0, 1, -
 METHOD_MSTAB, METHOD_IDRSTAB = 0, 1
 PREC_F64, PREC_F32_REFINE, PREC_F32_MATRIX = 0, 1, 2
 PRECOND_NONE, PRECOND_JACOBI = 0, 1
+REORDER_NONE, REORDER_RCM = 0, 1
 FETCH_THRESHOLD, FETCH_AT_LEVEL, FETCH_AT_END, FETCH_ONCE, FETCH_NEVER = 0, 1, 2, 3, 4
 K_SPMV, K_GAMMA, K_ETA, K_GRAM, K_POLY = 0, 1, 2, 3, 4
 KERNEL_CLASSES = {"spmv": K_SPMV, "gamma": K_GAMMA, "eta": K_ETA, "gram": K_GRAM, "poly": K_POLY}
@@ -31,7 +32,8 @@ EXPORTS = [
     "mstab_mv_count", "mstab_residual", "mstab_residual_history", "mstab_recycle_reset", "mstab_recycle_get",
     "mstab_recycle_set", "mstab_destroy", "mstab_status_str", "mstab_last_error",
     "mstab_set_profiling", "mstab_kernel_stats", "mstab_convdiff_nnz", "mstab_assemble_convdiff",
-    "mstab_jacobi_split", "mstab_spmv", "mstab_project", "mstab_rhs_step",
+    "mstab_jacobi_split", "mstab_permutation", "mstab_rcm_order", "mstab_spmv", "mstab_project",
+    "mstab_rhs_step",
     "mstab_cnn_param_count", "mstab_cnn_create", "mstab_cnn_destroy", "mstab_cnn_set_params",
     "mstab_cnn_get_params", "mstab_cnn_prepare", "mstab_cnn_forward", "mstab_cnn_gradient",
     "mstab_cnn_adam_step", "mstab_cnn_guess", "mstab_cnn_tensor", "mstab_cnn_last_error",
@@ -50,7 +52,8 @@ class mstab_options(ctypes.Structure):
                 ("fetch_rel", ctypes.c_double), ("fetch_level", ctypes.c_int64),
                 ("p_seed", ctypes.c_uint64), ("max_replacements", ctypes.c_int32),
                 ("inner_tol", ctypes.c_double), ("max_refinements", ctypes.c_int32),
-                ("precond", ctypes.c_int32), ("replace_every", ctypes.c_int32)]
+                ("precond", ctypes.c_int32), ("replace_every", ctypes.c_int32),
+                ("reorder", ctypes.c_int32)]
 
 
 class mstab_info(ctypes.Structure):
@@ -104,6 +107,8 @@ def load(path: str = LIB_PATH):
         "mstab_convdiff_nnz": (i64, [i32, i64]),
         "mstab_assemble_convdiff": (i32, [i32, i64, P, f64, P, P, P, P, P]),
         "mstab_jacobi_split": (i32, [ctypes.POINTER(mstab_csr), P, P, P, P]),
+        "mstab_permutation": (i32, [P, P]),
+        "mstab_rcm_order": (i32, [i64, P, P, P]),
         "mstab_spmv": (i32, [ctypes.POINTER(mstab_csr), P, P, P]),
         "mstab_project": (i32, [i64, i32, u64, P, P, P]),
         "mstab_rhs_step": (i32, [i64, P, f64, P, P, P]),
@@ -224,6 +229,18 @@ def solve_batch(solvers, bs, xs) -> list:
     return [i.as_dict() for i in infos]
 
 
+def mstab_rcm_order(row_ptr, col_idx):
+    """Reverse Cuthill-McKee order (perm[new] = old) of a host CSR pattern (NumPy int32)."""
+    import numpy as np
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int32)
+    ci = np.ascontiguousarray(col_idx, dtype=np.int32)
+    n = rp.shape[0] - 1
+    perm = np.empty(max(n, 0), dtype=np.int32)
+    P = ctypes.c_void_p
+    _check(load().mstab_rcm_order(n, rp.ctypes.data_as(P), ci.ctypes.data_as(P), perm.ctypes.data_as(P)))
+    return perm
+
+
 def mstab_jacobi_split(A: CSR, val_out, d=None, e=None, stream=None):
     """Values of L^-1 A R^-1 (L = R = |diag A|^1/2) into val_out; d, e optional."""
     _require_cuda(val_out, *(t for t in (d, e) if t is not None))
@@ -309,6 +326,13 @@ class Solver:
         n2 = ctypes.c_double()
         _check(self.lib.mstab_residual(self.h, _ptr(b), _ptr(x), _ptr(r), ctypes.byref(n2)), self.h)
         return n2.value
+
+    def permutation(self):
+        """The handle's row order, perm[new] = old (NumPy int32)."""
+        import numpy as np
+        perm = np.empty(self.A.n, dtype=np.int32)
+        _check(self.lib.mstab_permutation(self.h, perm.ctypes.data_as(ctypes.c_void_p)), self.h)
+        return perm
 
     def residual_history(self):
         n = ctypes.c_int64()

@@ -7,6 +7,7 @@
     python -m paper_1604_06043_amd.workloads fetch   # fetch policies of M(s)stab on 128^3 and 64^2
     python -m paper_1604_06043_amd.workloads jacobi  # split diagonal preconditioning on c3 and c5
     python -m paper_1604_06043_amd.workloads batch   # B independent 64^2 sequences solved together
+    python -m paper_1604_06043_amd.workloads reorder # c5 with reverse Cuthill-McKee reordering
 
 Each prints one JSON line per measurement (systems/s and MVs/system of
 M(s)stab(l) and IDR(s)stab(l), FP64 and FP32 + FP64 refinement, and the
@@ -160,6 +161,26 @@ def batch_throughput(B: int, systems: int = 10, n: int = 64, s: int = 4, ell: in
             "systems_per_s": B * systems / sec, "mvs_per_system": mv / (B * systems)}
 
 
+def reorder_compare(seq: Sequence, systems: int, s: int, ell: int, seed: int = 0):
+    """M(s)stab and IDR(s)stab on the caller's order and on the RCM order,
+    with and without the split diagonal preconditioning."""
+    out = {"workload": seq.name, "N": seq.N, "nnz": seq.A.nnz, "s": s, "ell": ell,
+           "systems": systems, "tol": 1e-8}
+    run(seq, 1, s, ell, seed=seed, reorder=M.REORDER_RCM)
+    for name, method, prec in (("mstab", M.METHOD_MSTAB, M.PREC_F64),
+                               ("idrstab", M.METHOD_IDRSTAB, M.PREC_F64),
+                               ("mstab_f32_matrix", M.METHOD_MSTAB, M.PREC_F32_MATRIX),
+                               ("idrstab_f32_matrix", M.METHOD_IDRSTAB, M.PREC_F32_MATRIX)):
+        for ro, pc, tag in ((M.REORDER_RCM, M.PRECOND_NONE, "rcm"),
+                            (M.REORDER_RCM, M.PRECOND_JACOBI, "rcm_jacobi")):
+            t, mv, infos, _ = run(seq, systems, s, ell, method=method, precision=prec, seed=seed,
+                                  reorder=ro, precond=pc)
+            out[f"{name}_{tag}"] = {"systems_per_s": systems / t, "mvs_per_system": mv,
+                                    "max_relres_true": max(i["relres_true"] for i in infos)}
+            log(f"[{seq.name}] {name} {tag}: {systems / t:.2f} systems/s, {mv:.1f} MVs/system")
+    return out
+
+
 def convdiff_sequence(name: str, n: int | None = None, seed: int = 0) -> Sequence:
     import torch
     cd = I.config(name, seed=seed, n=n)
@@ -187,7 +208,7 @@ def rgg_sequence(N: int, seed: int = 0, systems: int = 100) -> Sequence:
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
-    ap.add_argument("which", choices=["sweep", "c1", "c3", "c5", "c2", "fetch", "jacobi", "batch"])
+    ap.add_argument("which", choices=["sweep", "c1", "c3", "c5", "c2", "fetch", "jacobi", "batch", "reorder"])
     ap.add_argument("--n", type=int, default=None)
     ap.add_argument("--N", type=int, default=1 << 22)
     ap.add_argument("--systems", type=int, default=None)
@@ -201,6 +222,10 @@ def main():
         for s in (2, 4, 8):
             for ell in (1, 2, 4):
                 print(json.dumps(compare(seq, systems, s, ell, mixed=False)), flush=True)
+    elif a.which == "reorder":
+        systems = a.systems or 100
+        seq = rgg_sequence(a.N, 0, systems)
+        print(json.dumps(reorder_compare(seq, systems, 4, 2)), flush=True)
     elif a.which == "batch":
         import os
         for B in (1, 2, 4, 8, 16, 32):

@@ -841,3 +841,75 @@ def test_batch_matches_sequential(torch_dev, ms, orc):
     with pytest.raises(ms.MstabError, match="repeated"):
         ms.solve_batch([sv, sv], bs[:2], xs[:2])
     sv.close()
+
+
+# ---------------------------------------------------------------------------
+# Reverse Cuthill-McKee reordering (the handle iterates on P A P^T)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("jacobi", [False, True])
+def test_reordered_graph_teacher_forced(torch_dev, ms, orc, jacobi):
+    """A reordered handle runs Algorithm 1 on the permuted matrix, which is the
+    oracle's iteration on the original matrix with the cut-space basis and the
+    recycled U, V carried back through the order (rows of P and U, V permuted):
+    the teacher-forced bar, system by system, on the random-labelled graph."""
+    torch = torch_dev
+    s, ell, seed = 4, 2, 5
+    g = I.rgg(20000, seed)
+    Ao = orc.CSR(g.row_ptr, g.col, g.val)
+    Ag = upload_csr(torch, ms, Ao)
+    pc = ms.PRECOND_JACOBI if jacobi else ms.PRECOND_NONE
+    solver = ms.Solver(Ag, s, ell, p_seed=seed, reorder=ms.REORDER_RCM, precond=pc)
+    perm = solver.permutation()
+    N = Ao.n
+    assert np.array_equal(np.sort(perm), np.arange(N))
+    iperm = np.empty_like(perm)
+    iperm[perm] = np.arange(N, dtype=perm.dtype)
+    P = I.p_dense(seed, N, s)[iperm]           # row i of the original gets the reordered row's P
+    split = orc.jacobi_split(Ao) if jacobi else None
+    rng = np.random.default_rng(seed)
+    xo = np.zeros(N)
+    rec = orc.Recycle.empty(N, s)
+    errs = []
+    for k in range(5):
+        b = xo + 0.1 * rng.standard_normal(N)
+        if rec.have:
+            solver.recycle_set(dev(torch, rec.U[perm].T), dev(torch, rec.V[perm].T), rec.level)
+        else:
+            solver.recycle_reset()
+        x = dev(torch, xo)
+        ig = solver.solve_next(dev(torch, b), x)
+        if jacobi:
+            with orc.reversed_sums():
+                xr, ir, _, _ = orc.solve_jacobi(Ao, b, xo, s, ell, P, split=split, recycle=rec.copy())
+            xn, io, rec, _ = orc.solve_jacobi(Ao, b, xo, s, ell, P, split=split, recycle=rec)
+        else:
+            with orc.reversed_sums():
+                xr, ir, _, _ = orc.solve(Ao, b, xo, s, ell, P, recycle=rec.copy())
+            xn, io, rec, _ = orc.solve(Ao, b, xo, s, ell, P, recycle=rec)
+        err = np.linalg.norm(x.cpu().numpy() - xn) / np.linalg.norm(xn)
+        sen = np.linalg.norm(xr - xn) / np.linalg.norm(xn)
+        errs.append(err)
+        print(f"  system {k}: gpu mv {ig['mv_total']} oracle {io.mv_total}, err {err:.1e}, sens {sen:.1e}",
+              flush=True)
+        assert ig["converged"] and io.converged
+        assert ig["recycled"] == io.recycled
+        if near_threshold(io) or ir.mv_total != io.mv_total or sen > 1e-10:
+            assert abs(ig["cycles"] - io.cycles) <= 1
+            assert err <= 10 * 1e-8
+        else:
+            assert err <= max(1e-9, 10 * sen), (k, err, sen, errs)
+            assert ig["mv_total"] == io.mv_total, (k, ig, io)
+        xo = xn
+
+
+def test_reordered_handle_rejects_guess_and_residual(torch_dev, ms, orc):
+    torch = torch_dev
+    g = I.rgg(3000, 1)
+    Ag = upload_csr(torch, ms, orc.CSR(g.row_ptr, g.col, g.val))
+    solver = ms.Solver(Ag, 2, 1, reorder=ms.REORDER_RCM)
+    b = torch.ones(g.row_ptr.size - 1, dtype=torch.float64, device="cuda")
+    x = torch.zeros_like(b)
+    with pytest.raises(ms.MstabError, match="reordered"):
+        solver.residual(b, x, torch.empty_like(b))
+    assert solver.solve_next(b, x)["converged"]
+    solver.close()
