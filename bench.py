@@ -28,7 +28,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = ("systems/sec + MVs/system at rel-res 1e-8; SpMV HBM GB/s vs peak, "
           "M(s)stab vs IDRstab")
-PMC_RECORD = os.path.join(ROOT, "profiles", "spmv_dia_convdiff128_pmc.json")
+PMC_RECORD = os.path.join(ROOT, "profiles", "solver_convdiff128_pmc.json")
 HBM_PEAK_GBS = 8000.0
 EVENT_PERIOD = 16
 CLASS_NAMES = ["spmv", "gamma", "eta", "gram", "poly"]
@@ -90,19 +90,31 @@ def cpu_baseline(cd, s, ell, mvs_per_system):
             "mvs_per_s": rate}
 
 
-def measured_traffic(kernel_name_part: str):
-    """HBM bytes per dispatch from the committed counter record, if it was taken
-    with the current kernel sources (else None)."""
+def class_kernels(cls: str, s: int, ell: int):
+    """The kernels of one timing class of the FP64 solver."""
+    return {"spmv": [f"k_spmv_dia<double, {s}, double>", f"k_spmv<double, {s}, double>"],
+            "eta": [f"k_eta<double, {s}>", f"k_eta_low<double, {s}>"],
+            "gamma": [f"k_gamma<double, {s}>"],
+            "poly": [f"k_poly<double, {s}, {ell}>"],
+            "gram": [f"k_gram<double, {ell}>"]}[cls]
+
+
+def measured_traffic(name_parts):
+    """HBM bytes per dispatch, averaged over the dispatches of the named
+    kernels, from the committed counter record, if it was taken with the
+    current kernel sources (else None)."""
     from paper_1604_06043_amd import prof
     if not os.path.exists(PMC_RECORD):
         return None
     rec = json.load(open(PMC_RECORD))
     if rec.get("sources_sha256") != prof.sources_digest():
         return None
+    tot, disp = 0.0, 0
     for name, t in rec["traffic"].items():
-        if kernel_name_part in name:
-            return t["traffic_bytes"]
-    return None
+        if any(p + "(" in name for p in name_parts):
+            tot += t["traffic_bytes"] * t["dispatches"]
+            disp += t["dispatches"]
+    return tot / disp if disp else None
 
 
 def main():
@@ -118,6 +130,9 @@ def main():
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-events", action="store_true",
                     help="time the steps without per-kernel HIP events (no roofline)")
+    ap.add_argument("--matrix-format", choices=["auto", "diagonal", "sliced"], default="auto",
+                    help="device copy of A for the timed method (auto: constant diagonals when "
+                         "the matrix has them)")
     ap.add_argument("--calib", action="store_true",
                     help="first copy 256 MiB device-to-device with a plain copy kernel "
                          "(reference for the HBM byte counters)")
@@ -149,7 +164,8 @@ def main():
     torch.cuda.synchronize()
     log(f"[bench] N={cd.N} nnz={A.nnz} s={s} ell={ell} systems/step={args.systems}")
 
-    solver = ms.Solver(A, s, ell, p_seed=0, method=ms.METHOD_MSTAB)
+    fmt = {"auto": ms.FORMAT_AUTO, "diagonal": ms.FORMAT_DIAGONAL, "sliced": ms.FORMAT_SLICED}[args.matrix_format]
+    solver = ms.Solver(A, s, ell, p_seed=0, method=ms.METHOD_MSTAB, matrix_format=fmt)
     state = {}
 
     def step():
@@ -179,13 +195,21 @@ def main():
             kernels[c] = {"timed_launches": n, "ms_total_timed": round(msec, 3),
                           "us_per_launch": round(1e3 * msec / n, 2),
                           "GBs": round(by / (msec * 1e-3) / 1e9, 1)}
+    # which device copy the products read, from their counted bytes per launch
+    device_matrix = None
+    if stats["spmv"][0]:
+        per_row = stats["spmv"][2] / stats["spmv"][0] / cd.N
+        device_matrix = ("diagonal storage, one value per diagonal (constant coefficients, detected "
+                         "bit for bit from the CSR values)" if per_row < 30 else
+                         "diagonal storage, values streamed")
     roofline = None
     if not args.no_events:
         dom = max(stats, key=lambda c: stats[c][1])
         n, msec, by = stats[dom]
         achieved = by / (msec * 1e-3) / 1e9
-        traffic = measured_traffic(f"k_spmv_dia<double, {s}, double>") if dom == "spmv" else None
-        roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
+        names = class_kernels(dom, s, ell)
+        traffic = measured_traffic(names)
+        roofline = {"bound": "hbm", "kernel": dom, "kernels": names, "achieved": round(achieved, 1),
                     "timed": f"1 launch in {EVENT_PERIOD} of each kernel class, HIP events on the solver stream",
                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(achieved / HBM_PEAK_GBS, 4),
@@ -200,6 +224,14 @@ def main():
         variants["idrstab"] = {"systems_per_s": args.systems / ti,
                                "mvs_per_system": mvi / args.systems}
         log(f"[bench] IDR(s)stab(l): {args.systems / ti:.2f} systems/s")
+        # the same method with the diagonal values streamed from HBM instead of
+        # kept as one constant per diagonal (bit-identical iterates)
+        dg = ms.Solver(A, s, ell, p_seed=0, method=ms.METHOD_MSTAB, matrix_format=ms.FORMAT_DIAGONAL)
+        td, (mvd,) = timed(torch, lambda: run_sequence(torch, ms, dg, cd, f, args.systems)[1], 1, 0)
+        dg.close()
+        variants["diagonal_values_streamed"] = {"systems_per_s": args.systems / td,
+                                                "mvs_per_system": mvd / args.systems}
+        log(f"[bench] diagonal values streamed: {args.systems / td:.2f} systems/s")
         mix = ms.Solver(A, s, ell, p_seed=0, method=ms.METHOD_MSTAB, precision=ms.PREC_F32_REFINE)
         x64, _, _ = run_sequence(torch, ms, solver, cd, f, args.systems)
         holder = {}
@@ -250,7 +282,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"convdiff3d_{cd.n}cubed_pe100_dt1e-3_{args.systems}rhs",
                    "N": cd.N, "nnz": A.nnz, "s": s, "ell": ell, "tol": 1e-8,
-                   "method": "M(s)stab(l)", "systems_per_step": args.systems, "format": "csr_int32_f64"},
+                   "method": "M(s)stab(l)", "systems_per_step": args.systems, "format": "csr_int32_f64",
+                   "device_matrix": device_matrix},
         "mvs_per_system": round(mv_per_system, 2),
         "roofline": roofline,
         "kernels": kernels,

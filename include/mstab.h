@@ -95,6 +95,19 @@ typedef enum {
                                   PRECOND_JACOBI. */
 } mstab_reorder;
 
+typedef enum {
+    MSTAB_FORMAT_AUTO = 0,     /* the device copy of A the products read: a matrix whose entries lie on
+                                  at most 16 diagonals (column - row) with under 25% padding is kept
+                                  in diagonal storage (64-row slices of nd values, a 16-bit presence
+                                  mask per row), and if every diagonal then holds one value wherever
+                                  it is present (a constant-coefficient stencil, compared bit for
+                                  bit) only those nd values and the mask are kept; any other matrix
+                                  in sliced ELLPACK (64-row slices).  Every format gives the same
+                                  product bit for bit. */
+    MSTAB_FORMAT_DIAGONAL = 1, /* as AUTO without the constant-diagonal form (values streamed) */
+    MSTAB_FORMAT_SLICED = 2    /* always sliced ELLPACK */
+} mstab_format;
+
 /* CSR matrix; all arrays are device pointers, n rows, nnz entries. */
 typedef struct {
     int64_t n;
@@ -126,6 +139,7 @@ typedef struct {
                                   final replacements).  F32_REFINE replaces after every cycle
                                   by construction and ignores it. */
     int32_t reorder;           /* mstab_reorder; default NONE */
+    int32_t matrix_format;     /* mstab_format; default AUTO */
 } mstab_options;
 
 typedef struct {

@@ -326,6 +326,13 @@ struct DiaOffsets {
 };
 constexpr unsigned long long DIA_EMPTY = 0x8000000000000000ull;   // unused table slot
 
+// A diagonal-storage matrix whose every diagonal holds one value wherever it
+// is present (a constant-coefficient stencil) keeps only those values: c[d]
+// is the value in the copy's precision, widened to double.
+struct DiaConst {
+    double c[MAX_DIAG];
+};
+
 // Diagonal storage is sliced like the rows: the nd values of 64 consecutive
 // rows lie together, diagonal by diagonal, so a wavefront's loads of a slice
 // are one contiguous block of nd * 64 entries.
@@ -350,6 +357,9 @@ struct Sell {
     DiaOffsets doff{};
     uint16_t *dmask = nullptr;
     T *dval = nullptr;
+    // constant diagonals: dval is not kept, the values are cv.c[d]
+    bool dconst = false;
+    DiaConst cv{};
 };
 
 // Scatter CSR rows into the sliced layout (one thread per row).
@@ -439,6 +449,40 @@ __global__ __launch_bounds__(BLOCK) void k_to_dia(int64_t n, const int32_t *__re
             m |= 1u << d;
         }
         if (mask) mask[r] = (uint16_t)m;
+    }
+}
+
+// Smallest and largest bit pattern of the present values of each diagonal
+// (lohi[d] and lohi[MAX_DIAG + d], combined by atomic min/max; the caller
+// starts them at all ones and zero).  Equal patterns mean a constant diagonal.
+template <typename TD>
+__global__ __launch_bounds__(BLOCK) void k_dia_range(int64_t n, int nd, const uint16_t *__restrict__ mask,
+                                                     const TD *__restrict__ dval,
+                                                     unsigned long long *lohi)
+{
+    __shared__ unsigned long long s_lo[MAX_DIAG], s_hi[MAX_DIAG];
+    if (threadIdx.x < MAX_DIAG) {
+        s_lo[threadIdx.x] = ~0ull;
+        s_hi[threadIdx.x] = 0ull;
+    }
+    __syncthreads();
+    for (int64_t r = (int64_t)blockIdx.x * BLOCK + threadIdx.x; r < n;
+         r += (int64_t)gridDim.x * BLOCK) {
+        const uint32_t m = mask[r];
+        for (int d = 0; d < nd; ++d)
+            if ((m >> d) & 1u) {
+                const TD v = dval[dia_index(r, d, nd)];
+                unsigned long long bits;
+                if constexpr (sizeof(TD) == 8) bits = __builtin_bit_cast(unsigned long long, v);
+                else bits = (unsigned long long)__builtin_bit_cast(uint32_t, v);
+                atomicMin(&s_lo[d], bits);
+                atomicMax(&s_hi[d], bits);
+            }
+    }
+    __syncthreads();
+    if (threadIdx.x < nd) {
+        atomicMin(&lohi[threadIdx.x], s_lo[threadIdx.x]);
+        atomicMax(&lohi[MAX_DIAG + threadIdx.x], s_hi[threadIdx.x]);
     }
 }
 
@@ -628,13 +672,69 @@ __global__ __launch_bounds__(SPMV_BLOCK) void k_spmv(int64_t n, const int32_t *_
     spmv_finalize<S>(vals, ctl, part, stride, a);
 }
 
+// The rows of one thread for the diagonal-storage product.  CST: constant
+// diagonals (values from cv), else values streamed from dval.  x is gathered
+// wherever the column lies in [0, n) (the presence bits only select the sum),
+// so the gathers do not wait for the mask.
+template <bool CST, typename T, typename TM>
+__device__ __forceinline__ void dia_load8(int64_t r, int64_t n, int nd, int d0, const DiaOffsets &doff,
+                                          const DiaConst &cv, const TM *__restrict__ dval,
+                                          const T *__restrict__ x, T (&v)[8], T (&xv)[8])
+{
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+        if (d0 + j < nd) {
+            const int64_t c = r + doff.off[d0 + j];
+            if constexpr (CST)
+                v[j] = (T)cv.c[d0 + j];
+            else   // the matrix is streamed once per product: keep it out of the caches
+                v[j] = (T)__builtin_nontemporal_load(dval + dia_index(r, d0 + j, nd));
+            xv[j] = (c >= 0 && c < n) ? x[c] : (T)0;
+        }
+}
+
+template <typename T>
+__device__ __forceinline__ void dia_add8(int nd, int d0, uint32_t m, const T (&v)[8], const T (&xv)[8], T &sum)
+{
+#pragma clang fp contract(off)
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+        if (d0 + j < nd) {
+            const T prod = v[j] * xv[j];
+            const T nsum = sum + prod;
+            sum = ((m >> (d0 + j)) & 1u) ? nsum : sum;
+        }
+}
+
+template <bool CST, typename T, int S, typename TM>
+__device__ __forceinline__ void dia_rows(int64_t n, int nd, const DiaOffsets &doff, const DiaConst &cv,
+                                         const uint16_t *__restrict__ mask,
+                                         const TM *__restrict__ dval, const T *__restrict__ x,
+                                         T *__restrict__ y, const T *__restrict__ b, bool resid,
+                                         uint32_t pkey, double (&vals)[S + 2])
+{
+    for (int64_t r = (int64_t)blockIdx.x * SPMV_BLOCK + threadIdx.x; r < n;
+         r += (int64_t)gridDim.x * SPMV_BLOCK) {
+        const uint32_t m = mask[r];
+        T sum = (T)0;
+        for (int d0 = 0; d0 < nd; d0 += 8) {
+            T v[8], xv[8];
+            dia_load8<CST, T, TM>(r, n, nd, d0, doff, cv, dval, x, v, xv);
+            dia_add8(nd, d0, m, v, xv, sum);
+        }
+        spmv_row_out<T, S>(r, sum, resid, b, y, pkey, vals);
+    }
+}
+
 // The same product for a matrix in diagonal storage (stencil matrices): one
 // thread per row, the diagonals' values of 64 consecutive rows one 512-byte
-// read each, no column indices.  Present entries are multiplied, rounded and
-// added in ascending column order (the CSR order), so the result equals the
+// read each (or, for constant diagonals, no matrix reads at all beyond the
+// presence mask), no column indices.  Present entries are multiplied, rounded
+// and added in ascending column order (the CSR order), so the result equals the
 // sliced product bit for bit.
 template <typename T, int S, typename TM = T>
 __global__ __launch_bounds__(SPMV_BLOCK) void k_spmv_dia(int64_t n, int nd, DiaOffsets doff,
+                                                         DiaConst cv,
                                                          const uint16_t *__restrict__ mask,
                                                          const TM *__restrict__ dval,
                                                          const T *__restrict__ x,
@@ -642,38 +742,15 @@ __global__ __launch_bounds__(SPMV_BLOCK) void k_spmv_dia(int64_t n, int nd, DiaO
                                                          const T *__restrict__ b, Ctl *ctl,
                                                          double *part, int stride, SpmvArgs a)
 {
-#pragma clang fp contract(off)
     if (ctl->st.flags) return;
     const bool resid = (a.act == ACT_RESID || a.act == ACT_TRUE);
     double vals[S + 2];
 #pragma unroll
     for (int v = 0; v < S + 2; ++v) vals[v] = 0.0;
-    // x is gathered wherever the column lies in [0, n) (the presence bits only
-    // select the sum), so the gathers do not wait for the mask
-    for (int64_t r = (int64_t)blockIdx.x * SPMV_BLOCK + threadIdx.x; r < n;
-         r += (int64_t)gridDim.x * SPMV_BLOCK) {
-        const uint32_t m = mask[r];
-        T sum = (T)0;
-        for (int d0 = 0; d0 < nd; d0 += 8) {
-            T v[8], xv[8];
-#pragma unroll
-            for (int j = 0; j < 8; ++j)
-                if (d0 + j < nd) {
-                    const int64_t c = r + doff.off[d0 + j];
-                    // the matrix is streamed once per product: keep it out of the caches
-                    v[j] = (T)__builtin_nontemporal_load(dval + dia_index(r, d0 + j, nd));
-                    xv[j] = (c >= 0 && c < n) ? x[c] : (T)0;
-                }
-#pragma unroll
-            for (int j = 0; j < 8; ++j)
-                if (d0 + j < nd) {
-                    const T prod = v[j] * xv[j];
-                    const T nsum = sum + prod;
-                    sum = ((m >> (d0 + j)) & 1u) ? nsum : sum;
-                }
-        }
-        spmv_row_out<T, S>(r, sum, resid, b, y, a.pkey, vals);
-    }
+    if (dval)
+        dia_rows<false, T, S, TM>(n, nd, doff, cv, mask, dval, x, y, b, resid, a.pkey, vals);
+    else
+        dia_rows<true, T, S, TM>(n, nd, doff, cv, mask, dval, x, y, b, resid, a.pkey, vals);
     spmv_finalize<S>(vals, ctl, part, stride, a);
 }
 

@@ -331,7 +331,7 @@ inline void jacobi_split_dev(int64_t n, const int32_t *rp, const int32_t *ci, co
 // FP64 copy whose column array (or diagonal mask) this copy shares.
 template <typename T, typename TS>
 Sell<T> make_sell(int64_t n, const int32_t *rp, const int32_t *ci, const TS *va, hipStream_t st,
-                  const Sell<double> *like = nullptr)
+                  const Sell<double> *like = nullptr, int format = MSTAB_FORMAT_AUTO)
 {
     Sell<T> m;
     m.n = n;
@@ -341,21 +341,64 @@ Sell<T> make_sell(int64_t n, const int32_t *rp, const int32_t *ci, const TS *va,
     HIPCHK(hipStreamSynchronize(st));
     m.nnz = h[n];
     const int grid = grid_for(n, BLOCK, VEC_MAX_BLOCKS);
-    m.nd = like ? like->nd : detect_diagonals(n, m.nnz, rp, ci, st, &m.doff);
+    if (like) m.nd = like->nd;
+    else if (format != MSTAB_FORMAT_SLICED) m.nd = detect_diagonals(n, m.nnz, rp, ci, st, &m.doff);
     if (m.nd > 0) {
-        if (like) m.doff = like->doff;
-        const size_t cnt = (size_t)m.nd * (size_t)round_up(n, 64);   // whole slices
-        HIPCHK(hipMalloc(&m.dval, sizeof(T) * cnt));
-        HIPCHK(hipMemsetAsync(m.dval, 0, sizeof(T) * cnt, st));
         if (like) {
+            m.doff = like->doff;
             m.dmask = like->dmask;
+            if (like->dconst) {
+                // the same constant diagonals, rounded to this copy's precision
+                m.dconst = true;
+                for (int d = 0; d < MAX_DIAG; ++d) m.cv.c[d] = (double)(T)like->cv.c[d];
+                return m;
+            }
         } else {
             HIPCHK(hipMalloc(&m.dmask, sizeof(uint16_t) * (size_t)n));
         }
+        const size_t cnt = (size_t)m.nd * (size_t)round_up(n, 64);   // whole slices
+        HIPCHK(hipMalloc(&m.dval, sizeof(T) * cnt));
+        HIPCHK(hipMemsetAsync(m.dval, 0, sizeof(T) * cnt, st));
         hipLaunchKernelGGL((k_to_dia<T, TS>), dim3(grid), dim3(BLOCK), 0, st, n, rp, ci, va, m.nd,
                            m.doff, like ? nullptr : m.dmask, m.dval);
         HIPCHK(hipGetLastError());
         HIPCHK(hipStreamSynchronize(st));
+        if (!like && format == MSTAB_FORMAT_AUTO) {
+            // constant diagonals: keep one value each instead of the value array
+            unsigned long long *lohi = nullptr;
+            std::vector<unsigned long long> hl(2 * MAX_DIAG);
+            for (int d = 0; d < MAX_DIAG; ++d) { hl[d] = ~0ull; hl[MAX_DIAG + d] = 0ull; }
+            HIPCHK(hipMalloc(&lohi, sizeof(unsigned long long) * 2 * MAX_DIAG));
+            hipError_t e = hipMemcpyAsync(lohi, hl.data(), sizeof(unsigned long long) * 2 * MAX_DIAG,
+                                          hipMemcpyHostToDevice, st);
+            if (e == hipSuccess) {
+                hipLaunchKernelGGL((k_dia_range<T>), dim3(grid), dim3(BLOCK), 0, st, n, m.nd,
+                                   (const uint16_t *)m.dmask, (const T *)m.dval, lohi);
+                e = hipGetLastError();
+            }
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(hl.data(), lohi, sizeof(unsigned long long) * 2 * MAX_DIAG,
+                                   hipMemcpyDeviceToHost, st);
+            const hipError_t se = hipStreamSynchronize(st);
+            (void)hipFree(lohi);
+            HIPCHK(e);
+            HIPCHK(se);
+            bool same = true;
+            for (int d = 0; d < m.nd; ++d) same = same && hl[d] == hl[MAX_DIAG + d];
+            if (same) {
+                for (int d = 0; d < MAX_DIAG; ++d) {
+                    T v = (T)0;
+                    if (d < m.nd) {
+                        if constexpr (sizeof(T) == 8) v = __builtin_bit_cast(T, (unsigned long long)hl[d]);
+                        else v = __builtin_bit_cast(T, (uint32_t)hl[d]);
+                    }
+                    m.cv.c[d] = (double)v;
+                }
+                m.dconst = true;
+                (void)hipFree(m.dval);
+                m.dval = nullptr;
+            }
+        }
         return m;
     }
     const int64_t ns = (n + SLICE - 1) / SLICE;
@@ -408,7 +451,7 @@ double spmv_bytes(const Sell<TM> &A, bool with_b, double vsize)
 {
     const double n = (double)A.n;
     const double vecs = (with_b ? 3.0 : 2.0) * n * vsize;
-    if (A.nd > 0) return (double)A.nd * n * sizeof(TM) + 2.0 * n + vecs;
+    if (A.nd > 0) return (A.dconst ? 0.0 : (double)A.nd * n * sizeof(TM)) + 2.0 * n + vecs;
     return (n + 1) * 4 + (double)A.padded * (4 + sizeof(TM)) + (double)((A.n + SLICE - 1) / SLICE + 1) * 8 +
            vecs;
 }
@@ -424,7 +467,8 @@ void launch_spmv(int grid, hipStream_t stream, const Sell<TM> &A, const T *x, T 
 #define CASE(S)                                                                                   \
     case S:                                                                                       \
         hipLaunchKernelGGL((k_spmv_dia<T, S, TM>), dim3(grid), dim3(SPMV_BLOCK), 0, stream, A.n, A.nd, \
-                           A.doff, A.dmask, A.dval, x, y, b, ctl, part, PART_STRIDE, a);          \
+                           A.doff, A.cv, A.dmask, (const TM *)A.dval, x, y, b, ctl, part,         \
+                           PART_STRIDE, a);                                                       \
         break;
             CASE(0) CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
 #undef CASE
@@ -1384,6 +1428,8 @@ mstab_status mstab_create(const mstab_csr *A, int32_t s, int32_t ell, const msta
     if (h->opt.precond != MSTAB_PRECOND_NONE && h->opt.precond != MSTAB_PRECOND_JACOBI)
         fail(MSTAB_E_INVALID, "unknown preconditioner");
     if (h->opt.replace_every < 0) fail(MSTAB_E_INVALID, "replace_every < 0");
+    if (h->opt.matrix_format < MSTAB_FORMAT_AUTO || h->opt.matrix_format > MSTAB_FORMAT_SLICED)
+        fail(MSTAB_E_INVALID, "unknown matrix format");
     if (h->opt.reorder != MSTAB_REORDER_NONE && h->opt.reorder != MSTAB_REORDER_RCM)
         fail(MSTAB_E_INVALID, "unknown reordering");
     h->s = s; h->ell = ell; h->n = A->n; h->nnz = A->nnz;
@@ -1452,7 +1498,8 @@ mstab_status mstab_create(const mstab_csr *A, int32_t s, int32_t ell, const msta
         jacobi_split_dev(h->n, h->rp, h->ci, h->va, split_val, h->pd, h->pe, h->stream);
         h->va = split_val;
     }
-    Sell<double> A64 = make_sell<double, double>(h->n, h->rp, h->ci, h->va, h->stream);
+    Sell<double> A64 = make_sell<double, double>(h->n, h->rp, h->ci, h->va, h->stream, nullptr,
+                                                 h->opt.matrix_format);
     // the mixed form keeps a full FP64 engine for the FP64 fallback
     h->e64.alloc(h->n, s, ell, A64, true, h->pkey, h->stream, &h->prof);
     h->e64.replace_every = h->opt.replace_every;

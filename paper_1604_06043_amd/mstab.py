@@ -21,6 +21,7 @@ METHOD_MSTAB, METHOD_IDRSTAB = 0, 1
 PREC_F64, PREC_F32_REFINE, PREC_F32_MATRIX = 0, 1, 2
 PRECOND_NONE, PRECOND_JACOBI = 0, 1
 REORDER_NONE, REORDER_RCM = 0, 1
+FORMAT_AUTO, FORMAT_DIAGONAL, FORMAT_SLICED = 0, 1, 2
 FETCH_THRESHOLD, FETCH_AT_LEVEL, FETCH_AT_END, FETCH_ONCE, FETCH_NEVER = 0, 1, 2, 3, 4
 K_SPMV, K_GAMMA, K_ETA, K_GRAM, K_POLY = 0, 1, 2, 3, 4
 KERNEL_CLASSES = {"spmv": K_SPMV, "gamma": K_GAMMA, "eta": K_ETA, "gram": K_GRAM, "poly": K_POLY}
@@ -53,7 +54,7 @@ class mstab_options(ctypes.Structure):
                 ("p_seed", ctypes.c_uint64), ("max_replacements", ctypes.c_int32),
                 ("inner_tol", ctypes.c_double), ("max_refinements", ctypes.c_int32),
                 ("precond", ctypes.c_int32), ("replace_every", ctypes.c_int32),
-                ("reorder", ctypes.c_int32)]
+                ("reorder", ctypes.c_int32), ("matrix_format", ctypes.c_int32)]
 
 
 class mstab_info(ctypes.Structure):

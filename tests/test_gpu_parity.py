@@ -438,11 +438,53 @@ def test_kernel_profiling_counts(torch_dev, ms, orc):
     n_eta, _, _ = solver.kernel_stats(ms.K_ETA)
     # per level: s top-level steps and one pass over the lower levels
     assert n_eta == info["cycles"] * ell * (s + 1)
-    # the 5-point matrix runs in diagonal storage: 5 diagonals of values, a
-    # 2-byte mask, x and y (b in the residual products) per row
+    # the constant-coefficient 5-point matrix runs in diagonal storage with one
+    # value per diagonal: a 2-byte mask, x and y (b in the residual products)
+    # per row
     N = cd.N
     n_res = 1 + info["mv_check"]   # initial residual and true-residual checks read b
+    expect = n_spmv * (2 * N + 2 * 8 * N) + n_res * 8 * N
+    assert abs(by - expect) <= 1e-9 * expect
+    # with the values streamed: 5 diagonals of values per row on top
+    solver = ms.Solver(Ag, s, ell, method=1, matrix_format=ms.FORMAT_DIAGONAL)
+    solver.set_profiling(True)
+    x = torch.zeros(cd.N, dtype=torch.float64, device="cuda")
+    info = solver.solve_next(dev(torch, cd.f), x)
+    n_spmv, _, by = solver.kernel_stats(ms.K_SPMV)
+    n_res = 1 + info["mv_check"]
     expect = n_spmv * (5 * 8 * N + 2 * N + 2 * 8 * N) + n_res * 8 * N
+    assert abs(by - expect) <= 1e-9 * expect
+
+
+@pytest.mark.parametrize("name,n,const", [("c1", 48, True), ("c2", 16, True), ("c3", 14, False)])
+def test_matrix_formats(torch_dev, ms, orc, name, n, const):
+    """Constant diagonals (kept as one value each) and streamed diagonal values
+    give the same solves bit for bit (same kernel, same rows per thread, the
+    value source only); the sliced copy agrees to the teacher-forced bar.  The
+    constant form is taken exactly when every diagonal holds one value."""
+    torch = torch_dev
+    cd = I.config(name, seed=2, n=n)
+    Ag = gpu_assemble(ms, cd)
+    s, ell, systems = 4, 2, 3
+    out = {}
+    for fmt in (ms.FORMAT_AUTO, ms.FORMAT_DIAGONAL, ms.FORMAT_SLICED):
+        xs, infos, _ = run_sequence_gpu(torch, ms, Ag, cd, s, ell, systems, 0, matrix_format=fmt)
+        out[fmt] = (xs, [i["mv_total"] for i in infos])
+    for a, b in zip(out[ms.FORMAT_AUTO][0], out[ms.FORMAT_DIAGONAL][0]):
+        np.testing.assert_array_equal(a, b)
+    assert out[ms.FORMAT_AUTO][1] == out[ms.FORMAT_DIAGONAL][1]
+    for a, b in zip(out[ms.FORMAT_AUTO][0], out[ms.FORMAT_SLICED][0]):
+        assert np.linalg.norm(a - b) <= 10 * 1e-8 * np.linalg.norm(a)
+    # which form AUTO took: the product's counted bytes per row
+    solver = ms.Solver(Ag, s, ell, method=1)
+    solver.set_profiling(True)
+    x = torch.zeros(cd.N, dtype=torch.float64, device="cuda")
+    info = solver.solve_next(dev(torch, cd.f), x)
+    n_spmv, _, by = solver.kernel_stats(ms.K_SPMV)
+    n_res = 1 + info["mv_check"]
+    nd = 5 if cd.dim == 2 else 7
+    values = 0 if const else nd * 8 * cd.N
+    expect = n_spmv * (values + 2 * cd.N + 16 * cd.N) + n_res * 8 * cd.N
     assert abs(by - expect) <= 1e-9 * expect
 
 
