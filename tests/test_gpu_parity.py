@@ -955,3 +955,31 @@ def test_reordered_handle_rejects_guess_and_residual(torch_dev, ms, orc):
         solver.residual(b, x, torch.empty_like(b))
     assert solver.solve_next(b, x)["converged"]
     solver.close()
+
+
+@pytest.mark.parametrize("precision", ["F32_MATRIX", "F32_REFINE"])
+def test_reordered_graph_mixed_precision(torch_dev, ms, orc, precision):
+    """Reordering with the precision forms: every system meets the tolerance on
+    the original matrix (checked with the oracle's product in the caller's
+    order), and the error against the oracle's FP64 solve of the same system
+    is bounded."""
+    torch = torch_dev
+    g = I.rgg(20000, 6)
+    Ao = orc.CSR(g.row_ptr, g.col, g.val)
+    Ag = upload_csr(torch, ms, Ao)
+    solver = ms.Solver(Ag, 4, 2, p_seed=6, reorder=ms.REORDER_RCM,
+                       precision=getattr(ms, "PREC_" + precision))
+    P = I.p_dense(6, Ao.n, 4)
+    rng = np.random.default_rng(6)
+    xg = torch.zeros(Ao.n, dtype=torch.float64, device="cuda")
+    for k in range(4):
+        xprev = xg.cpu().numpy()
+        b = xprev + 0.1 * rng.standard_normal(Ao.n)
+        info = solver.solve_next(dev(torch, b), xg)
+        x = xg.cpu().numpy()
+        true = np.linalg.norm(b - orc.spmv(Ao, x)) / np.linalg.norm(b)
+        xo, io, _, _ = orc.solve(Ao, b, xprev, 4, 2, P)
+        err = np.linalg.norm(x - xo) / np.linalg.norm(xo)
+        print(f"  system {k}: true relres {true:.2e}, vs FP64 oracle {err:.2e}, MVs {info['mv_total']}")
+        assert info["converged"] and true <= 1e-8 * (1 + 1e-6)
+        assert err <= 1e-6
