@@ -92,7 +92,8 @@ def cpu_baseline(cd, s, ell, mvs_per_system):
 
 def class_kernels(cls: str, s: int, ell: int):
     """The kernels of one timing class of the FP64 solver."""
-    return {"spmv": [f"k_spmv_dia<double, {s}, double>", f"k_spmv<double, {s}, double>"],
+    return {"spmv": [f"k_spmv_dia<double, {s}, double, true>", f"k_spmv_dia<double, {s}, double, false>",
+                     f"k_spmv<double, {s}, double>"],
             "eta": [f"k_eta<double, {s}>", f"k_eta_low<double, {s}>"],
             "gamma": [f"k_gamma<double, {s}>"],
             "poly": [f"k_poly<double, {s}, {ell}>"],

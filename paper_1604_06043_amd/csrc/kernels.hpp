@@ -732,7 +732,8 @@ __device__ __forceinline__ void dia_rows(int64_t n, int nd, const DiaOffsets &do
 // presence mask), no column indices.  Present entries are multiplied, rounded
 // and added in ascending column order (the CSR order), so the result equals the
 // sliced product bit for bit.
-template <typename T, int S, typename TM = T>
+// CST: constant diagonals (dval unused), else values streamed from dval.
+template <typename T, int S, typename TM, bool CST>
 __global__ __launch_bounds__(SPMV_BLOCK) void k_spmv_dia(int64_t n, int nd, DiaOffsets doff,
                                                          DiaConst cv,
                                                          const uint16_t *__restrict__ mask,
@@ -747,10 +748,7 @@ __global__ __launch_bounds__(SPMV_BLOCK) void k_spmv_dia(int64_t n, int nd, DiaO
     double vals[S + 2];
 #pragma unroll
     for (int v = 0; v < S + 2; ++v) vals[v] = 0.0;
-    if (dval)
-        dia_rows<false, T, S, TM>(n, nd, doff, cv, mask, dval, x, y, b, resid, a.pkey, vals);
-    else
-        dia_rows<true, T, S, TM>(n, nd, doff, cv, mask, dval, x, y, b, resid, a.pkey, vals);
+    dia_rows<CST, T, S, TM>(n, nd, doff, cv, mask, dval, x, y, b, resid, a.pkey, vals);
     spmv_finalize<S>(vals, ctl, part, stride, a);
 }
 

@@ -466,9 +466,14 @@ void launch_spmv(int grid, hipStream_t stream, const Sell<TM> &A, const T *x, T 
         switch (a.s) {
 #define CASE(S)                                                                                   \
     case S:                                                                                       \
-        hipLaunchKernelGGL((k_spmv_dia<T, S, TM>), dim3(grid), dim3(SPMV_BLOCK), 0, stream, A.n, A.nd, \
-                           A.doff, A.cv, A.dmask, (const TM *)A.dval, x, y, b, ctl, part,         \
-                           PART_STRIDE, a);                                                       \
+        if (A.dconst)                                                                             \
+            hipLaunchKernelGGL((k_spmv_dia<T, S, TM, true>), dim3(grid), dim3(SPMV_BLOCK), 0, stream, \
+                               A.n, A.nd, A.doff, A.cv, A.dmask, (const TM *)A.dval, x, y, b, ctl,    \
+                               part, PART_STRIDE, a);                                                 \
+        else                                                                                      \
+            hipLaunchKernelGGL((k_spmv_dia<T, S, TM, false>), dim3(grid), dim3(SPMV_BLOCK), 0, stream,\
+                               A.n, A.nd, A.doff, A.cv, A.dmask, (const TM *)A.dval, x, y, b, ctl,    \
+                               part, PART_STRIDE, a);                                                 \
         break;
             CASE(0) CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
 #undef CASE
