@@ -255,6 +255,20 @@ mstab_status mstab_recycle_get(const mstab_solver *h, double *U, double *V, int6
  */
 mstab_status mstab_recycle_set(mstab_solver *h, const double *U, const double *V, int64_t level);
 
+/*
+ * Checkpoint and resume of the recycle state, the data a fetch writes out
+ * (Section 5, preliminaries): a self-describing host byte blob holding the
+ * level, the P^T V cache and U, V (with the s, n, cut-space seed,
+ * preconditioner and order they belong to).  export: dst (host, cap bytes)
+ * receives the blob and *len its size; dst NULL only sets *len.  import:
+ * installs a blob exported from a handle of the same problem (same s, n,
+ * p_seed, precond and reorder), so that the next solve starts as the
+ * exporting handle's would, bit for bit.  F64 and F32_MATRIX precision only.
+ * Errors: E_INVALID (NULL, cap too small, foreign or truncated blob), E_HIP.
+ */
+mstab_status mstab_recycle_export(const mstab_solver *h, void *dst, size_t cap, size_t *len);
+mstab_status mstab_recycle_import(mstab_solver *h, const void *src, size_t len);
+
 /* Free the handle and its device memory.  NULL is accepted. */
 mstab_status mstab_destroy(mstab_solver *h);
 

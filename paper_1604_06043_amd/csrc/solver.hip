@@ -1766,6 +1766,102 @@ mstab_status mstab_recycle_set(mstab_solver *h, const double *U, const double *V
     API_END(h)
 }
 
+namespace {
+// Layout of an exported recycle state (host byte blob): this header, then
+// the s x s P^T V cache (MAXS x MAXS doubles), then U and V (s columns of n
+// doubles each, column-major), the last two only when have is set.
+struct RecycleBlob {
+    char magic[8];
+    uint32_t version;
+    int32_t s;
+    int64_t n;
+    uint64_t p_seed;
+    int32_t precond, reorder;
+    int32_t have, pad;
+    int64_t level;
+};
+constexpr char RECYCLE_MAGIC[8] = {'M', 'S', 'T', 'A', 'B', 'R', 'E', 'C'};
+constexpr uint32_t RECYCLE_VERSION = 1;
+
+size_t recycle_blob_size(const mstab_solver *h, bool have)
+{
+    return sizeof(RecycleBlob) + sizeof(double) * MAXS * MAXS +
+           (have ? 2 * sizeof(double) * (size_t)h->s * (size_t)h->n : 0);
+}
+}  // namespace
+
+mstab_status mstab_recycle_export(const mstab_solver *h, void *dst, size_t cap, size_t *len)
+{
+    if (!h || !len) return MSTAB_E_INVALID;
+    mstab_solver *hh = const_cast<mstab_solver *>(h);
+    API_BEGIN
+    if (h->mixed()) fail(MSTAB_E_INVALID, "recycle_export needs F64 or F32_MATRIX precision");
+    const Engine<double> &E = h->e64;
+    const size_t need = recycle_blob_size(h, E.rec_have);
+    *len = need;
+    if (!dst) return MSTAB_OK;   // size query
+    if (cap < need) fail(MSTAB_E_INVALID, "buffer of %zu bytes, %zu needed", cap, need);
+    RecycleBlob hd{};
+    memcpy(hd.magic, RECYCLE_MAGIC, sizeof hd.magic);
+    hd.version = RECYCLE_VERSION;
+    hd.s = h->s;
+    hd.n = h->n;
+    hd.p_seed = h->opt.p_seed;
+    hd.precond = h->opt.precond;
+    hd.reorder = h->opt.reorder;
+    hd.have = E.rec_have ? 1 : 0;
+    hd.level = E.rec_level;
+    char *out = static_cast<char *>(dst);
+    memcpy(out, &hd, sizeof hd);
+    double *ptv = reinterpret_cast<double *>(out + sizeof hd);
+    HIPCHK(hipMemcpyAsync(ptv, E.rec_ptv, sizeof(double) * MAXS * MAXS, hipMemcpyDeviceToHost, h->stream));
+    if (E.rec_have) {
+        double *U = ptv + MAXS * MAXS;
+        double *V = U + (size_t)h->s * (size_t)h->n;
+        HIPCHK(hipMemcpy2DAsync(U, sizeof(double) * h->n, E.recU, sizeof(double) * E.ld,
+                                sizeof(double) * h->n, h->s, hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(hipMemcpy2DAsync(V, sizeof(double) * h->n, E.recV, sizeof(double) * E.ld,
+                                sizeof(double) * h->n, h->s, hipMemcpyDeviceToHost, h->stream));
+    }
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return MSTAB_OK;
+    API_END(hh)
+}
+
+mstab_status mstab_recycle_import(mstab_solver *h, const void *src, size_t len)
+{
+    if (!h) return MSTAB_E_INVALID;
+    API_BEGIN
+    if (h->mixed()) fail(MSTAB_E_INVALID, "recycle_import needs F64 or F32_MATRIX precision");
+    if (!src || len < sizeof(RecycleBlob)) fail(MSTAB_E_INVALID, "no recycle blob");
+    RecycleBlob hd;
+    memcpy(&hd, src, sizeof hd);
+    if (memcmp(hd.magic, RECYCLE_MAGIC, sizeof hd.magic) != 0 || hd.version != RECYCLE_VERSION)
+        fail(MSTAB_E_INVALID, "not a recycle blob of this version");
+    if (hd.s != h->s || hd.n != h->n || hd.p_seed != h->opt.p_seed || hd.precond != h->opt.precond ||
+        hd.reorder != h->opt.reorder)
+        fail(MSTAB_E_INVALID, "recycle blob of another problem (s, n, P seed, preconditioner or order differ)");
+    if (len < recycle_blob_size(h, hd.have != 0)) fail(MSTAB_E_INVALID, "recycle blob truncated");
+    Engine<double> &E = h->e64;
+    if (!hd.have) {
+        E.rec_have = false;
+        return MSTAB_OK;
+    }
+    const double *ptv = reinterpret_cast<const double *>(static_cast<const char *>(src) + sizeof hd);
+    const double *U = ptv + MAXS * MAXS;
+    const double *V = U + (size_t)h->s * (size_t)h->n;
+    HIPCHK(hipMemcpyAsync(E.rec_ptv, ptv, sizeof(double) * MAXS * MAXS, hipMemcpyHostToDevice, h->stream));
+    HIPCHK(hipMemcpy2DAsync(E.recU, sizeof(double) * E.ld, U, sizeof(double) * h->n,
+                            sizeof(double) * h->n, h->s, hipMemcpyHostToDevice, h->stream));
+    HIPCHK(hipMemcpy2DAsync(E.recV, sizeof(double) * E.ld, V, sizeof(double) * h->n,
+                            sizeof(double) * h->n, h->s, hipMemcpyHostToDevice, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    E.rec_level = hd.level;
+    E.rec_have = true;
+    return MSTAB_OK;
+    API_END(h)
+}
+
 mstab_status mstab_destroy(mstab_solver *h)
 {
     release_handle(h);

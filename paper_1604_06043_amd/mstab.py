@@ -31,7 +31,7 @@ EXPORTS = [
     "mstab_options_default", "mstab_create", "mstab_solve_next", "mstab_solve_batch",
     "mstab_solve_next_guess",
     "mstab_mv_count", "mstab_residual", "mstab_residual_history", "mstab_recycle_reset", "mstab_recycle_get",
-    "mstab_recycle_set", "mstab_destroy", "mstab_status_str", "mstab_last_error",
+    "mstab_recycle_set", "mstab_recycle_export", "mstab_recycle_import", "mstab_destroy", "mstab_status_str", "mstab_last_error",
     "mstab_set_profiling", "mstab_kernel_stats", "mstab_convdiff_nnz", "mstab_assemble_convdiff",
     "mstab_jacobi_split", "mstab_permutation", "mstab_rcm_order", "mstab_spmv", "mstab_project",
     "mstab_rhs_step",
@@ -99,6 +99,8 @@ def load(path: str = LIB_PATH):
         "mstab_recycle_reset": (i32, [P]),
         "mstab_recycle_get": (i32, [P, P, P, ctypes.POINTER(i64), ctypes.POINTER(i32)]),
         "mstab_recycle_set": (i32, [P, P, P, i64]),
+        "mstab_recycle_export": (i32, [P, P, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)]),
+        "mstab_recycle_import": (i32, [P, P, ctypes.c_size_t]),
         "mstab_destroy": (i32, [P]),
         "mstab_status_str": (ctypes.c_char_p, [i32]),
         "mstab_last_error": (ctypes.c_char_p, [P]),
@@ -362,6 +364,18 @@ class Solver:
         """U, V: (s, n) contiguous float64 device tensors (column q = row q)."""
         _require_cuda(U, V)
         _check(self.lib.mstab_recycle_set(self.h, _ptr(U), _ptr(V), int(level)), self.h)
+
+    def recycle_export(self) -> bytes:
+        """The recycle state as a byte blob (checkpoint)."""
+        need = ctypes.c_size_t()
+        _check(self.lib.mstab_recycle_export(self.h, None, 0, ctypes.byref(need)), self.h)
+        buf = ctypes.create_string_buffer(need.value)
+        _check(self.lib.mstab_recycle_export(self.h, buf, need, ctypes.byref(need)), self.h)
+        return buf.raw[:need.value]
+
+    def recycle_import(self, blob: bytes):
+        """Install a recycle state exported from a handle of the same problem."""
+        _check(self.lib.mstab_recycle_import(self.h, blob, len(blob)), self.h)
 
     def set_profiling(self, enable, every: int = 1):
         """Time one launch in `every` of each kernel class (False: stop)."""

@@ -983,3 +983,42 @@ def test_reordered_graph_mixed_precision(torch_dev, ms, orc, precision):
         print(f"  system {k}: true relres {true:.2e}, vs FP64 oracle {err:.2e}, MVs {info['mv_total']}")
         assert info["converged"] and true <= 1e-8 * (1 + 1e-6)
         assert err <= 1e-6
+
+
+def test_recycle_export_import_resumes_bit_for_bit(torch_dev, ms, orc):
+    """A handle resumed from an exported recycle state (a checkpoint of what a
+    fetch writes out) solves the next system exactly as the exporting handle
+    does; a blob of another problem is refused."""
+    torch = torch_dev
+    cd = I.config("c1", seed=3, n=48)
+    Ag = gpu_assemble(ms, cd)
+    s, ell = 4, 2
+    a = ms.Solver(Ag, s, ell, p_seed=3)
+    f = dev(torch, cd.f)
+    x = torch.zeros(cd.N, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(x)
+    empty = a.recycle_export()
+    for _ in range(3):
+        ms.mstab_rhs_step(x, cd.inv_dt, f, b)
+        a.solve_next(b, x)
+    blob = a.recycle_export()
+    assert len(blob) > len(empty)
+    resumed = ms.Solver(Ag, s, ell, p_seed=3)
+    resumed.recycle_import(blob)
+    ms.mstab_rhs_step(x, cd.inv_dt, f, b)
+    x2 = x.clone()
+    ia = a.solve_next(b, x)
+    ib = resumed.solve_next(b, x2)
+    assert ia["recycled"] and ib["recycled"]
+    np.testing.assert_array_equal(x.cpu().numpy(), x2.cpu().numpy())
+    assert ia["mv_total"] == ib["mv_total"]
+    # an empty state resets
+    resumed.recycle_import(empty)
+    assert resumed.recycle_get() is None
+    other = ms.Solver(Ag, s, ell, p_seed=4)
+    with pytest.raises(ms.MstabError, match="another problem"):
+        other.recycle_import(blob)
+    with pytest.raises(ms.MstabError, match="recycle blob"):
+        resumed.recycle_import(blob[:100])
+    for sv in (a, resumed, other):
+        sv.close()
