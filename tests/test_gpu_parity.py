@@ -1022,3 +1022,39 @@ def test_recycle_export_import_resumes_bit_for_bit(torch_dev, ms, orc):
         resumed.recycle_import(blob[:100])
     for sv in (a, resumed, other):
         sv.close()
+
+
+@pytest.mark.parametrize("eps", [1e-6, 1e-1])
+def test_corrupted_recycled_u_is_reported(torch_dev, ms, orc, eps):
+    """Recycled U perturbed so that V != A U: the recursive residual no longer
+    tracks b - A x.  The true-residual check catches it: a small perturbation
+    is repaired by replacement, a large one ends NOT_CONVERGED with the true
+    residual reported; the GPU reaches the oracle's outcome either way and never
+    reports convergence that the true residual does not confirm."""
+    torch = torch_dev
+    cd = I.config("c1", seed=5, n=32)
+    Ao = orc.assemble_convdiff(cd.dim, cd.n, cd.beta, cd.inv_dt)
+    Ag = gpu_assemble(ms, cd)
+    s, ell = 4, 2
+    P = I.p_dense(5, cd.N, s)
+    x1, _, rec, _ = orc.solve(Ao, cd.f, np.zeros(cd.N), s, ell, P)
+    b2 = orc.rhs_step(x1, cd.inv_dt, cd.f)
+    rng = np.random.default_rng(5)
+    rec.U = np.asfortranarray(rec.U + eps * np.linalg.norm(rec.U, axis=0) / np.sqrt(cd.N)
+                              * rng.standard_normal(rec.U.shape))
+    xo, io, _, _ = orc.solve(Ao, b2, x1, s, ell, P, recycle=rec.copy())
+    solver = ms.Solver(Ag, s, ell, p_seed=5)
+    solver.recycle_set(dev(torch, rec.U.T), dev(torch, rec.V.T), rec.level)
+    x = dev(torch, x1)
+    st, ig = solver.solve_next_raw(dev(torch, b2), x)
+    xg = x.cpu().numpy()
+    true = np.linalg.norm(b2 - orc.spmv(Ao, xg)) / np.linalg.norm(b2)
+    print(f"  eps {eps}: gpu status {st} true {true:.2e} repl {ig['replacements']}; "
+          f"oracle status {io.status} true {io.relres_true:.2e} repl {io.replacements}")
+    assert st == io.status and bool(ig["converged"]) == io.converged
+    assert abs(ig["relres_true"] - true) <= 1e-6 * true + 1e-15
+    if io.converged:
+        assert true <= 1e-8 * (1 + 1e-6) and ig["replacements"] >= 1
+    else:
+        assert st == ms.NOT_CONVERGED and true > 1e-8
+    solver.close()
