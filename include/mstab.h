@@ -369,7 +369,7 @@ mstab_status mstab_rhs_step(int64_t n, const double *x, double inv_dt, const dou
  * residual r0 = b^(i+1) - A x^(i) (mstab_residual) and x^(i): d solves
  * A d = r0, so the map is linear in r0 and, for a matrix with constant
  * coefficients, translation invariant, which a convolution can approximate
- * locally.  The solver stays the judge: mstab_solve_next_guess takes the
+ * locally.  The solver has the last word: mstab_solve_next_guess takes the
  * network's guess only if its true residual is below that of x^(i).
  *
  * Network: 6 layers of 3x3 convolutions with zero padding, channels

@@ -848,7 +848,7 @@ struct Engine {
 
     // Solve A X = b from the current X (b: n entries of T on the device).
     // check_true = false: stop on the recursive residual (inner solves of the
-    // mixed mode, whose FP64 outer residual is the judge).
+    // mixed mode, whose FP64 outer residual decides).
     SolveResult solve(const T *b, double tol, int64_t max_mv, int method, int fetch_policy,
                       double fetch_rel, int64_t fetch_level, int max_repl, bool check_true = true)
     {
