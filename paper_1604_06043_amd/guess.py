@@ -135,20 +135,32 @@ def train(cnn: M.Cnn, inp, tgt, epochs: int, batch: int, lr: float, seed: int = 
     return hist
 
 
-def network_guess(solver: M.Solver, cnn: M.Cnn, b, x, r, xg, rounds: int = 1):
-    """x_guess after ``rounds`` corrections x <- x + N(b - A x) starting from x
-    (the network N as an approximate inverse of A); one product with A per
-    round.  Returns the number of products."""
+def network_guess(solver: M.Solver, cnn: M.Cnn, b, x, r, xg, rounds: int = 1, smooth: int = 0,
+                  tmp=None, omega: float = 2.0 / 3.0):
+    """x_guess (into xg) after ``rounds`` corrections x <- x + N(b - A x)
+    starting from x (the network N as an approximate inverse of A), then
+    ``smooth`` damped Jacobi sweeps x <- x + (omega / unit)(b - A x) (unit: the
+    operator's diagonal entry), which damp the non-smooth part of the
+    network's error that A amplifies; the sweeps alternate between xg and tmp
+    (same shape, needed when smooth > 0).  One product with A per round and per
+    sweep.  Returns the number of products."""
+    bufs = (xg, tmp)
+    cur = bufs[smooth % 2]          # so that the last sweep writes xg
     solver.residual(b, x, r)
-    cnn.guess(x, r, xg)
+    cnn.guess(x, r, cur)
     for _ in range(rounds - 1):
-        solver.residual(b, xg, r)
-        cnn.guess(xg, r, xg)
-    return rounds
+        solver.residual(b, cur, r)
+        cnn.guess(cur, r, cur)
+    for k in range(smooth):
+        nxt = bufs[(smooth - k - 1) % 2]
+        solver.residual(b, cur, r)
+        M.mstab_rhs_step(r, omega / cnn.unit, cur, nxt)
+        cur = nxt
+    return rounds + smooth
 
 
 def evaluate(prob: Problem, cnn: M.Cnn | None, seed: int, steps: int, s: int = 4, ell: int = 2,
-             tol: float = 1e-8, method: int = M.METHOD_MSTAB, rounds: int = 1):
+             tol: float = 1e-8, method: int = M.METHOD_MSTAB, rounds: int = 1, smooth: int = 0):
     """Solve a sequence with (cnn given) or without the learned guess.
 
     Returns per-system MVs (all products with A, the guess's residuals and the
@@ -161,6 +173,7 @@ def evaluate(prob: Problem, cnn: M.Cnn | None, seed: int, steps: int, s: int = 4
     b = torch.empty_like(x)
     r0 = torch.empty_like(x)
     xg = torch.empty_like(x)
+    tmp = torch.empty_like(x) if smooth else None
     mv, acc, res = [], [], []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -170,7 +183,7 @@ def evaluate(prob: Problem, cnn: M.Cnn | None, seed: int, steps: int, s: int = 4
             info = solver.solve_next(b, x)
             mv.append(info["mv_total"])
         else:
-            extra = network_guess(solver, cnn, b, x, r0, xg, rounds)
+            extra = network_guess(solver, cnn, b, x, r0, xg, rounds, smooth, tmp)
             info = solver.solve_next_guess(b, x, xg, x)
             mv.append(info["mv_total"] + extra)
             acc.append(info["guess_accepted"])
