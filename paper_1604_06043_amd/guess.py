@@ -135,15 +135,28 @@ def train(cnn: M.Cnn, inp, tgt, epochs: int, batch: int, lr: float, seed: int = 
     return hist
 
 
+def jacobi_sweeps(solver: M.Solver, b, cur, r, bufs, unit: float, sweeps: int,
+                  omega: float = 2.0 / 3.0):
+    """``sweeps`` damped Jacobi steps x <- x + (omega / unit)(b - A x) from cur
+    (unit: the operator's constant diagonal entry), alternating between the
+    two buffers of bufs so that the last step writes bufs[0].  They damp the
+    non-smooth part of a guess's error, which A amplifies.  One product with A
+    each."""
+    for k in range(sweeps):
+        nxt = bufs[(sweeps - k - 1) % 2]
+        solver.residual(b, cur, r)
+        M.mstab_rhs_step(r, omega / unit, cur, nxt)
+        cur = nxt
+    return sweeps
+
+
 def network_guess(solver: M.Solver, cnn: M.Cnn, b, x, r, xg, rounds: int = 1, smooth: int = 0,
-                  tmp=None, omega: float = 2.0 / 3.0):
+                  tmp=None):
     """x_guess (into xg) after ``rounds`` corrections x <- x + N(b - A x)
     starting from x (the network N as an approximate inverse of A), then
-    ``smooth`` damped Jacobi sweeps x <- x + (omega / unit)(b - A x) (unit: the
-    operator's diagonal entry), which damp the non-smooth part of the
-    network's error that A amplifies; the sweeps alternate between xg and tmp
-    (same shape, needed when smooth > 0).  One product with A per round and per
-    sweep.  Returns the number of products."""
+    ``smooth`` damped Jacobi sweeps (tmp: a second buffer, needed when
+    smooth > 0).  One product with A per round and per sweep.  Returns the
+    number of products."""
     bufs = (xg, tmp)
     cur = bufs[smooth % 2]          # so that the last sweep writes xg
     solver.residual(b, x, r)
@@ -151,17 +164,14 @@ def network_guess(solver: M.Solver, cnn: M.Cnn, b, x, r, xg, rounds: int = 1, sm
     for _ in range(rounds - 1):
         solver.residual(b, cur, r)
         cnn.guess(cur, r, cur)
-    for k in range(smooth):
-        nxt = bufs[(smooth - k - 1) % 2]
-        solver.residual(b, cur, r)
-        M.mstab_rhs_step(r, omega / cnn.unit, cur, nxt)
-        cur = nxt
-    return rounds + smooth
+    return rounds + jacobi_sweeps(solver, b, cur, r, bufs, cnn.unit, smooth)
 
 
 def evaluate(prob: Problem, cnn: M.Cnn | None, seed: int, steps: int, s: int = 4, ell: int = 2,
              tol: float = 1e-8, method: int = M.METHOD_MSTAB, rounds: int = 1, smooth: int = 0):
-    """Solve a sequence with (cnn given) or without the learned guess.
+    """Solve a sequence with (cnn given) or without the learned guess.  With
+    cnn None and smooth > 0, the guess is x^(i) after ``smooth`` damped Jacobi
+    sweeps (the same gate; the control for what the network adds).
 
     Returns per-system MVs (all products with A, the guess's residuals and the
     gate's two checks included), seconds per system over the whole loop, and
@@ -179,11 +189,14 @@ def evaluate(prob: Problem, cnn: M.Cnn | None, seed: int, steps: int, s: int = 4
     t0 = time.perf_counter()
     for j in range(steps):
         M.mstab_rhs_step(x, prob.cd.inv_dt, F[j], b)
-        if cnn is None:
+        if cnn is None and smooth == 0:
             info = solver.solve_next(b, x)
             mv.append(info["mv_total"])
         else:
-            extra = network_guess(solver, cnn, b, x, r0, xg, rounds, smooth, tmp)
+            if cnn is None:
+                extra = jacobi_sweeps(solver, b, x, r0, (xg, tmp), prob.unit, smooth)
+            else:
+                extra = network_guess(solver, cnn, b, x, r0, xg, rounds, smooth, tmp)
             info = solver.solve_next_guess(b, x, xg, x)
             mv.append(info["mv_total"] + extra)
             acc.append(info["guess_accepted"])
@@ -234,7 +247,7 @@ def guess_quality(prob: Problem, cnn: M.Cnn, seed: int, steps: int, s: int = 4, 
 
 
 def run(n=512, train_seeds=10, steps=200, eval_steps=200, epochs=20, batch=8, lr=1e-3, s=4, ell=2,
-        seed=0, dilation=DILATION, rounds=1, log=print):
+        seed=0, dilation=DILATION, rounds=1, smooth=4, held_out=(1000, 1001), log=print):
     import torch
     torch.cuda.set_device(0)
     prob = Problem(n)
@@ -250,22 +263,28 @@ def run(n=512, train_seeds=10, steps=200, eval_steps=200, epochs=20, batch=8, lr
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     del inp, tgt
-    held = 1000 + seed
-    plain = evaluate(prob, None, held, eval_steps, s, ell)
-    learned = evaluate(prob, cnn, held, eval_steps, s, ell, rounds=rounds)
-    q, qe = guess_quality(prob, cnn, held, eval_steps, s, ell, rounds=max(rounds, 1))
+    evals = []
+    for held in held_out:
+        row = {"sequence_seed": held}
+        for name, net, sm in (("plain", None, 0), ("learned", cnn, 0),
+                              (f"learned_smooth{smooth}", cnn, smooth),
+                              (f"x_prev_smooth{smooth}", None, smooth)):
+            if name != "plain" and sm == 0 and net is None:
+                continue
+            r = evaluate(prob, net, held, eval_steps, s, ell, rounds=rounds, smooth=sm)
+            row[name] = {"mv_per_system": r["mv_per_system"], "seconds_per_system": r["seconds_per_system"],
+                         "accepted": int(np.sum(r["accepted"])) if r["accepted"] else None}
+            log(f"[{held}] {name}: {r['mv_per_system']:.1f} MVs/system, "
+                f"{1e3 * r['seconds_per_system']:.2f} ms/system")
+        evals.append(row)
+    q, qe = guess_quality(prob, cnn, held_out[0], eval_steps, s, ell, rounds=max(rounds, 1))
     return {
         "workload": f"convdiff2d_{n}x{n}_pe100_bumps", "n": n * n, "s": s, "ell": ell,
         "dilation": list(dilation), "rounds": rounds,
         "train_samples": gen["samples"], "epochs": epochs, "batch": batch,
         "seconds_generate": t_gen, "seconds_train": t_train,
         "loss_first_epoch": hist[0], "loss_last_epoch": hist[-1],
-        "eval_steps": eval_steps,
-        "plain": {"mv_per_system": plain["mv_per_system"],
-                  "seconds_per_system": plain["seconds_per_system"]},
-        "learned": {"mv_per_system": learned["mv_per_system"],
-                    "seconds_per_system": learned["seconds_per_system"],
-                    "accepted": int(np.sum(learned["accepted"]))},
+        "eval_steps": eval_steps, "smooth": smooth, "evaluations": evals,
         "guess_residual_ratio_median": [float(v) for v in np.median(q, axis=0)],
         "guess_error_ratio_median": [float(v) for v in np.median(qe, axis=0)],
     }
@@ -321,6 +340,8 @@ def main():
     ap.add_argument("--ell", type=int, default=2)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--rounds", type=int, default=1)
+    ap.add_argument("--smooth", type=int, default=4,
+                    help="damped Jacobi sweeps after the network's guess")
     ap.add_argument("--train-bench", action="store_true",
                     help="time the network alone on synthetic batches")
     ap.add_argument("--calib", action="store_true")
@@ -329,7 +350,7 @@ def main():
         print(json.dumps(train_bench(a.n, a.batch, calib=a.calib)), flush=True)
         return
     r = run(a.n, a.train_seeds, a.steps, a.eval_steps, a.epochs, a.batch, a.lr, a.s, a.ell, a.seed,
-            rounds=a.rounds, log=lambda m: print(m, flush=True))
+            rounds=a.rounds, smooth=a.smooth, log=lambda m: print(m, flush=True))
     print(json.dumps(r), flush=True)
 
 
