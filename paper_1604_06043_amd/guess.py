@@ -9,9 +9,10 @@ the paper's setting of one A and many right-hand sides.
     generate()  runs the GPU solver along sequences and keeps network samples
                 (prepared inputs and targets) in device memory;
     train()     Adam on the mstab_cnn_* kernels;
-    evaluate()  the same held-out sequence with and without the guess: MVs
-                and seconds per system, guesses accepted by the solver's
-                true-residual gate.
+    evaluate()  the same held-out sequence with and without the guess (or
+                the guess followed by damped Jacobi sweeps, or the sweeps
+                alone from x^(k-1)): MVs and seconds per system, guesses
+                accepted by the solver's true-residual gate.
 
 ``python -m paper_1604_06043_amd.guess --n 512`` runs all three and prints one
 JSON line.  Everything numeric runs in the library's kernels; this module
