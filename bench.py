@@ -140,7 +140,7 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported by this build "
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
               f"(the solve is a single-GPU kernel path)", file=sys.stderr)
         sys.exit(2)
 
