@@ -89,7 +89,7 @@ def summarize(kt_dir, fetch_dir, write_dir, kernel, command, copy_bytes=256 << 2
 
 
 def write_md(summary: dict, path: str, title: str):
-    lines = [f"# {title}", "", "Command (from the repository root, on the GPU box):", "",
+    lines = [f"# {title}", "", "Command (from the repository root, on an MI355X):", "",
              "```", summary["command"], "```", "",
              "## Kernel durations (rocprofv3 --kernel-trace --stats)", "",
              "| kernel | calls | avg us | min us | max us | % time |", "|---|---|---|---|---|---|"]
