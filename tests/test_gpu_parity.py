@@ -1058,3 +1058,21 @@ def test_corrupted_recycled_u_is_reported(torch_dev, ms, orc, eps):
     else:
         assert st == ms.NOT_CONVERGED and true > 1e-8
     solver.close()
+
+
+def test_reordered_stencil_matrix(torch_dev, ms, orc):
+    """Reordering a stencil matrix (its RCM order is banded but not diagonal):
+    the handle falls back to the sliced copy and solves the sequence to the
+    tolerance on the original matrix, close to the unreordered solves."""
+    torch = torch_dev
+    cd = I.config("c1", seed=2, n=32)
+    Ao = orc.assemble_convdiff(cd.dim, cd.n, cd.beta, cd.inv_dt)
+    Ag = gpu_assemble(ms, cd)
+    xs_r, inf_r, _ = run_sequence_gpu(torch, ms, Ag, cd, 4, 2, 4, 0, reorder=ms.REORDER_RCM)
+    xs_p, inf_p, _ = run_sequence_gpu(torch, ms, Ag, cd, 4, 2, 4, 0)
+    kappa = np.linalg.cond(Ao.dense())
+    for k, (xr, xp) in enumerate(zip(xs_r, xs_p)):
+        b = xs_r[k - 1] * cd.inv_dt + cd.f if k else cd.f
+        true = np.linalg.norm(b - orc.spmv(Ao, xr)) / np.linalg.norm(b)
+        assert inf_r[k]["converged"] and true <= 1e-8 * (1 + 1e-6)
+        assert np.linalg.norm(xr - xp) <= 4 * kappa * 1e-8 * np.linalg.norm(xp) * (k + 1)
