@@ -733,8 +733,12 @@ __device__ __forceinline__ void dia_rows(int64_t n, int nd, const DiaOffsets &do
 // and added in ascending column order (the CSR order), so the result equals the
 // sliced product bit for bit.
 // CST: constant diagonals (dval unused), else values streamed from dval.
+// With FP32 values, 8 wavefronts per SIMD fit without spills; left alone the
+// register allocator settles on 7 for some s, which cost a sequence on the
+// FP32 copy of a 256^3 matrix 12% of its throughput.
 template <typename T, int S, typename TM, bool CST>
-__global__ __launch_bounds__(SPMV_BLOCK) void k_spmv_dia(int64_t n, int nd, DiaOffsets doff,
+__global__ __launch_bounds__(SPMV_BLOCK)
+__attribute__((amdgpu_waves_per_eu(sizeof(TM) == 4 ? 8 : 1))) void k_spmv_dia(int64_t n, int nd, DiaOffsets doff,
                                                          DiaConst cv,
                                                          const uint16_t *__restrict__ mask,
                                                          const TM *__restrict__ dval,
