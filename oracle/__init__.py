@@ -15,6 +15,9 @@ Functions follow the paper (Neuenhofen, arXiv 1604.06043):
   reproduces for s = l = 1;
 * :func:`assemble_convdiff`, :func:`spmv` -- the upwind finite-difference
   matrices of the synthetic workloads and the plain CSR product;
+* :func:`cholqr`, :func:`recycle_start` -- orthonormalization of fetched
+  U, V (an option of this build) and the projection of a new right-hand side
+  onto recycled data (Section 4.2);
 * :func:`jacobi_split`, :func:`solve_jacobi` -- the split preconditioned
   system of Section 5.1, L^{-1} A R^{-1} y = L^{-1} b with x = R^{-1} y, for
   the diagonal splitting L = R = |D|^{1/2}.
@@ -64,7 +67,11 @@ def _load():
         _lib.orc_spmv.argtypes = [i64, P, P, P, P, P]
         _lib.orc_solve.restype = i32
         _lib.orc_solve.argtypes = [i64, P, P, P, i32, i32, P, f64, i64, i32, i32, f64, i64, i32,
-                                   i32, P, P, P, P, P, P, P, P, P, P, i64, P, i64, P]
+                                   i32, i32, P, P, P, P, P, P, P, P, P, P, i64, P, i64, P]
+        _lib.orc_cholqr.restype = i32
+        _lib.orc_cholqr.argtypes = [i64, i32, P, P]
+        _lib.orc_recycle_start.restype = i32
+        _lib.orc_recycle_start.argtypes = [i64, i32, P, P, P, P, P]
         _lib.orc_set_sum_order.restype = None
         _lib.orc_set_sum_order.argtypes = [i32]
         _lib.orc_bicgstab.restype = i32
@@ -165,11 +172,13 @@ class Info:
 def solve(A: CSR, b, x0, s: int, ell: int, P: np.ndarray, tol: float = 1e-8,
           max_mv: int = 10 ** 9, method: int = MSTAB, fetch: int = FETCH_THRESHOLD,
           fetch_rel: float | None = None, fetch_level: int = -1, max_repl: int = 3,
-          recycle: Recycle | None = None, dump_cycle: int = -1, replace_every: int = 0):
+          recycle: Recycle | None = None, dump_cycle: int = -1, replace_every: int = 0,
+          orthonormalize: bool = False):
     """Run Algorithm 1 on A x = b from x0.  Returns (x, info, recycle, dump).
 
     ``replace_every`` = k > 0 replaces the recursive residual by b - A x after
-    every k-th cycle (Section 5.1's ocean run: k = 1).
+    every k-th cycle (Section 5.1's ocean run: k = 1).  ``orthonormalize``
+    applies :func:`cholqr` to the U, V a solve fetches.
 
     ``recycle`` is updated in place (fetched data) and also returned.
     ``dump`` (if dump_cycle >= 0) is a dict with the state after the level
@@ -199,7 +208,8 @@ def solve(A: CSR, b, x0, s: int, ell: int, P: np.ndarray, tol: float = 1e-8,
         dump = np.zeros(n * (2 + ell + s * (ell + 2)) + ell + n * (2 + 2 * s))
     st = lib.orc_solve(n, _ptr(A.row_ptr), _ptr(A.col), _ptr(A.val), s, ell, _ptr(P),
                        float(tol), int(max_mv), int(method), int(fetch), float(fetch_rel),
-                       int(fetch_level), int(max_repl), int(replace_every), _ptr(b), _ptr(x),
+                       int(fetch_level), int(max_repl), int(replace_every), int(bool(orthonormalize)),
+                       _ptr(b), _ptr(x),
                        _ptr(recycle.U), _ptr(recycle.V), _ptr(lvl), _ptr(have),
                        _ptr(oi), _ptr(of), _ptr(hmv), _ptr(hres), cap, _ptr(hl),
                        int(dump_cycle), _ptr(dump))
@@ -229,19 +239,64 @@ def solve(A: CSR, b, x0, s: int, ell: int, P: np.ndarray, tol: float = 1e-8,
     return x, info, recycle, dd
 
 
-class reversed_sums:
-    """Context: every inner product of the oracle sums from the last index down.
+SUM_FORWARD, SUM_REVERSE, SUM_BLOCKED = 0, 1, 2
 
-    Same definition, other rounding order; comparing the two runs measures the
-    rounding sensitivity of the iteration itself."""
+
+class sum_order:
+    """Context: every inner product of the oracle uses another summation order.
+
+    ``SUM_REVERSE`` sums from the last index down; ``SUM_BLOCKED`` sums blocks
+    of 256 consecutive terms and adds the block sums pairwise.  Same
+    definition, other rounding; comparing runs measures the rounding
+    sensitivity of the iteration itself.  The order is a property of the
+    calling thread (solves in other threads keep theirs)."""
+
+    def __init__(self, order: int):
+        self.order = order
 
     def __enter__(self):
-        _load().orc_set_sum_order(1)
+        _load().orc_set_sum_order(self.order)
         return self
 
     def __exit__(self, *exc):
-        _load().orc_set_sum_order(0)
+        _load().orc_set_sum_order(SUM_FORWARD)
         return False
+
+
+def cholqr(U: np.ndarray, V: np.ndarray | None = None) -> bool:
+    """Orthonormalize recycled data in place (n x s, column-major): CholQR in
+    FP64, U := U R^{-1}, V := V R^{-1} with U^T U = R^T R.  Returns False,
+    leaving both untouched, when U^T U is not numerically positive definite."""
+    for M in (U, V):
+        if M is not None and not (M.flags.f_contiguous and M.dtype == np.float64):
+            raise ValueError("U, V must be Fortran-ordered float64")
+    n, s = U.shape
+    st = _load().orc_cholqr(n, s, _ptr(U), _ptr(V))
+    if st < 0:
+        raise ValueError("cholqr: bad arguments")
+    return st == 0
+
+
+def recycle_start(P: np.ndarray, U: np.ndarray, V: np.ndarray, r: np.ndarray, x: np.ndarray):
+    """The projection of a right-hand side onto recycled data (Section 4.2):
+    gamma with r - V gamma orthogonal to P; returns (r - V gamma, x + U gamma)."""
+    n, s = U.shape
+    P = np.asfortranarray(P, dtype=np.float64)
+    U = np.asfortranarray(U, dtype=np.float64)
+    V = np.asfortranarray(V, dtype=np.float64)
+    r = np.array(r, dtype=np.float64, copy=True)
+    x = np.array(x, dtype=np.float64, copy=True)
+    st = _load().orc_recycle_start(n, s, _ptr(P), _ptr(U), _ptr(V), _ptr(r), _ptr(x))
+    if st != 0:
+        raise RuntimeError("recycle_start: singular P^T V" if st == 1 else "recycle_start failed")
+    return r, x
+
+
+class reversed_sums(sum_order):
+    """Context: every inner product of the oracle sums from the last index down."""
+
+    def __init__(self):
+        super().__init__(SUM_REVERSE)
 
 
 def bicgstab(A: CSR, b, x0, rhat, iters: int) -> np.ndarray:

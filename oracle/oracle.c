@@ -40,6 +40,8 @@
  *   - A breakdown (singular small system) drops U, V and restarts from the
  *     true residual b - A x (one counted MV) with an Arnoldi basis, at most
  *     twice per solve; a third breakdown is returned as an error.
+ *   - Optionally (not in the paper) the fetched U, V are orthonormalized by
+ *     CholQR in FP64 (orc_cholqr), keeping V = A U.
  *
  * Build: gcc -O2 -ffp-contract=off -fPIC -shared (no FMA contraction, so every
  * a*b+c below rounds twice, as written).
@@ -176,20 +178,45 @@ void orc_spmv(int64_t n, const int32_t *rp, const int32_t *ci, const double *va,
     matvec(&A, x, y);
 }
 
-/* Inner products are plain sums; `sum_reverse` runs them from the last index
- * to the first.  Both orders compute the same definition; the tests compare
- * the two to measure how much the iteration amplifies rounding alone. */
-static int sum_reverse = 0;
+/* Inner products are plain sums in one of three orders: 0 from the first
+ * index to the last (the default), 1 from the last to the first, 2 in blocks
+ * of 256 consecutive terms, each summed from its first term, whose sums are
+ * then added pairwise (a balanced tree over the blocks).  All three compute the
+ * same definition; the tests compare them to measure how much the iteration
+ * amplifies rounding alone. */
+static _Thread_local int sum_order = 0;   /* per calling thread */
 
-void orc_set_sum_order(int reverse) { sum_reverse = reverse ? 1 : 0; }
+void orc_set_sum_order(int order) { sum_order = (order == 1 || order == 2) ? order : 0; }
+
+#define ORC_SUM_BLOCK 256
+
+static double tree_sum(const double *v, int64_t m)
+{
+    if (m == 1) return v[0];
+    int64_t h = m / 2;
+    return tree_sum(v, h) + tree_sum(v + h, m - h);
+}
 
 static double dot(int64_t n, const double *a, const double *b)
 {
     double s = 0.0;
-    if (sum_reverse)
+    if (sum_order == 1) {
         for (int64_t i = n - 1; i >= 0; --i) s += a[i] * b[i];
-    else
+    } else if (sum_order == 2 && n > 0) {
+        int64_t nb = (n + ORC_SUM_BLOCK - 1) / ORC_SUM_BLOCK;
+        double *blk = (double *)malloc((size_t)nb * sizeof(double));
+        if (!blk) abort();
+        for (int64_t k = 0; k < nb; ++k) {
+            double t = 0.0;
+            int64_t e = (k + 1) * ORC_SUM_BLOCK < n ? (k + 1) * ORC_SUM_BLOCK : n;
+            for (int64_t i = k * ORC_SUM_BLOCK; i < e; ++i) t += a[i] * b[i];
+            blk[k] = t;
+        }
+        s = tree_sum(blk, nb);
+        free(blk);
+    } else {
         for (int64_t i = 0; i < n; ++i) s += a[i] * b[i];
+    }
     return s;
 }
 
@@ -321,6 +348,36 @@ static int arnoldi(Work *w, const double *r)
  * If dump != NULL the state after the level loop is copied there before the
  * degree-l minimization, followed by tau.
  */
+/*
+ * The gamma step of level k: gamma such that r^(k) - V^(k) gamma is orthogonal
+ * to P, then r^(i) -= V^(i) gamma for i = 0..k and x += U gamma.  At k = 0 with
+ * recycled U, V this is the projection of a new right-hand side onto the
+ * recycled data (Section 4.2).  Returns 1 on a singular P^T V^(k).
+ */
+static int gamma_step(Work *w, int k, double *x)
+{
+    const int s = w->s;
+    const int64_t n = w->n;
+    double M[64], g[8], c[8], colp[8][8];
+    for (int q = 0; q < s; ++q) project(w, WCOL(w, k, q), colp[q]);
+    for (int a = 0; a < s; ++a)
+        for (int q = 0; q < s; ++q) M[a * s + q] = colp[q][a];
+    project(w, RCOL(w, k), g);
+    if (lu_solve(s, M, g, c)) return 1;
+    for (int i = 0; i <= k; ++i) {
+        double *ri = RCOL(w, i);
+        for (int q = 0; q < s; ++q) {
+            const double *vq = WCOL(w, i, q);
+            for (int64_t e = 0; e < n; ++e) ri[e] -= c[q] * vq[e];
+        }
+    }
+    for (int q = 0; q < s; ++q) {
+        const double *uq = WCOL(w, -1, q);
+        for (int64_t e = 0; e < n; ++e) x[e] += c[q] * uq[e];
+    }
+    return 0;
+}
+
 static int cycle(Work *w, double *x, double *dump)
 {
     const int s = w->s, ell = w->ell;
@@ -328,23 +385,7 @@ static int cycle(Work *w, double *x, double *dump)
     double M[64], g[8], c[8], colp[8][8];
 
     for (int k = 0; k < ell; ++k) {
-        /* gamma: r^(k) - V^(k) gamma orthogonal to P */
-        for (int q = 0; q < s; ++q) project(w, WCOL(w, k, q), colp[q]);
-        for (int a = 0; a < s; ++a)
-            for (int q = 0; q < s; ++q) M[a * s + q] = colp[q][a];
-        project(w, RCOL(w, k), g);
-        if (lu_solve(s, M, g, c)) return 1;
-        for (int i = 0; i <= k; ++i) {
-            double *ri = RCOL(w, i);
-            for (int q = 0; q < s; ++q) {
-                const double *vq = WCOL(w, i, q);
-                for (int64_t e = 0; e < n; ++e) ri[e] -= c[q] * vq[e];
-            }
-        }
-        for (int q = 0; q < s; ++q) {
-            const double *uq = WCOL(w, -1, q);
-            for (int64_t e = 0; e < n; ++e) x[e] += c[q] * uq[e];
-        }
+        if (gamma_step(w, k, x)) return 1;
         matvec(&w->A, RCOL(w, k), RCOL(w, k + 1));
 
         for (int q = 0; q < s; ++q) {
@@ -420,6 +461,78 @@ static int cycle(Work *w, double *x, double *dump)
 }
 
 /*
+ * Orthonormalize recycled data (not in the paper: an option of this build,
+ * applied where a solve fetches U, V).  CholQR in FP64: G = U^T U = R^T R
+ * (Cholesky, R upper triangular), then U := U R^{-1} and V := V R^{-1},
+ * column by column by forward substitution (u'_j = (u_j - sum_{i<j} R_ij u'_i)
+ * / R_jj).  U^T U becomes I, V = A U is kept (V R^{-1} = A U R^{-1}), and the
+ * ranges of U and V do not change, so the projection of the next right-hand
+ * side onto the recycled data is the same in exact arithmetic.  V may be NULL
+ * (U only).  Returns 1, leaving U and V untouched, when G is not numerically
+ * positive definite (a pivot d <= 0 or d <= 1e-28 G_jj).
+ */
+int orc_cholqr(int64_t n, int s, double *U, double *V)
+{
+    if (n < 1 || s < 1 || s > 8 || !U) return -1;
+    double G[64], L[64];
+    for (int i = 0; i < s; ++i)
+        for (int j = i; j < s; ++j) {
+            G[i * s + j] = dot(n, U + (int64_t)i * n, U + (int64_t)j * n);
+            G[j * s + i] = G[i * s + j];
+        }
+    /* G = L L^T, L lower; R = L^T */
+    memset(L, 0, sizeof(L));
+    for (int j = 0; j < s; ++j) {
+        double d = G[j * s + j];
+        for (int k = 0; k < j; ++k) d -= L[j * s + k] * L[j * s + k];
+        if (!(d > 0.0) || !(d > 1e-28 * G[j * s + j])) return 1;
+        L[j * s + j] = sqrt(d);
+        for (int i = j + 1; i < s; ++i) {
+            double e = G[i * s + j];
+            for (int k = 0; k < j; ++k) e -= L[i * s + k] * L[j * s + k];
+            L[i * s + j] = e / L[j * s + j];
+        }
+    }
+    for (int m = 0; m < (V ? 2 : 1); ++m) {
+        double *B = m == 0 ? U : V;
+        for (int j = 0; j < s; ++j) {
+            double *bj = B + (int64_t)j * n;
+            for (int64_t e = 0; e < n; ++e) {
+                double acc = bj[e];
+                for (int i = 0; i < j; ++i) acc -= L[j * s + i] * B[(int64_t)i * n + e];
+                bj[e] = acc / L[j * s + j];
+            }
+        }
+    }
+    return 0;
+}
+
+/*
+ * The projection of a right-hand side onto recycled data (Section 4.2: the
+ * first gamma step of a solve that starts from a former solve's U, V):
+ * gamma with r - V gamma orthogonal to P, then r -= V gamma, x += U gamma, in
+ * place.  P, U, V: n x s column-major.  Returns 1 on a singular P^T V.
+ */
+int orc_recycle_start(int64_t n, int s, const double *P, const double *U, const double *V,
+                      double *r, double *x)
+{
+    if (n <= 0 || s < 1 || s > 8) return -1;
+    Work w;
+    w.A.n = n; w.A.rp = NULL; w.A.ci = NULL; w.A.va = NULL; w.A.mv = 0;
+    w.s = s; w.ell = 1; w.n = n; w.P = P;
+    w.W = (double *)calloc((size_t)n * s * 3, sizeof(double));
+    w.R = (double *)calloc((size_t)n * 2, sizeof(double));
+    if (!w.W || !w.R) { free(w.W); free(w.R); return ORC_E_NOMEM; }
+    memcpy(WCOL(&w, -1, 0), U, (size_t)n * s * sizeof(double));
+    memcpy(WCOL(&w, 0, 0), V, (size_t)n * s * sizeof(double));
+    memcpy(RCOL(&w, 0), r, (size_t)n * sizeof(double));
+    int bd = gamma_step(&w, 0, x);
+    if (!bd) memcpy(r, RCOL(&w, 0), (size_t)n * sizeof(double));
+    free(w.W); free(w.R);
+    return bd;
+}
+
+/*
  * Solve A x = b (x holds x0 on entry).
  *
  * Recycle state (U, V: n x s column-major, *rec_level, *rec_have) is read when
@@ -439,7 +552,7 @@ static int cycle(Work *w, double *x, double *dump)
 int orc_solve(int64_t n, const int32_t *rp, const int32_t *ci, const double *va,
               int s, int ell, const double *P,
               double tol, int64_t max_mv, int method, int fetch, double fetch_rel,
-              int64_t fetch_level, int max_repl, int replace_every,
+              int64_t fetch_level, int max_repl, int replace_every, int orth,
               const double *b, double *x,
               double *U, double *V, int64_t *rec_level, int *rec_have,
               int64_t *out_i64, double *out_f64,
@@ -551,6 +664,7 @@ int orc_solve(int64_t n, const int32_t *rp, const int32_t *ci, const double *va,
             if (fire) {
                 memcpy(U, WCOL(&w, -1, 0), (size_t)n * s * sizeof(double));
                 memcpy(V, WCOL(&w, 0, 0), (size_t)n * s * sizeof(double));
+                if (orth) orc_cholqr(n, s, U, V);
                 fetched = level;
             }
         }
@@ -585,6 +699,7 @@ int orc_solve(int64_t n, const int32_t *rp, const int32_t *ci, const double *va,
                                       (fetch == ORC_FETCH_ONCE && !*rec_have))) {
         memcpy(U, WCOL(&w, -1, 0), (size_t)n * s * sizeof(double));
         memcpy(V, WCOL(&w, 0, 0), (size_t)n * s * sizeof(double));
+        if (orth) orc_cholqr(n, s, U, V);
         fetched = level;
     }
     if (fetched >= 0) { *rec_level = fetched; *rec_have = 1; }

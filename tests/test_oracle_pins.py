@@ -388,3 +388,134 @@ def test_reversed_sums_same_definition(orc):
     assert np.array_equal(x1, x3)           # the switch is restored
     assert not np.array_equal(x1, x2)
     assert np.linalg.norm(x1 - x2) <= 1e-9 * np.linalg.norm(x1)
+
+
+def test_blocked_sums_same_definition_and_per_thread(orc):
+    """Blocked pairwise summation changes rounding only, and the order is a
+    property of the calling thread: a solve in another thread with another
+    order leaves this thread's result bit for bit unchanged."""
+    import threading
+    cd, A = small_convdiff(orc, 3, 9, seed=7)     # N = 729: three blocks of 256 terms
+    P = I.p_dense(7, A.n, 4)
+    x1, i1, _, _ = orc.solve(A, cd.f, np.zeros(A.n), 4, 2, P, tol=1e-10)
+    with orc.sum_order(orc.SUM_BLOCKED):
+        x2, i2, _, _ = orc.solve(A, cd.f, np.zeros(A.n), 4, 2, P, tol=1e-10)
+    assert not np.array_equal(x1, x2)
+    assert np.linalg.norm(x1 - x2) <= 1e-9 * np.linalg.norm(x1)
+    assert i1.mv_total == i2.mv_total
+    out = {}
+
+    def other():
+        with orc.sum_order(orc.SUM_REVERSE):
+            out["x"] = orc.solve(A, cd.f, np.zeros(A.n), 4, 2, P, tol=1e-10)[0]
+
+    t = threading.Thread(target=other)
+    t.start()
+    x3, _, _, _ = orc.solve(A, cd.f, np.zeros(A.n), 4, 2, P, tol=1e-10)
+    t.join()
+    assert np.array_equal(x1, x3)
+    assert not np.array_equal(out["x"], x1)
+
+
+# --------------------------------------------------------------------------
+# Orthonormalization of the recycled basis (CholQR in FP64; an option of this
+# build, applied where a solve fetches U, V)
+# --------------------------------------------------------------------------
+def _fetched_pair(orc, s=4, ell=2, seed=2):
+    """U, V as a real solve fetches them: M(s)stab data at the threshold."""
+    cd, A = small_convdiff(orc, 2, 20, seed=seed)
+    P = I.p_dense(seed, A.n, s)
+    _, _, rec, _ = orc.solve(A, cd.f, np.zeros(A.n), s, ell, P)
+    assert rec.have
+    return cd, A, P, rec
+
+
+def test_cholqr_orthonormal_triangular_and_keeps_v_equal_au(orc):
+    """U^T U = I; U_old = U_new R with R = U_new^T U_old upper triangular (the
+    column order of Gram-Schmidt); V_old = V_new R; so V = A U is kept."""
+    cd, A, P, rec = _fetched_pair(orc)
+    U0, V0 = rec.U.copy(order="F"), rec.V.copy(order="F")
+    U, V = rec.U.copy(order="F"), rec.V.copy(order="F")
+    assert orc.cholqr(U, V)
+    s = U.shape[1]
+    # CholQR loses orthogonality like cond(U)^2 eps
+    kappa = np.linalg.cond(U0)
+    assert np.abs(U.T @ U - np.eye(s)).max() <= 10 * s * kappa ** 2 * np.finfo(float).eps
+    R = U.T @ U0
+    assert np.abs(np.tril(R, -1)).max() <= 1e-10 * np.abs(R).max()
+    assert np.all(np.diag(R) > 0)
+    assert np.linalg.norm(U @ R - U0) <= 1e-12 * np.linalg.norm(U0)
+    assert np.linalg.norm(V @ R - V0) <= 1e-12 * np.linalg.norm(V0)
+    AU = np.stack([orc.spmv(A, U[:, q]) for q in range(s)], axis=1)
+    AU0 = np.stack([orc.spmv(A, U0[:, q]) for q in range(s)], axis=1)
+    before = np.linalg.norm(V0 - AU0) / np.linalg.norm(V0)
+    after = np.linalg.norm(V - AU) / np.linalg.norm(V)
+    assert after <= 10 * before + 1e-13, (before, after)
+    # U only: V untouched
+    U2 = rec.U.copy(order="F")
+    assert orc.cholqr(U2)
+    np.testing.assert_array_equal(U2, U)
+
+
+def test_cholqr_keeps_the_projection_of_a_new_rhs(orc):
+    """The projection of the next right-hand side onto recycled data (Section
+    4.2) depends on range(U), range(V) and P only: the same r and x with and
+    without the orthonormalization, to rounding."""
+    cd, A, P, rec = _fetched_pair(orc)
+    rng = np.random.default_rng(5)
+    b = rng.standard_normal(A.n)
+    x0 = rng.standard_normal(A.n)
+    r0 = b - orc.spmv(A, x0)
+    r1, x1 = orc.recycle_start(P, rec.U, rec.V, r0, x0)
+    U, V = rec.U.copy(order="F"), rec.V.copy(order="F")
+    orc.cholqr(U, V)
+    r2, x2 = orc.recycle_start(P, U, V, r0, x0)
+    assert np.linalg.norm(r1 - r2) <= 1e-10 * np.linalg.norm(r1)
+    assert np.linalg.norm(x1 - x2) <= 1e-12 * np.linalg.norm(x1)
+    # the projected residual is orthogonal to P (an oblique projection: its
+    # norm may grow), and the step did move
+    assert np.abs(P.T @ r2).max() <= 1e-9 * np.abs(P).sum(axis=0).max() * np.abs(r2).max()
+    assert np.linalg.norm(r2 - r0) >= 1e-3 * np.linalg.norm(r0)
+
+
+def test_cholqr_leaves_s1_sequences_unchanged(orc):
+    """For s = 1 the iteration depends on the recycled vectors only through
+    their span (every small system is 1 x 1), so a sequence with the fetched
+    data normalized takes the same MVs and reaches the same x to rounding."""
+    cd, A = small_convdiff(orc, 2, 16, seed=4)
+    P = I.p_dense(4, A.n, 1)
+    outs = []
+    for orth in (False, True):
+        x, rec, res = np.zeros(A.n), orc.Recycle.empty(A.n, 1), []
+        for _ in range(5):
+            b = orc.rhs_step(x, cd.inv_dt, cd.f)
+            x, info, rec, _ = orc.solve(A, b, x, 1, 2, P, recycle=rec, orthonormalize=orth)
+            res.append((x.copy(), info.mv_total))
+        if orth:
+            assert abs(np.linalg.norm(rec.U) - 1.0) <= 1e-14
+        outs.append(res)
+    for (xa, ma), (xb, mb) in zip(*outs):
+        assert ma == mb
+        assert np.linalg.norm(xa - xb) <= 1e-10 * np.linalg.norm(xa)
+
+
+def test_cholqr_sequence_converges_with_orthonormal_data(orc):
+    """With the option on, every fetched U is orthonormal and every system of
+    an M(4)stab(2) sequence still meets the tolerance with V = A U kept."""
+    cd, A = small_convdiff(orc, 2, 20, seed=6)
+    P = I.p_dense(6, A.n, 4)
+    x, rec = np.zeros(A.n), orc.Recycle.empty(A.n, 4)
+    for _ in range(5):
+        b = orc.rhs_step(x, cd.inv_dt, cd.f)
+        x, info, rec, _ = orc.solve(A, b, x, 4, 2, P, recycle=rec, orthonormalize=True)
+        assert info.converged and info.relres_true <= 1e-8
+        assert np.abs(rec.U.T @ rec.U - np.eye(4)).max() <= 1e-10
+
+
+def test_cholqr_refuses_a_rank_deficient_basis(orc):
+    U = np.asfortranarray(np.tile(np.arange(1.0, 11.0)[:, None], (1, 3)))
+    V = np.asfortranarray(np.random.default_rng(0).standard_normal((10, 3)))
+    U0, V0 = U.copy(order="F"), V.copy(order="F")
+    assert not orc.cholqr(U, V)
+    np.testing.assert_array_equal(U, U0)
+    np.testing.assert_array_equal(V, V0)
