@@ -175,6 +175,8 @@ mstab_status mstab_options_default(mstab_options *o);
  * and l; 1 <= s <= 8, 1 <= l <= 8, n > s).  Allocates the workspace of
  * (s+1)(l+2) vectors (Table 1) plus the recycle store, on the current HIP
  * device.  o may be NULL (defaults).  The handle keeps the matrix pointers.
+ * A's structure is checked first (as mstab_csr_check does; no product runs
+ * on a malformed matrix).
  * Errors: E_INVALID, E_NOMEM, E_HIP; *out is NULL on failure.
  */
 mstab_status mstab_create(const mstab_csr *A, int32_t s, int32_t ell, const mstab_options *o,
@@ -226,7 +228,8 @@ mstab_status mstab_solve_next_guess(mstab_solver *h, const double *b, const doub
 mstab_status mstab_residual(mstab_solver *h, const double *b, const double *x, double *r,
                             double *norm2);
 
-/* Products with A: over the handle's lifetime and in the last solve. */
+/* Products with A (Table 1's #MV, counted as Table 1 does, plus the
+ * true-residual checks): over the handle's lifetime and in the last solve. */
 mstab_status mstab_mv_count(const mstab_solver *h, int64_t *total, int64_t *last_system);
 
 /*
@@ -316,6 +319,18 @@ mstab_status mstab_assemble_convdiff(int32_t dim, int64_t n, const double *beta,
                                      double *val, void *hip_stream);
 
 /*
+ * Structure check of an n-row CSR matrix in host memory (row_ptr n+1 and
+ * col_idx nnz int32 entries): row_ptr[0] = 0, row_ptr non-decreasing,
+ * row_ptr[n] = nnz, and every row's column indices strictly increasing and
+ * inside [0, n).  mstab_create, mstab_spmv and mstab_jacobi_split make the
+ * same checks on their device matrices (the row pointer on a host copy, the
+ * columns in one kernel that reads only col_idx) before any product gathers
+ * through the indices.  Host only.  Errors: E_INVALID naming the first
+ * violation.
+ */
+mstab_status mstab_csr_check(int64_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col_idx);
+
+/*
  * perm (host, n int32) receives the handle's row order: perm[new] = old, the
  * identity without MSTAB_REORDER_RCM.  Errors: E_INVALID, E_HIP.
  */
@@ -329,8 +344,8 @@ mstab_status mstab_permutation(const mstab_solver *h, int32_t *perm);
  * (a minimum-degree node of the last level of a search from that node), each
  * node's unvisited neighbours appended by increasing degree, then index; the
  * order is then reversed.  Host only (no device work).  Errors: E_INVALID
- * (n out of range, NULL, row_ptr not starting at 0 or decreasing, a column
- * outside [0, n)).
+ * (n out of range, NULL, or a pattern that mstab_csr_check refuses with
+ * nnz = row_ptr[n]).
  */
 mstab_status mstab_rcm_order(int64_t n, const int32_t *row_ptr, const int32_t *col_idx,
                              int32_t *perm);
@@ -346,7 +361,8 @@ mstab_status mstab_rcm_order(int64_t n, const int32_t *row_ptr, const int32_t *c
 mstab_status mstab_jacobi_split(const mstab_csr *A, double *val_out, double *d, double *e,
                                 void *hip_stream);
 
-/* y = A x (device, FP64), the plain sparse product used by the iteration. */
+/* y = A x (device, FP64), the plain sparse product used by the iteration.
+ * A's structure is checked first (E_INVALID as mstab_csr_check). */
 mstab_status mstab_spmv(const mstab_csr *A, const double *x, double *y, void *hip_stream);
 
 /*

@@ -362,6 +362,28 @@ struct Sell {
     DiaConst cv{};
 };
 
+// Structure check of a caller's CSR matrix before any kernel reads it through
+// its indices: every column index in [0, n) and strictly increasing within
+// its row.  The row pointer has already been checked on the host (rp[0] = 0,
+// non-decreasing, rp[n] = nnz), so every read stays inside col_idx[0, nnz).
+// *bad (zero beforehand) is set to 1 on the first violation.
+__global__ __launch_bounds__(BLOCK) void k_csr_check(int64_t n, const int32_t *__restrict__ rp,
+                                                     const int32_t *__restrict__ ci, int *bad)
+{
+    for (int64_t r = (int64_t)blockIdx.x * BLOCK + threadIdx.x; r < n;
+         r += (int64_t)gridDim.x * BLOCK) {
+        int64_t prev = -1;
+        for (int32_t j = rp[r]; j < rp[r + 1]; ++j) {
+            const int64_t c = ci[j];
+            if (c <= prev || c >= n) {
+                __hip_atomic_store(bad, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                break;
+            }
+            prev = c;
+        }
+    }
+}
+
 // Scatter CSR rows into the sliced layout (one thread per row).
 template <typename TD, typename TS>
 __global__ __launch_bounds__(BLOCK) void k_to_sell(int64_t n, const int32_t *__restrict__ rp,

@@ -156,6 +156,60 @@ struct Profiler {
     }
 };
 
+// CSR structure checks (the error contract: a malformed matrix is refused
+// with E_INVALID before any kernel gathers through its indices).
+// Host row pointer: rp[0] = 0, non-decreasing, rp[n] = nnz.
+void check_row_ptr(int64_t n, int64_t nnz, const int32_t *rp)
+{
+    if (rp[0] != 0) fail(MSTAB_E_INVALID, "row_ptr[0] = %d, not 0", rp[0]);
+    for (int64_t i = 0; i < n; ++i)
+        if (rp[i + 1] < rp[i]) fail(MSTAB_E_INVALID, "row_ptr decreases at row %lld", (long long)i);
+    if (rp[n] != nnz)
+        fail(MSTAB_E_INVALID, "row_ptr[n] = %d, not nnz = %lld", rp[n], (long long)nnz);
+}
+
+// Host column indices: in [0, n) and strictly increasing within each row
+// (the row pointer checked first).
+void check_columns_host(int64_t n, const int32_t *rp, const int32_t *ci)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t prev = -1;
+        for (int32_t k = rp[i]; k < rp[i + 1]; ++k) {
+            if (ci[k] <= prev || ci[k] >= n)
+                fail(MSTAB_E_INVALID, "row %lld: column index %d out of range or not increasing",
+                     (long long)i, ci[k]);
+            prev = ci[k];
+        }
+    }
+}
+
+// The same checks on a device CSR matrix: the row pointer on a host copy, the
+// columns by one kernel that reads only the (then known-sized) index array.
+void check_csr_dev(int64_t n, int64_t nnz, const int32_t *rp, const int32_t *ci, hipStream_t st)
+{
+    if (n < 1) return;
+    std::vector<int32_t> h((size_t)n + 1);
+    HIPCHK(hipMemcpyAsync(h.data(), rp, sizeof(int32_t) * (n + 1), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    check_row_ptr(n, nnz, h.data());
+    if (nnz == 0) return;
+    int *bad = nullptr;
+    int hbad = 0;
+    HIPCHK(hipMalloc(&bad, sizeof(int)));
+    hipError_t e = hipMemsetAsync(bad, 0, sizeof(int), st);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_csr_check, dim3(grid_for(n, BLOCK, VEC_MAX_BLOCKS)), dim3(BLOCK), 0, st,
+                           n, rp, ci, bad);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, st);
+    const hipError_t se = hipStreamSynchronize(st);
+    (void)hipFree(bad);
+    HIPCHK(e);
+    HIPCHK(se);
+    if (hbad) fail(MSTAB_E_INVALID, "a column index is outside [0, n) or not increasing within its row");
+}
+
 // Build the sliced ELLPACK copy of a device CSR matrix (setup only): slice
 // widths from a host copy of the row pointer, then one scatter kernel.
 // With share_col, the column array of `other` is reused.
@@ -1443,6 +1497,7 @@ mstab_status mstab_create(const mstab_csr *A, int32_t s, int32_t ell, const msta
     HIPCHK(hipGetDevice(&h->device));
     h->pkey = p_key_from_seed(h->opt.p_seed);
     h->prof.init(h->stream);
+    check_csr_dev(h->n, h->nnz, h->rp, h->ci, h->stream);
     if (h->opt.reorder == MSTAB_REORDER_RCM) {
         // host: the order and the symmetrically permuted CSR (columns re-sorted)
         const int64_t n = h->n;
@@ -1452,11 +1507,6 @@ mstab_status mstab_create(const mstab_csr *A, int32_t s, int32_t ell, const msta
         HIPCHK(hipMemcpyAsync(ci.data(), h->ci, sizeof(int32_t) * h->nnz, hipMemcpyDeviceToHost, h->stream));
         HIPCHK(hipMemcpyAsync(va.data(), h->va, sizeof(double) * h->nnz, hipMemcpyDeviceToHost, h->stream));
         HIPCHK(hipStreamSynchronize(h->stream));
-        if (rp[0] != 0 || rp[n] != h->nnz) fail(MSTAB_E_INVALID, "row_ptr does not span nnz");
-        for (int64_t i = 0; i < n; ++i)
-            if (rp[i + 1] < rp[i]) fail(MSTAB_E_INVALID, "row_ptr decreases at row %lld", (long long)i);
-        for (int64_t k = 0; k < h->nnz; ++k)
-            if (ci[k] < 0 || ci[k] >= n) fail(MSTAB_E_INVALID, "column index out of range");
         const std::vector<int32_t> perm = rcm_order(n, rp.data(), ci.data());
         if ((int64_t)perm.size() != n) fail(MSTAB_E_INVALID, "reordering lost rows");
         std::vector<int32_t> iperm((size_t)n);
@@ -1951,13 +2001,22 @@ mstab_status mstab_rcm_order(int64_t n, const int32_t *row_ptr, const int32_t *c
     if (n < 0 || n >= ((int64_t)1 << 29)) fail(MSTAB_E_INVALID, "n out of range");
     if (n == 0) return MSTAB_OK;
     if (!row_ptr || !col_idx || !perm) fail(MSTAB_E_INVALID, "NULL pointer");
-    if (row_ptr[0] != 0) fail(MSTAB_E_INVALID, "row_ptr[0] != 0");
-    for (int64_t i = 0; i < n; ++i)
-        if (row_ptr[i + 1] < row_ptr[i]) fail(MSTAB_E_INVALID, "row_ptr decreases at row %lld", (long long)i);
-    for (int64_t k = 0; k < row_ptr[n]; ++k)
-        if (col_idx[k] < 0 || col_idx[k] >= n) fail(MSTAB_E_INVALID, "column index out of range");
+    check_row_ptr(n, row_ptr[n], row_ptr);
+    check_columns_host(n, row_ptr, col_idx);
     const std::vector<int32_t> p = rcm_order(n, row_ptr, col_idx);
     std::copy(p.begin(), p.end(), perm);
+    return MSTAB_OK;
+    API_END(nullptr)
+}
+
+mstab_status mstab_csr_check(int64_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col_idx)
+{
+    API_BEGIN
+    if (n < 0 || n >= ((int64_t)1 << 29)) fail(MSTAB_E_INVALID, "n out of range");
+    if (nnz < 0 || nnz >= ((int64_t)1 << 31)) fail(MSTAB_E_INVALID, "nnz out of range");
+    if (!row_ptr || (nnz > 0 && !col_idx)) fail(MSTAB_E_INVALID, "NULL pointer");
+    check_row_ptr(n, nnz, row_ptr);
+    check_columns_host(n, row_ptr, col_idx);
     return MSTAB_OK;
     API_END(nullptr)
 }
@@ -1986,6 +2045,7 @@ mstab_status mstab_jacobi_split(const mstab_csr *A, double *val_out, double *d, 
         fail(MSTAB_E_INVALID, "size out of range");
     if (A->n == 0) return MSTAB_OK;
     hipStream_t st = (hipStream_t)hip_stream;
+    check_csr_dev(A->n, A->nnz, A->row_ptr, A->col_idx, st);
     if (!d) HIPCHK(hipMalloc(&td, sizeof(double) * (size_t)A->n));
     if (!e) HIPCHK(hipMalloc(&te, sizeof(double) * (size_t)A->n));
     jacobi_split_dev(A->n, A->row_ptr, A->col_idx, A->val, val_out, d ? d : td, e ? e : te, st);
@@ -2016,6 +2076,7 @@ mstab_status mstab_spmv(const mstab_csr *A, const double *x, double *y, void *hi
         fail(MSTAB_E_INVALID, "size out of range");
     if (A->n == 0) return MSTAB_OK;
     hipStream_t st = (hipStream_t)hip_stream;
+    check_csr_dev(A->n, A->nnz, A->row_ptr, A->col_idx, st);
     Scratch sc;
     sc.init(st);
     SpmvArgs a{ACT_NONE, 0, 0, 0, 1, 0u};

@@ -33,7 +33,7 @@ EXPORTS = [
     "mstab_mv_count", "mstab_residual", "mstab_residual_history", "mstab_recycle_reset", "mstab_recycle_get",
     "mstab_recycle_set", "mstab_recycle_export", "mstab_recycle_import", "mstab_destroy", "mstab_status_str", "mstab_last_error",
     "mstab_set_profiling", "mstab_kernel_stats", "mstab_convdiff_nnz", "mstab_assemble_convdiff",
-    "mstab_jacobi_split", "mstab_permutation", "mstab_rcm_order", "mstab_spmv", "mstab_project",
+    "mstab_jacobi_split", "mstab_permutation", "mstab_rcm_order", "mstab_csr_check", "mstab_spmv", "mstab_project",
     "mstab_rhs_step",
     "mstab_cnn_param_count", "mstab_cnn_create", "mstab_cnn_destroy", "mstab_cnn_set_params",
     "mstab_cnn_get_params", "mstab_cnn_prepare", "mstab_cnn_forward", "mstab_cnn_gradient",
@@ -112,6 +112,7 @@ def load(path: str = LIB_PATH):
         "mstab_jacobi_split": (i32, [ctypes.POINTER(mstab_csr), P, P, P, P]),
         "mstab_permutation": (i32, [P, P]),
         "mstab_rcm_order": (i32, [i64, P, P, P]),
+        "mstab_csr_check": (i32, [i64, i64, P, P]),
         "mstab_spmv": (i32, [ctypes.POINTER(mstab_csr), P, P, P]),
         "mstab_project": (i32, [i64, i32, u64, P, P, P]),
         "mstab_rhs_step": (i32, [i64, P, f64, P, P, P]),
@@ -242,6 +243,15 @@ def mstab_rcm_order(row_ptr, col_idx):
     P = ctypes.c_void_p
     _check(load().mstab_rcm_order(n, rp.ctypes.data_as(P), ci.ctypes.data_as(P), perm.ctypes.data_as(P)))
     return perm
+
+
+def mstab_csr_check(row_ptr, col_idx):
+    """Structure check of a host CSR pattern (NumPy int32); raises MstabError."""
+    import numpy as np
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int32)
+    ci = np.ascontiguousarray(col_idx, dtype=np.int32)
+    P = ctypes.c_void_p
+    _check(load().mstab_csr_check(rp.shape[0] - 1, ci.shape[0], rp.ctypes.data_as(P), ci.ctypes.data_as(P)))
 
 
 def mstab_jacobi_split(A: CSR, val_out, d=None, e=None, stream=None):

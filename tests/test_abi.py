@@ -100,3 +100,28 @@ def test_solve_batch_rejects_bad_arguments_without_a_device(lib):
     nulls = (P * 2)(None, None)
     assert lib.mstab_solve_batch(nulls, 2, nulls, nulls, None) == mstab.E_INVALID
     assert b"NULL entry" in lib.mstab_last_error(None)
+
+
+def test_csr_check_refuses_malformed_patterns(lib):
+    """The structure check that mstab_create, mstab_spmv and mstab_jacobi_split
+    run before any product (here its host entry point)."""
+    import numpy as np
+    rp = np.array([0, 2, 4, 5], dtype=np.int32)
+    ci = np.array([0, 1, 0, 2, 2], dtype=np.int32)
+    mstab.mstab_csr_check(rp, ci)                        # well formed
+    bad = [
+        (np.array([1, 2, 4, 5]), ci),                    # row_ptr[0] != 0
+        (np.array([0, 3, 2, 5]), ci),                    # decreasing row pointer
+        (np.array([0, 2, 4, 4]), ci),                    # row_ptr[n] != nnz
+        (rp, np.array([0, 1, 0, 3, 2])),                 # a column equal to n
+        (rp, np.array([0, 1, -1, 2, 2])),                # a negative column
+        (rp, np.array([1, 0, 0, 2, 2])),                 # columns not increasing
+        (rp, np.array([0, 0, 0, 2, 2])),                 # a repeated column
+    ]
+    for r, c in bad:
+        with pytest.raises(mstab.MstabError) as e:
+            mstab.mstab_csr_check(r, c)
+        assert e.value.status == mstab.E_INVALID
+    # the host order computation refuses the same patterns
+    with pytest.raises(mstab.MstabError):
+        mstab.mstab_rcm_order(rp, np.array([0, 1, 0, 3, 2], dtype=np.int32))

@@ -326,6 +326,40 @@ def small_problem(torch, ms, orc, n=16, seed=0):
     return cd, Ao, upload_csr(torch, ms, Ao)
 
 
+@pytest.mark.parametrize("defect", ["column_n", "column_negative", "row_ptr_end", "unsorted"])
+def test_create_refuses_malformed_csr(torch_dev, ms, orc, defect):
+    """A malformed caller matrix is refused with E_INVALID at create (every
+    format and transformation path) and by mstab_spmv, before any product
+    gathers through its indices."""
+    torch = torch_dev
+    cd, Ao, _ = small_problem(torch, ms, orc, n=8)
+    rp, ci = Ao.row_ptr.copy(), Ao.col.copy()
+    if defect == "column_n":
+        ci[-1] = Ao.n
+    elif defect == "column_negative":
+        ci[0] = -1
+    elif defect == "row_ptr_end":
+        rp[-1] -= 1
+    else:
+        k = rp[5]
+        ci[k], ci[k + 1] = ci[k + 1], ci[k]
+    bad = ms.CSR(dev(torch, rp), dev(torch, ci), dev(torch, Ao.val))
+    for opts in ({}, {"matrix_format": ms.FORMAT_SLICED}, {"reorder": ms.REORDER_RCM},
+                 {"precond": ms.PRECOND_JACOBI}, {"precision": ms.PREC_F32_REFINE}):
+        with pytest.raises(ms.MstabError) as e:
+            ms.Solver(bad, 4, 2, **opts)
+        assert e.value.status == ms.E_INVALID, opts
+    x = torch.zeros(Ao.n, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    with pytest.raises(ms.MstabError) as e:
+        ms.mstab_spmv(bad, x, y)
+    assert e.value.status == ms.E_INVALID
+    vo = torch.empty_like(bad.val)
+    with pytest.raises(ms.MstabError) as e:
+        ms.mstab_jacobi_split(bad, vo)
+    assert e.value.status == ms.E_INVALID
+
+
 def test_zero_rhs(torch_dev, ms, orc):
     torch = torch_dev
     cd, Ao, Ag = small_problem(torch, ms, orc)
