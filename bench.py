@@ -7,13 +7,17 @@ to relative residual 1e-8 with the recycle data carried from system to system.
 Every step starts from x = 0 with the recycle data dropped, so each step does
 the same work.  value = systems per second over the timed steps.
 
-Also reported on the same line: MVs per system; IDR(s)stab(l) on the same
-sequence (no recycling); the FP32+FP64-replacement form and the form with an
-FP32 copy of the matrix; the kernel roofline of
-the dominant kernel class (HIP events on the solver's stream over the timed
-steps); and the CPU oracle on a bounded sample.
+Also reported on the same line, each timed over the same warmup and timed
+steps with no kernel timing: IDR(s)stab(l) on the same sequence (no
+recycling), the same method with the diagonal values streamed, the
+FP32+FP64-replacement form and the form with an FP32 copy of the matrix.
+Then: the kernel roofline of the dominant kernel class (HIP events on the
+solver's stream in one extra, untimed step); the 256^3 lognormal-kappa
+workload at s = 8, l = 4 in FP64 and both FP32 forms, with and without the
+split diagonal preconditioning; and the CPU oracle on the host cores.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--s 4] [--ell 2]
+       [--no-variants] [--no-c3] [--no-cpu-baseline] [--no-events]
 """
 from __future__ import annotations
 
@@ -64,28 +68,33 @@ def timed(torch, fn, steps, warmup):
     return time.perf_counter() - t0, outs
 
 
-def cpu_baseline(cd, s, ell, mvs_per_system):
-    """The FP64 oracle on the first two systems of the same sequence (single
-    thread, recycling as on the GPU), scaled to systems/s at the sequence's
-    mean MVs per system (the first systems cost several times the mean)."""
+def cpu_baseline(cd, s, ell, mvs_per_system, threads):
+    """The FP64 oracle on the host cores: `threads` independent copies of the
+    first system of the same sequence (the oracle is sequential C; ctypes
+    releases the GIL, so the copies run on separate cores), their summed MVs
+    over the wall time, scaled to systems/s at the GPU sequence's mean MVs per
+    system (the first system costs several times the mean)."""
     import numpy as np
+    from concurrent.futures import ThreadPoolExecutor
     import oracle
     from paper_1604_06043_amd import inputs as I
     A = oracle.assemble_convdiff(cd.dim, cd.n, cd.beta, cd.inv_dt, cd.kappa)
     P = I.p_dense(0, cd.N, s)
-    x = np.zeros(cd.N)
-    rec = oracle.Recycle.empty(cd.N, s)
-    mv = 0
+    b = oracle.rhs_step(np.zeros(cd.N), cd.inv_dt, cd.f)
+
+    def one(_):
+        rec = oracle.Recycle.empty(cd.N, s)
+        _, info, _, _ = oracle.solve(A, b, np.zeros(cd.N), s, ell, P, recycle=rec)
+        return info.mv_total
     t0 = time.perf_counter()
-    for _ in range(2):
-        b = oracle.rhs_step(x, cd.inv_dt, cd.f)
-        x, info, rec, _ = oracle.solve(A, b, x, s, ell, P, recycle=rec)
-        mv += info.mv_total
+    with ThreadPoolExecutor(threads) as ex:
+        mvs = list(ex.map(one, range(threads)))
     dt = time.perf_counter() - t0
-    rate = mv / dt
-    return {"value": rate / mvs_per_system, "unit": "systems/s", "cores": 1, "kind": "oracle",
-            "sample": f"systems 1-2 of the 128^3 sequence ({mv} MVs in {dt:.1f} s, single-threaded C "
-                      f"FP64, {rate:.1f} MVs/s), scaled to the sequence mean of "
+    rate = sum(mvs) / dt
+    return {"value": rate / mvs_per_system, "unit": "systems/s", "cores": threads, "kind": "oracle",
+            "sample": f"system 1 of the 128^3 sequence solved by {threads} independent copies of the "
+                      f"single-threaded C FP64 oracle at once, one per host core ({sum(mvs)} MVs in "
+                      f"{dt:.1f} s, {rate:.1f} MVs/s), scaled to the GPU sequence mean of "
                       f"{mvs_per_system:.2f} MVs/system",
             "mvs_per_s": rate}
 
@@ -118,6 +127,47 @@ def measured_traffic(name_parts):
     return tot / disp if disp else None
 
 
+def c3_leg(torch, ms, n, systems):
+    """The 256^3 variable-coefficient workload (Pe = 200, kappa = exp(N(0,1))
+    per node, s = 8, l = 4): the first `systems` systems of its sequence in
+    FP64 and in the two FP32 forms, each with and without the split diagonal
+    preconditioning that Section 5.1 pairs with the method; error of each
+    FP32 form's last x against the FP64 path's (the FP64 oracle needs hours
+    at this size; the tests state the error against it on the same workload
+    at 14^3-48^3)."""
+    from paper_1604_06043_amd import inputs as I
+    cd = I.config("c3", seed=0, n=n)
+    kappa = torch.tensor(cd.kappa, device="cuda")
+    A = ms.mstab_assemble_convdiff(cd.dim, cd.n, cd.beta, cd.inv_dt, kappa)
+    f = torch.tensor(cd.f, device="cuda")
+    s, ell = 8, 4
+    out = {"workload": f"convdiff3d_{n}cubed_pe200_lognormal_kappa_{systems}rhs", "N": cd.N, "s": s,
+           "ell": ell, "tol": 1e-8, "systems_per_step": systems}
+    for pc_name, pc in (("none", ms.PRECOND_NONE), ("jacobi", ms.PRECOND_JACOBI)):
+        x64 = None
+        for key, prec in (("f64", ms.PREC_F64), ("f32_matrix", ms.PREC_F32_MATRIX),
+                          ("f32_refine", ms.PREC_F32_REFINE)):
+            sv = ms.Solver(A, s, ell, p_seed=0, precision=prec, precond=pc)
+            run_sequence(torch, ms, sv, cd, f, 1)             # warm-up
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            x, mv, infos = run_sequence(torch, ms, sv, cd, f, systems)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            sv.close()
+            rec = {"systems_per_s": systems / dt, "mvs_per_system": mv / systems,
+                   "max_relres_true": max(i["relres_true"] for i in infos)}
+            if x64 is None:
+                x64 = x.clone()
+            else:
+                rec["rel_err_vs_f64_path_last_system"] = float(torch.linalg.norm(x - x64) /
+                                                               torch.linalg.norm(x64))
+            out[f"{key}_{pc_name}"] = rec
+            log(f"[bench] c3 {key} precond={pc_name}: {rec['systems_per_s']:.3f} systems/s, "
+                f"{rec['mvs_per_system']:.1f} MVs/system")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -129,6 +179,12 @@ def main():
     ap.add_argument("--n", type=int, default=128)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--no-c3", action="store_true",
+                    help="skip the 256^3 lognormal-kappa mixed-precision leg")
+    ap.add_argument("--c3-n", type=int, default=256)
+    ap.add_argument("--c3-systems", type=int, default=3)
+    ap.add_argument("--cpu-threads", type=int, default=16,
+                    help="host cores for the oracle baseline (at most the available ones)")
     ap.add_argument("--no-events", action="store_true",
                     help="time the steps without per-kernel HIP events (no roofline)")
     ap.add_argument("--matrix-format", choices=["auto", "diagonal", "sliced"], default="auto",
@@ -179,16 +235,22 @@ def main():
         step()
         log(f"[bench] warmup step done, MVs/system {state['mv'] / args.systems:.1f}")
     torch.cuda.synchronize()
-    # one launch in EVENT_PERIOD of each class is timed with HIP events (timing
-    # every launch costs the sequence ~18% of its throughput)
-    solver.set_profiling(not args.no_events, EVENT_PERIOD)
+    # the timed steps run with no kernel timing at all
     t, mvs = timed(torch, step, args.steps, 0)
-    stats = {c: solver.kernel_stats(i) for i, c in enumerate(CLASS_NAMES)}
-    solver.set_profiling(False)
     log(f"[bench] timed {args.steps} steps in {t:.3f} s")
     systems = args.steps * args.systems
     value = systems / t
     mv_per_system = sum(mvs) / systems
+
+    # a separate pass with HIP events on the solver's stream gives the kernel
+    # classes' durations for the roofline (1 launch in EVENT_PERIOD timed)
+    stats = {c: (0, 0.0, 0.0) for c in CLASS_NAMES}
+    if not args.no_events:
+        solver.set_profiling(True, EVENT_PERIOD)
+        step()
+        torch.cuda.synchronize()
+        stats = {c: solver.kernel_stats(i) for i, c in enumerate(CLASS_NAMES)}
+        solver.set_profiling(False)
 
     kernels = {}
     for c, (n, msec, by) in stats.items():
@@ -211,7 +273,8 @@ def main():
         names = class_kernels(dom, s, ell)
         traffic = measured_traffic(names)
         roofline = {"bound": "hbm", "kernel": dom, "kernels": names, "achieved": round(achieved, 1),
-                    "timed": f"1 launch in {EVENT_PERIOD} of each kernel class, HIP events on the solver stream",
+                    "timed": f"1 launch in {EVENT_PERIOD} of each kernel class, HIP events on the solver "
+                             f"stream, in one extra untimed step",
                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(achieved / HBM_PEAK_GBS, 4),
                     "traffic": None if traffic is None else round(traffic),
@@ -219,53 +282,43 @@ def main():
 
     variants = {}
     if not args.no_variants:
-        idr = ms.Solver(A, s, ell, p_seed=0, method=ms.METHOD_IDRSTAB)
-        ti, (mvi,) = timed(torch, lambda: run_sequence(torch, ms, idr, cd, f, args.systems)[1], 1, 0)
-        idr.close()
-        variants["idrstab"] = {"systems_per_s": args.systems / ti,
-                               "mvs_per_system": mvi / args.systems}
-        log(f"[bench] IDR(s)stab(l): {args.systems / ti:.2f} systems/s")
+        # every variant: the same warmup and timed steps as the main line,
+        # no kernel timing
+        def variant(name, **opt):
+            sv = ms.Solver(A, s, ell, p_seed=0, **opt)
+            holder = {}
+
+            def vstep():
+                x, mv, infos = run_sequence(torch, ms, sv, cd, f, args.systems)
+                holder["x"] = x
+                return mv
+            for _ in range(args.warmup):
+                vstep()
+            tv, mvv = timed(torch, vstep, args.steps, 0)
+            sv.close()
+            rec = {"systems_per_s": systems / tv, "mvs_per_system": sum(mvv) / systems}
+            log(f"[bench] {name}: {rec['systems_per_s']:.2f} systems/s, {rec['mvs_per_system']:.2f} MVs/system")
+            return rec, holder["x"]
+
+        x64, _, _ = run_sequence(torch, ms, solver, cd, f, args.systems)
+        variants["idrstab"], _ = variant("IDR(s)stab(l)", method=ms.METHOD_IDRSTAB)
         # the same method with the diagonal values streamed from HBM instead of
         # kept as one constant per diagonal (bit-identical iterates)
-        dg = ms.Solver(A, s, ell, p_seed=0, method=ms.METHOD_MSTAB, matrix_format=ms.FORMAT_DIAGONAL)
-        td, (mvd,) = timed(torch, lambda: run_sequence(torch, ms, dg, cd, f, args.systems)[1], 1, 0)
-        dg.close()
-        variants["diagonal_values_streamed"] = {"systems_per_s": args.systems / td,
-                                                "mvs_per_system": mvd / args.systems}
-        log(f"[bench] diagonal values streamed: {args.systems / td:.2f} systems/s")
-        mix = ms.Solver(A, s, ell, p_seed=0, method=ms.METHOD_MSTAB, precision=ms.PREC_F32_REFINE)
-        x64, _, _ = run_sequence(torch, ms, solver, cd, f, args.systems)
-        holder = {}
-
-        def mixed_step():
-            x, mv, infos = run_sequence(torch, ms, mix, cd, f, args.systems)
-            holder["x"] = x
-            return mv
-        tm, (mvm,) = timed(torch, mixed_step, 1, 0)
-        err = float(torch.linalg.norm(holder["x"] - x64) / torch.linalg.norm(x64))
-        mix.close()
-        variants["f32_refine"] = {"systems_per_s": args.systems / tm,
-                                  "mvs_per_system": mvm / args.systems,
-                                  "rel_err_vs_f64_path_last_system": err}
-        log(f"[bench] FP32+refinement: {args.systems / tm:.2f} systems/s, err {err:.2e}")
-        low = ms.Solver(A, s, ell, p_seed=0, method=ms.METHOD_MSTAB, precision=ms.PREC_F32_MATRIX)
-
-        def low_step():
-            x, mv, infos = run_sequence(torch, ms, low, cd, f, args.systems)
-            holder["x"] = x
-            return mv
-        tl, (mvl,) = timed(torch, low_step, 1, 0)
-        errl = float(torch.linalg.norm(holder["x"] - x64) / torch.linalg.norm(x64))
-        low.close()
-        variants["f32_matrix"] = {"systems_per_s": args.systems / tl,
-                                  "mvs_per_system": mvl / args.systems,
-                                  "rel_err_vs_f64_path_last_system": errl}
-        log(f"[bench] FP32 matrix copy: {args.systems / tl:.2f} systems/s, err {errl:.2e}")
+        variants["diagonal_values_streamed"], _ = variant("values streamed", method=ms.METHOD_MSTAB,
+                                                          matrix_format=ms.FORMAT_DIAGONAL)
+        for key, prec in (("f32_refine", ms.PREC_F32_REFINE), ("f32_matrix", ms.PREC_F32_MATRIX)):
+            rec, xv = variant(key, method=ms.METHOD_MSTAB, precision=prec)
+            rec["rel_err_vs_f64_path_last_system"] = float(torch.linalg.norm(xv - x64) / torch.linalg.norm(x64))
+            variants[key] = rec
+    c3 = None
+    if not args.no_c3:
+        c3 = c3_leg(torch, ms, args.c3_n, args.c3_systems)
 
     cpu = None
     if not args.no_cpu_baseline:
-        log("[bench] CPU oracle sample ...")
-        cpu = cpu_baseline(cd, s, ell, mv_per_system)
+        threads = min(len(os.sched_getaffinity(0)), args.cpu_threads)
+        log(f"[bench] CPU oracle sample on {threads} cores ...")
+        cpu = cpu_baseline(cd, s, ell, mv_per_system, threads)
         log(f"[bench] CPU oracle: {cpu['value']:.4f} systems/s")
 
     out = {
@@ -289,6 +342,7 @@ def main():
         "roofline": roofline,
         "kernels": kernels,
         "variants": variants,
+        "c3_mixed_precision": c3,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

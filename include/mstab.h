@@ -140,6 +140,15 @@ typedef struct {
                                   by construction and ignores it. */
     int32_t reorder;           /* mstab_reorder; default NONE */
     int32_t matrix_format;     /* mstab_format; default AUTO */
+    int32_t orthonormalize_recycle; /* 1: orthonormalize the U, V a solve fetches (not in the
+                                  paper, which keeps them as the cycle leaves them): CholQR
+                                  in FP64, G = U^T U = R^T R, U := U R^-1, V := V R^-1 (so
+                                  V = A U and span U are kept and the projection of the next
+                                  right-hand side, Section 4.2, is unchanged in exact
+                                  arithmetic), with P^T V recomputed; F32_REFINE
+                                  orthonormalizes its FP32 U in FP64, then recomputes
+                                  V = A U.  If U^T U is not numerically positive definite
+                                  the data stay as fetched.  Default 0. */
 } mstab_options;
 
 typedef struct {
@@ -233,13 +242,20 @@ mstab_status mstab_residual(mstab_solver *h, const double *b, const double *x, d
 mstab_status mstab_mv_count(const mstab_solver *h, int64_t *total, int64_t *last_system);
 
 /*
- * Residual history of the last solve: pairs (products with A so far, recursive
- * relative residual) after the initial residual and after every cycle (the
- * points of the paper's convergence graphs).  Host arrays of capacity cap;
- * *len gets the full length (entries beyond cap are dropped).
+ * Residual history of one solve on the handle: pairs (products with A so far,
+ * recursive relative residual) after the initial residual and after every
+ * cycle (the points of the paper's convergence graphs, Section 5.1 and 5.2).
+ * system: 0-based index of the solve among all solves on the handle (in call
+ * order, mstab_solve_count of them), or -1 for the last.  Host arrays of
+ * capacity cap; *len gets the full length (entries beyond cap are dropped).
+ * The handle keeps every solve's history until it is destroyed (about 16 bytes
+ * per cycle).  Errors: E_INVALID (no such solve, NULL with cap > 0).
  */
-mstab_status mstab_residual_history(const mstab_solver *h, int64_t *mv, double *relres,
-                                    int64_t cap, int64_t *len);
+mstab_status mstab_residual_history(const mstab_solver *h, int64_t system, int64_t *mv,
+                                    double *relres, int64_t cap, int64_t *len);
+
+/* Number of solves made on the handle (each mstab_solve_next, _guess or batch entry). */
+mstab_status mstab_solve_count(const mstab_solver *h, int64_t *count);
 
 /* Drop the held recycle data (the next MSTAB solve starts like IDR(s)stab). */
 mstab_status mstab_recycle_reset(mstab_solver *h);
@@ -290,8 +306,10 @@ const char *mstab_last_error(const mstab_solver *h);
 typedef enum {
     MSTAB_K_SPMV = 0,          /* y = A x with the P-projection epilogue */
     MSTAB_K_GAMMA = 1,         /* r^(i) -= V^(i) gamma, x += U gamma */
-    MSTAB_K_ETA = 2,           /* v_q^(i) := r^(i+1) - [..] eta_q */
-    MSTAB_K_GRAM = 3,          /* Z^T Z, Z^T r^(0) */
+    MSTAB_K_ETA = 2,           /* v_q^(i) := r^(i+1) - [..] eta_q (the lower levels fused with
+                                  the next level's gamma step) */
+    MSTAB_K_GRAM = 3,          /* Z^T Z, Z^T r^(0) (fused with the last level's lower eta steps
+                                  for l <= 4) */
     MSTAB_K_POLY = 4,          /* degree-l update of x, r, U, V with projections */
     MSTAB_K_COUNT = 5
 } mstab_kernel_class;

@@ -50,6 +50,8 @@ struct Ctl {
     double tau[MAXL];
     double h[MAXS + 1];                 // Gram-Schmidt coefficients
     double prec[MAXS][MAXS];            // [q][a] = p_a . v_q of refreshed fetched data
+    double chol[MAXS][MAXS];            // Cholesky factor L (lower) of U^T U of fetched data
+    int32_t chol_ok;                    // U^T U was numerically positive definite
     unsigned int counter[4];            // last-workgroup counters (zero between launches)
 };
 
@@ -86,15 +88,27 @@ __device__ __forceinline__ double wave_sum(double v)
 }
 
 // ---------------------------------------------------------------------------
-// Small dense solves (FP64), cooperative in one wavefront: lane l holds entry
-// (i, j) = (l / 8, l % 8) of an m x m system (m <= 8) and y_i of its row.
-// Row exchanges and eliminations are lane shuffles; every lane executes the
-// same instruction stream, and the result is the same whichever wavefront runs
-// it.  The pivot is the first largest magnitude in the column (lowest row on
-// ties); a pivot <= 1e-14 times the largest magnitude of its column marks the
-// system singular.
+// Small dense solves (FP64) in one wavefront.  Callers hand over an m x m
+// system (m <= 8) with entry (i, j) in lane 8 i + j and y_i in the lanes of
+// row i; the solve gathers row i into lane i (eight independent shuffles) and
+// then works lane-per-row: the pivot row and every value a step needs from
+// another row come from v_readlane into scalar registers, so the dependent
+// chain of the elimination has no LDS round trips.  Every lane executes the
+// same instruction stream, and the result does not depend on which wavefront
+// runs it.  The pivot is the first largest magnitude in the column (lowest
+// row on ties); a pivot <= 1e-14 times the largest magnitude of its column
+// marks the system singular.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double shfl_d(double v, int src) { return __shfl(v, src); }
+
+// v of lane `src` (wavefront-uniform src) in every lane
+__device__ __forceinline__ double lane_d(double v, int src)
+{
+    const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u & 0xFFFFFFFFu), src);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), src);
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
 
 // Solves A c = y with partial pivoting; returns ok (uniform).  On return the
 // lanes of row i hold c_i in `c`.
@@ -102,79 +116,118 @@ __device__ bool wave_lu(int m, double a, double y, double &c)
 {
     const int lane = threadIdx.x & 63, i = lane >> 3, j = lane & 7;
     const bool in = (i < m) && (j < m);
-    // largest magnitude of column j (xor over the row bits keeps j)
+    // largest magnitude of column j (xor over the row bits keeps j); lane j
+    // (row 0) holds it for column j
     double cm = in ? fabs(a) : 0.0;
     for (int o = 8; o < 64; o <<= 1) cm = fmax(cm, __shfl_xor(cm, o));
+    // row (lane & 7) of the system into this lane
+    double r[8];
+#pragma unroll
+    for (int jj = 0; jj < 8; ++jj) r[jj] = shfl_d(a, (lane & 7) * 8 + jj);
+    double yr = shfl_d(y, (lane & 7) * 8);
     bool ok = true;
-    for (int k = 0; k < m; ++k) {
-        // pivot search among rows k..m-1 of column k
-        double v = (j == k && i >= k && i < m) ? fabs(a) : -1.0;
-        int vi = i;
-        for (int o = 8; o < 64; o <<= 1) {
-            const double v2 = __shfl_xor(v, o);
-            const int i2 = __shfl_xor(vi, o);
-            if (v2 > v || (v2 == v && i2 < vi)) { v = v2; vi = i2; }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        if (k >= m) break;
+        // pivot: first largest magnitude among rows k..m-1 of column k
+        double best = -1.0;
+        int piv = k;
+        for (int ii = k; ii < m; ++ii) {
+            const double v = fabs(lane_d(r[k], ii));
+            if (v > best) { best = v; piv = ii; }
         }
-        const double best = __shfl(v, k);
-        const int piv = __shfl(vi, k);
-        ok = ok && (best > 1e-14 * __shfl(cm, k));
+        ok = ok && (best > 1e-14 * lane_d(cm, k));
         // exchange rows k and piv
-        const int src = (i == k) ? (piv * 8 + j) : ((i == piv) ? (k * 8 + j) : lane);
-        a = shfl_d(a, src);
-        y = shfl_d(y, src);
-        // eliminate below the pivot
-        const double inv = 1.0 / shfl_d(a, k * 8 + k);
-        const double aik = shfl_d(a, (i & 7) * 8 + k);
-        const double akj = shfl_d(a, k * 8 + j);
-        const double yk = shfl_d(y, k * 8);
-        const double f = aik * inv;
-        if (i > k && i < m) {
-            if (j > k && j < m) a = fma(-f, akj, a);
-            y = fma(-f, yk, y);
+        double rk[8], rp[8];
+#pragma unroll
+        for (int jj = 0; jj < 8; ++jj) {
+            rk[jj] = lane_d(r[jj], k);
+            rp[jj] = lane_d(r[jj], piv);
+        }
+        const double yk = lane_d(yr, k), yp = lane_d(yr, piv);
+        if (lane == k) {
+#pragma unroll
+            for (int jj = 0; jj < 8; ++jj) r[jj] = rp[jj];
+            yr = yp;
+        } else if (lane == piv) {
+#pragma unroll
+            for (int jj = 0; jj < 8; ++jj) r[jj] = rk[jj];
+            yr = yk;
+        }
+        // eliminate below the pivot (its row is now rp, yp)
+        const double inv = 1.0 / rp[k];
+        if (lane > k && lane < m) {
+            const double f = r[k] * inv;
+#pragma unroll
+            for (int jj = k + 1; jj < 8; ++jj)
+                if (jj < m) r[jj] = fma(-f, rp[jj], r[jj]);
+            yr = fma(-f, yp, yr);
         }
     }
     // back substitution, column by column
     c = 0.0;
-    for (int k = m - 1; k >= 0; --k) {
-        const double ck = shfl_d(y, k * 8) / shfl_d(a, k * 8 + k);
-        const double aik = shfl_d(a, (i & 7) * 8 + k);
-        if (i < k) y = fma(-aik, ck, y);
+#pragma unroll
+    for (int k = 7; k >= 0; --k) {
+        if (k >= m) continue;
+        const double ck = lane_d(yr, k) / lane_d(r[k], k);
+        if (lane < k) yr = fma(-r[k], ck, yr);
         if (i == k) c = ck;
     }
     return ok;
 }
 
 // Normal equations G t = c (G SPD): right-looking Cholesky, then the two
-// triangular solves; LU when G is not numerically SPD.
+// triangular solves; LU when G is not numerically SPD.  Same lane-per-row
+// layout as wave_lu after the gather.
 __device__ bool wave_spd(int m, double g, double y, double &t)
 {
-    const int lane = threadIdx.x & 63, i = lane >> 3, j = lane & 7;
+    const int lane = threadIdx.x & 63, i = lane >> 3;
     const double g0 = g, y0 = y;
+    double r[8];
+#pragma unroll
+    for (int jj = 0; jj < 8; ++jj) r[jj] = shfl_d(g, (lane & 7) * 8 + jj);
+    double yr = shfl_d(y, (lane & 7) * 8);
     bool spd = true;
-    for (int k = 0; k < m; ++k) {
-        const double akk = shfl_d(g, k * 8 + k);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        if (k >= m) break;
+        const double akk = lane_d(r[k], k);
         spd = spd && (akk > 0.0);
         const double lkk = sqrt(fmax(akk, 0.0));
-        // L_ik for this lane's row
-        const double lv = (i == k) ? lkk : ((i > k && i < m) ? shfl_d(g, (i & 7) * 8 + k) / lkk : 0.0);
-        const double ljk = shfl_d(lv, (j & 7) * 8);
-        if (i > k && j > k && i < m && j < m) g = fma(-lv, ljk, g);
-        if (j == k && i >= k) g = lv;
+        // L_ik of this lane's row
+        const double lv = (lane == k) ? lkk : ((lane > k && lane < m) ? r[k] / lkk : 0.0);
+#pragma unroll
+        for (int jj = k + 1; jj < 8; ++jj) {
+            if (jj >= m) break;
+            const double ljk = lane_d(lv, jj);
+            if (lane > k && lane < m) r[jj] = fma(-lv, ljk, r[jj]);
+        }
+        if (lane >= k) r[k] = lv;
     }
     if (!spd) return wave_lu(m, g0, y0, t);
     // forward: L z = y
-    for (int k = 0; k < m; ++k) {
-        const double zk = shfl_d(y, k * 8) / shfl_d(g, k * 8 + k);
-        const double lik = shfl_d(g, (i & 7) * 8 + k);
-        if (i > k && i < m) y = fma(-lik, zk, y);
-        if (i == k) y = zk;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        if (k >= m) break;
+        const double zk = lane_d(yr, k) / lane_d(r[k], k);
+        if (lane > k && lane < m) yr = fma(-r[k], zk, yr);
+        if (lane == k) yr = zk;
     }
-    // backward: L^T t = z
+    // backward: L^T t = z (row k of L^T is column k of L: entry L_jk sits in lane j)
     t = 0.0;
-    for (int k = m - 1; k >= 0; --k) {
-        const double tk = shfl_d(y, k * 8) / shfl_d(g, k * 8 + k);
-        const double lki = shfl_d(g, k * 8 + (i & 7));
-        if (i < k) y = fma(-lki, tk, y);
+#pragma unroll
+    for (int k = 7; k >= 0; --k) {
+        if (k >= m) continue;
+        const double tk = lane_d(yr, k) / lane_d(r[k], k);
+        // L_ki for this lane's i < k is lane k's r[i]
+        double lki = 0.0;
+#pragma unroll
+        for (int ii = 0; ii < 8; ++ii)
+            if (ii < k) {
+                const double v = lane_d(r[ii], k);
+                if (lane == ii) lki = v;
+            }
+        if (lane < k) yr = fma(-lki, tk, yr);
         if (i == k) t = tk;
     }
     return true;
@@ -778,6 +831,7 @@ __attribute__((amdgpu_waves_per_eu(sizeof(TM) == 4 ? 8 : 1))) void k_spmv_dia(in
     spmv_finalize<S>(vals, ctl, part, stride, a);
 }
 
+
 // 16-byte vectors of T (2 doubles or 4 floats) for the streaming kernels.
 template <typename T> struct Vec16;
 template <> struct Vec16<double> { using type = double2; static constexpr int W = 2; };
@@ -920,10 +974,98 @@ __global__ __launch_bounds__(BLOCK) void k_eta_low(int64_t ld, T *__restrict__ W
     }
 }
 
+// k_eta_low of level k fused with the gamma step of level k + 1 (which
+// follows it in Algorithm 1: the level loop's next pass starts with gamma):
+//   v_q^(i) := r^(i+1) - sum_{p<q} eta_{q,p} v_p^(i+1) - sum_{p>=q} eta_{q,p} v_p^(i),
+//       i = k-1 .. -1 (as k_eta_low),
+//   r^(i) := r^(i) - V^(i) gamma, i = 0..k+1, and x := x + U gamma (as k_gamma),
+// where the gamma step reads the V levels this pass has just written (kept in
+// registers) and the eta step reads each r^(i) before its gamma update, as the
+// two kernels in sequence do.  Same operations in the same order per element.
+template <typename T, int S>
+__global__ __launch_bounds__(BLOCK) void k_eta_low_gamma(int64_t ld, T *__restrict__ W,
+                                                         T *__restrict__ R, T *__restrict__ X,
+                                                         int k, const Ctl *ctl)
+{
+    if (ctl->st.flags) return;
+    constexpr int VW = Vec16<T>::W;
+    T g[S];
+#pragma unroll
+    for (int q = 0; q < S; ++q) g[q] = (T)ctl->gamma[q];
+    for (int64_t e = ((int64_t)blockIdx.x * BLOCK + threadIdx.x) * VW; e < ld;
+         e += (int64_t)gridDim.x * BLOCK * VW) {
+        // r^(k+1) -= V^(k+1) gamma (level k+1 is final: the products of level k)
+        {
+            T acc[VW], w[VW];
+            ld16(R + (int64_t)(k + 1) * ld + e, acc);
+#pragma unroll
+            for (int q = 0; q < S; ++q) {
+                ld16(W + (int64_t)((k + 2) * S + q) * ld + e, w);
+#pragma unroll
+                for (int c = 0; c < VW; ++c) acc[c] = fmaT(-g[q], w[c], acc[c]);
+            }
+            st16(R + (int64_t)(k + 1) * ld + e, acc);
+        }
+        T up[S][VW];   // updated level i (starting with level k, written by k_eta)
+#pragma unroll
+        for (int p = 0; p < S; ++p) ld16(W + (int64_t)((k + 1) * S + p) * ld + e, up[p]);
+        for (int i = k; i >= 0; --i) {
+            // r^(i) before its gamma update feeds the eta step of level i - 1
+            T r[VW], old[S][VW];
+            ld16(R + (int64_t)i * ld + e, r);
+#pragma unroll
+            for (int p = 0; p < S; ++p) ld16(W + (int64_t)(i * S + p) * ld + e, old[p]);
+            // gamma step on r^(i) with the new V^(i)
+            {
+                T acc[VW];
+#pragma unroll
+                for (int c = 0; c < VW; ++c) acc[c] = r[c];
+#pragma unroll
+                for (int q = 0; q < S; ++q)
+#pragma unroll
+                    for (int c = 0; c < VW; ++c) acc[c] = fmaT(-g[q], up[q][c], acc[c]);
+                st16(R + (int64_t)i * ld + e, acc);
+            }
+            // eta steps of level i - 1
+#pragma unroll
+            for (int q = 0; q < S; ++q) {
+                T acc[VW];
+#pragma unroll
+                for (int c = 0; c < VW; ++c) acc[c] = r[c];
+#pragma unroll
+                for (int p = 0; p < S; ++p) {
+                    const T hp = (T)ctl->eta_all[q][p];
+#pragma unroll
+                    for (int c = 0; c < VW; ++c)
+                        acc[c] = fmaT(-hp, (p < q) ? up[p][c] : old[p][c], acc[c]);
+                }
+                st16(W + (int64_t)(i * S + q) * ld + e, acc);
+#pragma unroll
+                for (int c = 0; c < VW; ++c) old[q][c] = acc[c];
+            }
+#pragma unroll
+            for (int p = 0; p < S; ++p)
+#pragma unroll
+                for (int c = 0; c < VW; ++c) up[p][c] = old[p][c];
+        }
+        // x += U gamma with the new U = level -1
+        T acc[VW];
+        ld16(X + e, acc);
+#pragma unroll
+        for (int q = 0; q < S; ++q)
+#pragma unroll
+            for (int c = 0; c < VW; ++c) acc[c] = fmaT(g[q], up[q][c], acc[c]);
+        st16(X + e, acc);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Gram matrix of [r^(0), ..., r^(l)] (upper triangle, row-major pairs) and the
 // tau solve  (Z^T Z) tau = Z^T r^(0),  Z = [r^(1..l)].
 // ---------------------------------------------------------------------------
+template <int L>
+__device__ void gram_finalize(double (&acc)[(L + 1) * (L + 2) / 2], Ctl *ctl, double *part, int stride);
+
 template <typename T, int L>
 __global__ __launch_bounds__(BLOCK) void k_gram(int64_t ld, const T *__restrict__ R, Ctl *ctl,
                                                 double *part, int stride)
@@ -961,6 +1103,15 @@ __global__ __launch_bounds__(BLOCK) void k_gram(int64_t ld, const T *__restrict_
                     for (int j = i; j <= L; ++j) acc[v++] += (double)z[u][i][c] * (double)z[u][j][c];
             }
     }
+    gram_finalize<L>(acc, ctl, part, stride);
+}
+
+// The end of k_gram and k_eta_low_gram: workgroup partials of the Gram pairs,
+// the last workgroup's fixed-order totals and (wavefront 0) the tau solve.
+template <int L>
+__device__ void gram_finalize(double (&acc)[(L + 1) * (L + 2) / 2], Ctl *ctl, double *part, int stride)
+{
+    constexpr int NV = (L + 1) * (L + 2) / 2;
     block_partials<NV>(acc, NV, part, stride);
     __shared__ double tot[NV];
     if (!last_block_reduce(part, stride, NV, &ctl->counter[1], tot)) return;
@@ -985,6 +1136,70 @@ __global__ __launch_bounds__(BLOCK) void k_gram(int64_t ld, const T *__restrict_
             ctl->st.where = WHERE_TAU;
         }
     }
+}
+
+// k_eta_low of the last level (k = l - 1) fused with the Gram matrix of
+// [r^(0), ..., r^(l)] and the tau solve that follow it in Algorithm 1: the
+// eta steps read r^(0..l-1) anyway, and the residual levels are final after
+// the last product of the level loop.  The eta updates are those of
+// k_eta_low; the Gram pairs are summed per thread in element order and then
+// as in k_gram.  Launch with at most MAX_PARTIAL_BLOCKS workgroups.
+template <typename T, int S, int L>
+__global__ __launch_bounds__(BLOCK) void k_eta_low_gram(int64_t ld, T *__restrict__ W,
+                                                        const T *__restrict__ R, Ctl *ctl,
+                                                        double *part, int stride)
+{
+    if (ctl->st.flags) return;
+    constexpr int VW = Vec16<T>::W;
+    constexpr int NV = (L + 1) * (L + 2) / 2;
+    constexpr int K = L - 1;
+    double acc[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) acc[v] = 0.0;
+    for (int64_t e = ((int64_t)blockIdx.x * BLOCK + threadIdx.x) * VW; e < ld;
+         e += (int64_t)gridDim.x * BLOCK * VW) {
+        T z[L + 1][VW];
+        ld16(R + (int64_t)L * ld + e, z[L]);
+        T up[S][VW];   // updated level i + 1
+#pragma unroll
+        for (int p = 0; p < S; ++p) ld16(W + (int64_t)((K + 1) * S + p) * ld + e, up[p]);
+#pragma unroll
+        for (int i = K - 1; i >= -1; --i) {
+            T old[S][VW];
+            ld16(R + (int64_t)(i + 1) * ld + e, z[i + 1]);
+#pragma unroll
+            for (int p = 0; p < S; ++p) ld16(W + (int64_t)((i + 1) * S + p) * ld + e, old[p]);
+#pragma unroll
+            for (int q = 0; q < S; ++q) {
+                T a2[VW];
+#pragma unroll
+                for (int c = 0; c < VW; ++c) a2[c] = z[i + 1][c];
+#pragma unroll
+                for (int p = 0; p < S; ++p) {
+                    const T hp = (T)ctl->eta_all[q][p];
+#pragma unroll
+                    for (int c = 0; c < VW; ++c)
+                        a2[c] = fmaT(-hp, (p < q) ? up[p][c] : old[p][c], a2[c]);
+                }
+                st16(W + (int64_t)((i + 1) * S + q) * ld + e, a2);
+#pragma unroll
+                for (int c = 0; c < VW; ++c) old[q][c] = a2[c];
+            }
+#pragma unroll
+            for (int p = 0; p < S; ++p)
+#pragma unroll
+                for (int c = 0; c < VW; ++c) up[p][c] = old[p][c];
+        }
+#pragma unroll
+        for (int c = 0; c < VW; ++c) {
+            int v = 0;
+#pragma unroll
+            for (int i = 0; i <= L; ++i)
+#pragma unroll
+                for (int j = i; j <= L; ++j) acc[v++] += (double)z[i][c] * (double)z[j][c];
+        }
+    }
+    gram_finalize<L>(acc, ctl, part, stride);
 }
 
 // ---------------------------------------------------------------------------
@@ -1297,7 +1512,8 @@ __global__ __launch_bounds__(BLOCK) void k_correct(int64_t n, const float *__res
         x[e] = fma(sigma, (double)d[e], x[e]);
 }
 
-// P^T y and ||y||^2 of one vector.  dst 0: ptv[0][q] (recycled V); dst 1: ptt, tt.
+// P^T y and ||y||^2 of one vector.  dst 0: ptv[0][q] (recycled V); dst 1: ptt, tt;
+// dst 2: prec[q] (fetched V).
 template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_project(int64_t n, const T *__restrict__ y,
                                                    uint32_t pkey, int s, int dst, int q, Ctl *ctl,
@@ -1323,9 +1539,113 @@ __global__ __launch_bounds__(BLOCK) void k_project(int64_t n, const T *__restric
     if (threadIdx.x != 0) return;
     if (dst == 0) {
         for (int a = 0; a < s; ++a) ctl->ptv[0][q][a] = tot[a];
+    } else if (dst == 2) {
+        for (int a = 0; a < s; ++a) ctl->prec[q][a] = tot[a];
     } else {
         for (int a = 0; a < s; ++a) ctl->ptt[a] = tot[a];
         ctl->st.tt = tot[s];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Orthonormalization of fetched recycle data (an option; the paper keeps U, V
+// as a cycle leaves them): CholQR in FP64.  G = U^T U = L L^T, then
+// U := U L^-T and V := V L^-T column by column, which keeps V = A U and the
+// span of U (so the projection of the next right-hand side, Section 4.2, is
+// unchanged in exact arithmetic).
+// ---------------------------------------------------------------------------
+
+// Upper triangle of U^T U (FP64 sums of products of the stored values), then
+// in one thread the Cholesky factor: d_j = g_jj - sum_k l_jk^2,
+// l_jj = sqrt(d_j), l_ij = (g_ij - sum_k l_ik l_jk) / l_jj, each product
+// rounded before its subtraction.  d_j <= 1e-28 g_jj (or not positive) means
+// G is not numerically positive definite: chol_ok = 0 and the data stay as
+// fetched.
+template <typename T, int S>
+__global__ __launch_bounds__(BLOCK) void k_chol_gram(int64_t ld, const T *__restrict__ U, Ctl *ctl,
+                                                     double *part, int stride)
+{
+#pragma clang fp contract(off)
+    constexpr int NV = S * (S + 1) / 2;
+    double acc[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) acc[v] = 0.0;
+    for (int64_t e = (int64_t)blockIdx.x * BLOCK + threadIdx.x; e < ld;
+         e += (int64_t)gridDim.x * BLOCK) {
+        double u[S];
+#pragma unroll
+        for (int i = 0; i < S; ++i) u[i] = (double)U[(int64_t)i * ld + e];
+        int v = 0;
+#pragma unroll
+        for (int i = 0; i < S; ++i)
+#pragma unroll
+            for (int j = i; j < S; ++j) acc[v++] += u[i] * u[j];
+    }
+    block_partials<NV>(acc, NV, part, stride);
+    __shared__ double tot[NV];
+    if (!last_block_reduce(part, stride, NV, &ctl->counter[3], tot)) return;
+    if (threadIdx.x != 0) return;
+    double G[S][S], L[S][S];
+    int v = 0;
+#pragma unroll
+    for (int i = 0; i < S; ++i)
+#pragma unroll
+        for (int j = i; j < S; ++j) {
+            G[i][j] = G[j][i] = tot[v++];
+            L[i][j] = L[j][i] = 0.0;
+        }
+    bool ok = true;
+#pragma unroll
+    for (int j = 0; j < S; ++j) {
+        double d = G[j][j];
+#pragma unroll
+        for (int k = 0; k < j; ++k) d -= L[j][k] * L[j][k];
+        ok = ok && (d > 0.0) && (d > 1e-28 * G[j][j]);
+        L[j][j] = sqrt(d);
+#pragma unroll
+        for (int i = j + 1; i < S; ++i) {
+            double t = G[i][j];
+#pragma unroll
+            for (int k = 0; k < j; ++k) t -= L[i][k] * L[j][k];
+            L[i][j] = t / L[j][j];
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < S; ++i)
+#pragma unroll
+        for (int j = 0; j < S; ++j) ctl->chol[i][j] = L[i][j];
+    ctl->chol_ok = ok ? 1 : 0;
+}
+
+// B := B L^-T for the s columns of U and (if not NULL) V, element by element:
+// x_j = (b_j - sum_{i<j} l_ji x_i) / l_jj in FP64 with each product rounded,
+// the result rounded to T.  Nothing is written unless chol_ok.
+template <typename T, int S>
+__global__ __launch_bounds__(BLOCK) void k_chol_apply(int64_t ld, T *__restrict__ U, T *__restrict__ V,
+                                                      const Ctl *ctl)
+{
+#pragma clang fp contract(off)
+    if (!ctl->chol_ok) return;
+    double L[S][S];
+#pragma unroll
+    for (int i = 0; i < S; ++i)
+#pragma unroll
+        for (int j = 0; j <= i; ++j) L[i][j] = ctl->chol[i][j];
+    for (int64_t e = (int64_t)blockIdx.x * BLOCK + threadIdx.x; e < ld;
+         e += (int64_t)gridDim.x * BLOCK) {
+        for (int m = 0; m < (V ? 2 : 1); ++m) {
+            T *B = m == 0 ? U : V;
+            double x[S];
+#pragma unroll
+            for (int j = 0; j < S; ++j) {
+                double a = (double)B[(int64_t)j * ld + e];
+#pragma unroll
+                for (int i = 0; i < j; ++i) a -= L[j][i] * x[i];
+                x[j] = a / L[j][j];
+            }
+#pragma unroll
+            for (int j = 0; j < S; ++j) B[(int64_t)j * ld + e] = (T)x[j];
+        }
     }
 }
 

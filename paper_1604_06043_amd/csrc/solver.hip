@@ -714,6 +714,58 @@ struct Engine {
         if (prof) prof->end(slot);
     }
 
+    // k_eta_low(k) fused with gamma(k + 1) (k + 1 < l)
+    void eta_low_gamma(int k)
+    {
+        const int grid = grid_for(ld / Vec16<T>::W, BLOCK, VEC_MAX_BLOCKS);
+        int slot = prof ? prof->begin(MSTAB_K_ETA, vbytes(2 * s + 4 + 2 * (k + 1) * (s + 1))) : -1;
+        switch (s) {
+#define CASE(S)                                                                                   \
+    case S:                                                                                       \
+        hipLaunchKernelGGL((k_eta_low_gamma<T, S>), dim3(grid), dim3(BLOCK), 0, stream, ld, W, R, \
+                           X, k, ctl);                                                            \
+        break;
+            CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
+#undef CASE
+        }
+        HIPCHK(hipGetLastError());
+        if (prof) prof->end(slot);
+    }
+
+    template <int S>
+    void eta_low_gram_s(int grid)
+    {
+        switch (ell) {
+#define CASE(L)                                                                                  \
+    case L:                                                                                      \
+        hipLaunchKernelGGL((k_eta_low_gram<T, S, L>), dim3(grid), dim3(BLOCK), 0, stream, ld, W, \
+                           (const T *)R, ctl, part, PART_STRIDE);                                \
+        break;
+            CASE(1) CASE(2) CASE(3) CASE(4)
+#undef CASE
+        }
+    }
+
+    // k_eta_low(l - 1) fused with the Gram matrix and the tau solve (l <= 4)
+    void eta_low_gram()
+    {
+        const int grid = grid_for(ld / Vec16<T>::W, BLOCK, GRAM_MAX_BLOCKS);
+        const int k = ell - 1;
+        int slot = prof ? prof->begin(MSTAB_K_GRAM, vbytes(s + 1 + (k + 1) * (s + 1) + s * (k + 1))) : -1;
+        switch (s) {
+        case 1: eta_low_gram_s<1>(grid); break;
+        case 2: eta_low_gram_s<2>(grid); break;
+        case 3: eta_low_gram_s<3>(grid); break;
+        case 4: eta_low_gram_s<4>(grid); break;
+        case 5: eta_low_gram_s<5>(grid); break;
+        case 6: eta_low_gram_s<6>(grid); break;
+        case 7: eta_low_gram_s<7>(grid); break;
+        default: eta_low_gram_s<8>(grid); break;
+        }
+        HIPCHK(hipGetLastError());
+        if (prof) prof->end(slot);
+    }
+
     void gram()
     {
         const int grid = grid_for(ld / Vec16<T>::W, BLOCK, GRAM_MAX_BLOCKS);
@@ -856,18 +908,32 @@ struct Engine {
         small(SMALL_GAMMA0);
     }
 
+    // One cycle of Algorithm 1: the level loop (gamma, the r product, the s
+    // eta steps and v products), then the degree-l minimization and update.
+    // Kernels that follow each other without a reduction between them are
+    // fused: the lower levels' eta steps of level k with the gamma step of
+    // level k + 1, and those of the last level with the Gram matrix and tau.
     void cycle()
     {
+        // the fused Gram kernel holds all l + 1 residual levels and both V
+        // levels of its pass in registers: used while that stays small
+        const bool fuse_gram = ell <= 4 && s * ell * Vec16<T>::W <= 16;
+        gamma(0);
         for (int k = 0; k < ell; ++k) {
-            gamma(k);
             spmv(Rc(k), Rc(k + 1), nullptr, ACT_R, k, 0);
             for (int q = 0; q < s; ++q) {
                 eta(k, q);
                 spmv(Wc(k, q), Wc(k + 1, q), nullptr, ACT_V, k, q);
             }
-            eta_low(k);
+            if (k + 1 < ell) {
+                eta_low_gamma(k);
+            } else if (fuse_gram) {
+                eta_low_gram();
+            } else {
+                eta_low(k);
+                gram();
+            }
         }
-        gram();
         poly();
     }
 
@@ -882,13 +948,52 @@ struct Engine {
     // 1's prior requirement V = A U, which FP32 rounding erodes over the
     // hundreds of cycles that chained recycle data live through.
     bool refresh_v = false;
+    // Orthonormalize the fetched data (CholQR in FP64: U := U R^-1,
+    // V := V R^-1 with U^T U = R^T R), and recompute their P^T V.
+    bool orthonormalize = false;
+
+    template <int S>
+    void cholqr_s(T *V)
+    {
+        const int g = grid_for(ld, BLOCK, GRAM_MAX_BLOCKS);
+        hipLaunchKernelGGL((k_chol_gram<T, S>), dim3(g), dim3(BLOCK), 0, stream, ld,
+                           (const T *)recU, ctl, part, PART_STRIDE);
+        HIPCHK(hipGetLastError());
+        const int ga = grid_for(ld, BLOCK, VEC_MAX_BLOCKS);
+        hipLaunchKernelGGL((k_chol_apply<T, S>), dim3(ga), dim3(BLOCK), 0, stream, ld, recU, V,
+                           (const Ctl *)ctl);
+        HIPCHK(hipGetLastError());
+    }
+
+    // recU (and V unless NULL) := B R^-1; unchanged if U^T U is not
+    // numerically positive definite
+    void cholqr(T *V)
+    {
+        switch (s) {
+        case 1: cholqr_s<1>(V); break;
+        case 2: cholqr_s<2>(V); break;
+        case 3: cholqr_s<3>(V); break;
+        case 4: cholqr_s<4>(V); break;
+        case 5: cholqr_s<5>(V); break;
+        case 6: cholqr_s<6>(V); break;
+        case 7: cholqr_s<7>(V); break;
+        default: cholqr_s<8>(V); break;
+        }
+    }
 
     void fetch(int64_t level)
     {
         copy_vecs(recU, Wc(-1, 0), s);
         if (refresh_v) {
+            if (orthonormalize) cholqr(nullptr);
             for (int q = 0; q < s; ++q)
                 spmv(recU + (int64_t)q * ld, recV + (int64_t)q * ld, nullptr, ACT_RECV, 0, q);
+            HIPCHK(hipMemcpyAsync(rec_ptv, &ctl->prec[0][0], sizeof(double) * MAXS * MAXS,
+                                  hipMemcpyDeviceToDevice, stream));
+        } else if (orthonormalize) {
+            copy_vecs(recV, Wc(0, 0), s);
+            cholqr(recV);
+            for (int q = 0; q < s; ++q) project(recV + (int64_t)q * ld, 2, q);
             HIPCHK(hipMemcpyAsync(rec_ptv, &ctl->prec[0][0], sizeof(double) * MAXS * MAXS,
                                   hipMemcpyDeviceToDevice, stream));
         } else {
@@ -1128,6 +1233,9 @@ struct mstab_solver {
     int64_t mv_total = 0, mv_last = 0;
     std::vector<int64_t> hist_mv;
     std::vector<double> hist_res;
+    // the histories of every solve on the handle, in order
+    std::vector<std::vector<int64_t>> hist_mv_all;
+    std::vector<std::vector<double>> hist_res_all;
     std::string err;
     bool mixed() const { return opt.precision == MSTAB_PREC_F32_REFINE; }
 };
@@ -1205,9 +1313,25 @@ int grid1(int64_t n) { return grid_for(n, BLOCK, VEC_MAX_BLOCKS); }
 // defect-correction step; two or three suffice in practice)
 constexpr int LOW_MATRIX_REPLACEMENTS = 10;
 
+// Files the history of the solve that ends with this guard's scope.
+struct HistoryArchive {
+    mstab_solver *h;
+    ~HistoryArchive()
+    {
+        try {
+            h->hist_mv_all.push_back(h->hist_mv);
+            h->hist_res_all.push_back(h->hist_res);
+        } catch (...) {
+        }
+    }
+};
+
 mstab_status solve_f64(mstab_solver *h, const double *b, double *x, mstab_info *info,
                        int extra_checks, int accepted)
 {
+    HistoryArchive archive{h};
+    h->hist_mv.clear();
+    h->hist_res.clear();
     auto t0 = std::chrono::steady_clock::now();
     Engine<double> &E = h->e64;
     HIPCHK(hipMemcpyAsync(E.X, x, sizeof(double) * h->n, hipMemcpyDeviceToDevice, h->stream));
@@ -1253,6 +1377,7 @@ constexpr double FOLD_GROWTH = 1e2;
 mstab_status solve_mixed(mstab_solver *h, const double *b, double *x, mstab_info *info,
                          int extra_checks, int accepted)
 {
+    HistoryArchive archive{h};
     // One FP32 Krylov process per refinement.  At the end of a cycle where
     // its residual has fallen far enough (reliable updating), its iterate is
     // folded into the FP64 x and its recursive residual is replaced by the
@@ -1491,6 +1616,8 @@ mstab_status mstab_create(const mstab_csr *A, int32_t s, int32_t ell, const msta
         fail(MSTAB_E_INVALID, "unknown matrix format");
     if (h->opt.reorder != MSTAB_REORDER_NONE && h->opt.reorder != MSTAB_REORDER_RCM)
         fail(MSTAB_E_INVALID, "unknown reordering");
+    if (h->opt.orthonormalize_recycle != 0 && h->opt.orthonormalize_recycle != 1)
+        fail(MSTAB_E_INVALID, "orthonormalize_recycle must be 0 or 1");
     h->s = s; h->ell = ell; h->n = A->n; h->nnz = A->nnz;
     h->rp = A->row_ptr; h->ci = A->col_idx; h->va = A->val;
     h->stream = (hipStream_t)hip_stream;
@@ -1558,6 +1685,7 @@ mstab_status mstab_create(const mstab_csr *A, int32_t s, int32_t ell, const msta
     // the mixed form keeps a full FP64 engine for the FP64 fallback
     h->e64.alloc(h->n, s, ell, A64, true, h->pkey, h->stream, &h->prof);
     h->e64.replace_every = h->opt.replace_every;
+    h->e64.orthonormalize = h->opt.orthonormalize_recycle != 0;
     if (h->opt.precision == MSTAB_PREC_F32_MATRIX) {
         h->e64.A_low = make_sell<float, double>(h->n, h->rp, h->ci, h->va, h->stream, &A64);
         h->e64.use_low = true;
@@ -1569,6 +1697,7 @@ mstab_status mstab_create(const mstab_csr *A, int32_t s, int32_t ell, const msta
         Sell<float> A32 = make_sell<float, double>(h->n, h->rp, h->ci, h->va, h->stream, &A64);
         h->e32.alloc(h->n, s, ell, A32, false, h->pkey, h->stream, &h->prof);
         h->e32.refresh_v = true;
+        h->e32.orthonormalize = h->opt.orthonormalize_recycle != 0;
     }
     HIPCHK(hipStreamSynchronize(h->stream));
     // the device copies hold the split (and reordered) values; the reordered
@@ -1742,6 +1871,13 @@ mstab_status mstab_residual(mstab_solver *h, const double *b, const double *x, d
     API_END(h)
 }
 
+mstab_status mstab_solve_count(const mstab_solver *h, int64_t *count)
+{
+    if (!h || !count) return MSTAB_E_INVALID;
+    *count = (int64_t)h->hist_mv_all.size();
+    return MSTAB_OK;
+}
+
 mstab_status mstab_mv_count(const mstab_solver *h, int64_t *total, int64_t *last_system)
 {
     if (!h) return MSTAB_E_INVALID;
@@ -1750,12 +1886,25 @@ mstab_status mstab_mv_count(const mstab_solver *h, int64_t *total, int64_t *last
     return MSTAB_OK;
 }
 
-mstab_status mstab_residual_history(const mstab_solver *h, int64_t *mv, double *relres,
-                                    int64_t cap, int64_t *len)
+mstab_status mstab_residual_history(const mstab_solver *h, int64_t system, int64_t *mv,
+                                    double *relres, int64_t cap, int64_t *len)
 {
-    if (!h || !len || cap < 0 || (cap > 0 && (!mv || !relres))) return MSTAB_E_INVALID;
-    const std::vector<int64_t> &hm = h->mixed() ? h->hist_mv : h->hist_mv;
-    const std::vector<double> &hr = h->hist_res;
+    if (!h) { g_tls_error = "handle is NULL"; return MSTAB_E_INVALID; }
+    if (!len || cap < 0 || (cap > 0 && (!mv || !relres))) {
+        g_tls_error = "len NULL, cap < 0, or output arrays NULL";
+        return MSTAB_E_INVALID;
+    }
+    const int64_t count = (int64_t)h->hist_mv_all.size();
+    if (system < -1 || system >= count || (system == -1 && count == 0)) {
+        char buf[128];
+        snprintf(buf, sizeof buf, "system %lld outside -1..%lld", (long long)system, (long long)count - 1);
+        g_tls_error = buf;
+        const_cast<mstab_solver *>(h)->err = buf;
+        return MSTAB_E_INVALID;
+    }
+    const size_t k = system < 0 ? (size_t)(count - 1) : (size_t)system;
+    const std::vector<int64_t> &hm = h->hist_mv_all[k];
+    const std::vector<double> &hr = h->hist_res_all[k];
     *len = (int64_t)hm.size();
     for (int64_t i = 0; i < std::min<int64_t>(cap, (int64_t)hm.size()); ++i) {
         mv[i] = hm[i];

@@ -30,7 +30,7 @@ KERNEL_CLASSES = {"spmv": K_SPMV, "gamma": K_GAMMA, "eta": K_ETA, "gram": K_GRAM
 EXPORTS = [
     "mstab_options_default", "mstab_create", "mstab_solve_next", "mstab_solve_batch",
     "mstab_solve_next_guess",
-    "mstab_mv_count", "mstab_residual", "mstab_residual_history", "mstab_recycle_reset", "mstab_recycle_get",
+    "mstab_mv_count", "mstab_solve_count", "mstab_residual", "mstab_residual_history", "mstab_recycle_reset", "mstab_recycle_get",
     "mstab_recycle_set", "mstab_recycle_export", "mstab_recycle_import", "mstab_destroy", "mstab_status_str", "mstab_last_error",
     "mstab_set_profiling", "mstab_kernel_stats", "mstab_convdiff_nnz", "mstab_assemble_convdiff",
     "mstab_jacobi_split", "mstab_permutation", "mstab_rcm_order", "mstab_csr_check", "mstab_spmv", "mstab_project",
@@ -54,7 +54,8 @@ class mstab_options(ctypes.Structure):
                 ("p_seed", ctypes.c_uint64), ("max_replacements", ctypes.c_int32),
                 ("inner_tol", ctypes.c_double), ("max_refinements", ctypes.c_int32),
                 ("precond", ctypes.c_int32), ("replace_every", ctypes.c_int32),
-                ("reorder", ctypes.c_int32), ("matrix_format", ctypes.c_int32)]
+                ("reorder", ctypes.c_int32), ("matrix_format", ctypes.c_int32),
+                ("orthonormalize_recycle", ctypes.c_int32)]
 
 
 class mstab_info(ctypes.Structure):
@@ -95,7 +96,8 @@ def load(path: str = LIB_PATH):
         "mstab_solve_next_guess": (i32, [P, P, P, P, P, ctypes.POINTER(mstab_info)]),
         "mstab_mv_count": (i32, [P, ctypes.POINTER(i64), ctypes.POINTER(i64)]),
         "mstab_residual": (i32, [P, P, P, P, ctypes.POINTER(f64)]),
-        "mstab_residual_history": (i32, [P, P, P, i64, ctypes.POINTER(i64)]),
+        "mstab_residual_history": (i32, [P, i64, P, P, i64, ctypes.POINTER(i64)]),
+        "mstab_solve_count": (i32, [P, ctypes.POINTER(i64)]),
         "mstab_recycle_reset": (i32, [P]),
         "mstab_recycle_get": (i32, [P, P, P, ctypes.POINTER(i64), ctypes.POINTER(i32)]),
         "mstab_recycle_set": (i32, [P, P, P, i64]),
@@ -347,15 +349,21 @@ class Solver:
         _check(self.lib.mstab_permutation(self.h, perm.ctypes.data_as(ctypes.c_void_p)), self.h)
         return perm
 
-    def residual_history(self):
+    def residual_history(self, system: int = -1):
+        """(MVs, relative residuals) of solve number `system` on this handle (-1: the last)."""
         n = ctypes.c_int64()
-        _check(self.lib.mstab_residual_history(self.h, None, None, 0, ctypes.byref(n)))
+        _check(self.lib.mstab_residual_history(self.h, system, None, None, 0, ctypes.byref(n)), self.h)
         mv = (ctypes.c_int64 * max(n.value, 1))()
         rr = (ctypes.c_double * max(n.value, 1))()
-        _check(self.lib.mstab_residual_history(self.h, ctypes.cast(mv, ctypes.c_void_p),
+        _check(self.lib.mstab_residual_history(self.h, system, ctypes.cast(mv, ctypes.c_void_p),
                                                ctypes.cast(rr, ctypes.c_void_p), n.value,
-                                               ctypes.byref(n)))
+                                               ctypes.byref(n)), self.h)
         return list(mv[:n.value]), list(rr[:n.value])
+
+    def solve_count(self) -> int:
+        c = ctypes.c_int64()
+        _check(self.lib.mstab_solve_count(self.h, ctypes.byref(c)), self.h)
+        return c.value
 
     def recycle_reset(self):
         _check(self.lib.mstab_recycle_reset(self.h), self.h)
