@@ -390,6 +390,19 @@ mstab_status mstab_spmv(const mstab_csr *A, const double *x, double *y, void *hi
 mstab_status mstab_project(int64_t n, int32_t s, uint64_t p_seed, const double *y, double *out,
                            void *hip_stream);
 
+/*
+ * mstab_project without any device allocation, for callers that cannot
+ * allocate (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments, result and errors as mstab_project; its
+ * control block and workgroup partials live in a fixed device array of
+ * ~76 KB that the library holds on each GPU it runs on until the process
+ * ends.  n must be below 2^29 (E_INVALID otherwise).  Every call on one GPU
+ * shares that array: calls that overlap on one GPU (other streams or host
+ * threads) race and must be serialized by the caller.
+ */
+mstab_status mstab_project_noalloc(int64_t n, int32_t s, uint64_t p_seed, const double *y,
+                                   double *out, void *hip_stream);
+
 /* Implicit Euler right-hand side b = x inv_dt + f (device, n doubles, no contraction). */
 mstab_status mstab_rhs_step(int64_t n, const double *x, double inv_dt, const double *f, double *b,
                             void *hip_stream);

@@ -20,6 +20,7 @@
 #include <cstdio>
 #include <cstring>
 #include <functional>
+#include <mutex>
 #include <new>
 #include <string>
 #include <thread>
@@ -2257,6 +2258,79 @@ mstab_status mstab_project(int64_t n, int32_t s, uint64_t p_seed, const double *
                        p_key_from_seed(p_seed), s, 1, 0, sc.ctl, sc.part, PART_STRIDE);
     HIPCHK(hipGetLastError());
     HIPCHK(hipMemcpyAsync(out, sc.ctl->ptt, sizeof(double) * s, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    return MSTAB_OK;
+    API_END(nullptr)
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Scratch of mstab_project_noalloc: a control block and the workgroup partials
+// of one projection (s + 1 <= MAXS + 1 values from at most GRAM_MAX_BLOCKS
+// workgroups), in a file-scope device array that each GPU holds from load
+// until the process ends.  Host code uses the per-device address that
+// hipGetSymbolAddress returns, never the array's name.
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr size_t NOALLOC_CTL_BYTES = (sizeof(Ctl) + 255) / 256 * 256;
+constexpr size_t NOALLOC_PART_BYTES = sizeof(double) * (size_t)(MAXS + 1) * PART_STRIDE;
+constexpr size_t NOALLOC_BYTES = NOALLOC_CTL_BYTES + NOALLOC_PART_BYTES;
+static_assert(GRAM_MAX_BLOCKS <= PART_STRIDE, "projection grid exceeds the partials in scratch");
+
+static __device__ __align__(256) unsigned char scratch[NOALLOC_BYTES];
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[NOALLOC_MAX_DEVICES] = {};
+
+// The device address of scratch on the current device (looked up once per device).
+unsigned char *scratch_on_current_device()
+{
+    int dev = -1;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) fail(MSTAB_E_INVALID, "device %d out of range", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) fail(MSTAB_E_HIP, "no device address for the scratch array");
+        g_scratch_ptr[dev] = p;
+    }
+    return (unsigned char *)g_scratch_ptr[dev];
+}
+
+// zero the last-workgroup counters of a control block (a kernel, not a
+// memset, so that the call can be captured in a graph)
+__global__ void k_clear_counters(Ctl *ctl)
+{
+    if (threadIdx.x < 4) ctl->counter[threadIdx.x] = 0u;
+}
+
+}  // namespace
+
+extern "C" {
+
+mstab_status mstab_project_noalloc(int64_t n, int32_t s, uint64_t p_seed, const double *y,
+                                   double *out, void *hip_stream)
+{
+    API_BEGIN
+    if (!y || !out) fail(MSTAB_E_INVALID, "NULL pointer");
+    if (s < 1 || s > MAXS) fail(MSTAB_E_INVALID, "s=%d outside 1..%d", s, MAXS);
+    if (n < 1 || n >= ((int64_t)1 << 29))
+        fail(MSTAB_E_INVALID, "n=%lld outside 1..2^29-1 (the largest size this call serves)", (long long)n);
+    hipStream_t st = (hipStream_t)hip_stream;
+    unsigned char *base = scratch_on_current_device();
+    Ctl *ctl = (Ctl *)base;
+    double *part = (double *)(base + NOALLOC_CTL_BYTES);
+    hipLaunchKernelGGL(k_clear_counters, dim3(1), dim3(64), 0, st, ctl);
+    HIPCHK(hipGetLastError());
+    const int grid = grid_for(n, BLOCK, GRAM_MAX_BLOCKS);
+    hipLaunchKernelGGL((k_project<double>), dim3(grid), dim3(BLOCK), 0, st, n, y,
+                       p_key_from_seed(p_seed), s, 1, 0, ctl, part, PART_STRIDE);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(out, ctl->ptt, sizeof(double) * s, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     return MSTAB_OK;
     API_END(nullptr)

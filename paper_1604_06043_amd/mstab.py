@@ -33,7 +33,7 @@ EXPORTS = [
     "mstab_mv_count", "mstab_solve_count", "mstab_residual", "mstab_residual_history", "mstab_recycle_reset", "mstab_recycle_get",
     "mstab_recycle_set", "mstab_recycle_export", "mstab_recycle_import", "mstab_destroy", "mstab_status_str", "mstab_last_error",
     "mstab_set_profiling", "mstab_kernel_stats", "mstab_convdiff_nnz", "mstab_assemble_convdiff",
-    "mstab_jacobi_split", "mstab_permutation", "mstab_rcm_order", "mstab_csr_check", "mstab_spmv", "mstab_project",
+    "mstab_jacobi_split", "mstab_permutation", "mstab_rcm_order", "mstab_csr_check", "mstab_spmv", "mstab_project", "mstab_project_noalloc",
     "mstab_rhs_step",
     "mstab_cnn_param_count", "mstab_cnn_create", "mstab_cnn_destroy", "mstab_cnn_set_params",
     "mstab_cnn_get_params", "mstab_cnn_prepare", "mstab_cnn_forward", "mstab_cnn_gradient",
@@ -117,6 +117,7 @@ def load(path: str = LIB_PATH):
         "mstab_csr_check": (i32, [i64, i64, P, P]),
         "mstab_spmv": (i32, [ctypes.POINTER(mstab_csr), P, P, P]),
         "mstab_project": (i32, [i64, i32, u64, P, P, P]),
+        "mstab_project_noalloc": (i32, [i64, i32, u64, P, P, P]),
         "mstab_rhs_step": (i32, [i64, P, f64, P, P, P]),
         "mstab_cnn_param_count": (i64, []),
         "mstab_cnn_create": (i32, [i64, i64, i32, f64, P, P, ctypes.POINTER(P)]),
@@ -277,6 +278,15 @@ def mstab_project(y, s: int, p_seed: int, stream=None):
     out = (ctypes.c_double * s)()
     _check(load().mstab_project(y.numel(), s, p_seed, _ptr(y), ctypes.cast(out, ctypes.c_void_p),
                                 _stream(stream)))
+    return list(out)
+
+
+def mstab_project_noalloc(y, s: int, p_seed: int, stream=None):
+    """mstab_project through the entry point that allocates nothing."""
+    _require_cuda(y)
+    out = (ctypes.c_double * s)()
+    _check(load().mstab_project_noalloc(y.numel(), s, p_seed, _ptr(y), ctypes.cast(out, ctypes.c_void_p),
+                                        _stream(stream)))
     return list(out)
 
 
