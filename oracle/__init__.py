@@ -20,7 +20,10 @@ Functions follow the paper (Neuenhofen, arXiv 1604.06043):
   onto recycled data (Section 4.2);
 * :func:`jacobi_split`, :func:`solve_jacobi` -- the split preconditioned
   system of Section 5.1, L^{-1} A R^{-1} y = L^{-1} b with x = R^{-1} y, for
-  the diagonal splitting L = R = |D|^{1/2}.
+  the diagonal splitting L = R = |D|^{1/2};
+* :func:`multicolour`, :func:`ilu0`, :func:`solve_ilu` -- the same split form
+  with the ILU(0) factors that Section 5.1 uses, computed in a greedy
+  multicolour order of the matrix.
 """
 from __future__ import annotations
 
@@ -37,7 +40,7 @@ _lib = None
 
 OK, NOT_CONVERGED, E_INVALID, E_NOMEM, E_BREAKDOWN, E_NONFINITE = 0, 1, -1, -3, -4, -5
 MSTAB, IDRSTAB = 0, 1
-FETCH_THRESHOLD, FETCH_AT_LEVEL, FETCH_AT_END, FETCH_ONCE, FETCH_NEVER = 0, 1, 2, 3, 4
+FETCH_THRESHOLD, FETCH_AT_LEVEL, FETCH_AT_END, FETCH_ONCE, FETCH_NEVER, FETCH_ESTIMATE = 0, 1, 2, 3, 4, 5
 
 
 def build(force: bool = True) -> str:
@@ -67,7 +70,16 @@ def _load():
         _lib.orc_spmv.argtypes = [i64, P, P, P, P, P]
         _lib.orc_solve.restype = i32
         _lib.orc_solve.argtypes = [i64, P, P, P, i32, i32, P, f64, i64, i32, i32, f64, i64, i32,
-                                   i32, i32, P, P, P, P, P, P, P, P, P, P, i64, P, i64, P]
+                                   i32, i32, P, P, P, P, P, P, P, P, P, P, i64, P, i64, P, P, P]
+        _lib.orc_ilu0.restype = i32
+        _lib.orc_ilu0.argtypes = [i64, P, P, P, P]
+        for fn in ("orc_ilu_lower", "orc_ilu_upper", "orc_ilu_upper_mul"):
+            getattr(_lib, fn).restype = None
+            getattr(_lib, fn).argtypes = [i64, P, P, P, P, P]
+        _lib.orc_multicolour.restype = i32
+        _lib.orc_multicolour.argtypes = [i64, P, P, P, P]
+        _lib.orc_estimate_fetch_cycle.restype = i64
+        _lib.orc_estimate_fetch_cycle.argtypes = [P, i64]
         _lib.orc_cholqr.restype = i32
         _lib.orc_cholqr.argtypes = [i64, i32, P, P]
         _lib.orc_recycle_start.restype = i32
@@ -133,18 +145,20 @@ def spmv(A: CSR, x: np.ndarray) -> np.ndarray:
 
 @dataclass
 class Recycle:
-    """Recycled data of M(s)stab: U, V (n x s, column-major) and their level."""
+    """Recycled data of M(s)stab: U, V (n x s, column-major) and their level;
+    est: the fetch cycle that FETCH_ESTIMATE took from the last solve (-1: none)."""
     U: np.ndarray
     V: np.ndarray
     level: int = 0
     have: bool = False
+    est: int = -1
 
     @staticmethod
     def empty(n: int, s: int) -> "Recycle":
         return Recycle(np.zeros((n, s), order="F"), np.zeros((n, s), order="F"), 0, False)
 
     def copy(self) -> "Recycle":
-        return Recycle(self.U.copy(order="F"), self.V.copy(order="F"), self.level, self.have)
+        return Recycle(self.U.copy(order="F"), self.V.copy(order="F"), self.level, self.have, self.est)
 
 
 @dataclass
@@ -173,12 +187,16 @@ def solve(A: CSR, b, x0, s: int, ell: int, P: np.ndarray, tol: float = 1e-8,
           max_mv: int = 10 ** 9, method: int = MSTAB, fetch: int = FETCH_THRESHOLD,
           fetch_rel: float | None = None, fetch_level: int = -1, max_repl: int = 3,
           recycle: Recycle | None = None, dump_cycle: int = -1, replace_every: int = 0,
-          orthonormalize: bool = False):
+          orthonormalize: bool = False, ilu: np.ndarray | None = None):
     """Run Algorithm 1 on A x = b from x0.  Returns (x, info, recycle, dump).
 
     ``replace_every`` = k > 0 replaces the recursive residual by b - A x after
     every k-th cycle (Section 5.1's ocean run: k = 1).  ``orthonormalize``
     applies :func:`cholqr` to the U, V a solve fetches.
+
+    ``ilu`` (the ILU(0) factors of A in its pattern, :func:`ilu0`) makes the
+    operator L^{-1} A U^{-1}: the split preconditioned system of Section 5.1,
+    whose right-hand side and start the caller prepares (:func:`solve_ilu`).
 
     ``recycle`` is updated in place (fetched data) and also returned.
     ``dump`` (if dump_cycle >= 0) is a dict with the state after the level
@@ -203,6 +221,7 @@ def solve(A: CSR, b, x0, s: int, ell: int, P: np.ndarray, tol: float = 1e-8,
     hmv = np.zeros(cap, dtype=np.int64)
     hres = np.zeros(cap)
     hl = np.zeros(1, dtype=np.int64)
+    est = np.array([recycle.est], dtype=np.int64)
     dump = None
     if dump_cycle >= 0:
         dump = np.zeros(n * (2 + ell + s * (ell + 2)) + ell + n * (2 + 2 * s))
@@ -212,8 +231,10 @@ def solve(A: CSR, b, x0, s: int, ell: int, P: np.ndarray, tol: float = 1e-8,
                        _ptr(b), _ptr(x),
                        _ptr(recycle.U), _ptr(recycle.V), _ptr(lvl), _ptr(have),
                        _ptr(oi), _ptr(of), _ptr(hmv), _ptr(hres), cap, _ptr(hl),
-                       int(dump_cycle), _ptr(dump))
+                       int(dump_cycle), _ptr(dump), _ptr(est),
+                       None if ilu is None else _ptr(np.ascontiguousarray(ilu, dtype=np.float64)))
     recycle.level = int(lvl[0])
+    recycle.est = int(est[0])
     recycle.have = bool(have[0])
     h = int(min(hl[0], cap))
     info = Info(int(st), int(oi[0]), int(oi[1]), int(oi[2]), int(oi[3]), int(oi[4]), bool(oi[5]),
@@ -261,6 +282,15 @@ class sum_order:
     def __exit__(self, *exc):
         _load().orc_set_sum_order(SUM_FORWARD)
         return False
+
+
+def estimate_fetch_cycle(hist_res) -> int:
+    """The fetch point "shortly before the residual drops" (Section 5, how to
+    choose the fetching point) from a solve's history of recursive relative
+    residuals (initial, then one per cycle): the cycle before the largest
+    one-cycle reduction (at least cycle 1); -1 for no cycle."""
+    h = np.ascontiguousarray(hist_res, dtype=np.float64)
+    return int(_load().orc_estimate_fetch_cycle(_ptr(h), h.shape[0]))
 
 
 def cholqr(U: np.ndarray, V: np.ndarray | None = None) -> bool:
@@ -347,6 +377,70 @@ def solve_jacobi(A: CSR, b, x0, s: int, ell: int, P: np.ndarray, split=None, **k
     return y * d, info, rec, dd
 
 
+def multicolour(A: CSR):
+    """Greedy multicolour order of A's symmetrized pattern: (perm, colour_ptr)
+    with perm[new] = old, colours in order, index order within a colour."""
+    n = A.n
+    perm = np.zeros(n, dtype=np.int32)
+    cp = np.zeros(n + 1, dtype=np.int32)
+    nc = _load().orc_multicolour(n, _ptr(A.row_ptr), _ptr(A.col), _ptr(perm), _ptr(cp))
+    if nc < 0:
+        raise MemoryError("multicolour")
+    return perm, cp[:nc + 1].copy()
+
+
+def permute(A: CSR, perm: np.ndarray) -> CSR:
+    """The symmetrically permuted matrix Pi A Pi^T (row new = row perm[new]),
+    columns sorted within each row."""
+    import scipy.sparse as sp
+    M = A.scipy()[perm][:, perm].tocsr()
+    M.sort_indices()
+    return CSR(M.indptr.astype(np.int32), M.indices.astype(np.int32), M.data.astype(np.float64))
+
+
+def ilu0(A: CSR) -> np.ndarray:
+    """ILU(0) factors in A's pattern (L below the diagonal, U on and above)."""
+    lu = np.empty(A.nnz)
+    st = _load().orc_ilu0(A.n, _ptr(A.row_ptr), _ptr(A.col), _ptr(A.val), _ptr(lu))
+    if st != 0:
+        raise ValueError("ilu0: missing or zero pivot")
+    return lu
+
+
+def ilu_apply(A: CSR, lu: np.ndarray, which: str, v: np.ndarray) -> np.ndarray:
+    """'lower': L^{-1} v; 'upper': U^{-1} v; 'upper_mul': U v."""
+    fn = {"lower": "orc_ilu_lower", "upper": "orc_ilu_upper", "upper_mul": "orc_ilu_upper_mul"}[which]
+    v = np.ascontiguousarray(v, dtype=np.float64)
+    out = np.empty(A.n)
+    getattr(_load(), fn)(A.n, _ptr(A.row_ptr), _ptr(A.col), _ptr(lu), _ptr(v), _ptr(out))
+    return out
+
+
+def ilu_split(A: CSR):
+    """The split ILU(0) preconditioning in a multicolour order: (A', lu,
+    perm) with A' = Pi A Pi^T and lu its ILU(0) factors."""
+    perm, _ = multicolour(A)
+    Ap = permute(A, perm)
+    return Ap, ilu0(Ap), perm
+
+
+def solve_ilu(A: CSR, b, x0, s: int, ell: int, P: np.ndarray, split=None, **kw):
+    """:func:`solve` on the split system of Section 5.1 with ILU(0) factors of
+    the multicolour-ordered matrix: L^{-1} A' U^{-1} y = L^{-1} b', x' = U^{-1} y,
+    with b' = b[perm], y0 = U x0[perm] and x[perm] = x'.  P (n x s) is the
+    cut-space basis of the iteration (permuted) space.  The tolerance and the
+    residual history refer to the preconditioned residual.  Returns (x, info,
+    recycle, dump) as :func:`solve`."""
+    Ap, lu, perm = split if split is not None else ilu_split(A)
+    b = np.asarray(b, dtype=np.float64)
+    bh = ilu_apply(Ap, lu, "lower", b[perm])
+    y0 = ilu_apply(Ap, lu, "upper_mul", np.asarray(x0, dtype=np.float64)[perm])
+    y, info, rec, dd = solve(Ap, bh, y0, s, ell, P, ilu=lu, **kw)
+    x = np.empty(A.n)
+    x[perm] = ilu_apply(Ap, lu, "upper", y)
+    return x, info, rec, dd
+
+
 def rhs_step(x: np.ndarray, inv_dt: float, f: np.ndarray) -> np.ndarray:
     """Implicit Euler right-hand side b = x inv_dt + f (multiply, then add)."""
     return x * inv_dt + f
@@ -354,17 +448,21 @@ def rhs_step(x: np.ndarray, inv_dt: float, f: np.ndarray) -> np.ndarray:
 
 def solve_sequence(A: CSR, f, inv_dt: float, s: int, ell: int, P, systems: int,
                    method: int = MSTAB, tol: float = 1e-8, fetch: int = FETCH_THRESHOLD,
-                   jacobi: bool = False, **kw):
+                   jacobi: bool = False, ilu: bool = False, **kw):
     """Time-stepping sequence: b^(k+1) = x^(k) inv_dt + f, x0 = x^(k), x^(0) = 0.
 
-    ``jacobi`` solves every system in the split diagonally preconditioned form."""
+    ``jacobi`` solves every system in the split diagonally preconditioned form,
+    ``ilu`` in the split ILU(0) form of a multicolour order."""
     x = np.zeros(A.n)
     rec = Recycle.empty(A.n, s)
     xs, infos = [], []
-    split = jacobi_split(A) if jacobi else None
+    split = jacobi_split(A) if jacobi else (ilu_split(A) if ilu else None)
     for _ in range(systems):
         b = rhs_step(x, inv_dt, f)
-        if jacobi:
+        if ilu:
+            x, info, rec, _ = solve_ilu(A, b, x, s, ell, P, split=split, tol=tol, method=method,
+                                        fetch=fetch, recycle=rec, **kw)
+        elif jacobi:
             x, info, rec, _ = solve_jacobi(A, b, x, s, ell, P, split=split, tol=tol, method=method,
                                            fetch=fetch, recycle=rec, **kw)
         else:

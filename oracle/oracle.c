@@ -66,6 +66,7 @@
 #define ORC_FETCH_AT_END 2
 #define ORC_FETCH_ONCE 3
 #define ORC_FETCH_NEVER 4
+#define ORC_FETCH_ESTIMATE 5
 
 #define ORC_MAX_RESTARTS 2
 
@@ -159,22 +160,169 @@ typedef struct {
     const int32_t *rp, *ci;
     const double *va;
     int64_t mv; /* products with A performed */
+    /* optional ILU(0) split preconditioning (Section 5.1): the factors in A's
+       pattern (lu) and one scratch vector; the operator is then
+       L^{-1} A U^{-1} */
+    const double *lu;
+    double *tmp;
 } Mat;
 
-static void matvec(Mat *A, const double *x, double *y)
+static void plain_product(const Mat *A, const double *x, double *y)
 {
     for (int64_t i = 0; i < A->n; ++i) {
         double acc = 0.0;
         for (int64_t k = A->rp[i]; k < A->rp[i + 1]; ++k) acc += A->va[k] * x[A->ci[k]];
         y[i] = acc;
     }
+}
+
+/* y = L^{-1} w for the unit lower factor stored below the diagonal of lu
+   (rows in order; y may alias w): y_i = w_i - sum_{k<i} l_ik y_k, the
+   products subtracted in column order. */
+void orc_ilu_lower(int64_t n, const int32_t *rp, const int32_t *ci, const double *lu,
+                   const double *w, double *y)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        double acc = w[i];
+        for (int64_t k = rp[i]; k < rp[i + 1] && ci[k] < i; ++k) acc -= lu[k] * y[ci[k]];
+        y[i] = acc;
+    }
+}
+
+/* x = U^{-1} z for the upper factor stored on and above the diagonal of lu
+   (rows from the last; x may alias z): x_i = (z_i - sum_{j>i} u_ij x_j) / u_ii,
+   the products subtracted in column order. */
+void orc_ilu_upper(int64_t n, const int32_t *rp, const int32_t *ci, const double *lu,
+                   const double *z, double *x)
+{
+    for (int64_t i = n - 1; i >= 0; --i) {
+        double acc = z[i];
+        int64_t dk = -1;
+        for (int64_t k = rp[i]; k < rp[i + 1]; ++k) {
+            if (ci[k] == i) dk = k;
+            else if (ci[k] > i) acc -= lu[k] * x[ci[k]];
+        }
+        x[i] = acc / lu[dk];
+    }
+}
+
+/* y = U x with the same upper factor: y_i = u_ii x_i + sum_{j>i} u_ij x_j in
+   column order. */
+void orc_ilu_upper_mul(int64_t n, const int32_t *rp, const int32_t *ci, const double *lu,
+                       const double *x, double *y)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        double acc = 0.0;
+        for (int64_t k = rp[i]; k < rp[i + 1]; ++k)
+            if (ci[k] >= i) acc += lu[k] * x[ci[k]];
+        y[i] = acc;
+    }
+}
+
+static void matvec(Mat *A, const double *x, double *y)
+{
+    if (A->lu) {
+        orc_ilu_upper(A->n, A->rp, A->ci, A->lu, x, A->tmp);
+        plain_product(A, A->tmp, y);
+        orc_ilu_lower(A->n, A->rp, A->ci, A->lu, y, y);
+    } else {
+        plain_product(A, x, y);
+    }
     A->mv++;
+}
+
+/*
+ * ILU(0) of a CSR matrix with sorted columns (Section 5.1 preconditions with
+ * an incomplete LU factorization without fill-in): L unit lower and U upper
+ * in A's pattern with (LU)_ij = a_ij on that pattern.  Rows in order; in row
+ * i, for each k < i of its pattern in column order: l_ik = a_ik / u_kk, then
+ * a_ij -= l_ik u_kj for every j > k of row i's pattern that row k also holds.
+ * lu (nnz) receives L below the diagonal and U on and above it.  Returns 0,
+ * or 1 if a row lacks its diagonal entry or a pivot u_ii is zero or not
+ * finite.
+ */
+int orc_ilu0(int64_t n, const int32_t *rp, const int32_t *ci, const double *va, double *lu)
+{
+    memcpy(lu, va, sizeof(double) * (size_t)rp[n]);
+    int64_t *dpos = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    if (!dpos) return ORC_E_NOMEM;
+    for (int64_t i = 0; i < n; ++i) {
+        dpos[i] = -1;
+        for (int64_t k = rp[i]; k < rp[i + 1]; ++k)
+            if (ci[k] == i) dpos[i] = k;
+        if (dpos[i] < 0) { free(dpos); return 1; }
+    }
+    for (int64_t i = 0; i < n; ++i) {
+        for (int64_t kk = rp[i]; kk < rp[i + 1] && ci[kk] < i; ++kk) {
+            const int64_t k = ci[kk];
+            lu[kk] = lu[kk] / lu[dpos[k]];
+            const double lik = lu[kk];
+            /* row k's entries right of column k, merged with row i's right of kk */
+            int64_t p = dpos[k] + 1;
+            for (int64_t jj = kk + 1; jj < rp[i + 1]; ++jj) {
+                while (p < rp[k + 1] && ci[p] < ci[jj]) ++p;
+                if (p < rp[k + 1] && ci[p] == ci[jj]) lu[jj] -= lik * lu[p];
+            }
+        }
+        const double d = lu[dpos[i]];
+        if (!(d != 0.0) || !isfinite(d)) { free(dpos); return 1; }
+    }
+    free(dpos);
+    return 0;
+}
+
+/*
+ * A multicolour order of the symmetrized pattern (A + A^T, diagonal ignored):
+ * nodes in index order each take the smallest colour that none of their
+ * already coloured neighbours has.  perm[new] = old lists colour 0 first,
+ * then colour 1, ..., index order within a colour; colour_ptr[c] is the first
+ * new index of colour c (colour_ptr[ncolours] = n).  No two neighbours share
+ * a colour, so in this order the rows of one colour have no entries in each
+ * other's columns.  Returns the number of colours, or -1 on allocation
+ * failure.  colour_ptr needs room for n + 1 entries.
+ */
+int orc_multicolour(int64_t n, const int32_t *rp, const int32_t *ci, int32_t *perm, int32_t *colour_ptr)
+{
+    const int64_t nnz = rp[n];
+    int32_t *tp = calloc((size_t)n + 1, sizeof(int32_t));
+    int32_t *tc = malloc(sizeof(int32_t) * (size_t)(nnz > 0 ? nnz : 1));
+    int32_t *col = malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    int64_t *mark = malloc(sizeof(int64_t) * (size_t)(n + 1));
+    int32_t *fill = calloc((size_t)n + 1, sizeof(int32_t));
+    if (!tp || !tc || !col || !mark || !fill) {
+        free(tp); free(tc); free(col); free(mark); free(fill);
+        return -1;
+    }
+    /* transposed pattern */
+    for (int64_t k = 0; k < nnz; ++k) tp[ci[k] + 1]++;
+    for (int64_t i = 0; i < n; ++i) tp[i + 1] += tp[i];
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t k = rp[i]; k < rp[i + 1]; ++k) tc[tp[ci[k]] + fill[ci[k]]++] = (int32_t)i;
+    int ncol = 0;
+    for (int64_t c = 0; c <= n; ++c) mark[c] = -1;
+    for (int64_t i = 0; i < n; ++i) {
+        for (int64_t k = rp[i]; k < rp[i + 1]; ++k)
+            if (ci[k] < i) mark[col[ci[k]]] = i;
+        for (int64_t k = tp[i]; k < tp[i + 1]; ++k)
+            if (tc[k] < i) mark[col[tc[k]]] = i;
+        int c = 0;
+        while (mark[c] == i) ++c;
+        col[i] = c;
+        if (c + 1 > ncol) ncol = c + 1;
+    }
+    for (int c = 0; c <= ncol; ++c) colour_ptr[c] = 0;
+    for (int64_t i = 0; i < n; ++i) colour_ptr[col[i] + 1]++;
+    for (int c = 0; c < ncol; ++c) colour_ptr[c + 1] += colour_ptr[c];
+    for (int c = 0; c <= ncol; ++c) fill[c] = 0;
+    for (int64_t i = 0; i < n; ++i) perm[colour_ptr[col[i]] + fill[col[i]]++] = (int32_t)i;
+    free(tp); free(tc); free(col); free(mark); free(fill);
+    return ncol;
 }
 
 void orc_spmv(int64_t n, const int32_t *rp, const int32_t *ci, const double *va,
               const double *x, double *y)
 {
-    Mat A = {n, rp, ci, va, 0};
+    Mat A = {n, rp, ci, va, 0, NULL, NULL};
     matvec(&A, x, y);
 }
 
@@ -519,6 +667,7 @@ int orc_recycle_start(int64_t n, int s, const double *P, const double *U, const 
     if (n <= 0 || s < 1 || s > 8) return -1;
     Work w;
     w.A.n = n; w.A.rp = NULL; w.A.ci = NULL; w.A.va = NULL; w.A.mv = 0;
+    w.A.lu = NULL; w.A.tmp = NULL;
     w.s = s; w.ell = 1; w.n = n; w.P = P;
     w.W = (double *)calloc((size_t)n * s * 3, sizeof(double));
     w.R = (double *)calloc((size_t)n * 2, sizeof(double));
@@ -530,6 +679,27 @@ int orc_recycle_start(int64_t n, int s, const double *P, const double *U, const 
     if (!bd) memcpy(r, RCOL(&w, 0), (size_t)n * sizeof(double));
     free(w.W); free(w.R);
     return bd;
+}
+
+/*
+ * The fetch point "shortly before the residual drops" (Section 5, how to
+ * choose the fetching point), estimated from a finished solve's convergence:
+ * the cycle k* with the largest one-cycle reduction of the recursive
+ * residual, res[k-1] / res[k] over cycles k >= 1 of the history (the first
+ * such cycle on ties), and the fetch at the end of the cycle before it,
+ * max(1, k* - 1).  hist_res[0] is the initial residual, hist_res[k] the one
+ * after cycle k.  Returns -1 when the solve ran no cycle.
+ */
+int64_t orc_estimate_fetch_cycle(const double *hist_res, int64_t len)
+{
+    int64_t best_k = -1;
+    double best = -1.0;
+    for (int64_t k = 1; k < len; ++k) {
+        const double f = hist_res[k] > 0.0 ? hist_res[k - 1] / hist_res[k] : INFINITY;
+        if (f > best) { best = f; best_k = k; }
+    }
+    if (best_k < 0) return -1;
+    return best_k > 1 ? best_k - 1 : 1;
 }
 
 /*
@@ -545,6 +715,11 @@ int orc_recycle_start(int64_t n, int s, const double *P, const double *U, const 
  * out_f64[0..1]: final recursive and true relative residual
  * hist: (total MVs, recursive relative residual) after the initial residual
  *       and after every cycle.
+ * est_cycle (FETCH_ESTIMATE; in/out): the fetch cycle estimated from the
+ *       previous solve of the sequence (-1: none yet, so this solve fetches
+ *       nothing and the next one starts like IDR(s)stab); this solve fetches
+ *       at the end of that cycle (or of its last one, if it stops earlier),
+ *       and on return holds the estimate from this solve's history.
  * dump: if dump_cycle >= 0, the state after the level loop of that cycle:
  *       x, R[0..l], W[-1..l] (n each) then tau (l values); after it, the
  *       state after the same cycle's update: x, r, U, V.
@@ -557,17 +732,23 @@ int orc_solve(int64_t n, const int32_t *rp, const int32_t *ci, const double *va,
               double *U, double *V, int64_t *rec_level, int *rec_have,
               int64_t *out_i64, double *out_f64,
               int64_t *hist_mv, double *hist_res, int64_t hist_cap, int64_t *hist_len,
-              int64_t dump_cycle, double *dump)
+              int64_t dump_cycle, double *dump, int64_t *est_cycle, const double *ilu)
 {
     if (n <= 0 || s < 1 || s > 8 || ell < 1 || ell > 8 || n <= s) return ORC_E_INVALID;
     Work w;
     w.A.n = n; w.A.rp = rp; w.A.ci = ci; w.A.va = va; w.A.mv = 0;
+    w.A.lu = ilu; w.A.tmp = NULL;
     w.s = s; w.ell = ell; w.n = n; w.P = P;
     w.W = (double *)calloc((size_t)n * s * (ell + 2), sizeof(double));
     w.R = (double *)calloc((size_t)n * (ell + 1), sizeof(double));
     double *t = (double *)calloc((size_t)n, sizeof(double));
-    if (!w.W || !w.R || !t) { free(w.W); free(w.R); free(t); return ORC_E_NOMEM; }
+    if (ilu) w.A.tmp = (double *)calloc((size_t)n, sizeof(double));
+    if (!w.W || !w.R || !t || (ilu && !w.A.tmp)) {
+        free(w.W); free(w.R); free(t); free(w.A.tmp);
+        return ORC_E_NOMEM;
+    }
 
+    const int64_t est_in = est_cycle ? *est_cycle : -1;
     int64_t mv_check = 0, cycles = 0, hl = 0, fetched = -1, level = 0;
     int converged = 0, recycled = 0, restarts = 0, repl = 0, repl_end = 0, status = ORC_OK;
     int64_t since_true = 0;   /* cycles since r was last the true residual */
@@ -659,6 +840,7 @@ int orc_solve(int64_t n, const int32_t *rp, const int32_t *ci, const double *va,
             case ORC_FETCH_THRESHOLD: fire = (fetched < 0 && rel <= fetch_rel); break;
             case ORC_FETCH_AT_LEVEL: fire = (level == fetch_level); break;
             case ORC_FETCH_ONCE: fire = (!*rec_have && fetched < 0 && rel <= fetch_rel); break;
+            case ORC_FETCH_ESTIMATE: fire = (est_in > 0 && fetched < 0 && cycles == est_in); break;
             default: break;
             }
             if (fire) {
@@ -696,13 +878,16 @@ int orc_solve(int64_t n, const int32_t *rp, const int32_t *ci, const double *va,
     if (!converged && status == ORC_OK) status = ORC_NOT_CONVERGED;
     if (cycles > 0 && fetched < 0 && (fetch == ORC_FETCH_AT_END ||
                                       (fetch == ORC_FETCH_THRESHOLD) ||
-                                      (fetch == ORC_FETCH_ONCE && !*rec_have))) {
+                                      (fetch == ORC_FETCH_ONCE && !*rec_have) ||
+                                      (fetch == ORC_FETCH_ESTIMATE && est_in > 0))) {
         memcpy(U, WCOL(&w, -1, 0), (size_t)n * s * sizeof(double));
         memcpy(V, WCOL(&w, 0, 0), (size_t)n * s * sizeof(double));
         if (orth) orc_cholqr(n, s, U, V);
         fetched = level;
     }
     if (fetched >= 0) { *rec_level = fetched; *rec_have = 1; }
+    if (fetch == ORC_FETCH_ESTIMATE && est_cycle)
+        *est_cycle = orc_estimate_fetch_cycle(hist_res, hl < hist_cap ? hl : hist_cap);
 
 done:
     out_i64[0] = w.A.mv;
@@ -717,7 +902,7 @@ done:
     out_f64[0] = nb2 > 0.0 ? sqrt(rr / nb2) : 0.0;
     out_f64[1] = relres_true;
     *hist_len = hl;
-    free(w.W); free(w.R); free(t);
+    free(w.W); free(w.R); free(t); free(w.A.tmp);
     return status;
 #undef HIST
 }
@@ -729,7 +914,7 @@ done:
 int orc_bicgstab(int64_t n, const int32_t *rp, const int32_t *ci, const double *va,
                  const double *b, double *x, const double *rhat, int iters)
 {
-    Mat A = {n, rp, ci, va, 0};
+    Mat A = {n, rp, ci, va, 0, NULL, NULL};
     double *r = calloc((size_t)n, sizeof(double)), *p = calloc((size_t)n, sizeof(double));
     double *v = calloc((size_t)n, sizeof(double)), *sv = calloc((size_t)n, sizeof(double));
     double *tv = calloc((size_t)n, sizeof(double));

@@ -248,6 +248,62 @@ def test_finite_termination_worked_example(orc, seed):
         assert hr[k - 1] > 1e-5, (run["name"], seed, hr[k - 1])
 
 
+def test_estimate_fetch_cycle_closed_forms(orc):
+    """The cycle before the largest one-cycle reduction of the residual."""
+    assert orc.estimate_fetch_cycle([1.0]) == -1                       # no cycle
+    assert orc.estimate_fetch_cycle([1.0, 0.5]) == 1                   # one cycle: at least 1
+    assert orc.estimate_fetch_cycle([1.0, 0.5, 0.25, 1e-6, 5e-7]) == 2   # drop in cycle 3
+    assert orc.estimate_fetch_cycle([1.0, 1e-3, 0.5, 5e-4]) == 1       # ties: the first
+    assert orc.estimate_fetch_cycle([1.0, 2.0, 4.0, 1.0]) == 2          # growth then a drop
+    assert orc.estimate_fetch_cycle([1.0, 0.9, 0.0]) == 1               # exact zero: the drop
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 3])
+@pytest.mark.parametrize("s,ell,level", [(2, 1, 19), (4, 1, 9), (4, 2, 8)])
+def test_estimated_fetch_point_reproduces_the_worked_example(orc, seed, s, ell, level):
+    """FETCH_ESTIMATE (Section 5, how to choose the fetching point: solve two
+    systems, the first one's convergence estimates the second's).  The first
+    solve of b1 fetches nothing and leaves the estimate; the second solve of b1
+    (again from a fresh Arnoldi basis) fetches there, which is the point the
+    Section 5.2 example chose by hand "shortly before the residual drops": G_19
+    for IDR(2)stab(1), G_9 for IDR(4)stab(1), G_8 for IDR(4)stab(2).  With that
+    data M(s)stab on b2 terminates where the example says."""
+    g = json.load(open(os.path.join(GOLDEN, "finite_termination.json")))
+    A = _tridiag(orc)
+    P = I.p_dense(seed, 40, s)
+    rec = orc.Recycle.empty(40, s)
+    _, i1, rec, _ = orc.solve(A, _rhs("b1"), np.zeros(40), s, ell, P, tol=1e-15, method=orc.MSTAB,
+                              fetch=orc.FETCH_ESTIMATE, recycle=rec, max_repl=0)
+    assert not i1.recycled and i1.fetched == -1 and not rec.have
+    assert rec.est * ell == level, (rec.est, level)
+    _, i2, rec, _ = orc.solve(A, _rhs("b1"), np.zeros(40), s, ell, P, tol=1e-15, method=orc.MSTAB,
+                              fetch=orc.FETCH_ESTIMATE, recycle=rec, max_repl=0)
+    assert not i2.recycled and i2.fetched == level and rec.have and rec.level == level
+    run = next(r for r in g["runs"] if r["method"] == "mstab" and r["s"] == s and r["ell"] == ell
+               and r["source"] == {"s": s, "ell": ell, "level": level})
+    _, i3, _, _ = orc.solve(A, _rhs("b2"), np.zeros(40), s, ell, P, tol=1e-15, method=orc.MSTAB,
+                            fetch=orc.FETCH_NEVER, recycle=rec.copy(), max_repl=0)
+    hm, hr = list(i3.hist_mv), list(i3.hist_res)
+    k = hm.index(run["drop_mv"])
+    assert hr[k] < 1e-6 and hr[k - 1] > 1e-5, (run["name"], seed, hr[k - 1], hr[k])
+
+
+def test_estimate_policy_chains_and_reports_its_fetches(orc):
+    """Along a time-stepping sequence the policy fetches nothing in the first
+    solve, fetches at the estimated cycle from the second on (the second still
+    starting from an Arnoldi basis), and every solve converges."""
+    cd = I.config("c1", seed=0, n=20)
+    A = orc.assemble_convdiff(cd.dim, cd.n, cd.beta, cd.inv_dt)
+    s, ell = 4, 2
+    P = I.p_dense(0, cd.N, s)
+    xs, infos = orc.solve_sequence(A, cd.f, cd.inv_dt, s, ell, P, 5, fetch=orc.FETCH_ESTIMATE)
+    assert all(i.converged for i in infos)
+    assert infos[0].fetched == -1 and not infos[0].recycled and not infos[1].recycled
+    for i in infos[1:]:
+        assert i.fetched > 0
+    assert all(i.recycled for i in infos[2:])
+
+
 # --------------------------------------------------------------------------
 # Recycling semantics
 # --------------------------------------------------------------------------
