@@ -101,12 +101,13 @@ def cpu_baseline(cd, s, ell, mvs_per_system, threads):
 
 def class_kernels(cls: str, s: int, ell: int):
     """The kernels of one timing class of the FP64 solver."""
-    return {"spmv": [f"k_spmv_dia<double, {s}, double, true>", f"k_spmv_dia<double, {s}, double, false>",
+    return {"spmv": [f"k_spmv_dia_const<double, {s}, 7>", f"k_spmv_dia_const<double, {s}, 5>",
+                     f"k_spmv_dia<double, {s}, double, true>", f"k_spmv_dia<double, {s}, double, false>",
                      f"k_spmv<double, {s}, double>"],
-            "eta": [f"k_eta<double, {s}>", f"k_eta_low<double, {s}>"],
+            "eta": [f"k_eta<double, {s}>", f"k_eta_low<double, {s}>", f"k_eta_low_gamma<double, {s}>"],
             "gamma": [f"k_gamma<double, {s}>"],
             "poly": [f"k_poly<double, {s}, {ell}>"],
-            "gram": [f"k_gram<double, {ell}>"]}[cls]
+            "gram": [f"k_gram<double, {ell}>", f"k_eta_low_gram<double, {s}, {ell}>"]}[cls]
 
 
 def measured_traffic(name_parts):
@@ -302,6 +303,10 @@ def main():
 
         x64, _, _ = run_sequence(torch, ms, solver, cd, f, args.systems)
         variants["idrstab"], _ = variant("IDR(s)stab(l)", method=ms.METHOD_IDRSTAB)
+        # the fetch point estimated from the previous solve's convergence
+        # (Section 5, how to choose the fetching point) instead of sqrt(tol)
+        variants["mstab_fetch_estimate"], _ = variant("M(s)stab(l), estimated fetch point",
+                                                      method=ms.METHOD_MSTAB, fetch=ms.FETCH_ESTIMATE)
         # the same method with the diagonal values streamed from HBM instead of
         # kept as one constant per diagonal (bit-identical iterates)
         variants["diagonal_values_streamed"], _ = variant("values streamed", method=ms.METHOD_MSTAB,

@@ -68,12 +68,21 @@ typedef enum {
     MSTAB_FETCH_AT_LEVEL = 1,  /* cycle end at which the level of U, V equals fetch_level */
     MSTAB_FETCH_AT_END = 2,    /* last cycle end of the solve */
     MSTAB_FETCH_ONCE = 3,      /* THRESHOLD on the first solve, then keep that data for all */
-    MSTAB_FETCH_NEVER = 4      /* never replace the held data */
+    MSTAB_FETCH_NEVER = 4,     /* never replace the held data */
+    MSTAB_FETCH_ESTIMATE = 5   /* the fetch point "shortly before the residual drops" estimated
+                                  from the previous solve (Section 5, how to choose the fetching
+                                  point: the first system's convergence estimates the second's):
+                                  the cycle before that solve's largest one-cycle reduction of the
+                                  residual (at least 1).  The first solve of a sequence (or after
+                                  mstab_recycle_reset) fetches nothing and only estimates, so the
+                                  second also starts like IDR(s)stab and fetches at the estimate;
+                                  from then on each solve fetches at the cycle estimated from the
+                                  one before (at its last cycle if it stops earlier). */
 } mstab_fetch;
 
 typedef enum {
     MSTAB_PRECOND_NONE = 0,    /* solve A x = b as given */
-    MSTAB_PRECOND_JACOBI = 1   /* split diagonal preconditioning, Section 5.1's split form
+    MSTAB_PRECOND_JACOBI = 1,  /* split diagonal preconditioning, Section 5.1's split form
                                   L^-1 A R^-1 y = L^-1 b, x = R^-1 y, with L = R = |D|^(1/2)
                                   (D = diag(A)).  The handle iterates on the split system:
                                   tol, relres_recursive, relres_true, the residual history and
@@ -81,6 +90,18 @@ typedef enum {
                                   residual L^-1 (b - A x), and recycled U, V (recycle_get/set)
                                   live in the split system's space.  Every row needs a stored,
                                   finite, nonzero diagonal entry (else E_INVALID at create). */
+    MSTAB_PRECOND_ILU0 = 2     /* the same split form with the incomplete LU factorization without
+                                  fill-in that Section 5.1 uses: A' = P A P^T in a greedy
+                                  multicolour order of A's symmetrized pattern (no entry couples
+                                  two rows of one colour), A' ~ L U with (LU)_ij = a'_ij on A''s
+                                  pattern, and the iteration runs on L^-1 A' U^-1 y = L^-1 b',
+                                  x' = U^-1 y (one triangular-solve launch per colour, in order
+                                  for L, in reverse for U).  Each product with that operator counts
+                                  as one MV.  As for JACOBI, tol, the residual history and the
+                                  replacements refer to the preconditioned residual, and recycled
+                                  U, V and mstab_permutation refer to the ordered, split system.
+                                  F64 precision and REORDER_NONE only; a missing diagonal entry or
+                                  a zero pivot is E_INVALID at create. */
 } mstab_precond;
 
 typedef enum {
@@ -257,7 +278,8 @@ mstab_status mstab_residual_history(const mstab_solver *h, int64_t system, int64
 /* Number of solves made on the handle (each mstab_solve_next, _guess or batch entry). */
 mstab_status mstab_solve_count(const mstab_solver *h, int64_t *count);
 
-/* Drop the held recycle data (the next MSTAB solve starts like IDR(s)stab). */
+/* Drop the held recycle data (the next MSTAB solve starts like IDR(s)stab) and
+ * FETCH_ESTIMATE's estimate. */
 mstab_status mstab_recycle_reset(mstab_solver *h);
 
 /*
@@ -277,7 +299,7 @@ mstab_status mstab_recycle_set(mstab_solver *h, const double *U, const double *V
 /*
  * Checkpoint and resume of the recycle state, the data a fetch writes out
  * (Section 5, preliminaries): a self-describing host byte blob holding the
- * level, the P^T V cache and U, V (with the s, n, cut-space seed,
+ * level, the P^T V cache, U, V and FETCH_ESTIMATE's estimate (with the s, n, cut-space seed,
  * preconditioner and order they belong to).  export: dst (host, cap bytes)
  * receives the blob and *len its size; dst NULL only sets *len.  import:
  * installs a blob exported from a handle of the same problem (same s, n,

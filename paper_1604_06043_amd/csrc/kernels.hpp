@@ -801,6 +801,67 @@ __device__ __forceinline__ void dia_rows(int64_t n, int nd, const DiaOffsets &do
     }
 }
 
+// The rows of one thread for a constant-diagonal matrix with a compile-time
+// number of diagonals (ND = 7: the 3-D seven-point stencils, ND = 5: the 2-D
+// five-point ones).  The offsets and values sit in scalar registers for the
+// whole launch, indices are 32-bit, and each gather's column is clamped to
+// the row itself when it falls outside [0, n) (the presence bit of such an
+// entry is always clear), so the ND gathers issue back to back with no
+// branch; products are rounded and added in ascending column order exactly
+// as in dia_rows.
+#ifndef MSTAB_DIA_RPI
+#define MSTAB_DIA_RPI 1
+#endif
+template <typename T, int S, int ND, int RPI = MSTAB_DIA_RPI>
+__device__ __forceinline__ void dia_rows_const(int64_t n, const DiaOffsets &doff, const DiaConst &cv,
+                                               const uint16_t *__restrict__ mask, const T *__restrict__ x,
+                                               T *__restrict__ y, const T *__restrict__ b, bool resid,
+                                               uint32_t pkey, double (&vals)[S + 2])
+{
+#pragma clang fp contract(off)
+    const int32_t n32 = (int32_t)n;
+    int32_t off[ND];
+    T cst[ND];
+#pragma unroll
+    for (int d = 0; d < ND; ++d) {
+        off[d] = (int32_t)doff.off[d];
+        cst[d] = (T)cv.c[d];
+    }
+    // RPI rows per pass (grid-stride apart, so each wavefront's loads stay
+    // contiguous): all their gathers are issued before the first is summed
+    const int32_t stride = (int32_t)(gridDim.x * SPMV_BLOCK);
+    for (int32_t r0 = (int32_t)(blockIdx.x * SPMV_BLOCK + threadIdx.x); r0 < n32; r0 += RPI * stride) {
+        T xv[RPI][ND];
+#pragma unroll
+        for (int u = 0; u < RPI; ++u) {
+            const int32_t r = r0 + u * stride;
+            const int32_t rr = r < n32 ? r : r0;
+#pragma unroll
+            for (int d = 0; d < ND; ++d) {
+                const uint32_t c = (uint32_t)(rr + off[d]);
+                xv[u][d] = x[c < (uint32_t)n32 ? c : (uint32_t)rr];
+            }
+        }
+        // the presence mask is needed only by the sum: keep its load behind the
+        // gathers, so that waiting for it does not hold their issue back
+        asm volatile("" ::: "memory");
+#pragma unroll
+        for (int u = 0; u < RPI; ++u) {
+            const int32_t r = r0 + u * stride;
+            if (u > 0 && r >= n32) break;
+            const uint32_t m = mask[r];
+            T sum = (T)0;
+#pragma unroll
+            for (int d = 0; d < ND; ++d) {
+                const T prod = cst[d] * xv[u][d];
+                const T nsum = sum + prod;
+                sum = ((m >> d) & 1u) ? nsum : sum;
+            }
+            spmv_row_out<T, S>(r, sum, resid, b, y, pkey, vals);
+        }
+    }
+}
+
 // The same product for a matrix in diagonal storage (stencil matrices): one
 // thread per row, the diagonals' values of 64 consecutive rows one 512-byte
 // read each (or, for constant diagonals, no matrix reads at all beyond the
@@ -831,6 +892,24 @@ __attribute__((amdgpu_waves_per_eu(sizeof(TM) == 4 ? 8 : 1))) void k_spmv_dia(in
     spmv_finalize<S>(vals, ctl, part, stride, a);
 }
 
+// Constant diagonals, ND of them (5 or 7): the product's common case.
+template <typename T, int S, int ND>
+__global__ __launch_bounds__(SPMV_BLOCK)
+__attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 8 : 1))) void k_spmv_dia_const(int64_t n, DiaOffsets doff, DiaConst cv,
+                                                               const uint16_t *__restrict__ mask,
+                                                               const T *__restrict__ x,
+                                                               T *__restrict__ y,
+                                                               const T *__restrict__ b, Ctl *ctl,
+                                                               double *part, int stride, SpmvArgs a)
+{
+    if (ctl->st.flags) return;
+    const bool resid = (a.act == ACT_RESID || a.act == ACT_TRUE);
+    double vals[S + 2];
+#pragma unroll
+    for (int v = 0; v < S + 2; ++v) vals[v] = 0.0;
+    dia_rows_const<T, S, ND>(n, doff, cv, mask, x, y, b, resid, a.pkey, vals);
+    spmv_finalize<S>(vals, ctl, part, stride, a);
+}
 
 // 16-byte vectors of T (2 doubles or 4 floats) for the streaming kernels.
 template <typename T> struct Vec16;

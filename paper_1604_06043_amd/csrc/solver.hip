@@ -8,6 +8,7 @@
 // residual scaled by its FP64 norm, replacing the FP32 residual by the FP64
 // true residual after its cycles and keeping the FP32 recycle data across
 // systems.
+#include "ilu.hpp"
 #include "kernels.hpp"
 #include "mstab.h"
 
@@ -82,7 +83,14 @@ int grid_for(int64_t work, int per_block, int cap)
     return (int)g;
 }
 
-constexpr int SPMV_MAX_BLOCKS = 1024;
+#ifndef MSTAB_SPMV_MAX_BLOCKS
+#define MSTAB_SPMV_MAX_BLOCKS 1024
+#endif
+constexpr int SPMV_MAX_BLOCKS = MSTAB_SPMV_MAX_BLOCKS;
+// The constant-diagonal product: two workgroups per compute unit, all
+// resident at once, eight rows per thread (24.1 us against 28.0 us with 1024
+// workgroups at 128^3; fewer partials for its final reduction, too).
+constexpr int SPMV_CONST_MAX_BLOCKS = 512;
 constexpr int VEC_MAX_BLOCKS = 8192;
 constexpr int GRAM_MAX_BLOCKS = 1024;
 constexpr int POLY_MAX_BLOCKS = 1024;
@@ -330,6 +338,78 @@ std::vector<int32_t> rcm_order(int64_t n, const int32_t *rp, const int32_t *ci)
     return order;
 }
 
+// A multicolour order of the symmetrized pattern of a CSR matrix (host
+// arrays; diagonal ignored): nodes in index order take the smallest colour
+// that none of their already coloured neighbours (in A or A^T) has.  Returns
+// perm[new] = old, colour by colour, index order within a colour; cp receives
+// the first new index of each colour and n.  No entry then couples two rows
+// of one colour.
+std::vector<int32_t> multicolour_order(int64_t n, const int32_t *rp, const int32_t *ci,
+                                       std::vector<int64_t> &cp)
+{
+    // transposed pattern
+    std::vector<int64_t> tptr((size_t)n + 1, 0);
+    for (int64_t k = 0; k < rp[n]; ++k) tptr[(size_t)ci[k] + 1]++;
+    for (int64_t i = 0; i < n; ++i) tptr[i + 1] += tptr[i];
+    std::vector<int32_t> tcol((size_t)std::max<int64_t>(rp[n], 1));
+    {
+        std::vector<int64_t> pos(tptr.begin(), tptr.end() - 1);
+        for (int64_t i = 0; i < n; ++i)
+            for (int64_t k = rp[i]; k < rp[i + 1]; ++k) tcol[(size_t)pos[ci[k]]++] = (int32_t)i;
+    }
+    std::vector<int32_t> colour((size_t)n, 0);
+    std::vector<int64_t> used;   // used[c] == i: colour c taken by a neighbour of node i
+    int ncol = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        auto take = [&](int32_t j) {
+            if (j < i) {
+                const int c = colour[j];
+                if ((int)used.size() <= c) used.resize((size_t)c + 1, -1);
+                used[c] = i;
+            }
+        };
+        for (int64_t k = rp[i]; k < rp[i + 1]; ++k) take(ci[k]);
+        for (int64_t k = tptr[i]; k < tptr[i + 1]; ++k) take(tcol[k]);
+        int c = 0;
+        while (c < (int)used.size() && used[c] == i) ++c;
+        colour[i] = c;
+        ncol = std::max(ncol, c + 1);
+    }
+    cp.assign((size_t)ncol + 1, 0);
+    for (int64_t i = 0; i < n; ++i) cp[(size_t)colour[i] + 1]++;
+    for (int c = 0; c < ncol; ++c) cp[c + 1] += cp[c];
+    std::vector<int32_t> perm((size_t)n);
+    std::vector<int64_t> pos(cp.begin(), cp.end() - 1);
+    for (int64_t i = 0; i < n; ++i) perm[(size_t)pos[colour[i]]++] = (int32_t)i;
+    return perm;
+}
+
+// The symmetrically permuted CSR matrix P A P^T (row new = row perm[new]),
+// columns re-sorted, on the host.
+void permute_csr(int64_t n, const std::vector<int32_t> &rp, const std::vector<int32_t> &ci,
+                 const std::vector<double> &va, const std::vector<int32_t> &perm,
+                 std::vector<int32_t> &prp, std::vector<int32_t> &pci, std::vector<double> &pva)
+{
+    std::vector<int32_t> iperm((size_t)n);
+    for (int64_t i = 0; i < n; ++i) iperm[perm[i]] = (int32_t)i;
+    prp.assign((size_t)n + 1, 0);
+    pci.resize(ci.size());
+    pva.resize(va.size());
+    std::vector<std::pair<int32_t, double>> row;
+    for (int64_t i = 0; i < n; ++i) {
+        const int32_t o = perm[i];
+        row.clear();
+        for (int32_t k = rp[o]; k < rp[o + 1]; ++k) row.emplace_back(iperm[ci[k]], va[k]);
+        std::sort(row.begin(), row.end(),
+                  [](const std::pair<int32_t, double> &a, const std::pair<int32_t, double> &b) {
+                      return a.first < b.first;
+                  });
+        int64_t w = prp[i];
+        for (const auto &e : row) { pci[w] = e.first; pva[w] = e.second; ++w; }
+        prp[i + 1] = (int32_t)w;
+    }
+}
+
 // dst[i] = src[perm[i]] (times w[i] if w), and its inverse dst[perm[i]] = src[i] (times w[i]).
 __global__ __launch_bounds__(BLOCK) void k_gather(int64_t n, const int32_t *__restrict__ perm,
                                                   const double *__restrict__ src,
@@ -517,6 +597,22 @@ template <typename T, typename TM = T>
 void launch_spmv(int grid, hipStream_t stream, const Sell<TM> &A, const T *x, T *y, const T *b,
                  Ctl *ctl, double *part, SpmvArgs a)
 {
+    if (A.nd > 0 && A.dconst && (A.nd == 7 || A.nd == 5)) {
+        switch (a.s) {
+#define CASE(S)                                                                                      \
+    case S:                                                                                          \
+        if (A.nd == 7)                                                                               \
+            hipLaunchKernelGGL((k_spmv_dia_const<T, S, 7>), dim3(grid), dim3(SPMV_BLOCK), 0, stream, \
+                               A.n, A.doff, A.cv, A.dmask, x, y, b, ctl, part, PART_STRIDE, a);      \
+        else                                                                                         \
+            hipLaunchKernelGGL((k_spmv_dia_const<T, S, 5>), dim3(grid), dim3(SPMV_BLOCK), 0, stream, \
+                               A.n, A.doff, A.cv, A.dmask, x, y, b, ctl, part, PART_STRIDE, a);      \
+        break;
+            CASE(0) CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
+#undef CASE
+        }
+        return;
+    }
     if (A.nd > 0) {
         switch (a.s) {
 #define CASE(S)                                                                                   \
@@ -546,6 +642,24 @@ void launch_spmv(int grid, hipStream_t stream, const Sell<TM> &A, const T *x, T 
     }
 }
 
+// The fetch point "shortly before the residual drops" (Section 5, how to
+// choose the fetching point), estimated from a finished solve's history of
+// recursive relative residuals (initial, then one per cycle): the cycle before
+// the largest one-cycle reduction, res[k-1] / res[k] (the first on ties), at
+// least cycle 1; -1 when no cycle ran.  FETCH_ESTIMATE applies it to the next
+// solve of the sequence.
+int64_t estimate_fetch_cycle(const std::vector<double> &h)
+{
+    int64_t best_k = -1;
+    double best = -1.0;
+    for (size_t k = 1; k < h.size(); ++k) {
+        const double f = h[k] > 0.0 ? h[k - 1] / h[k] : INFINITY;
+        if (f > best) { best = f; best_k = (int64_t)k; }
+    }
+    if (best_k < 0) return -1;
+    return best_k > 1 ? best_k - 1 : 1;
+}
+
 struct SolveResult {
     int status = MSTAB_OK;
     bool converged = false;
@@ -554,6 +668,50 @@ struct SolveResult {
     int replacements = 0;
     int64_t mv = 0, mv_check = 0, cycles = 0, level = 0, fetched = -1;
     double relres_rec = 0, relres_true = -1;
+};
+
+// ILU(0) factors of the multicolour-ordered matrix A' (device), for the
+// preconditioned operator L^-1 A' U^-1.
+struct IluData {
+    int64_t n = 0, nnz = 0;
+    const int32_t *rp = nullptr, *ci = nullptr;   // A''s CSR structure (device)
+    double *lu = nullptr;                          // L below, U on and above the diagonal
+    int32_t *dpos = nullptr;                       // position of each row's diagonal
+    std::vector<int64_t> cp;                       // first row of each colour, and n
+    double *t1 = nullptr, *t2 = nullptr;           // scratch vectors of the operator
+
+    int colours() const { return (int)cp.size() - 1; }
+    // x := U^-1 z, colour by colour from the last (z and x distinct)
+    void upper_solve(const double *z, double *x, hipStream_t st) const
+    {
+        for (int c = colours() - 1; c >= 0; --c) {
+            const int64_t rows = cp[c + 1] - cp[c];
+            hipLaunchKernelGGL(k_ilu_upper_rows, dim3(grid_for(rows, BLOCK, VEC_MAX_BLOCKS)), dim3(BLOCK), 0,
+                               st, cp[c], cp[c + 1], rp, ci, (const double *)lu, (const int32_t *)dpos, z, x);
+            HIPCHK(hipGetLastError());
+        }
+    }
+    // y := L^-1 y in place, colour by colour (colour 0 has no lower entries)
+    void lower_solve(double *y, hipStream_t st) const
+    {
+        for (int c = 1; c < colours(); ++c) {
+            const int64_t rows = cp[c + 1] - cp[c];
+            hipLaunchKernelGGL(k_ilu_lower_rows, dim3(grid_for(rows, BLOCK, VEC_MAX_BLOCKS)), dim3(BLOCK), 0,
+                               st, cp[c], cp[c + 1], rp, ci, (const double *)lu, (const int32_t *)dpos, y);
+            HIPCHK(hipGetLastError());
+        }
+    }
+    void upper_mul(const double *x, double *y, hipStream_t st) const
+    {
+        hipLaunchKernelGGL(k_ilu_upper_mul, dim3(grid_for(n, BLOCK, VEC_MAX_BLOCKS)), dim3(BLOCK), 0, st, n,
+                           rp, ci, (const double *)lu, (const int32_t *)dpos, x, y);
+        HIPCHK(hipGetLastError());
+    }
+    void release()
+    {
+        (void)hipFree(lu); (void)hipFree(dpos); (void)hipFree(t1); (void)hipFree(t2);
+        lu = nullptr; dpos = nullptr; t1 = t2 = nullptr;
+    }
 };
 
 // ---------------------------------------------------------------------------
@@ -573,6 +731,8 @@ struct Engine {
     double *rec_ptv = nullptr;         // device, MAXS*MAXS
     int64_t rec_level = 0;
     bool rec_have = false;
+    // FETCH_ESTIMATE: the fetch cycle estimated from the last solve (-1: none)
+    int64_t est_cycle = -1;
 
     Ctl *ctl = nullptr;
     Status *st_host = nullptr;         // pinned
@@ -644,12 +804,58 @@ struct Engine {
     // the two grows with the correction made since then)
     double low_drop = 1e-3;
 
+    // ILU(0) split preconditioning: the products are L^-1 A U^-1 (FP64 only)
+    const IluData *ilu = nullptr;
+
+    template <int S>
+    void vec_out_s(int grid, const T *t, const T *b, T *y, const SpmvArgs &a)
+    {
+        hipLaunchKernelGGL((k_vec_out<T, S>), dim3(grid), dim3(SPMV_BLOCK), 0, stream, n, t, b, y, ctl, part,
+                           PART_STRIDE, a);
+    }
+
+    // y = L^-1 A U^-1 x (or b - that), then the product's epilogue for `act`
+    void ilu_product(const T *x, T *y, const T *b, const SpmvArgs &a)
+    {
+        if constexpr (sizeof(T) == 8) {
+            ilu->upper_solve(x, ilu->t1, stream);
+            SpmvArgs none{ACT_NONE, 0, 0, 0, 1, pkey};
+            launch_spmv<T>(grid_for(n, SPMV_BLOCK, SPMV_MAX_BLOCKS), stream, A, ilu->t1, ilu->t2, nullptr,
+                           ctl, part, none);
+            HIPCHK(hipGetLastError());
+            ilu->lower_solve(ilu->t2, stream);
+            const int grid = grid_for(n, SPMV_BLOCK, SPMV_MAX_BLOCKS);
+            switch (s) {
+            case 1: vec_out_s<1>(grid, ilu->t2, b, y, a); break;
+            case 2: vec_out_s<2>(grid, ilu->t2, b, y, a); break;
+            case 3: vec_out_s<3>(grid, ilu->t2, b, y, a); break;
+            case 4: vec_out_s<4>(grid, ilu->t2, b, y, a); break;
+            case 5: vec_out_s<5>(grid, ilu->t2, b, y, a); break;
+            case 6: vec_out_s<6>(grid, ilu->t2, b, y, a); break;
+            case 7: vec_out_s<7>(grid, ilu->t2, b, y, a); break;
+            default: vec_out_s<8>(grid, ilu->t2, b, y, a); break;
+            }
+            HIPCHK(hipGetLastError());
+        }
+    }
+
     void spmv(const T *x, T *y, const T *b, int act, int k, int q)
     {
         SpmvArgs a{act, k, q, s, ell, pkey};
-        const int grid = grid_for(n, SPMV_BLOCK, SPMV_MAX_BLOCKS);
+        if (ilu) {
+            // factors read twice (lower and upper halves), the product, and the
+            // vectors: x, t1 (write, read), t2 (write, read, write), y (and b)
+            const double lub = 12.0 * (double)ilu->nnz + 8.0 * (double)n;
+            const double bytes = lub + spmv_bytes(A, false, sizeof(T)) + (b ? 8.0 : 6.0) * n * sizeof(T);
+            int slot = prof ? prof->begin(MSTAB_K_SPMV, bytes) : -1;
+            ilu_product(x, y, b, a);
+            if (prof) prof->end(slot);
+            return;
+        }
         // the FP64 matrix for true residuals and the initial residual
         const bool low = use_low && act != ACT_TRUE && act != ACT_RESID;
+        const bool cst = low ? A_low.dconst : A.dconst;
+        const int grid = grid_for(n, SPMV_BLOCK, cst ? SPMV_CONST_MAX_BLOCKS : SPMV_MAX_BLOCKS);
         const double bytes = low ? spmv_bytes(A_low, b != nullptr, sizeof(T))
                                  : spmv_bytes(A, b != nullptr, sizeof(T));
         int slot = prof ? prof->begin(MSTAB_K_SPMV, bytes) : -1;
@@ -1061,6 +1267,7 @@ struct Engine {
             small(SMALL_GAMMA0);
         }
         const bool had_rec = rec_have;
+        const int64_t est_in = est_cycle;
         int64_t fetched = -1;
 
         for (;;) {
@@ -1153,6 +1360,7 @@ struct Engine {
                 case MSTAB_FETCH_THRESHOLD: fire = (fetched < 0 && rel <= fetch_rel); break;
                 case MSTAB_FETCH_AT_LEVEL: fire = (level == fetch_level); break;
                 case MSTAB_FETCH_ONCE: fire = (!had_rec && fetched < 0 && rel <= fetch_rel); break;
+                case MSTAB_FETCH_ESTIMATE: fire = (est_in > 0 && fetched < 0 && res.cycles == est_in); break;
                 default: break;
                 }
                 if (fire) {
@@ -1189,10 +1397,12 @@ struct Engine {
         if (!res.converged) res.status = MSTAB_NOT_CONVERGED;
         if (res.cycles > 0 && fetched < 0 &&
             (fetch_policy == MSTAB_FETCH_AT_END || fetch_policy == MSTAB_FETCH_THRESHOLD ||
-             (fetch_policy == MSTAB_FETCH_ONCE && !had_rec))) {
+             (fetch_policy == MSTAB_FETCH_ONCE && !had_rec) ||
+             (fetch_policy == MSTAB_FETCH_ESTIMATE && est_in > 0))) {
             fetch(level);
             fetched = level;
         }
+        if (fetch_policy == MSTAB_FETCH_ESTIMATE) est_cycle = estimate_fetch_cycle(hist_res);
     out:
         sync_status();
         mv = st_host->mv;   // includes products of a fetch refresh after the last cycle
@@ -1229,6 +1439,9 @@ struct mstab_solver {
     // use by the sliced product), and the reordered iterate
     int32_t *perm = nullptr, *rp_perm = nullptr, *ci_perm = nullptr;
     double *va_perm = nullptr, *xwork = nullptr;
+    // PRECOND_ILU0: the factors of the multicolour-ordered matrix (perm is that
+    // order; rp_perm and ci_perm its structure)
+    IluData ilu;
     bool transformed() const { return pd || perm; }
     Profiler prof;
     int64_t mv_total = 0, mv_last = 0;
@@ -1276,6 +1489,7 @@ void release_handle(mstab_solver *h)
     (void)hipFree(h->ci_perm);
     (void)hipFree(h->va_perm);
     (void)hipFree(h->xwork);
+    h->ilu.release();
     h->prof.destroy();
     delete h;
 }
@@ -1610,13 +1824,20 @@ mstab_status mstab_create(const mstab_csr *A, int32_t s, int32_t ell, const msta
     if (h->opt.precision != MSTAB_PREC_F64 && h->opt.precision != MSTAB_PREC_F32_REFINE &&
         h->opt.precision != MSTAB_PREC_F32_MATRIX)
         fail(MSTAB_E_INVALID, "unknown precision");
-    if (h->opt.precond != MSTAB_PRECOND_NONE && h->opt.precond != MSTAB_PRECOND_JACOBI)
+    if (h->opt.precond != MSTAB_PRECOND_NONE && h->opt.precond != MSTAB_PRECOND_JACOBI &&
+        h->opt.precond != MSTAB_PRECOND_ILU0)
         fail(MSTAB_E_INVALID, "unknown preconditioner");
+    if (h->opt.precond == MSTAB_PRECOND_ILU0 && h->opt.precision != MSTAB_PREC_F64)
+        fail(MSTAB_E_INVALID, "ILU(0) preconditioning runs in F64 precision only");
+    if (h->opt.precond == MSTAB_PRECOND_ILU0 && h->opt.reorder != MSTAB_REORDER_NONE)
+        fail(MSTAB_E_INVALID, "ILU(0) preconditioning orders the matrix itself; reorder must be NONE");
     if (h->opt.replace_every < 0) fail(MSTAB_E_INVALID, "replace_every < 0");
     if (h->opt.matrix_format < MSTAB_FORMAT_AUTO || h->opt.matrix_format > MSTAB_FORMAT_SLICED)
         fail(MSTAB_E_INVALID, "unknown matrix format");
     if (h->opt.reorder != MSTAB_REORDER_NONE && h->opt.reorder != MSTAB_REORDER_RCM)
         fail(MSTAB_E_INVALID, "unknown reordering");
+    if (h->opt.fetch < MSTAB_FETCH_THRESHOLD || h->opt.fetch > MSTAB_FETCH_ESTIMATE)
+        fail(MSTAB_E_INVALID, "unknown fetch policy");
     if (h->opt.orthonormalize_recycle != 0 && h->opt.orthonormalize_recycle != 1)
         fail(MSTAB_E_INVALID, "orthonormalize_recycle must be 0 or 1");
     h->s = s; h->ell = ell; h->n = A->n; h->nnz = A->nnz;
@@ -1626,8 +1847,10 @@ mstab_status mstab_create(const mstab_csr *A, int32_t s, int32_t ell, const msta
     h->pkey = p_key_from_seed(h->opt.p_seed);
     h->prof.init(h->stream);
     check_csr_dev(h->n, h->nnz, h->rp, h->ci, h->stream);
-    if (h->opt.reorder == MSTAB_REORDER_RCM) {
-        // host: the order and the symmetrically permuted CSR (columns re-sorted)
+    const bool use_ilu = h->opt.precond == MSTAB_PRECOND_ILU0;
+    if (h->opt.reorder == MSTAB_REORDER_RCM || use_ilu) {
+        // host: the order (reverse Cuthill-McKee, or the multicolour order of
+        // the ILU(0) splitting) and the symmetrically permuted CSR
         const int64_t n = h->n;
         std::vector<int32_t> rp((size_t)n + 1), ci((size_t)h->nnz);
         std::vector<double> va((size_t)h->nnz);
@@ -1635,26 +1858,13 @@ mstab_status mstab_create(const mstab_csr *A, int32_t s, int32_t ell, const msta
         HIPCHK(hipMemcpyAsync(ci.data(), h->ci, sizeof(int32_t) * h->nnz, hipMemcpyDeviceToHost, h->stream));
         HIPCHK(hipMemcpyAsync(va.data(), h->va, sizeof(double) * h->nnz, hipMemcpyDeviceToHost, h->stream));
         HIPCHK(hipStreamSynchronize(h->stream));
-        const std::vector<int32_t> perm = rcm_order(n, rp.data(), ci.data());
+        std::vector<int64_t> cp;
+        const std::vector<int32_t> perm = use_ilu ? multicolour_order(n, rp.data(), ci.data(), cp)
+                                                  : rcm_order(n, rp.data(), ci.data());
         if ((int64_t)perm.size() != n) fail(MSTAB_E_INVALID, "reordering lost rows");
-        std::vector<int32_t> iperm((size_t)n);
-        for (int64_t i = 0; i < n; ++i) iperm[perm[i]] = (int32_t)i;
-        std::vector<int32_t> prp((size_t)n + 1), pci((size_t)h->nnz);
-        std::vector<double> pva((size_t)h->nnz);
-        std::vector<std::pair<int32_t, double>> row;
-        prp[0] = 0;
-        for (int64_t i = 0; i < n; ++i) {
-            const int32_t o = perm[i];
-            row.clear();
-            for (int32_t k = rp[o]; k < rp[o + 1]; ++k) row.emplace_back(iperm[ci[k]], va[k]);
-            std::sort(row.begin(), row.end(),
-                      [](const std::pair<int32_t, double> &a, const std::pair<int32_t, double> &b) {
-                          return a.first < b.first;
-                      });
-            int64_t w = prp[i];
-            for (const auto &e : row) { pci[w] = e.first; pva[w] = e.second; ++w; }
-            prp[i + 1] = (int32_t)w;
-        }
+        std::vector<int32_t> prp, pci;
+        std::vector<double> pva;
+        permute_csr(n, rp, ci, va, perm, prp, pci, pva);
         HIPCHK(hipMalloc(&h->perm, sizeof(int32_t) * (size_t)n));
         HIPCHK(hipMalloc(&h->rp_perm, sizeof(int32_t) * (size_t)(n + 1)));
         HIPCHK(hipMalloc(&h->ci_perm, sizeof(int32_t) * (size_t)std::max<int64_t>(h->nnz, 1)));
@@ -1665,6 +1875,44 @@ mstab_status mstab_create(const mstab_csr *A, int32_t s, int32_t ell, const msta
         HIPCHK(hipMemcpyAsync(h->rp_perm, prp.data(), sizeof(int32_t) * (n + 1), hipMemcpyHostToDevice, h->stream));
         HIPCHK(hipMemcpyAsync(h->ci_perm, pci.data(), sizeof(int32_t) * h->nnz, hipMemcpyHostToDevice, h->stream));
         HIPCHK(hipMemcpyAsync(h->va_perm, pva.data(), sizeof(double) * h->nnz, hipMemcpyHostToDevice, h->stream));
+        if (use_ilu) {
+            // diagonal positions, then the factorization colour by colour
+            std::vector<int32_t> dpos((size_t)n, -1);
+            for (int64_t i = 0; i < n; ++i)
+                for (int32_t k = prp[i]; k < prp[i + 1]; ++k)
+                    if (pci[k] == i) dpos[i] = k;
+            for (int64_t i = 0; i < n; ++i)
+                if (dpos[i] < 0) fail(MSTAB_E_INVALID, "ILU(0): row %lld has no diagonal entry", (long long)i);
+            IluData &L = h->ilu;
+            L.n = n;
+            L.nnz = h->nnz;
+            L.rp = h->rp_perm;
+            L.ci = h->ci_perm;
+            L.cp = cp;
+            HIPCHK(hipMalloc(&L.lu, sizeof(double) * (size_t)std::max<int64_t>(h->nnz, 1)));
+            HIPCHK(hipMalloc(&L.dpos, sizeof(int32_t) * (size_t)n));
+            HIPCHK(hipMalloc(&L.t1, sizeof(double) * (size_t)round_up(n, 256)));
+            HIPCHK(hipMalloc(&L.t2, sizeof(double) * (size_t)round_up(n, 256)));
+            HIPCHK(hipMemcpyAsync(L.dpos, dpos.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, h->stream));
+            HIPCHK(hipMemcpyAsync(L.lu, pva.data(), sizeof(double) * h->nnz, hipMemcpyHostToDevice, h->stream));
+            int *bad = nullptr;
+            HIPCHK(hipMalloc(&bad, sizeof(int)));
+            int hbad = 0;
+            hipError_t e = hipMemsetAsync(bad, 0, sizeof(int), h->stream);
+            for (int c = 0; c < L.colours() && e == hipSuccess; ++c) {
+                const int64_t rows = cp[c + 1] - cp[c];
+                hipLaunchKernelGGL(k_ilu0_rows, dim3(grid_for(rows, BLOCK, VEC_MAX_BLOCKS)), dim3(BLOCK), 0,
+                                   h->stream, cp[c], cp[c + 1], (const int32_t *)L.rp, (const int32_t *)L.ci,
+                                   L.lu, (const int32_t *)L.dpos, bad);
+                e = hipGetLastError();
+            }
+            if (e == hipSuccess) e = hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, h->stream);
+            const hipError_t se = hipStreamSynchronize(h->stream);
+            (void)hipFree(bad);
+            HIPCHK(e);
+            HIPCHK(se);
+            if (hbad) fail(MSTAB_E_INVALID, "ILU(0): a zero or non-finite pivot");
+        }
         HIPCHK(hipStreamSynchronize(h->stream));   // the host vectors go out of scope
         h->rp = h->rp_perm;
         h->ci = h->ci_perm;
@@ -1685,6 +1933,7 @@ mstab_status mstab_create(const mstab_csr *A, int32_t s, int32_t ell, const msta
                                                  h->opt.matrix_format);
     // the mixed form keeps a full FP64 engine for the FP64 fallback
     h->e64.alloc(h->n, s, ell, A64, true, h->pkey, h->stream, &h->prof);
+    if (use_ilu) h->e64.ilu = &h->ilu;
     h->e64.replace_every = h->opt.replace_every;
     h->e64.orthonormalize = h->opt.orthonormalize_recycle != 0;
     if (h->opt.precision == MSTAB_PREC_F32_MATRIX) {
@@ -1705,9 +1954,11 @@ mstab_status mstab_create(const mstab_csr *A, int32_t s, int32_t ell, const msta
     // row pointer stays (the sliced product reads it); the rest is released
     (void)hipFree(h->split_tmp);
     h->split_tmp = nullptr;
-    (void)hipFree(h->ci_perm);
+    if (!use_ilu) {   // the ILU(0) solves keep reading the ordered structure
+        (void)hipFree(h->ci_perm);
+        h->ci_perm = nullptr;
+    }
     (void)hipFree(h->va_perm);
-    h->ci_perm = nullptr;
     h->va_perm = nullptr;
     h->va = h->perm ? nullptr : A->val;
     h->ci = h->perm ? nullptr : A->col_idx;
@@ -1738,6 +1989,35 @@ mstab_status mstab_solve_next(mstab_solver *h, const double *b, double *x, mstab
     if (!h->transformed())
         return h->mixed() ? solve_mixed(h, b, x, info, 0, 0) : solve_f64(h, b, x, info, 0, 0);
     const int grid = grid1(h->n);
+    if (h->ilu.lu) {
+        // ILU(0) split system in the multicolour order: b^ = L^-1 b[perm],
+        // y0 = U x0[perm]; afterwards x[perm] = U^-1 y (also after a failure)
+        const IluData &L = h->ilu;
+        hipLaunchKernelGGL(k_gather, dim3(grid), dim3(BLOCK), 0, h->stream, h->n, h->perm, b,
+                           (const double *)nullptr, h->bhat);
+        HIPCHK(hipGetLastError());
+        L.lower_solve(h->bhat, h->stream);
+        hipLaunchKernelGGL(k_gather, dim3(grid), dim3(BLOCK), 0, h->stream, h->n, h->perm, x,
+                           (const double *)nullptr, L.t1);
+        HIPCHK(hipGetLastError());
+        L.upper_mul(L.t1, h->xwork, h->stream);
+        auto finish = [&]() {
+            L.upper_solve(h->xwork, L.t1, h->stream);
+            hipLaunchKernelGGL(k_scatter, dim3(grid), dim3(BLOCK), 0, h->stream, h->n, h->perm,
+                               (const double *)L.t1, (const double *)nullptr, x);
+        };
+        mstab_status st;
+        try {
+            st = solve_f64(h, h->bhat, h->xwork, info, 0, 0);
+        } catch (...) {
+            finish();
+            throw;
+        }
+        finish();
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipStreamSynchronize(h->stream));
+        return st;
+    }
     if (h->perm) {
         // reordered (and possibly split) system: b' = L^-1 b[perm], y0 = R x0[perm];
         // afterwards x[perm] = R^-1 y (also after a failure)
@@ -1919,6 +2199,8 @@ mstab_status mstab_recycle_reset(mstab_solver *h)
     if (!h) return MSTAB_E_INVALID;
     h->e64.rec_have = false;
     h->e32.rec_have = false;
+    h->e64.est_cycle = -1;
+    h->e32.est_cycle = -1;
     return MSTAB_OK;
 }
 
@@ -1979,9 +2261,10 @@ struct RecycleBlob {
     int32_t precond, reorder;
     int32_t have, pad;
     int64_t level;
+    int64_t est_cycle;   // FETCH_ESTIMATE's fetch cycle for the next solve (-1: none)
 };
 constexpr char RECYCLE_MAGIC[8] = {'M', 'S', 'T', 'A', 'B', 'R', 'E', 'C'};
-constexpr uint32_t RECYCLE_VERSION = 1;
+constexpr uint32_t RECYCLE_VERSION = 2;
 
 size_t recycle_blob_size(const mstab_solver *h, bool have)
 {
@@ -2011,6 +2294,7 @@ mstab_status mstab_recycle_export(const mstab_solver *h, void *dst, size_t cap, 
     hd.reorder = h->opt.reorder;
     hd.have = E.rec_have ? 1 : 0;
     hd.level = E.rec_level;
+    hd.est_cycle = E.est_cycle;
     char *out = static_cast<char *>(dst);
     memcpy(out, &hd, sizeof hd);
     double *ptv = reinterpret_cast<double *>(out + sizeof hd);
@@ -2043,6 +2327,7 @@ mstab_status mstab_recycle_import(mstab_solver *h, const void *src, size_t len)
         fail(MSTAB_E_INVALID, "recycle blob of another problem (s, n, P seed, preconditioner or order differ)");
     if (len < recycle_blob_size(h, hd.have != 0)) fail(MSTAB_E_INVALID, "recycle blob truncated");
     Engine<double> &E = h->e64;
+    E.est_cycle = hd.est_cycle;
     if (!hd.have) {
         E.rec_have = false;
         return MSTAB_OK;

@@ -58,6 +58,19 @@ def init_params(seed: int, last_scale: float = 0.1) -> np.ndarray:
     return p
 
 
+def constant_diagonal(A: M.CSR) -> float:
+    """The diagonal entry of A if every row stores the same one (bit for bit),
+    else ValueError: the scalar Jacobi sweeps below divide by one value."""
+    rp = A.row_ptr.cpu().numpy()
+    ci = A.col_idx.cpu().numpy()
+    va = A.val.cpu().numpy()
+    rows = np.repeat(np.arange(A.n), np.diff(rp))
+    d = va[ci == rows]
+    if d.size != A.n or not np.all(d.view(np.uint64) == d[:1].view(np.uint64)):
+        raise ValueError("the operator's diagonal is not one constant: scalar Jacobi sweeps do not apply")
+    return float(d[0])
+
+
 class Problem:
     """The matrix (on the device) and the forcing of any sequence seed."""
 
@@ -66,6 +79,10 @@ class Problem:
         self.cd = I.config("c4", seed=MATRIX_SEED, n=n)
         self.A = M.mstab_assemble_convdiff(2, n, self.cd.beta, self.cd.inv_dt)
         self.unit = diag_unit(self.cd)
+        # the Jacobi sweeps use one diagonal value for every row: hold them to it
+        self.diag = constant_diagonal(self.A)
+        if abs(self.diag - self.unit) > 1e-12 * self.unit:
+            raise ValueError(f"diagonal {self.diag} differs from the formula's {self.unit}")
 
     def forcing(self, seed: int, steps: int):
         """Device tensor (steps, N): f^(1..steps) of sequence ``seed``."""
@@ -139,7 +156,8 @@ def train(cnn: M.Cnn, inp, tgt, epochs: int, batch: int, lr: float, seed: int = 
 def jacobi_sweeps(solver: M.Solver, b, cur, r, bufs, unit: float, sweeps: int,
                   omega: float = 2.0 / 3.0):
     """``sweeps`` damped Jacobi steps x <- x + (omega / unit)(b - A x) from cur
-    (unit: the operator's constant diagonal entry), alternating between the
+    (unit: the operator's diagonal entry, which must be the same in every row:
+    Problem checks it with constant_diagonal), alternating between the
     two buffers of bufs so that the last step writes bufs[0].  They damp the
     non-smooth part of a guess's error, which A amplifies.  One product with A
     each."""
@@ -152,12 +170,15 @@ def jacobi_sweeps(solver: M.Solver, b, cur, r, bufs, unit: float, sweeps: int,
 
 
 def network_guess(solver: M.Solver, cnn: M.Cnn, b, x, r, xg, rounds: int = 1, smooth: int = 0,
-                  tmp=None):
+                  tmp=None, diag: float | None = None):
     """x_guess (into xg) after ``rounds`` corrections x <- x + N(b - A x)
     starting from x (the network N as an approximate inverse of A), then
     ``smooth`` damped Jacobi sweeps (tmp: a second buffer, needed when
-    smooth > 0).  One product with A per round and per sweep.  Returns the
-    number of products."""
+    smooth > 0; diag: the operator's constant diagonal, Problem.diag, needed
+    when smooth > 0).  One product with A per round and per sweep.  Returns
+    the number of products."""
+    if smooth > 0 and diag is None:
+        raise ValueError("Jacobi sweeps need the operator's checked constant diagonal")
     bufs = (xg, tmp)
     cur = bufs[smooth % 2]          # so that the last sweep writes xg
     solver.residual(b, x, r)
@@ -165,7 +186,7 @@ def network_guess(solver: M.Solver, cnn: M.Cnn, b, x, r, xg, rounds: int = 1, sm
     for _ in range(rounds - 1):
         solver.residual(b, cur, r)
         cnn.guess(cur, r, cur)
-    return rounds + jacobi_sweeps(solver, b, cur, r, bufs, cnn.unit, smooth)
+    return rounds + jacobi_sweeps(solver, b, cur, r, bufs, diag, smooth)
 
 
 def evaluate(prob: Problem, cnn: M.Cnn | None, seed: int, steps: int, s: int = 4, ell: int = 2,
@@ -195,9 +216,9 @@ def evaluate(prob: Problem, cnn: M.Cnn | None, seed: int, steps: int, s: int = 4
             mv.append(info["mv_total"])
         else:
             if cnn is None:
-                extra = jacobi_sweeps(solver, b, x, r0, (xg, tmp), prob.unit, smooth)
+                extra = jacobi_sweeps(solver, b, x, r0, (xg, tmp), prob.diag, smooth)
             else:
-                extra = network_guess(solver, cnn, b, x, r0, xg, rounds, smooth, tmp)
+                extra = network_guess(solver, cnn, b, x, r0, xg, rounds, smooth, tmp, prob.diag)
             info = solver.solve_next_guess(b, x, xg, x)
             mv.append(info["mv_total"] + extra)
             acc.append(info["guess_accepted"])

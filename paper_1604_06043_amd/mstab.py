@@ -19,10 +19,10 @@ LIB_PATH = os.environ.get("MSTAB_LIBRARY") or os.path.join(HERE, "libmstab.so")
 OK, NOT_CONVERGED, E_INVALID, E_HIP, E_NOMEM, E_BREAKDOWN, E_NONFINITE = 0, 1, -1, -2, -3, -4, -5
 METHOD_MSTAB, METHOD_IDRSTAB = 0, 1
 PREC_F64, PREC_F32_REFINE, PREC_F32_MATRIX = 0, 1, 2
-PRECOND_NONE, PRECOND_JACOBI = 0, 1
+PRECOND_NONE, PRECOND_JACOBI, PRECOND_ILU0 = 0, 1, 2
 REORDER_NONE, REORDER_RCM = 0, 1
 FORMAT_AUTO, FORMAT_DIAGONAL, FORMAT_SLICED = 0, 1, 2
-FETCH_THRESHOLD, FETCH_AT_LEVEL, FETCH_AT_END, FETCH_ONCE, FETCH_NEVER = 0, 1, 2, 3, 4
+FETCH_THRESHOLD, FETCH_AT_LEVEL, FETCH_AT_END, FETCH_ONCE, FETCH_NEVER, FETCH_ESTIMATE = 0, 1, 2, 3, 4, 5
 K_SPMV, K_GAMMA, K_ETA, K_GRAM, K_POLY = 0, 1, 2, 3, 4
 KERNEL_CLASSES = {"spmv": K_SPMV, "gamma": K_GAMMA, "eta": K_ETA, "gram": K_GRAM, "poly": K_POLY}
 

@@ -6,6 +6,7 @@
     python -m paper_1604_06043_amd.workloads c5      # 4M-row random geometric graph, 100 RHS
     python -m paper_1604_06043_amd.workloads fetch   # fetch policies of M(s)stab on 128^3 and 64^2
     python -m paper_1604_06043_amd.workloads jacobi  # split diagonal preconditioning on c3 and c5
+    python -m paper_1604_06043_amd.workloads ilu     # split ILU(0) (multicolour order) against it
     python -m paper_1604_06043_amd.workloads batch   # B independent 64^2 sequences solved together
     python -m paper_1604_06043_amd.workloads reorder # c5 with reverse Cuthill-McKee reordering
 
@@ -131,6 +132,21 @@ def jacobi_compare(seq: Sequence, systems: int, s: int, ell: int, seed: int = 0)
     return out
 
 
+def ilu_compare(seq: Sequence, systems: int, s: int, ell: int, seed: int = 0):
+    """M(s)stab and IDR(s)stab (FP64) with the split diagonal and the split
+    ILU(0) preconditioning (Section 5.1's form), per-cycle replacement off."""
+    out = {"workload": seq.name, "N": seq.N, "nnz": seq.A.nnz, "s": s, "ell": ell,
+           "systems": systems, "tol": 1e-8}
+    run(seq, 1, s, ell, seed=seed, precond=M.PRECOND_ILU0)
+    for name, method in (("mstab", M.METHOD_MSTAB), ("idrstab", M.METHOD_IDRSTAB)):
+        for tag, pc in (("jacobi", M.PRECOND_JACOBI), ("ilu0", M.PRECOND_ILU0)):
+            t, mv, infos, _ = run(seq, systems, s, ell, method=method, seed=seed, precond=pc)
+            out[f"{name}_{tag}"] = {"systems_per_s": systems / t, "mvs_per_system": mv,
+                                    "max_relres_true": max(i["relres_true"] for i in infos)}
+            log(f"[{seq.name}] {name} {tag}: {systems / t:.3f} systems/s, {mv:.1f} MVs/system")
+    return out
+
+
 def batch_throughput(B: int, systems: int = 10, n: int = 64, s: int = 4, ell: int = 2):
     """B independent c1-type sequences (seeds 0..B-1), each on its own handle
     and stream, advanced together by mstab_solve_batch; aggregate systems/s."""
@@ -208,7 +224,8 @@ def rgg_sequence(N: int, seed: int = 0, systems: int = 100) -> Sequence:
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
-    ap.add_argument("which", choices=["sweep", "c1", "c3", "c5", "c2", "fetch", "jacobi", "batch", "reorder"])
+    ap.add_argument("which", choices=["sweep", "c1", "c3", "c5", "c2", "fetch", "jacobi", "ilu", "batch",
+                                      "reorder"])
     ap.add_argument("--n", type=int, default=None)
     ap.add_argument("--N", type=int, default=1 << 22)
     ap.add_argument("--systems", type=int, default=None)
@@ -244,7 +261,8 @@ def main():
         seq = convdiff_sequence("c3", a.n)
         print(json.dumps(compare(seq, a.systems or 20, 8, 4)), flush=True)
     elif a.which == "fetch":
-        policies = {"threshold": M.FETCH_THRESHOLD, "once": M.FETCH_ONCE, "at_end": M.FETCH_AT_END}
+        policies = {"threshold": M.FETCH_THRESHOLD, "once": M.FETCH_ONCE, "at_end": M.FETCH_AT_END,
+                    "estimate": M.FETCH_ESTIMATE}
         for name, n, systems in (("c1", 64, 10), ("c2", 64, 30), ("c2", 128, 50)):
             seq = convdiff_sequence(name, n)
             row = {"workload": seq.name, "systems": systems, "s": 4, "ell": 2}
@@ -261,6 +279,11 @@ def main():
         systems = a.systems or 100
         seq = rgg_sequence(a.N, 0, systems)
         print(json.dumps(compare(seq, systems, 4, 2)), flush=True)
+    elif a.which == "ilu":
+        for seq, systems, s, ell in ((convdiff_sequence("c3", a.n), a.systems or 20, 8, 4),
+                                     (rgg_sequence(a.N, 0, a.systems or 100), a.systems or 100, 4, 2)):
+            print(json.dumps(ilu_compare(seq, systems, s, ell)), flush=True)
+            del seq
     elif a.which == "jacobi":
         for seq, systems, s, ell in ((convdiff_sequence("c3", a.n), a.systems or 20, 8, 4),
                                      (rgg_sequence(a.N, 0, a.systems or 100), a.systems or 100, 4, 2)):
