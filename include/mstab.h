@@ -129,6 +129,24 @@ typedef enum {
     MSTAB_FORMAT_SLICED = 2    /* always sliced ELLPACK */
 } mstab_format;
 
+typedef enum {
+    MSTAB_ENGINE_GRID = 0,     /* each step of a cycle is one or more grid-wide kernels (all CUs work
+                                  on one system); the host reads the status after every cycle */
+    MSTAB_ENGINE_WORKGROUP = 1 /* one workgroup runs a whole solve (Algorithm 1 with the same
+                                  readings: initial residual, Arnoldi or recycled start, cycles,
+                                  replacements, fetch, stopping test) in one kernel, with
+                                  workgroup barriers between its steps and the small solves in
+                                  LDS; mstab_solve_batch then advances its handles with one
+                                  launch, one workgroup each.  For many small systems (a 64 x 64
+                                  grid has 4096 rows), which one at a time use a few of the
+                                  chip's 256 CUs.  Products read the caller's CSR arrays.
+                                  Requires n <= 2^20, F64 precision, PRECOND_NONE, REORDER_NONE
+                                  and orthonormalize_recycle = 0 (E_INVALID at create otherwise).
+                                  The residual history keeps the first 256 entries of a solve
+                                  (the estimate of FETCH_ESTIMATE uses all of them);
+                                  mstab_kernel_stats does not cover its kernel. */
+} mstab_engine;
+
 /* CSR matrix; all arrays are device pointers, n rows, nnz entries. */
 typedef struct {
     int64_t n;
@@ -170,6 +188,7 @@ typedef struct {
                                   orthonormalizes its FP32 U in FP64, then recomputes
                                   V = A U.  If U^T U is not numerically positive definite
                                   the data stay as fetched.  Default 0. */
+    int32_t engine;            /* mstab_engine; default GRID */
 } mstab_options;
 
 typedef struct {
@@ -195,7 +214,7 @@ typedef struct {
 
 typedef struct mstab_solver mstab_solver;
 
-#define MSTAB_MAX_BATCH 256   /* handles per mstab_solve_batch call */
+#define MSTAB_MAX_BATCH 4096  /* handles per mstab_solve_batch call */
 
 /* Fill o with defaults.  Errors: E_INVALID if o is NULL. */
 mstab_status mstab_options_default(mstab_options *o);
@@ -224,16 +243,21 @@ mstab_status mstab_create(const mstab_csr *A, int32_t s, int32_t ell, const msta
 mstab_status mstab_solve_next(mstab_solver *h, const double *b, double *x, mstab_info *info);
 
 /*
- * mstab_solve_next on count independent handles at once (count <= 256): one
- * host thread per handle, each enqueueing on its handle's stream, so that
- * the small kernels of several latency-bound sequences share the GPU (the
- * sequences stay independent; handles on distinct streams run concurrently,
- * handles on one stream in turn).  h, b, x: host arrays of count entries
- * (b[i], x[i]: device, n_i doubles each, as for mstab_solve_next); info:
- * NULL or count entries.  Handles must be distinct.  Returns the first
- * negative status of any handle (mstab_last_error(NULL) names it), else
- * NOT_CONVERGED if any did not converge, else OK; each handle's own status
- * is in info[i].status and its error text in mstab_last_error(h[i]).
+ * mstab_solve_next on count independent handles at once (count <=
+ * MSTAB_MAX_BATCH).  Handles of ENGINE_GRID: up to 16 host threads take the
+ * handles in turn, each enqueueing on its handle's stream, so that the small
+ * kernels of several latency-bound sequences share the GPU (handles on
+ * distinct streams run concurrently, handles on one stream in turn).
+ * Handles of ENGINE_WORKGROUP: one kernel launch per distinct s on h[0]'s
+ * stream (after every handle's stream has drained), one workgroup per
+ * handle; all handles must then be of that engine and on one device.  Either
+ * way each handle's result equals that of mstab_solve_next on it alone.
+ * h, b, x: host arrays of count entries (b[i], x[i]: device, n_i doubles
+ * each, as for mstab_solve_next); info: NULL or count entries.  Handles must
+ * be distinct.  Returns the first negative status of any handle
+ * (mstab_last_error(NULL) names it), else NOT_CONVERGED if any did not
+ * converge, else OK; each handle's own status is in info[i].status and its
+ * error text in mstab_last_error(h[i]).
  */
 mstab_status mstab_solve_batch(mstab_solver *const *h, int32_t count, const double *const *b,
                                double *const *x, mstab_info *info);

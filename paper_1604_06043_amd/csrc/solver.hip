@@ -11,6 +11,7 @@
 #include "ilu.hpp"
 #include "kernels.hpp"
 #include "mstab.h"
+#include "wg.hpp"
 
 #include <hip/hip_runtime.h>
 
@@ -24,6 +25,7 @@
 #include <mutex>
 #include <new>
 #include <string>
+#include <atomic>
 #include <thread>
 #include <vector>
 
@@ -1442,6 +1444,13 @@ struct mstab_solver {
     // PRECOND_ILU0: the factors of the multicolour-ordered matrix (perm is that
     // order; rp_perm and ci_perm its structure)
     IluData ilu;
+    // ENGINE_WORKGROUP: the job array and histories of the launches this
+    // handle leads (as h[0] of a batch, or alone), grown on demand
+    wg::Job *wg_jobs = nullptr;
+    int64_t *wg_hmv = nullptr;
+    double *wg_hres = nullptr;
+    int wg_cap = 0;
+    bool workgroup() const { return opt.engine == MSTAB_ENGINE_WORKGROUP; }
     bool transformed() const { return pd || perm; }
     Profiler prof;
     int64_t mv_total = 0, mv_last = 0;
@@ -1490,6 +1499,9 @@ void release_handle(mstab_solver *h)
     (void)hipFree(h->va_perm);
     (void)hipFree(h->xwork);
     h->ilu.release();
+    (void)hipFree(h->wg_jobs);
+    (void)hipFree(h->wg_hmv);
+    (void)hipFree(h->wg_hres);
     h->prof.destroy();
     delete h;
 }
@@ -1541,9 +1553,13 @@ struct HistoryArchive {
     }
 };
 
+mstab_status wg_run(mstab_solver *const *h, int count, const double *const *b, double *const *x,
+                    mstab_info *info, int extra_checks, int accepted);
+
 mstab_status solve_f64(mstab_solver *h, const double *b, double *x, mstab_info *info,
                        int extra_checks, int accepted)
 {
+    if (h->workgroup()) return wg_run(&h, 1, &b, &x, info, extra_checks, accepted);
     HistoryArchive archive{h};
     h->hist_mv.clear();
     h->hist_res.clear();
@@ -1574,6 +1590,147 @@ mstab_status solve_f64(mstab_solver *h, const double *b, double *x, mstab_info *
         if (low) info->mv_f64 = 1 + r.restarts + r.mv_check;
     }
     return (mstab_status)r.status;
+}
+
+// ENGINE_WORKGROUP: the next system of each handle, one workgroup each.
+// Handles are grouped by s and a bound on l (template parameters of the
+// kernel) into one launch per group on h[0]'s stream; every handle's stream is drained first,
+// and the launch is synchronized before the results are filed.
+int wg_lc(int ell) { return ell <= 2 ? 2 : (ell <= 4 ? 4 : 8); }
+
+template <int S>
+void wg_launch(int count, int lc, wg::Job *jobs, hipStream_t st)
+{
+    switch (lc) {
+    case 2: hipLaunchKernelGGL((wg::k_solve<S, 2>), dim3(count), dim3(wg::NT), 0, st, jobs); break;
+    case 4: hipLaunchKernelGGL((wg::k_solve<S, 4>), dim3(count), dim3(wg::NT), 0, st, jobs); break;
+    default: hipLaunchKernelGGL((wg::k_solve<S, 8>), dim3(count), dim3(wg::NT), 0, st, jobs); break;
+    }
+}
+
+mstab_status wg_run(mstab_solver *const *h, int count, const double *const *b, double *const *x,
+                    mstab_info *info, int extra_checks, int accepted)
+{
+    mstab_solver *h0 = h[0];
+    auto t0 = std::chrono::steady_clock::now();
+    for (int i = 0; i < count; ++i) {
+        if (!h[i]->workgroup()) fail(MSTAB_E_INVALID, "handle %d is not of ENGINE_WORKGROUP", i);
+        if (h[i]->device != h0->device) fail(MSTAB_E_INVALID, "handle %d is on another device", i);
+    }
+    std::vector<hipStream_t> streams;
+    for (int i = 0; i < count; ++i)
+        if (std::find(streams.begin(), streams.end(), h[i]->stream) == streams.end())
+            streams.push_back(h[i]->stream);
+    for (hipStream_t st : streams) HIPCHK(hipStreamSynchronize(st));
+    if (h0->wg_cap < count) {
+        (void)hipFree(h0->wg_jobs);
+        (void)hipFree(h0->wg_hmv);
+        (void)hipFree(h0->wg_hres);
+        h0->wg_jobs = nullptr;
+        h0->wg_hmv = nullptr;
+        h0->wg_hres = nullptr;
+        h0->wg_cap = 0;
+        HIPCHK(hipMalloc(&h0->wg_jobs, sizeof(wg::Job) * (size_t)count));
+        HIPCHK(hipMalloc(&h0->wg_hmv, sizeof(int64_t) * wg::HIST * (size_t)count));
+        HIPCHK(hipMalloc(&h0->wg_hres, sizeof(double) * wg::HIST * (size_t)count));
+        h0->wg_cap = count;
+    }
+    // job p is handle order[p]: grouped by s and the bound on l
+    std::vector<int> order((size_t)count);
+    for (int i = 0; i < count; ++i) order[(size_t)i] = i;
+    auto key = [&](int i) { return h[i]->s * 16 + wg_lc(h[i]->ell); };
+    std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return key(a) < key(c); });
+    std::vector<wg::Job> jobs((size_t)count);
+    for (int p = 0; p < count; ++p) {
+        const int i = order[(size_t)p];
+        mstab_solver *hi = h[i];
+        Engine<double> &E = hi->e64;
+        wg::Job &J = jobs[(size_t)p];
+        memset(&J, 0, sizeof J);
+        J.rp = hi->rp; J.ci = hi->ci; J.va = hi->va;
+        J.b = b[i]; J.x = x[i];
+        J.W = E.W; J.R = E.R; J.T = E.Tv;
+        J.recU = E.recU; J.recV = E.recV; J.rec_ptv = E.rec_ptv;
+        J.hist_mv = h0->wg_hmv + (size_t)p * wg::HIST;
+        J.hist_res = h0->wg_hres + (size_t)p * wg::HIST;
+        J.n = hi->n; J.ld = E.ld;
+        J.max_mv = hi->opt.max_mv; J.fetch_level = hi->opt.fetch_level;
+        J.tol = hi->opt.tol; J.fetch_rel = hi->opt.fetch_rel;
+        J.pkey = hi->pkey;
+        J.s = hi->s; J.ell = hi->ell; J.method = hi->opt.method; J.fetch = hi->opt.fetch;
+        J.max_repl = hi->opt.max_replacements; J.replace_every = hi->opt.replace_every;
+        J.rec_have = E.rec_have ? 1 : 0; J.rec_level = E.rec_level; J.est_cycle = E.est_cycle;
+    }
+    hipStream_t st = h0->stream;
+    HIPCHK(hipMemcpyAsync(h0->wg_jobs, jobs.data(), sizeof(wg::Job) * (size_t)count, hipMemcpyHostToDevice, st));
+    for (int p0 = 0; p0 < count;) {
+        const int kv = key(order[(size_t)p0]);
+        const int sv = h[order[(size_t)p0]]->s, lc = wg_lc(h[order[(size_t)p0]]->ell);
+        int p1 = p0;
+        while (p1 < count && key(order[(size_t)p1]) == kv) ++p1;
+        wg::Job *jp = h0->wg_jobs + p0;
+        switch (sv) {
+        case 1: wg_launch<1>(p1 - p0, lc, jp, st); break;
+        case 2: wg_launch<2>(p1 - p0, lc, jp, st); break;
+        case 3: wg_launch<3>(p1 - p0, lc, jp, st); break;
+        case 4: wg_launch<4>(p1 - p0, lc, jp, st); break;
+        case 5: wg_launch<5>(p1 - p0, lc, jp, st); break;
+        case 6: wg_launch<6>(p1 - p0, lc, jp, st); break;
+        case 7: wg_launch<7>(p1 - p0, lc, jp, st); break;
+        default: wg_launch<8>(p1 - p0, lc, jp, st); break;
+        }
+        HIPCHK(hipGetLastError());
+        p0 = p1;
+    }
+    std::vector<int64_t> hmv((size_t)count * wg::HIST);
+    std::vector<double> hres((size_t)count * wg::HIST);
+    HIPCHK(hipMemcpyAsync(jobs.data(), h0->wg_jobs, sizeof(wg::Job) * (size_t)count, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(hmv.data(), h0->wg_hmv, sizeof(int64_t) * hmv.size(), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(hres.data(), h0->wg_hres, sizeof(double) * hres.size(), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    mstab_status worst = MSTAB_OK;
+    for (int p = 0; p < count; ++p) {
+        const int i = order[(size_t)p];
+        mstab_solver *hi = h[i];
+        const wg::Job &J = jobs[(size_t)p];
+        Engine<double> &E = hi->e64;
+        E.rec_have = J.rec_have != 0;
+        E.rec_level = J.rec_level;
+        E.est_cycle = J.est_cycle;
+        const int64_t kept = std::min<int64_t>(J.hist_len, wg::HIST);
+        hi->hist_mv.assign(hmv.begin() + (size_t)p * wg::HIST, hmv.begin() + (size_t)p * wg::HIST + kept);
+        hi->hist_res.assign(hres.begin() + (size_t)p * wg::HIST, hres.begin() + (size_t)p * wg::HIST + kept);
+        hi->hist_mv_all.push_back(hi->hist_mv);
+        hi->hist_res_all.push_back(hi->hist_res);
+        SolveResult r;
+        r.status = J.status;
+        r.converged = J.converged != 0;
+        r.recycled = J.recycled != 0;
+        r.restarts = J.restarts;
+        r.replacements = J.replacements;
+        r.mv = J.mv;
+        r.mv_check = J.mv_check + extra_checks;
+        r.cycles = J.cycles;
+        r.level = J.level;
+        r.fetched = J.fetched;
+        r.relres_rec = J.relres_rec;
+        r.relres_true = J.relres_true;
+        hi->mv_last = r.mv + r.mv_check;
+        hi->mv_total += hi->mv_last;
+        if (info) {
+            fill_info(&info[i], r, secs);
+            info[i].guess_accepted = accepted;
+        }
+        const mstab_status sti = (mstab_status)r.status;
+        if (sti < 0) {
+            hi->err = "solve failed with status " + std::to_string((int)sti);
+            if (worst >= 0) worst = sti;
+        } else if (sti == MSTAB_NOT_CONVERGED && worst == MSTAB_OK) {
+            worst = MSTAB_NOT_CONVERGED;
+        }
+    }
+    return worst;
 }
 
 // The F32_REFINE mode.
@@ -1840,6 +1997,15 @@ mstab_status mstab_create(const mstab_csr *A, int32_t s, int32_t ell, const msta
         fail(MSTAB_E_INVALID, "unknown fetch policy");
     if (h->opt.orthonormalize_recycle != 0 && h->opt.orthonormalize_recycle != 1)
         fail(MSTAB_E_INVALID, "orthonormalize_recycle must be 0 or 1");
+    if (h->opt.engine != MSTAB_ENGINE_GRID && h->opt.engine != MSTAB_ENGINE_WORKGROUP)
+        fail(MSTAB_E_INVALID, "unknown engine");
+    if (h->opt.engine == MSTAB_ENGINE_WORKGROUP) {
+        if (A->n > wg::MAX_N) fail(MSTAB_E_INVALID, "ENGINE_WORKGROUP: n=%lld above 2^20", (long long)A->n);
+        if (h->opt.precision != MSTAB_PREC_F64 || h->opt.precond != MSTAB_PRECOND_NONE ||
+            h->opt.reorder != MSTAB_REORDER_NONE || h->opt.orthonormalize_recycle)
+            fail(MSTAB_E_INVALID, "ENGINE_WORKGROUP: F64, no preconditioner, no reordering and "
+                                  "no orthonormalization only");
+    }
     h->s = s; h->ell = ell; h->n = A->n; h->nnz = A->nnz;
     h->rp = A->row_ptr; h->ci = A->col_idx; h->va = A->val;
     h->stream = (hipStream_t)hip_stream;
@@ -2074,25 +2240,47 @@ mstab_status mstab_solve_batch(mstab_solver *const *h, int32_t count, const doub
         for (int j = 0; j < i; ++j)
             if (h[j] == h[i]) fail(MSTAB_E_INVALID, "handle %d repeated", i);
     }
+    if (h[0]->workgroup()) {
+        for (int i = 0; i < count; ++i)
+            if (!h[i]->workgroup()) fail(MSTAB_E_INVALID, "handle %d is not of ENGINE_WORKGROUP like handle 0", i);
+        HIPCHK(hipSetDevice(h[0]->device));
+        const mstab_status w = wg_run(h, count, b, x, info, 0, 0);
+        if (w < 0)
+            for (int i = 0; i < count; ++i)
+                if (info && info[i].status < 0) {
+                    g_tls_error = "handle " + std::to_string(i) + ": " + h[i]->err;
+                    break;
+                }
+        return w;
+    }
+    for (int i = 0; i < count; ++i)
+        if (h[i]->workgroup()) fail(MSTAB_E_INVALID, "handle %d is of ENGINE_WORKGROUP, handle 0 is not", i);
     std::vector<mstab_status> st((size_t)count, MSTAB_OK);
     std::vector<std::thread> pool;
-    pool.reserve((size_t)count);
-    auto work = [&](int i) {
-        // each handle's calls run on its own host thread and stream
-        if (hipSetDevice(h[i]->device) != hipSuccess) {
-            h[i]->err = "hipSetDevice failed in a batch worker";
-            st[i] = MSTAB_E_HIP;
-            return;
+    // each worker takes the next handle; each handle's calls run on one host
+    // thread at a time and on the handle's stream
+    std::atomic<int> next{1};
+    auto work = [&]() {
+        for (int i = 0; i < count; i = next.fetch_add(1)) {
+            if (i == 0) continue;   // handle 0 is the calling thread's
+            if (hipSetDevice(h[i]->device) != hipSuccess) {
+                h[i]->err = "hipSetDevice failed in a batch worker";
+                st[i] = MSTAB_E_HIP;
+                continue;
+            }
+            st[i] = mstab_solve_next(h[i], b[i], x[i], info ? &info[i] : nullptr);
         }
-        st[i] = mstab_solve_next(h[i], b[i], x[i], info ? &info[i] : nullptr);
     };
+    const int workers = std::min(count - 1, 15);
+    pool.reserve((size_t)workers);
     try {
-        for (int i = 1; i < count; ++i) pool.emplace_back(work, i);
+        for (int t = 0; t < workers; ++t) pool.emplace_back(work);
     } catch (...) {
         for (auto &t : pool) t.join();
-        fail(MSTAB_E_NOMEM, "could not start %d host threads", count - 1);
+        fail(MSTAB_E_NOMEM, "could not start %d host threads", workers);
     }
-    work(0);
+    st[0] = mstab_solve_next(h[0], b[0], x[0], info ? &info[0] : nullptr);
+    work();
     for (auto &t : pool) t.join();
     mstab_status worst = MSTAB_OK;
     for (int i = 0; i < count; ++i) {

@@ -20,6 +20,8 @@ OK, NOT_CONVERGED, E_INVALID, E_HIP, E_NOMEM, E_BREAKDOWN, E_NONFINITE = 0, 1, -
 METHOD_MSTAB, METHOD_IDRSTAB = 0, 1
 PREC_F64, PREC_F32_REFINE, PREC_F32_MATRIX = 0, 1, 2
 PRECOND_NONE, PRECOND_JACOBI, PRECOND_ILU0 = 0, 1, 2
+ENGINE_GRID, ENGINE_WORKGROUP = 0, 1
+MAX_BATCH = 4096
 REORDER_NONE, REORDER_RCM = 0, 1
 FORMAT_AUTO, FORMAT_DIAGONAL, FORMAT_SLICED = 0, 1, 2
 FETCH_THRESHOLD, FETCH_AT_LEVEL, FETCH_AT_END, FETCH_ONCE, FETCH_NEVER, FETCH_ESTIMATE = 0, 1, 2, 3, 4, 5
@@ -55,7 +57,7 @@ class mstab_options(ctypes.Structure):
                 ("inner_tol", ctypes.c_double), ("max_refinements", ctypes.c_int32),
                 ("precond", ctypes.c_int32), ("replace_every", ctypes.c_int32),
                 ("reorder", ctypes.c_int32), ("matrix_format", ctypes.c_int32),
-                ("orthonormalize_recycle", ctypes.c_int32)]
+                ("orthonormalize_recycle", ctypes.c_int32), ("engine", ctypes.c_int32)]
 
 
 class mstab_info(ctypes.Structure):

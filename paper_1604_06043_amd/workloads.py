@@ -177,6 +177,38 @@ def batch_throughput(B: int, systems: int = 10, n: int = 64, s: int = 4, ell: in
             "systems_per_s": B * systems / sec, "mvs_per_system": mv / (B * systems)}
 
 
+def batch_workgroup(B: int, systems: int = 10, n: int = 64, s: int = 4, ell: int = 2):
+    """B independent c1-type sequences (seeds 0..B-1) on handles of the
+    one-workgroup engine: each step forms every right-hand side with one
+    mstab_rhs_step over the B x N block, then one mstab_solve_batch launch
+    solves all B systems (one workgroup each).  Aggregate systems/s."""
+    import torch
+    cds = [I.config("c1", seed=k, n=n) for k in range(B)]
+    N = cds[0].N
+    inv_dt = cds[0].inv_dt
+    assert all(cd.inv_dt == inv_dt for cd in cds)
+    mats = [M.mstab_assemble_convdiff(cd.dim, cd.n, cd.beta, cd.inv_dt, None) for cd in cds]
+    solvers = [M.Solver(A, s, ell, p_seed=0, engine=M.ENGINE_WORKGROUP) for A in mats]
+    F = torch.tensor(np.stack([cd.f for cd in cds]), device="cuda")
+    X = torch.zeros((B, N), dtype=torch.float64, device="cuda")
+    Bv = torch.empty_like(X)
+    xs, bs = [X[i] for i in range(B)], [Bv[i] for i in range(B)]
+    torch.cuda.synchronize()
+    mv, t0 = 0, time.perf_counter()
+    for _ in range(systems):
+        M.mstab_rhs_step(X.view(-1), inv_dt, F.view(-1), Bv.view(-1))
+        infos = M.solve_batch(solvers, bs, xs)
+        if not all(i["converged"] for i in infos):
+            raise RuntimeError("a batched system did not converge")
+        mv += sum(i["mv_total"] for i in infos)
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    for sv in solvers:
+        sv.close()
+    return {"workload": f"c1_n{n}", "engine": "workgroup", "sequences": B, "systems_each": systems,
+            "s": s, "ell": ell, "systems_per_s": B * systems / sec, "mvs_per_system": mv / (B * systems)}
+
+
 def reorder_compare(seq: Sequence, systems: int, s: int, ell: int, seed: int = 0):
     """M(s)stab and IDR(s)stab on the caller's order and on the RCM order,
     with and without the split diagonal preconditioning."""
@@ -225,7 +257,7 @@ def rgg_sequence(N: int, seed: int = 0, systems: int = 100) -> Sequence:
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("which", choices=["sweep", "c1", "c3", "c5", "c2", "fetch", "jacobi", "ilu", "batch",
-                                      "reorder"])
+                                      "wgbatch", "reorder"])
     ap.add_argument("--n", type=int, default=None)
     ap.add_argument("--N", type=int, default=1 << 22)
     ap.add_argument("--systems", type=int, default=None)
@@ -250,6 +282,13 @@ def main():
             r = batch_throughput(B, a.systems or 10)
             r["gpu_max_hw_queues"] = os.environ.get("GPU_MAX_HW_QUEUES", "default")
             log(f"[batch] {B} sequences: {r['systems_per_s']:.0f} systems/s, {r['mvs_per_system']:.1f} MVs/system")
+            print(json.dumps(r), flush=True)
+    elif a.which == "wgbatch":
+        for B in (1, 8, 64, 256, 512, 1024, 2048):
+            batch_workgroup(min(B, 64), 1)   # warm-up
+            r = batch_workgroup(B, a.systems or 10)
+            log(f"[wgbatch] {B} sequences: {r['systems_per_s']:.0f} systems/s, "
+                f"{r['mvs_per_system']:.1f} MVs/system")
             print(json.dumps(r), flush=True)
     elif a.which == "c1":
         seq = convdiff_sequence("c1", a.n)

@@ -68,6 +68,23 @@ def test_create_rejects_bad_arguments_without_a_device(lib):
     assert lib.mstab_solve_next(None, None, None, None) == mstab.E_INVALID
 
 
+def test_workgroup_engine_option_checks_without_a_device(lib):
+    """ENGINE_WORKGROUP refuses what its kernel does not do, before any device
+    work (dummy matrix pointers are never dereferenced)."""
+    h = ctypes.c_void_p()
+    csr = mstab.mstab_csr(100, 280, 8, 8, 8)
+    for over in (dict(engine=2), dict(engine=1, precision=mstab.PREC_F32_MATRIX),
+                 dict(engine=1, precond=mstab.PRECOND_JACOBI), dict(engine=1, reorder=mstab.REORDER_RCM),
+                 dict(engine=1, orthonormalize_recycle=1)):
+        o = mstab.mstab_options_default(**over)
+        assert lib.mstab_create(ctypes.byref(csr), 4, 2, ctypes.byref(o), None, ctypes.byref(h)) == mstab.E_INVALID
+        assert h.value is None
+        assert b"engine" in lib.mstab_last_error(None).lower() or b"ENGINE" in lib.mstab_last_error(None)
+    csr.n = (1 << 20) + 1
+    o = mstab.mstab_options_default(engine=1)
+    assert lib.mstab_create(ctypes.byref(csr), 4, 2, ctypes.byref(o), None, ctypes.byref(h)) == mstab.E_INVALID
+
+
 def test_struct_layouts_match_header(tmp_path):
     """ctypes layouts equal what a C compiler makes of include/mstab.h."""
     import subprocess
@@ -95,7 +112,7 @@ def test_solve_batch_rejects_bad_arguments_without_a_device(lib):
     P = ctypes.c_void_p
     assert lib.mstab_solve_batch(None, 0, None, None, None) == mstab.OK
     assert lib.mstab_solve_batch(None, -1, None, None, None) == mstab.E_INVALID
-    assert lib.mstab_solve_batch(None, 257, None, None, None) == mstab.E_INVALID
+    assert lib.mstab_solve_batch(None, mstab.MAX_BATCH + 1, None, None, None) == mstab.E_INVALID
     assert lib.mstab_solve_batch(None, 2, None, None, None) == mstab.E_INVALID
     nulls = (P * 2)(None, None)
     assert lib.mstab_solve_batch(nulls, 2, nulls, nulls, None) == mstab.E_INVALID

@@ -233,10 +233,16 @@ def tipping(io, alt_infos, tol=1e-8):
     return False
 
 
-def check_teacher_forced(k, ig, io, err, sen, differ, errs):
+def check_teacher_forced(k, ig, io, err, sen, differ, errs, oracle_may_fail=False):
     """The per-system bar of a teacher-forced comparison (differ: the oracle's
-    orders end with different counts or its stopping test could tip)."""
-    assert ig["converged"] and io.converged, (k, ig, io)
+    orders end with different counts or its stopping test could tip).  With
+    oracle_may_fail a system the oracle itself leaves unconverged must end
+    the same way on the GPU (same count, same x to the bar)."""
+    if oracle_may_fail and not io.converged:
+        print(f"    system {k}: the oracle does not converge (true relres {io.relres_true:.1e})", flush=True)
+        assert not ig["converged"], (k, ig, io)
+    else:
+        assert ig["converged"] and io.converged, (k, ig, io)
     assert ig["recycled"] == io.recycled, (k, ig, io)
     assert err <= max(1e-9, 10 * sen), (k, err, sen, errs)
     if differ or near_threshold(io):
@@ -296,13 +302,13 @@ def test_sequence_free_running_c1(torch_dev, ms, orc, method, s, ell):
 
 
 def teacher_forced(torch, ms, orc, cd, Ao, Ag, s, ell, seed, method, systems, fetch=0, orth=0,
-                   check_recycle=False):
+                   check_recycle=False, replace_every=0, **opt):
     """Systems 1..systems from the oracle's x^(i) and recycled U, V, each
     compared with the oracle's solve at the teacher-forced bar.  Returns the
-    per-system errors."""
+    per-system errors.  opt: further handle options (the engine)."""
     P = I.p_dense(seed, cd.N, s)
     solver = ms.Solver(Ag, s, ell, p_seed=seed, method=method, fetch=fetch,
-                       orthonormalize_recycle=orth)
+                       orthonormalize_recycle=orth, replace_every=replace_every, **opt)
     xo = np.zeros(cd.N)
     rec = orc.Recycle.empty(cd.N, s)
     errs, sens = [], []
@@ -321,7 +327,7 @@ def teacher_forced(torch, ms, orc, cd, Ao, Ag, s, ell, seed, method, systems, fe
         alts = []
         xn, io, sen, differ = oracle_with_sensitivity(
             orc, lambda r: orc.solve(Ao, b, xo, s, ell, P, recycle=r, method=method, fetch=fetch,
-                                     orthonormalize=bool(orth)), rec, alts)
+                                     orthonormalize=bool(orth), replace_every=replace_every), rec, alts)
         err = rel(x.cpu().numpy(), xn)
         errs.append(err)
         sens.append(sen)
@@ -329,6 +335,9 @@ def teacher_forced(torch, ms, orc, cd, Ao, Ag, s, ell, seed, method, systems, fe
               f"{io.cycles}), fetched {ig['fetched_level']}/{io.fetched}, err {err:.1e}, sens {sen:.1e}, "
               f"orders differ {differ}", flush=True)
         check_teacher_forced(k, ig, io, err, sen, differ, errs)
+        if ig["mv_total"] == io.mv_total and ig["cycles"] == io.cycles:
+            hm, _ = solver.residual_history()
+            assert list(hm) == list(io.hist_mv), (k, hm, io.hist_mv)
         if method == 0:
             got = solver.recycle_get()
             if not rec.have:   # FETCH_ESTIMATE's first solve fetches nothing
@@ -1109,7 +1118,9 @@ def test_ilu_teacher_forced(torch_dev, ms, orc, name, n, seed, s, ell, method, r
     to 1e-17 while the true one stays near 1e-4 to 1e-1.  On grids below 24^3
     a single cycle cuts the split residual by 1e-7 to 1e-12 and the data
     fetched there do not carry a recycled start at all (true residual 1e11
-    and more in the oracle, with or without replacement)."""
+    and more in the oracle, with or without replacement).  Even at 24^3 the
+    oracle's fifth system ends 1e-7 above the tolerance after its three
+    final replacements; the GPU must then end the same way."""
     torch = torch_dev
     print(f"[ilu teacher-forced {name} n={n} s={s} l={ell} method={method} repl={repl}]", flush=True)
     Ao, Ag, rhs = ilu_problem(torch, ms, orc, name, n, seed)
@@ -1137,7 +1148,7 @@ def test_ilu_teacher_forced(torch_dev, ms, orc, name, n, seed, s, ell, method, r
         errs.append(err)
         print(f"  system {k}: gpu mv {ig['mv_total']} oracle {io.mv_total}, err {err:.1e}, "
               f"sens {sen:.1e}, orders differ {differ}", flush=True)
-        check_teacher_forced(k, ig, io, err, sen, differ, errs)
+        check_teacher_forced(k, ig, io, err, sen, differ, errs, oracle_may_fail=s * ell >= 32)
         xo = xn
 
 

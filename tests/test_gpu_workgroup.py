@@ -1,0 +1,148 @@
+"""The one-workgroup-per-system engine (ENGINE_WORKGROUP): a whole solve of
+Algorithm 1 in one kernel, one workgroup per system, many systems per launch.
+
+Parity against the oracle at the same bars as the grid engine (the sums run
+in another order, so the oracle's own summation-order spread sets the bar),
+and equality between a batch and the same handles solved one at a time."""
+import numpy as np
+import pytest
+
+from paper_1604_06043_amd import inputs as I
+from test_gpu_parity import (compare_free, dev, gpu_assemble, ms, oracle_sequence_orders,  # noqa: F401
+                             run_sequence_gpu, teacher_forced, torch_dev)
+
+pytestmark = pytest.mark.gpu
+
+WG = dict(engine=1)
+
+
+@pytest.mark.parametrize("name,n,seed,s,ell,method,fetch,repl", [
+    ("c1", 64, 0, 4, 2, 0, 0, 0), ("c1", 64, 0, 4, 2, 1, 0, 0), ("c1", 64, 0, 8, 4, 0, 0, 0),
+    ("c1", 64, 0, 2, 1, 0, 0, 0), ("c1", 64, 1, 3, 3, 0, 0, 0), ("c1", 48, 2, 1, 1, 0, 0, 0),
+    ("c1", 50, 3, 4, 2, 0, 0, 0), ("c1", 64, 0, 6, 6, 0, 0, 0), ("c2", 16, 3, 4, 2, 0, 0, 0),
+    ("c3", 14, 4, 8, 4, 0, 0, 1),
+    # the other fetch policies (Section 5, choosing the fetch point)
+    ("c1", 64, 0, 4, 2, 0, 2, 0), ("c1", 64, 0, 4, 2, 0, 3, 0), ("c1", 64, 0, 4, 2, 0, 5, 0),
+    ("c1", 64, 1, 2, 1, 0, 5, 0),
+    # residual replacement after every cycle (Section 5.1)
+    ("c1", 64, 0, 4, 2, 0, 0, 1)])
+def test_workgroup_teacher_forced(torch_dev, ms, orc, name, n, seed, s, ell, method, fetch, repl):
+    """System by system from the oracle's x^(i) and recycled U, V, through the
+    one-workgroup kernel: x within max(1e-9, 10 x the oracle's sum-order
+    spread), equal MV counts (one cycle apart only where the oracle's orders
+    differ or its stopping test could tip), the same residual-history MV
+    entries, and the fetched U, V against the oracle's."""
+    torch = torch_dev
+    print(f"[workgroup teacher-forced {name} n={n} s={s} l={ell} method={method} fetch={fetch} "
+          f"repl={repl}]", flush=True)
+    cd = I.config(name, seed=seed, n=n)
+    Ao = orc.assemble_convdiff(cd.dim, cd.n, cd.beta, cd.inv_dt, cd.kappa)
+    Ag = gpu_assemble(ms, cd)
+    teacher_forced(torch, ms, orc, cd, Ao, Ag, s, ell, seed, method, 6, fetch=fetch,
+                   check_recycle=True, replace_every=repl, **WG)
+
+
+@pytest.mark.parametrize("method", [0, 1])
+@pytest.mark.parametrize("s,ell", [(4, 2), (8, 4), (2, 1)])
+def test_workgroup_free_running_c1(torch_dev, ms, orc, method, s, ell):
+    """The 64^2 workload (10 implicit Euler steps) on the workgroup engine and
+    on the oracle, each on its own."""
+    torch = torch_dev
+    print(f"[workgroup c1 sequence s={s} l={ell} method={method}]", flush=True)
+    cd = I.config("c1", seed=0)
+    Ao = orc.assemble_convdiff(cd.dim, cd.n, cd.beta, cd.inv_dt)
+    Ag = gpu_assemble(ms, cd)
+    xs_g, inf_g, _ = run_sequence_gpu(torch, ms, Ag, cd, s, ell, 10, method, **WG)
+    P = I.p_dense(0, cd.N, s)
+    fwd, alts = oracle_sequence_orders(
+        orc, lambda: orc.solve_sequence(Ao, cd.f, cd.inv_dt, s, ell, P, 10, method=method))
+    compare_free(xs_g, inf_g, fwd, alts, ell * (s + 1))
+
+
+def test_workgroup_batch_equals_one_at_a_time(torch_dev, ms, orc):
+    """Handles advanced together by mstab_solve_batch (one launch per (s,
+    bound on l) group, one workgroup per handle; here three groups) give x bit
+    for bit and the MV counts of the same handles solved one at a time, and
+    the two engines cannot be mixed in a batch."""
+    torch = torch_dev
+    systems = 4
+    cases = [(k, 4, 2) for k in range(5)] + [(5, 8, 4), (6, 2, 1), (7, 8, 4), (8, 3, 3)]
+    cds = [I.config("c1", seed=k, n=40 + 2 * k) for k, _, _ in cases]
+    mats = [gpu_assemble(ms, cd) for cd in cds]
+    ref = [run_sequence_gpu(torch, ms, A, cd, s, ell, systems, 0, **WG)
+           for cd, A, (_, s, ell) in zip(cds, mats, cases)]
+    solvers = [ms.Solver(A, s, ell, p_seed=0, method=0, **WG) for A, (_, s, ell) in zip(mats, cases)]
+    xs = [torch.zeros(cd.N, dtype=torch.float64, device="cuda") for cd in cds]
+    bs = [torch.empty_like(x) for x in xs]
+    fs = [dev(torch, cd.f) for cd in cds]
+    for k in range(systems):
+        for i in range(len(cases)):
+            ms.mstab_rhs_step(xs[i], cds[i].inv_dt, fs[i], bs[i])
+        infos = ms.solve_batch(solvers, bs, xs)
+        for i in range(len(cases)):
+            np.testing.assert_array_equal(xs[i].cpu().numpy(), ref[i][0][k])
+            assert infos[i]["mv_total"] == ref[i][1][k]["mv_total"]
+            assert infos[i]["converged"] and infos[i]["status"] == 0
+            assert solvers[i].residual_history() == ref[i][2][k]
+    grid = ms.Solver(mats[0], 4, 2)
+    with pytest.raises(ms.MstabError):
+        ms.solve_batch([solvers[1], grid], bs[:2], xs[:2])
+    with pytest.raises(ms.MstabError):
+        ms.solve_batch([grid, solvers[1]], bs[:2], xs[:2])
+    grid.close()
+    for sv in solvers:
+        sv.close()
+
+
+def test_workgroup_edge_cases(torch_dev, ms, orc):
+    """A zero right-hand side gives x = 0 with no product; the smallest system
+    the method admits (n = s + 1) converges; U, V fetched by a grid-engine
+    handle start a workgroup-engine handle through recycle_get/set."""
+    torch = torch_dev
+    cd = I.config("c1", seed=0, n=24)
+    Ag = gpu_assemble(ms, cd)
+    sv = ms.Solver(Ag, 4, 2, **WG)
+    x = torch.ones(cd.N, dtype=torch.float64, device="cuda")
+    info = sv.solve_next(torch.zeros_like(x), x)
+    assert info["converged"] and info["mv_total"] == 0 and not x.any()
+    sv.close()
+    # n = s + 1 = 5: tridiag(2, 3, 1), as the finite-termination example
+    n = 5
+    rows, cols, vals = [], [], []
+    for i in range(n):
+        for j, v in ((i - 1, 2.0), (i, 3.0), (i + 1, 1.0)):
+            if 0 <= j < n:
+                rows.append(i); cols.append(j); vals.append(v)
+    rp = np.searchsorted(rows, np.arange(n + 1)).astype(np.int32)
+    A = ms.CSR(dev(torch, rp), dev(torch, np.array(cols, dtype=np.int32)), dev(torch, np.array(vals)))
+    D = np.zeros((n, n))
+    D[rows, cols] = vals
+    b = np.arange(1.0, n + 1)
+    for s, ell in ((4, 1), (4, 2), (1, 1)):
+        sv = ms.Solver(A, s, ell, **WG)
+        x = torch.zeros(n, dtype=torch.float64, device="cuda")
+        info = sv.solve_next(dev(torch, b), x)
+        assert info["converged"], (s, ell, info)
+        assert np.linalg.norm(D @ x.cpu().numpy() - b) <= 1e-8 * np.linalg.norm(b)
+        sv.close()
+    # recycle data fetched by a grid handle start a workgroup handle
+    cd = I.config("c1", seed=1, n=32)
+    Ag = gpu_assemble(ms, cd)
+    g = ms.Solver(Ag, 4, 2, p_seed=0)
+    w = ms.Solver(Ag, 4, 2, p_seed=0, **WG)
+    f = dev(torch, cd.f)
+    x = torch.zeros(cd.N, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(x)
+    ms.mstab_rhs_step(x, cd.inv_dt, f, b)
+    g.solve_next(b, x)
+    U, V, lev = g.recycle_get()
+    w.recycle_set(U, V, lev)
+    ms.mstab_rhs_step(x, cd.inv_dt, f, b)
+    xw = x.clone()
+    iw = w.solve_next(b, xw)
+    ig = g.solve_next(b, x)
+    assert iw["recycled"] and ig["recycled"] and iw["converged"]
+    assert abs(iw["mv_total"] - ig["mv_total"]) <= 2 * 5
+    assert float(torch.linalg.norm(xw - x) / torch.linalg.norm(x)) <= 1e-7
+    g.close()
+    w.close()
