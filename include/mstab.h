@@ -139,7 +139,8 @@ typedef enum {
                                   LDS; mstab_solve_batch then advances its handles with one
                                   launch, one workgroup each.  For many small systems (a 64 x 64
                                   grid has 4096 rows), which one at a time use a few of the
-                                  chip's 256 CUs.  Products read the caller's CSR arrays.
+                                  chip's 256 CUs.  Products read the handle's device copy of
+                                  A (matrix_format applies).
                                   Requires n <= 2^20, F64 precision, PRECOND_NONE, REORDER_NONE
                                   and orthonormalize_recycle = 0 (E_INVALID at create otherwise).
                                   The residual history keeps the first 256 entries of a solve

@@ -1646,8 +1646,7 @@ mstab_status wg_run(mstab_solver *const *h, int count, const double *const *b, d
         mstab_solver *hi = h[i];
         Engine<double> &E = hi->e64;
         wg::Job &J = jobs[(size_t)p];
-        memset(&J, 0, sizeof J);
-        J.rp = hi->rp; J.ci = hi->ci; J.va = hi->va;
+        J.A = E.A;
         J.b = b[i]; J.x = x[i];
         J.W = E.W; J.R = E.R; J.T = E.Tv;
         J.recU = E.recU; J.recV = E.recV; J.rec_ptv = E.rec_ptv;

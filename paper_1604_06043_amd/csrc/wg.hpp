@@ -14,8 +14,10 @@
 // of the launch.  The control flow is that of the host loop of the grid
 // engine, taken by every thread on values read from LDS after a barrier.
 //
-// The matrix is read from the caller's CSR arrays (products rounded, then
-// added in CSR order, contraction off).
+// The matrix is read from the handle's device copy (diagonal storage with
+// streamed or constant values, or sliced ELLPACK, as for the grid engine);
+// products are rounded, then added in column order (contraction off), so a
+// product equals the sequential CSR product bit for bit.
 #pragma once
 
 #include "kernels.hpp"
@@ -24,7 +26,13 @@
 namespace mstab {
 namespace wg {
 
-constexpr int NT = 256;                                 // threads per workgroup
+#ifndef MSTAB_WG_NT
+#define MSTAB_WG_NT 256
+#endif
+#ifndef MSTAB_WG_U
+#define MSTAB_WG_U 4
+#endif
+constexpr int NT = MSTAB_WG_NT;                         // threads per workgroup
 constexpr int NW = NT / 64;
 constexpr int HIST = 256;                               // history entries kept per solve
 constexpr int NV = (MAXL + 1) * (MAXL + 2) / 2;         // largest reduction (the Gram pairs)
@@ -32,8 +40,7 @@ constexpr int64_t MAX_N = (int64_t)1 << 20;
 
 // One system of a launch: inputs set by the host, results written by thread 0.
 struct Job {
-    const int32_t *rp, *ci;
-    const double *va;
+    Sell<double> A;                     // the handle's device copy of the matrix
     const double *b;
     double *x;                          // x0 in, x out (n entries)
     double *W, *R, *T;                  // s(l+2), l+1 and 1 vectors of ld entries
@@ -124,6 +131,8 @@ __device__ __forceinline__ double rfl(double v)
 // S: s; LC: a bound on l (l <= LC <= MAXL) that sizes the per-thread arrays
 template <int S, int LC>
 struct Solver {
+    // rows a thread loads before it uses any of them (rows NT apart)
+    static constexpr int U = S <= 4 ? MSTAB_WG_U : (MSTAB_WG_U + 1) / 2;
     const Job &J;
     Shared &sh;
     int n, ell;
@@ -141,6 +150,51 @@ struct Solver {
     __device__ double *Wc(int lev, int q) const { return W + ((int64_t)(lev + 1) * S + q) * ld; }
     __device__ double *Rc(int i) const { return R + (int64_t)i * ld; }
 
+    // The rows of a thread for a matrix in diagonal storage with at most 8
+    // diagonals: the loads of UU rows (gathers, and the values unless they are
+    // constant) are issued before any is used; present entries are added in
+    // ascending column order.  out(e, sum, b_e) finishes row e.
+    template <bool CST, int UU, typename Out>
+    __device__ __forceinline__ void dia_block(const Sell<double> &A, int nd, const double *src, Out &out)
+    {
+#pragma clang fp contract(off)
+        const bool resid = out.resid;
+        for (int e0 = threadIdx.x; e0 < n; e0 += UU * NT) {
+            double v[CST ? 1 : UU][8], xv[UU][8], bv[UU];
+#pragma unroll
+            for (int u = 0; u < UU; ++u) {
+                const int e = e0 + u * NT;
+                const int er = e < n ? e : e0;
+#pragma unroll
+                for (int d = 0; d < 8; ++d) {
+                    if (d < nd) {
+                        const int64_t c = er + A.doff.off[d];
+                        if constexpr (!CST) v[u][d] = A.dval[dia_index(er, d, nd)];
+                        xv[u][d] = (c >= 0 && c < n) ? src[c] : 0.0;
+                    }
+                }
+                bv[u] = resid ? J.b[er] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < UU; ++u) {
+                const int e = e0 + u * NT;
+                if (e >= n) break;
+                const uint32_t m = A.dmask[e];
+                double sum = 0.0;
+#pragma unroll
+                for (int d = 0; d < 8; ++d) {
+                    if (d < nd) {
+                        const double val = CST ? A.cv.c[d] : v[CST ? 0 : u][d];
+                        const double prod = val * xv[u][d];
+                        const double nsum = sum + prod;
+                        sum = ((m >> d) & 1u) ? nsum : sum;
+                    }
+                }
+                out(e, sum, bv[u]);
+            }
+        }
+    }
+
     // y = A x (or b - A x) with P^T y, ||y||^2 (and ||b||^2), then the
     // bookkeeping and small solve of the product's role (spmv_finalize's).
     __device__ __forceinline__ void product(const double *src, double *dst, int act, int k, int q)
@@ -151,23 +205,56 @@ struct Solver {
         double vals[S + 2];
 #pragma unroll
         for (int v = 0; v < S + 2; ++v) vals[v] = 0.0;
-        for (int e = threadIdx.x; e < n; e += NT) {
-            const int32_t k0 = J.rp[e], k1 = J.rp[e + 1];
-            double sum = 0.0;
-            for (int32_t kk = k0; kk < k1; ++kk) {
-                const double prod = J.va[kk] * src[J.ci[kk]];
-                sum = sum + prod;
-            }
-            double yv = sum;
-            if (resid) {
-                const double bv = J.b[e];
-                yv = bv - sum;
-                vals[S + 1] += bv * bv;
-            }
-            dst[e] = yv;
-            vals[S] += yv * yv;
+        const Sell<double> &A = J.A;
+        const int nd = A.nd;
+        struct Out {
+            bool resid;
+            double *dst;
+            uint32_t pkey;
+            double (&vals)[S + 2];
+            __device__ __forceinline__ void operator()(int e, double sum, double bv)
+            {
+#pragma clang fp contract(off)
+                double yv = sum;
+                if (resid) {
+                    yv = bv - sum;
+                    vals[S + 1] += bv * bv;
+                }
+                dst[e] = yv;
+                vals[S] += yv * yv;
 #pragma unroll
-            for (int a = 0; a < S; ++a) vals[a] += pval(J.pkey, (uint32_t)e, a) * yv;
+                for (int a = 0; a < S; ++a) vals[a] += pval(pkey, (uint32_t)e, a) * yv;
+            }
+        } out{resid, dst, J.pkey, vals};
+        if (nd > 0 && nd <= 8) {
+            if (A.dconst) dia_block<true, U>(A, nd, src, out);
+            else dia_block<false, 2>(A, nd, src, out);
+        } else {
+            for (int e = threadIdx.x; e < n; e += NT) {
+                double sum = 0.0;
+                if (nd > 0) {
+                    // diagonal storage: present entries in ascending column order
+                    const uint32_t m = A.dmask[e];
+                    for (int d = 0; d < nd; ++d) {
+                        const int64_t c = e + A.doff.off[d];
+                        const double v = A.dconst ? A.cv.c[d] : A.dval[dia_index(e, d, nd)];
+                        const double xv = (c >= 0 && c < n) ? src[c] : 0.0;
+                        const double prod = v * xv;
+                        const double nsum = sum + prod;
+                        sum = ((m >> d) & 1u) ? nsum : sum;
+                    }
+                } else {
+                    // sliced ELLPACK: entry j of row e at slice_ptr[e / 64] + 64 j + e % 64
+                    const int64_t k0 = A.slice_ptr[e >> 6] + (e & 63);
+                    const int32_t len = A.rp[e + 1] - A.rp[e];
+                    for (int32_t j = 0; j < len; ++j) {
+                        const int64_t kk = k0 + (int64_t)j * SLICE;
+                        const double prod = A.val[kk] * src[A.col[kk]];
+                        sum = sum + prod;
+                    }
+                }
+                out(e, sum, resid ? J.b[e] : 0.0);
+            }
         }
         reduce<S + 2>(vals, S + 2, sh);
         if (threadIdx.x < 64) {
@@ -243,24 +330,36 @@ struct Solver {
         __syncthreads();
     }
 
-    // r^(i) -= V^(i) gamma (i = 0..k), x += U gamma
+    // r^(i) -= V^(i) gamma (i = 0..k), x += U gamma: one pass per level
+    // (each element's operations as k_gamma's)
     __device__ void gamma_step(int k)
     {
         if (rfl(sh.flags)) return;
         double g[S];
 #pragma unroll
         for (int q = 0; q < S; ++q) g[q] = rfl(sh.gamma[q]);
-        for (int e = threadIdx.x; e < n; e += NT) {
-            for (int i = 0; i <= k; ++i) {
-                double acc = Rc(i)[e];
+        for (int i = -1; i <= k; ++i) {
+            // i = -1: x += U gamma; else r^(i) -= V^(i) gamma
+            double *y = i < 0 ? J.x : Rc(i);
+            const double sg = i < 0 ? 1.0 : -1.0;
+            for (int e0 = threadIdx.x; e0 < n; e0 += U * NT) {
+                double acc[U], w[U][S];
 #pragma unroll
-                for (int q = 0; q < S; ++q) acc = fmaT(-g[q], Wc(i, q)[e], acc);
-                Rc(i)[e] = acc;
+                for (int u = 0; u < U; ++u) {
+                    const int e = min(e0 + u * NT, n - 1);
+                    acc[u] = y[e];
+#pragma unroll
+                    for (int q = 0; q < S; ++q) w[u][q] = Wc(i, q)[e];
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int e = e0 + u * NT;
+                    if (e >= n) break;
+#pragma unroll
+                    for (int q = 0; q < S; ++q) acc[u] = fmaT(sg * g[q], w[u][q], acc[u]);
+                    y[e] = acc[u];
+                }
             }
-            double acc = J.x[e];
-#pragma unroll
-            for (int q = 0; q < S; ++q) acc = fmaT(g[q], Wc(-1, q)[e], acc);
-            J.x[e] = acc;
         }
         __syncthreads();
     }
@@ -272,11 +371,23 @@ struct Solver {
         double h[S];
 #pragma unroll
         for (int p = 0; p < S; ++p) h[p] = rfl(sh.eta_all[q][p]);
-        for (int e = threadIdx.x; e < n; e += NT) {
-            double acc = Rc(k + 1)[e];
+        for (int e0 = threadIdx.x; e0 < n; e0 += U * NT) {
+            double acc[U], w[U][S];
 #pragma unroll
-            for (int p = 0; p < S; ++p) acc = fmaT(-h[p], ((p < q) ? Wc(k + 1, p) : Wc(k, p))[e], acc);
-            Wc(k, q)[e] = acc;
+            for (int u = 0; u < U; ++u) {
+                const int e = min(e0 + u * NT, n - 1);
+                acc[u] = Rc(k + 1)[e];
+#pragma unroll
+                for (int p = 0; p < S; ++p) w[u][p] = ((p < q) ? Wc(k + 1, p) : Wc(k, p))[e];
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int e = e0 + u * NT;
+                if (e >= n) break;
+#pragma unroll
+                for (int p = 0; p < S; ++p) acc[u] = fmaT(-h[p], w[u][p], acc[u]);
+                Wc(k, q)[e] = acc[u];
+            }
         }
         __syncthreads();
     }
@@ -288,25 +399,45 @@ struct Solver {
     {
         if (rfl(sh.flags)) return;
         const volatile double *eta = &sh.eta_all[0][0];
-        for (int e = threadIdx.x; e < n; e += NT) {
-            double up[S];
+        for (int e0 = threadIdx.x; e0 < n; e0 += U * NT) {
+            double up[U][S];
 #pragma unroll
-            for (int p = 0; p < S; ++p) up[p] = Wc(k, p)[e];
+            for (int u = 0; u < U; ++u) {
+                const int e = min(e0 + u * NT, n - 1);
+#pragma unroll
+                for (int p = 0; p < S; ++p) up[u][p] = Wc(k, p)[e];
+            }
             for (int i = k - 1; i >= -1; --i) {
-                double old[S];
-                const double r = Rc(i + 1)[e];
+                double old[U][S], r[U];
 #pragma unroll
-                for (int p = 0; p < S; ++p) old[p] = Wc(i, p)[e];
+                for (int u = 0; u < U; ++u) {
+                    const int e = min(e0 + u * NT, n - 1);
+                    r[u] = Rc(i + 1)[e];
 #pragma unroll
-                for (int q = 0; q < S; ++q) {
-                    double acc = r;
-#pragma unroll
-                    for (int p = 0; p < S; ++p) acc = fmaT(-eta[q * MAXS + p], (p < q) ? up[p] : old[p], acc);
-                    Wc(i, q)[e] = acc;
-                    old[q] = acc;
+                    for (int p = 0; p < S; ++p) old[u][p] = Wc(i, p)[e];
                 }
 #pragma unroll
-                for (int p = 0; p < S; ++p) up[p] = old[p];
+                for (int q = 0; q < S; ++q) {
+                    double acc[U];
+#pragma unroll
+                    for (int u = 0; u < U; ++u) acc[u] = r[u];
+#pragma unroll
+                    for (int p = 0; p < S; ++p) {
+                        const double c = eta[q * MAXS + p];
+#pragma unroll
+                        for (int u = 0; u < U; ++u) acc[u] = fmaT(-c, (p < q) ? up[u][p] : old[u][p], acc[u]);
+                    }
+#pragma unroll
+                    for (int u = 0; u < U; ++u) {
+                        const int e = e0 + u * NT;
+                        if (e < n) Wc(i, q)[e] = acc[u];
+                        old[u][q] = acc[u];
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+#pragma unroll
+                    for (int p = 0; p < S; ++p) up[u][p] = old[u][p];
             }
         }
         __syncthreads();
@@ -320,18 +451,26 @@ struct Solver {
         double acc[NGL];
 #pragma unroll
         for (int v = 0; v < NGL; ++v) acc[v] = 0.0;
-        for (int e = threadIdx.x; e < n; e += NT) {
-            double z[LC + 1];
+        for (int e0 = threadIdx.x; e0 < n; e0 += U * NT) {
+            double z[U][LC + 1];
 #pragma unroll
-            for (int i = 0; i <= LC; ++i) z[i] = (i <= ell) ? Rc(i)[e] : 0.0;
-            int v = 0;
+            for (int u = 0; u < U; ++u) {
+                const int e = e0 + u * NT;
 #pragma unroll
-            for (int i = 0; i <= LC; ++i)
+                for (int i = 0; i <= LC; ++i) z[u][i] = (i <= ell && e < n) ? Rc(i)[e] : 0.0;
+            }
 #pragma unroll
-                for (int j = i; j <= LC; ++j) {
-                    if (j <= ell) acc[v] += z[i] * z[j];
-                    ++v;
-                }
+            for (int u = 0; u < U; ++u) {
+                if (e0 + u * NT >= n) break;
+                int v = 0;
+#pragma unroll
+                for (int i = 0; i <= LC; ++i)
+#pragma unroll
+                    for (int j = i; j <= LC; ++j) {
+                        if (j <= ell) acc[v] += z[u][i] * z[u][j];
+                        ++v;
+                    }
+            }
         }
         // pair (i, j), i <= j <= LC, at i*(LC+1) - i*(i-1)/2 + (j - i)
         reduce<NGL>(acc, NGL, sh);
@@ -369,23 +508,33 @@ struct Solver {
             double acc[S + 1];
 #pragma unroll
             for (int v = 0; v <= S; ++v) acc[v] = 0.0;
-            for (int e = threadIdx.x; e < n; e += NT) {
-                double xa = J.x[e];
-                double ra = Rc(0)[e];
-                double prev = ra;
+            for (int e0 = threadIdx.x; e0 < n; e0 += U * NT) {
+                double xa[U], z[U][LC + 1];
 #pragma unroll
-                for (int i = 1; i <= LC; ++i) {
-                    if (i > ell) break;
-                    const double ri = Rc(i)[e];
-                    xa = fmaT(tau[i - 1], prev, xa);
-                    ra = fmaT(-tau[i - 1], ri, ra);
-                    prev = ri;
+                for (int u = 0; u < U; ++u) {
+                    const int e = min(e0 + u * NT, n - 1);
+                    xa[u] = J.x[e];
+#pragma unroll
+                    for (int i = 0; i <= LC; ++i)
+                        if (i <= ell) z[u][i] = Rc(i)[e];
                 }
-                J.x[e] = xa;
-                Rc(0)[e] = ra;
 #pragma unroll
-                for (int a = 0; a < S; ++a) acc[a] += pval(J.pkey, (uint32_t)e, a) * ra;
-                acc[S] += ra * ra;
+                for (int u = 0; u < U; ++u) {
+                    const int e = e0 + u * NT;
+                    if (e >= n) break;
+                    double ra = z[u][0];
+#pragma unroll
+                    for (int i = 1; i <= LC; ++i) {
+                        if (i > ell) break;
+                        xa[u] = fmaT(tau[i - 1], z[u][i - 1], xa[u]);
+                        ra = fmaT(-tau[i - 1], z[u][i], ra);
+                    }
+                    J.x[e] = xa[u];
+                    Rc(0)[e] = ra;
+#pragma unroll
+                    for (int a = 0; a < S; ++a) acc[a] += pval(J.pkey, (uint32_t)e, a) * ra;
+                    acc[S] += ra * ra;
+                }
             }
             reduce<S + 1>(acc, S + 1, sh);
             if (threadIdx.x < 64) {
@@ -398,22 +547,31 @@ struct Solver {
             double acc[S];
 #pragma unroll
             for (int v = 0; v < S; ++v) acc[v] = 0.0;
-            for (int e = threadIdx.x; e < n; e += NT) {
-                double ua = Wc(-1, q)[e];
-                double prev = Wc(0, q)[e];
-                double va = prev;
+            for (int e0 = threadIdx.x; e0 < n; e0 += U * NT) {
+                double z[U][LC + 2];   // v_q^(-1..l)
 #pragma unroll
-                for (int i = 1; i <= LC; ++i) {
-                    if (i > ell) break;
-                    const double vi = Wc(i, q)[e];
-                    ua = fmaT(-tau[i - 1], prev, ua);
-                    va = fmaT(-tau[i - 1], vi, va);
-                    prev = vi;
+                for (int u = 0; u < U; ++u) {
+                    const int e = min(e0 + u * NT, n - 1);
+#pragma unroll
+                    for (int i = -1; i <= LC; ++i)
+                        if (i <= ell) z[u][i + 1] = Wc(i, q)[e];
                 }
-                Wc(-1, q)[e] = ua;
-                Wc(0, q)[e] = va;
 #pragma unroll
-                for (int a = 0; a < S; ++a) acc[a] += pval(J.pkey, (uint32_t)e, a) * va;
+                for (int u = 0; u < U; ++u) {
+                    const int e = e0 + u * NT;
+                    if (e >= n) break;
+                    double ua = z[u][0], va = z[u][1];
+#pragma unroll
+                    for (int i = 1; i <= LC; ++i) {
+                        if (i > ell) break;
+                        ua = fmaT(-tau[i - 1], z[u][i], ua);
+                        va = fmaT(-tau[i - 1], z[u][i + 1], va);
+                    }
+                    Wc(-1, q)[e] = ua;
+                    Wc(0, q)[e] = va;
+#pragma unroll
+                    for (int a = 0; a < S; ++a) acc[a] += pval(J.pkey, (uint32_t)e, a) * va;
+                }
             }
             reduce<S>(acc, S, sh);
             if (threadIdx.x < S) sh.ptv[0][q][threadIdx.x] = sh.tot[threadIdx.x];
@@ -594,8 +752,11 @@ struct Solver {
     }
 };
 
+#ifndef MSTAB_WG_WAVES
+#define MSTAB_WG_WAVES 2
+#endif
 template <int S, int LC>
-__global__ __launch_bounds__(NT) void k_solve(Job *jobs)
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MSTAB_WG_WAVES))) void k_solve(Job *jobs)
 {
     __shared__ Shared sh;
     Job &J = jobs[blockIdx.x];
