@@ -257,7 +257,7 @@ def rgg_sequence(N: int, seed: int = 0, systems: int = 100) -> Sequence:
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("which", choices=["sweep", "c1", "c3", "c5", "c2", "fetch", "jacobi", "ilu", "batch",
-                                      "wgbatch", "reorder"])
+                                      "wgbatch", "reorder", "fetchsweep"])
     ap.add_argument("--n", type=int, default=None)
     ap.add_argument("--N", type=int, default=1 << 22)
     ap.add_argument("--systems", type=int, default=None)
@@ -314,6 +314,25 @@ def main():
                                          "mvs": [i["mv_total"] for i in infos]}
                 log(f"[{seq.name}] fetch {pname}: {mv:.1f} MVs/system (IDR {row['idrstab']['mvs_per_system']:.1f})")
             print(json.dumps(row), flush=True)
+    elif a.which == "fetchsweep":
+        # the bench sequence under every fetch policy and THRESHOLD level
+        seq = convdiff_sequence("c2", a.n)
+        systems = a.systems or 50
+        run(seq, 2, 4, 2)   # warm-up
+        rows = {"idrstab": dict(method=M.METHOD_IDRSTAB)}
+        for lvl in (1e-1, 1e-2, 1e-3, 1e-4, 1e-5, 1e-6):
+            rows[f"threshold_{lvl:g}"] = dict(fetch_rel=lvl)
+        rows["estimate"] = dict(fetch=M.FETCH_ESTIMATE)
+        rows["at_end"] = dict(fetch=M.FETCH_AT_END)
+        rows["threshold_orth"] = dict(orthonormalize_recycle=1)
+        rows["estimate_orth"] = dict(fetch=M.FETCH_ESTIMATE, orthonormalize_recycle=1)
+        out = {"workload": seq.name, "systems": systems, "s": 4, "ell": 2}
+        for name, opt in rows.items():
+            t, mv, infos, _ = run(seq, systems, 4, 2, **opt)
+            out[name] = {"systems_per_s": systems / t, "mvs_per_system": mv,
+                         "mvs": [i["mv_total"] for i in infos]}
+            log(f"[fetchsweep] {name}: {mv:.2f} MVs/system, {systems / t:.1f} systems/s")
+        print(json.dumps(out), flush=True)
     elif a.which == "c5":
         systems = a.systems or 100
         seq = rgg_sequence(a.N, 0, systems)
