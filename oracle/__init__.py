@@ -88,6 +88,8 @@ def _load():
         _lib.orc_set_sum_order.argtypes = [i32]
         _lib.orc_bicgstab.restype = i32
         _lib.orc_bicgstab.argtypes = [i64, P, P, P, P, P, P, i32]
+        _lib.orc_gmres.restype = i32
+        _lib.orc_gmres.argtypes = [i64, P, P, P, i32, f64, i64, P, P, P, P, P, P, i64, P, P]
     return _lib
 
 
@@ -339,6 +341,56 @@ def bicgstab(A: CSR, b, x0, rhat, iters: int) -> np.ndarray:
     if st != OK:
         raise RuntimeError("bicgstab failed")
     return x
+
+
+@dataclass
+class GmresInfo:
+    status: int
+    mv: int
+    steps: int
+    cycles: int
+    converged: bool
+    relres_est: float
+    relres_true: float
+    hist_mv: np.ndarray
+    hist_res: np.ndarray
+
+
+def gmres(A: CSR, b, x0, m: int, tol: float = 1e-8, max_mv: int = 100000, ilu=None):
+    """Restarted GMRES(m), a comparison method of Section 5.1 (oracle.c's
+    orc_gmres: classical Gram-Schmidt applied twice, Givens rotations, the
+    true residual at every restart decides).  ilu: optional factors (in A's
+    pattern) for the split operator L^{-1} A U^{-1}.  Returns (x, GmresInfo)."""
+    lib = _load()
+    x = np.array(x0, dtype=np.float64, copy=True)
+    b = np.ascontiguousarray(b, dtype=np.float64)
+    oi = np.zeros(4, dtype=np.int64)
+    of = np.zeros(2)
+    cap = int(min(max_mv, 1 << 20)) + 2
+    hm = np.zeros(cap, dtype=np.int64)
+    hr = np.zeros(cap)
+    hl = ctypes.c_int64()
+    st = lib.orc_gmres(A.n, _ptr(A.row_ptr), _ptr(A.col), _ptr(A.val), int(m), float(tol), int(max_mv),
+                       _ptr(b), _ptr(x), _ptr(oi), _ptr(of), _ptr(hm), _ptr(hr), cap, ctypes.byref(hl),
+                       _ptr(None if ilu is None else np.ascontiguousarray(ilu, dtype=np.float64)))
+    if st < 0:
+        raise RuntimeError(f"orc_gmres failed with status {st}")
+    k = min(hl.value, cap)
+    return x, GmresInfo(int(st), int(oi[0]), int(oi[1]), int(oi[2]), bool(oi[3]), float(of[0]),
+                        float(of[1]), hm[:k].copy(), hr[:k].copy())
+
+
+def gmres_ilu(A: CSR, b, x0, m: int, split=None, **kw):
+    """:func:`gmres` on the ILU(0) split system of :func:`solve_ilu` (same
+    order, factors and transforms); returns (x, GmresInfo)."""
+    Ap, lu, perm = split if split is not None else ilu_split(A)
+    b = np.asarray(b, dtype=np.float64)
+    bh = ilu_apply(Ap, lu, "lower", b[perm])
+    y0 = ilu_apply(Ap, lu, "upper_mul", np.asarray(x0, dtype=np.float64)[perm])
+    y, info = gmres(Ap, bh, y0, m, ilu=lu, **kw)
+    x = np.empty(A.n)
+    x[perm] = ilu_apply(Ap, lu, "upper", y)
+    return x, info
 
 
 def jacobi_split(A: CSR):

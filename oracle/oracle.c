@@ -938,3 +938,145 @@ int orc_bicgstab(int64_t n, const int32_t *rp, const int32_t *ci, const double *
     free(r); free(p); free(v); free(sv); free(tv);
     return ORC_OK;
 }
+
+/*
+ * Restarted GMRES(m) (Saad and Schultz), one of the comparison methods of
+ * Section 5.1, for A x = b from x (in/out).
+ *
+ * Each restart cycle starts from the true residual r = b - A x, beta = ||r||,
+ * v_1 = r (1 / beta), g = beta e_1.  Arnoldi step j: w = A v_j, orthogonalized
+ * against v_1..v_j by classical Gram-Schmidt applied twice (c = V^T w, then
+ * w -= V c element by element in basis order; the Hessenberg column is the
+ * sum of the two passes' c), h_{j+1,j} = ||w||.  The column is rotated by
+ * the cycle's earlier Givens rotations, a new rotation (c, s) = (h_jj, h_{j+1,j})
+ * / hypot(h_jj, h_{j+1,j}) zeroes h_{j+1,j}, and |g_{j+1}| after it is the
+ * residual norm of the least-squares solution over the Krylov space.  The
+ * cycle ends after m steps, when that estimate is <= tol ||b||, when
+ * h_{j+1,j} = 0 (the Krylov space is invariant: the least-squares solution is
+ * exact) or when the product budget is spent; then y solves the rotated
+ * triangular system by back substitution and x += V y.  The next cycle's
+ * true residual decides convergence (||r|| <= tol ||b||).  A zero rotation
+ * denominator (h_jj = h_{j+1,j} = 0) ends the cycle before that column; a
+ * cycle that keeps no column is a breakdown.  Every product with A counts,
+ * the true residuals included.  A zero b gives x = 0 with no product.
+ * ilu: optional split ILU(0) operator L^{-1} A U^{-1} (as orc_solve).
+ *
+ * out_i64[0..3]: mv, Arnoldi steps, restart cycles, converged
+ * out_f64[0..1]: last estimate and true relative residual
+ * hist: (MVs, relative residual) after the initial residual and after every
+ *       Arnoldi step (the estimate).
+ */
+int orc_gmres(int64_t n, const int32_t *rp, const int32_t *ci, const double *va, int m,
+              double tol, int64_t max_mv, const double *b, double *x,
+              int64_t *out_i64, double *out_f64,
+              int64_t *hist_mv, double *hist_res, int64_t hist_cap, int64_t *hist_len,
+              const double *ilu)
+{
+    if (n <= 0 || m < 1) return ORC_E_INVALID;
+    Mat A = {n, rp, ci, va, 0, ilu, NULL};
+    double *V = calloc((size_t)n * (size_t)(m + 1), sizeof(double));
+    double *w = calloc((size_t)n, sizeof(double));
+    double *H = calloc((size_t)(m + 1) * (size_t)m, sizeof(double));   /* H[i * m + j] */
+    double *cs = calloc((size_t)m, sizeof(double)), *sn = calloc((size_t)m, sizeof(double));
+    double *g = calloc((size_t)(m + 1), sizeof(double)), *y = calloc((size_t)m, sizeof(double));
+    double *c = calloc((size_t)(m + 1), sizeof(double));
+    if (ilu) A.tmp = calloc((size_t)n, sizeof(double));
+    int status = ORC_OK;
+    int64_t steps = 0, cycles = 0, hl = 0;
+    int converged = 0;
+    double est = -1.0, relres_true = -1.0, nb = 0.0;
+    if (!V || !w || !H || !cs || !sn || !g || !y || !c || (ilu && !A.tmp)) { status = ORC_E_NOMEM; goto done; }
+
+#define GHIST(res) do { if (hl < hist_cap) { hist_mv[hl] = A.mv; hist_res[hl] = (res); } ++hl; } while (0)
+
+    nb = sqrt(dot(n, b, b));
+    if (!isfinite(nb)) { status = ORC_E_NONFINITE; goto done; }
+    if (nb == 0.0) {
+        for (int64_t e = 0; e < n; ++e) x[e] = 0.0;
+        converged = 1;
+        relres_true = 0.0;
+        est = 0.0;
+        goto done;
+    }
+    const double thr = tol * nb;
+    for (;;) {
+        /* the true residual */
+        matvec(&A, x, V);
+        for (int64_t e = 0; e < n; ++e) V[e] = b[e] - V[e];
+        const double beta = sqrt(dot(n, V, V));
+        if (!isfinite(beta)) { status = ORC_E_NONFINITE; break; }
+        if (cycles == 0) GHIST(beta / nb);
+        relres_true = beta / nb;
+        if (beta <= thr) { converged = 1; break; }
+        if (A.mv >= max_mv) break;
+        const double inv = 1.0 / beta;
+        for (int64_t e = 0; e < n; ++e) V[e] = V[e] * inv;
+        for (int i = 0; i <= m; ++i) g[i] = 0.0;
+        g[0] = beta;
+        for (int64_t i = 0; i < (int64_t)(m + 1) * m; ++i) H[i] = 0.0;
+        int k = 0;
+        for (int j = 0; j < m; ++j) {
+            const double *vj = V + (size_t)j * n;
+            matvec(&A, vj, w);
+            ++steps;
+            for (int pass = 0; pass < 2; ++pass) {
+                for (int i = 0; i <= j; ++i) c[i] = dot(n, V + (size_t)i * n, w);
+                for (int64_t e = 0; e < n; ++e) {
+                    double a = w[e];
+                    for (int i = 0; i <= j; ++i) a = fma(-c[i], V[(size_t)i * n + e], a);
+                    w[e] = a;
+                }
+                for (int i = 0; i <= j; ++i) H[i * m + j] += c[i];
+            }
+            const double hn = sqrt(dot(n, w, w));
+            if (!isfinite(hn)) { status = ORC_E_NONFINITE; goto done; }
+            for (int i = 0; i < j; ++i) {
+                const double t = cs[i] * H[i * m + j] + sn[i] * H[(i + 1) * m + j];
+                H[(i + 1) * m + j] = -sn[i] * H[i * m + j] + cs[i] * H[(i + 1) * m + j];
+                H[i * m + j] = t;
+            }
+            const double d = hypot(H[j * m + j], hn);
+            if (!(d > 0.0)) break;   /* singular on the Krylov space: keep columns 0..j-1 */
+            cs[j] = H[j * m + j] / d;
+            sn[j] = hn / d;
+            H[j * m + j] = d;
+            g[j + 1] = -sn[j] * g[j];
+            g[j] = cs[j] * g[j];
+            k = j + 1;
+            est = fabs(g[j + 1]);
+            GHIST(est / nb);
+            if (est <= thr || !(hn > 0.0) || A.mv >= max_mv) break;
+            const double ih = 1.0 / hn;
+            double *vn = V + (size_t)(j + 1) * n;
+            for (int64_t e = 0; e < n; ++e) vn[e] = w[e] * ih;
+        }
+        if (k == 0) { status = ORC_E_BREAKDOWN; break; }
+        for (int i = k - 1; i >= 0; --i) {
+            double a = g[i];
+            for (int l = i + 1; l < k; ++l) a -= H[i * m + l] * y[l];
+            y[i] = a / H[i * m + i];
+        }
+        for (int64_t e = 0; e < n; ++e) {
+            double a = x[e];
+            for (int i = 0; i < k; ++i) a = fma(y[i], V[(size_t)i * n + e], a);
+            x[e] = a;
+        }
+        ++cycles;
+    }
+#undef GHIST
+    if (status == ORC_OK && !converged) status = ORC_NOT_CONVERGED;
+done:
+    if (out_i64) {
+        out_i64[0] = A.mv;
+        out_i64[1] = steps;
+        out_i64[2] = cycles;
+        out_i64[3] = converged;
+    }
+    if (out_f64) {
+        out_f64[0] = est < 0 ? -1.0 : est / (nb > 0 ? nb : 1.0);
+        out_f64[1] = relres_true;
+    }
+    if (hist_len) *hist_len = hl;
+    free(V); free(w); free(H); free(cs); free(sn); free(g); free(y); free(c); free(A.tmp);
+    return status;
+}
