@@ -48,7 +48,20 @@ typedef enum {
 
 typedef enum {
     MSTAB_METHOD_MSTAB = 0,    /* use recycled P, U, V when the handle holds them (Section 4.2) */
-    MSTAB_METHOD_IDRSTAB = 1   /* Arnoldi U, V of level s for every system (Section 5) */
+    MSTAB_METHOD_IDRSTAB = 1,  /* Arnoldi U, V of level s for every system (Section 5) */
+    MSTAB_METHOD_GMRES = 2     /* restarted GMRES(m), m = gmres_restart, one of Section 5.1's
+                                  comparison methods (BiCGStab, the other, is IDRSTAB with
+                                  s = l = 1, Section 2.3): Arnoldi with classical Gram-Schmidt
+                                  applied twice, Givens rotations, |g_{j+1}| <= tol ||b|| ends a
+                                  cycle early, and the true residual that starts every cycle
+                                  decides convergence.  s and l are not used (pass 1, 1).  Every
+                                  product counts in mv (the true residuals included); cycles
+                                  counts Arnoldi steps, restarts the cycles after the first,
+                                  relres_recursive the last step's estimate; the residual
+                                  history holds the initial residual and every step's estimate.
+                                  F64 precision and ENGINE_GRID only; split preconditioning and
+                                  reordering apply as for the other methods.  The handle keeps
+                                  m + 2 extra vectors. */
 } mstab_method;
 
 typedef enum {
@@ -190,6 +203,7 @@ typedef struct {
                                   V = A U.  If U^T U is not numerically positive definite
                                   the data stay as fetched.  Default 0. */
     int32_t engine;            /* mstab_engine; default GRID */
+    int32_t gmres_restart;     /* METHOD_GMRES: the restart length m, 1..1024; default 30 */
 } mstab_options;
 
 typedef struct {

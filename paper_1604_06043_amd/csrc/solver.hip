@@ -8,6 +8,7 @@
 // residual scaled by its FP64 norm, replacing the FP32 residual by the FP64
 // true residual after its cycles and keeping the FP32 recycle data across
 // systems.
+#include "gmres.hpp"
 #include "ilu.hpp"
 #include "kernels.hpp"
 #include "mstab.h"
@@ -785,6 +786,8 @@ struct Engine {
         (void)hipFree(W); (void)hipFree(R); (void)hipFree(X); (void)hipFree(Tv);
         (void)hipFree(recU); (void)hipFree(recV); (void)hipFree(rec_ptv);
         (void)hipFree(ctl); (void)hipFree(part);
+        (void)hipFree(gmV); (void)hipFree(gm_state);
+        gmV = nullptr; gm_state = nullptr;
         if (st_host) (void)hipHostFree(st_host);
         W = R = X = Tv = recU = recV = nullptr;
         rec_ptv = nullptr; ctl = nullptr; part = nullptr; st_host = nullptr;
@@ -808,6 +811,20 @@ struct Engine {
 
     // ILU(0) split preconditioning: the products are L^-1 A U^-1 (FP64 only)
     const IluData *ilu = nullptr;
+
+    // GMRES(m): basis v_1..v_{m+1} and the work vector w (m + 2 vectors of
+    // ld), and the cycle's small state (GmLayout)
+    T *gmV = nullptr;
+    double *gm_state = nullptr;
+    int gm_m = 0;
+    void alloc_gmres(int m)
+    {
+        gm_m = m;
+        HIPCHK(hipMalloc(&gmV, (size_t)ld * sizeof(T) * (size_t)(m + 2)));
+        HIPCHK(hipMemsetAsync(gmV, 0, (size_t)ld * sizeof(T) * (size_t)(m + 2), stream));
+        HIPCHK(hipMalloc(&gm_state, sizeof(double) * (size_t)GmLayout{m}.size()));
+        HIPCHK(hipStreamSynchronize(stream));
+    }
 
     template <int S>
     void vec_out_s(int grid, const T *t, const T *b, T *y, const SpmvArgs &a)
@@ -1214,6 +1231,116 @@ struct Engine {
         rec_have = true;
     }
 
+    // Restarted GMRES(m) for A X = b from the current X (Section 5.1's
+    // comparison method; the kernels are in gmres.hpp).  Every product counts
+    // in res.mv (the true residual that starts each cycle and ends the solve
+    // included); res.cycles counts Arnoldi steps, res.restarts the cycles
+    // after the first; the history holds the initial residual and every
+    // step's estimate.  A zero b gives x = 0 with no product.
+    SolveResult gmres(const T *b, double tol, int64_t max_mv)
+    {
+        SolveResult res;
+        hist_mv.clear();
+        hist_res.clear();
+        const int m = gm_m;
+        const GmLayout L{m};
+        T *w = gmV + (int64_t)(m + 1) * ld;
+        auto V = [&](int j) { return gmV + (int64_t)j * ld; };
+        const int gv = grid_for(ld, BLOCK, VEC_MAX_BLOCKS);
+        const int gd = grid_for(ld, BLOCK, GRAM_MAX_BLOCKS);
+        int64_t mv = 0, cycles = 0;
+        double nb = 0.0, thr = 0.0, est = -1.0;
+        double scal[GM_SCAL];
+        small(SMALL_CLEAR);
+        for (;;) {
+            // the true residual into v_1
+            spmv(X, V(0), b, ACT_TRUE, 0, 0);
+            ++mv;
+            sync_status();
+            if (st_host->flags & FLAG_NONFINITE) { res.status = MSTAB_E_NONFINITE; break; }
+            if (cycles == 0) {
+                nb = std::sqrt(st_host->bb);
+                if (!std::isfinite(nb)) { res.status = MSTAB_E_NONFINITE; break; }
+                if (nb == 0.0) {
+                    fill(X, ld, (T)0);
+                    HIPCHK(hipStreamSynchronize(stream));
+                    mv = 0;
+                    res.converged = true;
+                    res.relres_true = 0.0;
+                    est = 0.0;
+                    break;
+                }
+                thr = tol * nb;
+            }
+            const double beta = std::sqrt(st_host->tt);
+            if (!std::isfinite(beta)) { res.status = MSTAB_E_NONFINITE; break; }
+            if (cycles == 0) {
+                hist_mv.push_back(mv);
+                hist_res.push_back(beta / nb);
+            }
+            res.relres_true = beta / nb;
+            if (beta <= thr) { res.converged = true; break; }
+            if (mv >= max_mv) break;
+            hipLaunchKernelGGL((k_gm_start<T>), dim3(gv), dim3(BLOCK), 0, stream, ld, V(0), gm_state, m,
+                               (const Ctl *)ctl);
+            HIPCHK(hipGetLastError());
+            int k = 0;
+            for (int j = 0; j < m; ++j) {
+                spmv(V(j), w, nullptr, ACT_NONE, 0, 0);
+                ++mv;
+                ++res.cycles;
+                for (int pass = 0; pass < 2; ++pass) {
+                    double *c = gm_state + L.c(pass);
+                    for (int j0 = 0; j0 <= j; j0 += MAXS) {
+                        const int nv = std::min(MAXS, j + 1 - j0);
+                        hipLaunchKernelGGL((k_gm_dots<T>), dim3(gd), dim3(BLOCK), 0, stream, ld, (const T *)gmV,
+                                           j0, nv, (const T *)w, c, ctl, part, PART_STRIDE);
+                        HIPCHK(hipGetLastError());
+                    }
+                    for (int j0 = 0; j0 <= j; j0 += MAXS) {
+                        const int nv = std::min(MAXS, j + 1 - j0);
+                        hipLaunchKernelGGL((k_gm_axpy<T>), dim3(gv), dim3(BLOCK), 0, stream, ld, (const T *)gmV,
+                                           j0, nv, (const double *)c, -1.0, w, (const Ctl *)ctl);
+                        HIPCHK(hipGetLastError());
+                    }
+                }
+                hipLaunchKernelGGL((k_gm_dots<T>), dim3(gd), dim3(BLOCK), 0, stream, ld, (const T *)gmV, 0, 0,
+                                   (const T *)w, gm_state + L.c(0), ctl, part, PART_STRIDE);
+                HIPCHK(hipGetLastError());
+                hipLaunchKernelGGL(k_gm_column, dim3(1), dim3(64), 0, stream, gm_state, m, j, (const Ctl *)ctl);
+                HIPCHK(hipGetLastError());
+                HIPCHK(hipMemcpyAsync(scal, gm_state + L.scal(), sizeof scal, hipMemcpyDeviceToHost, stream));
+                sync_status();
+                if (st_host->flags & FLAG_NONFINITE) { res.status = MSTAB_E_NONFINITE; goto out; }
+                if (scal[GM_SINGULAR] != 0.0) break;   // keep columns 0..j-1
+                k = j + 1;
+                est = scal[GM_EST];
+                hist_mv.push_back(mv);
+                hist_res.push_back(est / nb);
+                if (est <= thr || !(scal[GM_HN] > 0.0) || mv >= max_mv) break;
+                hipLaunchKernelGGL((k_gm_scale<T>), dim3(gv), dim3(BLOCK), 0, stream, ld, (const T *)w, V(j + 1),
+                                   (const double *)gm_state, m);
+                HIPCHK(hipGetLastError());
+            }
+            if (k == 0) { res.status = MSTAB_E_BREAKDOWN; break; }
+            hipLaunchKernelGGL(k_gm_solve, dim3(1), dim3(64), 0, stream, gm_state, m, k);
+            HIPCHK(hipGetLastError());
+            for (int j0 = 0; j0 < k; j0 += MAXS) {
+                const int nv = std::min(MAXS, k - j0);
+                hipLaunchKernelGGL((k_gm_axpy<T>), dim3(gv), dim3(BLOCK), 0, stream, ld, (const T *)gmV, j0, nv,
+                                   (const double *)(gm_state + L.y()), 1.0, X, (const Ctl *)ctl);
+                HIPCHK(hipGetLastError());
+            }
+            ++cycles;
+        }
+        if (res.status == MSTAB_OK && !res.converged) res.status = MSTAB_NOT_CONVERGED;
+    out:
+        res.mv = mv;
+        res.restarts = cycles > 0 ? (int)(cycles - 1) : 0;
+        res.relres_rec = est < 0 ? -1.0 : est / (nb > 0 ? nb : 1.0);
+        return res;
+    }
+
     // Solve A X = b from the current X (b: n entries of T on the device).
     // check_true = false: stop on the recursive residual (inner solves of the
     // mixed mode, whose FP64 outer residual decides).
@@ -1572,8 +1699,10 @@ mstab_status solve_f64(mstab_solver *h, const double *b, double *x, mstab_info *
     const bool low = h->opt.precision == MSTAB_PREC_F32_MATRIX;
     const int max_repl = low ? std::max(h->opt.max_replacements, LOW_MATRIX_REPLACEMENTS)
                              : h->opt.max_replacements;
-    SolveResult r = E.solve(b, h->opt.tol, h->opt.max_mv, h->opt.method, h->opt.fetch,
-                            h->opt.fetch_rel, h->opt.fetch_level, max_repl);
+    SolveResult r = h->opt.method == MSTAB_METHOD_GMRES
+                        ? E.gmres(b, h->opt.tol, h->opt.max_mv)
+                        : E.solve(b, h->opt.tol, h->opt.max_mv, h->opt.method, h->opt.fetch,
+                                  h->opt.fetch_rel, h->opt.fetch_level, max_repl);
     HIPCHK(hipMemcpyAsync(x, E.X, sizeof(double) * h->n, hipMemcpyDeviceToDevice, h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));
     r.mv_check += extra_checks;
@@ -1955,6 +2084,7 @@ mstab_status mstab_options_default(mstab_options *o)
     o->max_replacements = 3;
     o->inner_tol = 1e-4;
     o->max_refinements = 20;
+    o->gmres_restart = 30;
     return MSTAB_OK;
 }
 
@@ -1998,6 +2128,15 @@ mstab_status mstab_create(const mstab_csr *A, int32_t s, int32_t ell, const msta
         fail(MSTAB_E_INVALID, "orthonormalize_recycle must be 0 or 1");
     if (h->opt.engine != MSTAB_ENGINE_GRID && h->opt.engine != MSTAB_ENGINE_WORKGROUP)
         fail(MSTAB_E_INVALID, "unknown engine");
+    if (h->opt.method != MSTAB_METHOD_MSTAB && h->opt.method != MSTAB_METHOD_IDRSTAB &&
+        h->opt.method != MSTAB_METHOD_GMRES)
+        fail(MSTAB_E_INVALID, "unknown method");
+    if (h->opt.method == MSTAB_METHOD_GMRES) {
+        if (h->opt.gmres_restart < 1 || h->opt.gmres_restart > 1024)
+            fail(MSTAB_E_INVALID, "gmres_restart=%d outside 1..1024", h->opt.gmres_restart);
+        if (h->opt.precision != MSTAB_PREC_F64 || h->opt.engine != MSTAB_ENGINE_GRID)
+            fail(MSTAB_E_INVALID, "GMRES: F64 precision and ENGINE_GRID only");
+    }
     if (h->opt.engine == MSTAB_ENGINE_WORKGROUP) {
         if (A->n > wg::MAX_N) fail(MSTAB_E_INVALID, "ENGINE_WORKGROUP: n=%lld above 2^20", (long long)A->n);
         if (h->opt.precision != MSTAB_PREC_F64 || h->opt.precond != MSTAB_PRECOND_NONE ||
@@ -2099,6 +2238,7 @@ mstab_status mstab_create(const mstab_csr *A, int32_t s, int32_t ell, const msta
     // the mixed form keeps a full FP64 engine for the FP64 fallback
     h->e64.alloc(h->n, s, ell, A64, true, h->pkey, h->stream, &h->prof);
     if (use_ilu) h->e64.ilu = &h->ilu;
+    if (h->opt.method == MSTAB_METHOD_GMRES) h->e64.alloc_gmres(h->opt.gmres_restart);
     h->e64.replace_every = h->opt.replace_every;
     h->e64.orthonormalize = h->opt.orthonormalize_recycle != 0;
     if (h->opt.precision == MSTAB_PREC_F32_MATRIX) {

@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("MSTAB_LIBRARY") or os.path.join(HERE, "libmstab.so")
 
 OK, NOT_CONVERGED, E_INVALID, E_HIP, E_NOMEM, E_BREAKDOWN, E_NONFINITE = 0, 1, -1, -2, -3, -4, -5
-METHOD_MSTAB, METHOD_IDRSTAB = 0, 1
+METHOD_MSTAB, METHOD_IDRSTAB, METHOD_GMRES = 0, 1, 2
 PREC_F64, PREC_F32_REFINE, PREC_F32_MATRIX = 0, 1, 2
 PRECOND_NONE, PRECOND_JACOBI, PRECOND_ILU0 = 0, 1, 2
 ENGINE_GRID, ENGINE_WORKGROUP = 0, 1
@@ -57,7 +57,8 @@ class mstab_options(ctypes.Structure):
                 ("inner_tol", ctypes.c_double), ("max_refinements", ctypes.c_int32),
                 ("precond", ctypes.c_int32), ("replace_every", ctypes.c_int32),
                 ("reorder", ctypes.c_int32), ("matrix_format", ctypes.c_int32),
-                ("orthonormalize_recycle", ctypes.c_int32), ("engine", ctypes.c_int32)]
+                ("orthonormalize_recycle", ctypes.c_int32), ("engine", ctypes.c_int32),
+                ("gmres_restart", ctypes.c_int32)]
 
 
 class mstab_info(ctypes.Structure):

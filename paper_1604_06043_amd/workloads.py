@@ -177,6 +177,21 @@ def batch_throughput(B: int, systems: int = 10, n: int = 64, s: int = 4, ell: in
             "systems_per_s": B * systems / sec, "mvs_per_system": mv / (B * systems)}
 
 
+def gmres_compare(seq: Sequence, systems: int, s: int, ell: int, restarts=(10, 30), seed: int = 0, **opt):
+    """Section 5.1's comparison on one sequence: M(s)stab(l) and IDR(s)stab(l)
+    against restarted GMRES(m), each with the same options (a splitting)."""
+    out = {"workload": seq.name, "N": seq.N, "systems": systems, "s": s, "ell": ell, "tol": 1e-8}
+    run(seq, 1, s, ell, seed=seed, **opt)   # warm-up
+    rows = [("mstab", dict(method=M.METHOD_MSTAB), s, ell), ("idrstab", dict(method=M.METHOD_IDRSTAB), s, ell)]
+    rows += [(f"gmres_{m}", dict(method=M.METHOD_GMRES, gmres_restart=m), 1, 1) for m in restarts]
+    for name, mopt, ss, ll in rows:
+        t, mv, infos, _ = run(seq, systems, ss, ll, seed=seed, **mopt, **opt)
+        out[name] = {"systems_per_s": systems / t, "mvs_per_system": mv,
+                     "max_relres_true": max(i["relres_true"] for i in infos)}
+        log(f"[{seq.name}] {name}: {systems / t:.3f} systems/s, {mv:.1f} MVs/system")
+    return out
+
+
 def batch_workgroup(B: int, systems: int = 10, n: int = 64, s: int = 4, ell: int = 2):
     """B independent c1-type sequences (seeds 0..B-1) on handles of the
     one-workgroup engine: each step forms every right-hand side with one
@@ -257,7 +272,7 @@ def rgg_sequence(N: int, seed: int = 0, systems: int = 100) -> Sequence:
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("which", choices=["sweep", "c1", "c3", "c5", "c2", "fetch", "jacobi", "ilu", "batch",
-                                      "wgbatch", "reorder", "fetchsweep"])
+                                      "wgbatch", "reorder", "fetchsweep", "gmres"])
     ap.add_argument("--n", type=int, default=None)
     ap.add_argument("--N", type=int, default=1 << 22)
     ap.add_argument("--systems", type=int, default=None)
@@ -314,6 +329,12 @@ def main():
                                          "mvs": [i["mv_total"] for i in infos]}
                 log(f"[{seq.name}] fetch {pname}: {mv:.1f} MVs/system (IDR {row['idrstab']['mvs_per_system']:.1f})")
             print(json.dumps(row), flush=True)
+    elif a.which == "gmres":
+        print(json.dumps(gmres_compare(convdiff_sequence("c2", a.n), a.systems or 10, 4, 2)), flush=True)
+        print(json.dumps(gmres_compare(convdiff_sequence("c3", a.n), a.systems or 5, 8, 4,
+                                       precond=M.PRECOND_JACOBI)), flush=True)
+        print(json.dumps(gmres_compare(rgg_sequence(a.N, 0, a.systems or 10), a.systems or 10, 4, 2,
+                                       reorder=M.REORDER_RCM, precond=M.PRECOND_JACOBI)), flush=True)
     elif a.which == "fetchsweep":
         # the bench sequence under every fetch policy and THRESHOLD level
         seq = convdiff_sequence("c2", a.n)
