@@ -122,3 +122,80 @@ __global__ __launch_bounds__(SPMV_BLOCK) void k_vec_out(int64_t n, const T *__re
 }
 
 }  // namespace mstab
+
+namespace mstab {
+
+// The factors in the product's sliced layout, for the solves of every
+// product: the strictly lower entries of each row (L) and the strictly upper
+// ones (U) each in 64-row slices, entry j of row r at sp[r / 64] + 64 j + r % 64
+// (row lengths from A''s row pointer and the diagonal positions), and U's
+// diagonal per row.  The j-th entries of a wavefront's 64 rows are one
+// contiguous load.
+struct IluSell {
+    int64_t *lsp = nullptr, *usp = nullptr;   // n_slices + 1
+    int32_t *lcol = nullptr, *ucol = nullptr;
+    double *lval = nullptr, *uval = nullptr;
+    double *udiag = nullptr;                  // n
+};
+
+// Copies the factors of rows [0, n) from CSR (lu) into the sliced arrays.
+__global__ __launch_bounds__(BLOCK) void k_ilu_to_sell(int64_t n, const int32_t *__restrict__ rp,
+                                                       const int32_t *__restrict__ ci,
+                                                       const double *__restrict__ lu,
+                                                       const int32_t *__restrict__ dpos, IluSell f)
+{
+    for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < n; i += (int64_t)gridDim.x * BLOCK) {
+        const int32_t b = rp[i], d = dpos[i], e = rp[i + 1];
+        const int64_t lb = f.lsp[i / SLICE] + (i % SLICE), ub = f.usp[i / SLICE] + (i % SLICE);
+        for (int32_t k = b; k < d; ++k) {
+            f.lcol[lb + (int64_t)(k - b) * SLICE] = ci[k];
+            f.lval[lb + (int64_t)(k - b) * SLICE] = lu[k];
+        }
+        for (int32_t k = d + 1; k < e; ++k) {
+            f.ucol[ub + (int64_t)(k - d - 1) * SLICE] = ci[k];
+            f.uval[ub + (int64_t)(k - d - 1) * SLICE] = lu[k];
+        }
+        f.udiag[i] = lu[d];
+    }
+}
+
+// Rows [r0, r1) of y := L^-1 y in place from the sliced factors: the same
+// operations in the same order as k_ilu_lower_rows.
+__global__ __launch_bounds__(BLOCK) void k_ilu_lower_sell(int64_t r0, int64_t r1, const int32_t *__restrict__ rp,
+                                                          const int32_t *__restrict__ dpos, IluSell f, double *y)
+{
+#pragma clang fp contract(off)
+    for (int64_t i = r0 + (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < r1;
+         i += (int64_t)gridDim.x * BLOCK) {
+        double acc = y[i];
+        const int32_t len = dpos[i] - rp[i];
+        const int64_t base = f.lsp[i / SLICE] + (i % SLICE);
+        for (int32_t j = 0; j < len; ++j) {
+            const int64_t k = base + (int64_t)j * SLICE;
+            acc = acc - f.lval[k] * y[f.lcol[k]];
+        }
+        y[i] = acc;
+    }
+}
+
+// Rows [r0, r1) of x := U^-1 z from the sliced factors: the same operations
+// in the same order as k_ilu_upper_rows.
+__global__ __launch_bounds__(BLOCK) void k_ilu_upper_sell(int64_t r0, int64_t r1, const int32_t *__restrict__ rp,
+                                                          const int32_t *__restrict__ dpos, IluSell f,
+                                                          const double *__restrict__ z, double *x)
+{
+#pragma clang fp contract(off)
+    for (int64_t i = r0 + (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < r1;
+         i += (int64_t)gridDim.x * BLOCK) {
+        double acc = z[i];
+        const int32_t len = rp[i + 1] - dpos[i] - 1;
+        const int64_t base = f.usp[i / SLICE] + (i % SLICE);
+        for (int32_t j = 0; j < len; ++j) {
+            const int64_t k = base + (int64_t)j * SLICE;
+            acc = acc - f.uval[k] * x[f.ucol[k]];
+        }
+        x[i] = acc / f.udiag[i];
+    }
+}
+
+}  // namespace mstab

@@ -682,6 +682,7 @@ struct IluData {
     int32_t *dpos = nullptr;                       // position of each row's diagonal
     std::vector<int64_t> cp;                       // first row of each colour, and n
     double *t1 = nullptr, *t2 = nullptr;           // scratch vectors of the operator
+    IluSell f;                                     // the factors sliced, for the solves
 
     int colours() const { return (int)cp.size() - 1; }
     // x := U^-1 z, colour by colour from the last (z and x distinct)
@@ -689,8 +690,8 @@ struct IluData {
     {
         for (int c = colours() - 1; c >= 0; --c) {
             const int64_t rows = cp[c + 1] - cp[c];
-            hipLaunchKernelGGL(k_ilu_upper_rows, dim3(grid_for(rows, BLOCK, VEC_MAX_BLOCKS)), dim3(BLOCK), 0,
-                               st, cp[c], cp[c + 1], rp, ci, (const double *)lu, (const int32_t *)dpos, z, x);
+            hipLaunchKernelGGL(k_ilu_upper_sell, dim3(grid_for(rows, BLOCK, VEC_MAX_BLOCKS)), dim3(BLOCK), 0,
+                               st, cp[c], cp[c + 1], rp, (const int32_t *)dpos, f, z, x);
             HIPCHK(hipGetLastError());
         }
     }
@@ -699,10 +700,44 @@ struct IluData {
     {
         for (int c = 1; c < colours(); ++c) {
             const int64_t rows = cp[c + 1] - cp[c];
-            hipLaunchKernelGGL(k_ilu_lower_rows, dim3(grid_for(rows, BLOCK, VEC_MAX_BLOCKS)), dim3(BLOCK), 0,
-                               st, cp[c], cp[c + 1], rp, ci, (const double *)lu, (const int32_t *)dpos, y);
+            hipLaunchKernelGGL(k_ilu_lower_sell, dim3(grid_for(rows, BLOCK, VEC_MAX_BLOCKS)), dim3(BLOCK), 0,
+                               st, cp[c], cp[c + 1], rp, (const int32_t *)dpos, f, y);
             HIPCHK(hipGetLastError());
         }
+    }
+    // the sliced copies of the factors (host row pointer and diagonal
+    // positions; lu final on the device)
+    void make_sell(const std::vector<int32_t> &hrp, const std::vector<int32_t> &hdpos, hipStream_t st)
+    {
+        const int64_t ns = (n + SLICE - 1) / SLICE;
+        std::vector<int64_t> lsp((size_t)ns + 1, 0), usp((size_t)ns + 1, 0);
+        for (int64_t t = 0; t < ns; ++t) {
+            int64_t lw = 0, uw = 0;
+            for (int64_t r = t * SLICE; r < std::min(n, (t + 1) * SLICE); ++r) {
+                lw = std::max<int64_t>(lw, hdpos[r] - hrp[r]);
+                uw = std::max<int64_t>(uw, hrp[r + 1] - hdpos[r] - 1);
+            }
+            lsp[t + 1] = lsp[t] + lw * SLICE;
+            usp[t + 1] = usp[t] + uw * SLICE;
+        }
+        const size_t ln = (size_t)std::max<int64_t>(lsp[ns], 1), un = (size_t)std::max<int64_t>(usp[ns], 1);
+        HIPCHK(hipMalloc(&f.lsp, sizeof(int64_t) * (ns + 1)));
+        HIPCHK(hipMalloc(&f.usp, sizeof(int64_t) * (ns + 1)));
+        HIPCHK(hipMalloc(&f.lcol, sizeof(int32_t) * ln));
+        HIPCHK(hipMalloc(&f.ucol, sizeof(int32_t) * un));
+        HIPCHK(hipMalloc(&f.lval, sizeof(double) * ln));
+        HIPCHK(hipMalloc(&f.uval, sizeof(double) * un));
+        HIPCHK(hipMalloc(&f.udiag, sizeof(double) * (size_t)n));
+        HIPCHK(hipMemsetAsync(f.lcol, 0, sizeof(int32_t) * ln, st));
+        HIPCHK(hipMemsetAsync(f.ucol, 0, sizeof(int32_t) * un, st));
+        HIPCHK(hipMemsetAsync(f.lval, 0, sizeof(double) * ln, st));
+        HIPCHK(hipMemsetAsync(f.uval, 0, sizeof(double) * un, st));
+        HIPCHK(hipMemcpyAsync(f.lsp, lsp.data(), sizeof(int64_t) * (ns + 1), hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(f.usp, usp.data(), sizeof(int64_t) * (ns + 1), hipMemcpyHostToDevice, st));
+        hipLaunchKernelGGL(k_ilu_to_sell, dim3(grid_for(n, BLOCK, VEC_MAX_BLOCKS)), dim3(BLOCK), 0, st, n, rp, ci,
+                           (const double *)lu, (const int32_t *)dpos, f);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipStreamSynchronize(st));   // the host slice pointers go out of scope
     }
     void upper_mul(const double *x, double *y, hipStream_t st) const
     {
@@ -714,6 +749,9 @@ struct IluData {
     {
         (void)hipFree(lu); (void)hipFree(dpos); (void)hipFree(t1); (void)hipFree(t2);
         lu = nullptr; dpos = nullptr; t1 = t2 = nullptr;
+        (void)hipFree(f.lsp); (void)hipFree(f.usp); (void)hipFree(f.lcol); (void)hipFree(f.ucol);
+        (void)hipFree(f.lval); (void)hipFree(f.uval); (void)hipFree(f.udiag);
+        f = IluSell{};
     }
 };
 
@@ -2216,6 +2254,7 @@ mstab_status mstab_create(const mstab_csr *A, int32_t s, int32_t ell, const msta
             HIPCHK(e);
             HIPCHK(se);
             if (hbad) fail(MSTAB_E_INVALID, "ILU(0): a zero or non-finite pivot");
+            L.make_sell(prp, dpos, h->stream);
         }
         HIPCHK(hipStreamSynchronize(h->stream));   // the host vectors go out of scope
         h->rp = h->rp_perm;
