@@ -133,7 +133,8 @@ def c3_leg(torch, ms, n, systems):
     per node, s = 8, l = 4): the first `systems` systems of its sequence in
     FP64 and in the two FP32 forms, each with and without the split diagonal
     preconditioning that Section 5.1 pairs with the method; error of each
-    FP32 form's last x against the FP64 path's (the FP64 oracle needs hours
+    FP32 form's last x against the FP64 path's, and the FP64 path with the
+    ILU(0) splitting of a multicolour order (the FP64 oracle needs hours
     at this size; the tests state the error against it on the same workload
     at 14^3-48^3)."""
     from paper_1604_06043_amd import inputs as I
@@ -144,10 +145,11 @@ def c3_leg(torch, ms, n, systems):
     s, ell = 8, 4
     out = {"workload": f"convdiff3d_{n}cubed_pe200_lognormal_kappa_{systems}rhs", "N": cd.N, "s": s,
            "ell": ell, "tol": 1e-8, "systems_per_step": systems}
-    for pc_name, pc in (("none", ms.PRECOND_NONE), ("jacobi", ms.PRECOND_JACOBI)):
+    for pc_name, pc in (("none", ms.PRECOND_NONE), ("jacobi", ms.PRECOND_JACOBI), ("ilu0", ms.PRECOND_ILU0)):
         x64 = None
-        for key, prec in (("f64", ms.PREC_F64), ("f32_matrix", ms.PREC_F32_MATRIX),
-                          ("f32_refine", ms.PREC_F32_REFINE)):
+        forms = (("f64", ms.PREC_F64), ("f32_matrix", ms.PREC_F32_MATRIX), ("f32_refine", ms.PREC_F32_REFINE))
+        # the ILU(0) splitting runs in FP64 only
+        for key, prec in forms[:1] if pc == ms.PRECOND_ILU0 else forms:
             sv = ms.Solver(A, s, ell, p_seed=0, precision=prec, precond=pc)
             run_sequence(torch, ms, sv, cd, f, 1)             # warm-up
             torch.cuda.synchronize()
