@@ -276,6 +276,7 @@ def main():
     ap.add_argument("--n", type=int, default=None)
     ap.add_argument("--N", type=int, default=1 << 22)
     ap.add_argument("--systems", type=int, default=None)
+    ap.add_argument("--B", type=int, default=None, help="wgbatch: one batch size only")
     a = ap.parse_args()
     import torch
     torch.cuda.set_device(0)
@@ -299,7 +300,7 @@ def main():
             log(f"[batch] {B} sequences: {r['systems_per_s']:.0f} systems/s, {r['mvs_per_system']:.1f} MVs/system")
             print(json.dumps(r), flush=True)
     elif a.which == "wgbatch":
-        for B in (1, 8, 64, 256, 512, 1024, 2048):
+        for B in ((a.B,) if a.B else (1, 8, 64, 256, 512, 1024, 2048)):
             batch_workgroup(min(B, 64), 1)   # warm-up
             r = batch_workgroup(B, a.systems or 10)
             log(f"[wgbatch] {B} sequences: {r['systems_per_s']:.0f} systems/s, "
