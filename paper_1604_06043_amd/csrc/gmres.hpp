@@ -5,9 +5,9 @@
 //
 // Arnoldi step j: w = A v_j (the product kernels, no projection state), then
 // classical Gram-Schmidt applied twice: c = V^T w over the basis vectors in
-// chunks of up to 8 (k_gm_dots), w -= V c element by element in basis order
-// (k_gm_axpy), again, then ||w||^2; k_gm_column sums the two passes'
-// coefficients into the Hessenberg column, rotates it by the cycle's earlier
+// chunks of up to 32 (k_gm_dots), w -= V c element by element in basis order
+// (k_gm_axpy), again, the second update also reducing ||w||^2; k_gm_column
+// sums the two passes' coefficients into the Hessenberg column, rotates it by the cycle's earlier
 // Givens rotations, forms the new rotation and updates g, whose entry j+1 is
 // the residual norm of the least-squares solution.  At the cycle's end
 // k_gm_solve back-substitutes the rotated triangular system and k_gm_axpy adds
@@ -34,52 +34,69 @@ struct GmLayout {
     __host__ __device__ int64_t size() const { return scal() + GM_SCAL; }
 };
 
-// out[j0 + i] = v_{j0+i} . w (i < nv <= 8) and, in slot 8, ||w||^2 into
-// ctl->st.aux.  Workgroup partials, the last workgroup's fixed-order totals.
-template <typename T>
+// Basis vectors a launch of k_gm_dots or k_gm_axpy covers at most; the
+// kernels come in widths CH = 8 and 32 (the narrow one for the first steps of
+// a cycle and short restarts: fewer registers, more wavefronts per SIMD).
+constexpr int GM_CHUNK = 32;
+
+// out[j0 + i] = v_{j0+i} . w (i < nv <= CH) and ||w||^2 into ctl->st.aux.
+// Workgroup partials, the last workgroup's fixed-order totals.
+template <typename T, int CH>
 __global__ __launch_bounds__(BLOCK) void k_gm_dots(int64_t ld, const T *__restrict__ V, int j0, int nv,
                                                    const T *__restrict__ w, double *out, Ctl *ctl,
                                                    double *part, int stride)
 {
     if (ctl->st.flags) return;
-    double acc[MAXS + 1];
+    double acc[CH + 1];
 #pragma unroll
-    for (int v = 0; v <= MAXS; ++v) acc[v] = 0.0;
+    for (int v = 0; v <= CH; ++v) acc[v] = 0.0;
     const T *V0 = V + (int64_t)j0 * ld;
     for (int64_t e = (int64_t)blockIdx.x * BLOCK + threadIdx.x; e < ld; e += (int64_t)gridDim.x * BLOCK) {
         const double wv = (double)w[e];
 #pragma unroll
-        for (int i = 0; i < MAXS; ++i)
+        for (int i = 0; i < CH; ++i)
             if (i < nv) acc[i] += (double)V0[(int64_t)i * ld + e] * wv;
-        acc[MAXS] += wv * wv;
+        acc[CH] += wv * wv;
     }
-    block_partials<MAXS + 1>(acc, MAXS + 1, part, stride);
-    __shared__ double tot[MAXS + 1];
-    if (!last_block_reduce(part, stride, MAXS + 1, &ctl->counter[3], tot)) return;
+    block_partials<CH + 1>(acc, CH + 1, part, stride);
+    __shared__ double tot[CH + 1];
+    if (!last_block_reduce(part, stride, CH + 1, &ctl->counter[3], tot)) return;
     if (threadIdx.x != 0) return;
     for (int i = 0; i < nv; ++i) out[j0 + i] = tot[i];
-    ctl->st.aux = tot[MAXS];
-    if (!isfinite(tot[MAXS])) ctl->st.flags |= FLAG_NONFINITE;
+    ctl->st.aux = tot[CH];
+    if (!isfinite(tot[CH])) ctl->st.flags |= FLAG_NONFINITE;
 }
 
-// w += sign * sum_{i<nv} coef[j0+i] v_{j0+i}, one fused multiply-add per
-// basis vector in basis order
-template <typename T>
+// w += sign * sum_{i<nv} coef[j0+i] v_{j0+i} (nv <= CH), one fused
+// multiply-add per basis vector in basis order.  With norm, also ||w||^2 of
+// the updated w into ctl->st.aux (the second Gram-Schmidt pass's last chunk:
+// the norm that gives h_{j+1,j}), as k_gm_dots reduces it.
+template <typename T, int CH>
 __global__ __launch_bounds__(BLOCK) void k_gm_axpy(int64_t ld, const T *__restrict__ V, int j0, int nv,
-                                                   const double *coef, double sign, T *w, const Ctl *ctl)
+                                                   const double *coef, double sign, T *w, Ctl *ctl, int norm,
+                                                   double *part, int stride)
 {
     if (ctl->st.flags) return;
-    T c[MAXS];
+    T c[CH];
 #pragma unroll
-    for (int i = 0; i < MAXS; ++i) c[i] = (i < nv) ? (T)(sign * coef[j0 + i]) : (T)0;
+    for (int i = 0; i < CH; ++i) c[i] = (i < nv) ? (T)(sign * coef[j0 + i]) : (T)0;
     const T *V0 = V + (int64_t)j0 * ld;
+    double acc[1] = {0.0};
     for (int64_t e = (int64_t)blockIdx.x * BLOCK + threadIdx.x; e < ld; e += (int64_t)gridDim.x * BLOCK) {
         T a = w[e];
 #pragma unroll
-        for (int i = 0; i < MAXS; ++i)
+        for (int i = 0; i < CH; ++i)
             if (i < nv) a = fmaT(c[i], V0[(int64_t)i * ld + e], a);
         w[e] = a;
+        acc[0] += (double)a * (double)a;
     }
+    if (!norm) return;
+    block_partials<1>(acc, 1, part, stride);
+    __shared__ double tot[1];
+    if (!last_block_reduce(part, stride, 1, &ctl->counter[3], tot)) return;
+    if (threadIdx.x != 0) return;
+    ctl->st.aux = tot[0];
+    if (!isfinite(tot[0])) ctl->st.flags |= FLAG_NONFINITE;
 }
 
 // Start of a cycle: beta = sqrt(||r||^2) (st.tt of the true-residual product),

@@ -1289,6 +1289,16 @@ struct Engine {
         int64_t mv = 0, cycles = 0;
         double nb = 0.0, thr = 0.0, est = -1.0;
         double scal[GM_SCAL];
+        // w += sign V[:, j0:j0+nv] coef[j0:j0+nv] (and ||w||^2 with norm)
+        auto axpy = [&](int j0, int nv, const double *coef, double sign, T *y, int norm) {
+            if (nv <= 8)
+                hipLaunchKernelGGL((k_gm_axpy<T, 8>), dim3(norm ? gd : gv), dim3(BLOCK), 0, stream, ld,
+                                   (const T *)gmV, j0, nv, coef, sign, y, ctl, norm, part, PART_STRIDE);
+            else
+                hipLaunchKernelGGL((k_gm_axpy<T, GM_CHUNK>), dim3(norm ? gd : gv), dim3(BLOCK), 0, stream, ld,
+                                   (const T *)gmV, j0, nv, coef, sign, y, ctl, norm, part, PART_STRIDE);
+            HIPCHK(hipGetLastError());
+        };
         small(SMALL_CLEAR);
         for (;;) {
             // the true residual into v_1
@@ -1329,22 +1339,23 @@ struct Engine {
                 ++res.cycles;
                 for (int pass = 0; pass < 2; ++pass) {
                     double *c = gm_state + L.c(pass);
-                    for (int j0 = 0; j0 <= j; j0 += MAXS) {
-                        const int nv = std::min(MAXS, j + 1 - j0);
-                        hipLaunchKernelGGL((k_gm_dots<T>), dim3(gd), dim3(BLOCK), 0, stream, ld, (const T *)gmV,
-                                           j0, nv, (const T *)w, c, ctl, part, PART_STRIDE);
+                    for (int j0 = 0; j0 <= j; j0 += GM_CHUNK) {
+                        const int nv = std::min(GM_CHUNK, j + 1 - j0);
+                        if (nv <= 8)
+                            hipLaunchKernelGGL((k_gm_dots<T, 8>), dim3(gd), dim3(BLOCK), 0, stream, ld,
+                                               (const T *)gmV, j0, nv, (const T *)w, c, ctl, part, PART_STRIDE);
+                        else
+                            hipLaunchKernelGGL((k_gm_dots<T, GM_CHUNK>), dim3(gd), dim3(BLOCK), 0, stream, ld,
+                                               (const T *)gmV, j0, nv, (const T *)w, c, ctl, part, PART_STRIDE);
                         HIPCHK(hipGetLastError());
                     }
-                    for (int j0 = 0; j0 <= j; j0 += MAXS) {
-                        const int nv = std::min(MAXS, j + 1 - j0);
-                        hipLaunchKernelGGL((k_gm_axpy<T>), dim3(gv), dim3(BLOCK), 0, stream, ld, (const T *)gmV,
-                                           j0, nv, (const double *)c, -1.0, w, (const Ctl *)ctl);
-                        HIPCHK(hipGetLastError());
+                    for (int j0 = 0; j0 <= j; j0 += GM_CHUNK) {
+                        const int nv = std::min(GM_CHUNK, j + 1 - j0);
+                        // the last update of the second pass also gives ||w||^2
+                        const int norm = pass == 1 && j0 + GM_CHUNK > j;
+                        axpy(j0, nv, c, -1.0, w, norm);
                     }
                 }
-                hipLaunchKernelGGL((k_gm_dots<T>), dim3(gd), dim3(BLOCK), 0, stream, ld, (const T *)gmV, 0, 0,
-                                   (const T *)w, gm_state + L.c(0), ctl, part, PART_STRIDE);
-                HIPCHK(hipGetLastError());
                 hipLaunchKernelGGL(k_gm_column, dim3(1), dim3(64), 0, stream, gm_state, m, j, (const Ctl *)ctl);
                 HIPCHK(hipGetLastError());
                 HIPCHK(hipMemcpyAsync(scal, gm_state + L.scal(), sizeof scal, hipMemcpyDeviceToHost, stream));
@@ -1363,12 +1374,8 @@ struct Engine {
             if (k == 0) { res.status = MSTAB_E_BREAKDOWN; break; }
             hipLaunchKernelGGL(k_gm_solve, dim3(1), dim3(64), 0, stream, gm_state, m, k);
             HIPCHK(hipGetLastError());
-            for (int j0 = 0; j0 < k; j0 += MAXS) {
-                const int nv = std::min(MAXS, k - j0);
-                hipLaunchKernelGGL((k_gm_axpy<T>), dim3(gv), dim3(BLOCK), 0, stream, ld, (const T *)gmV, j0, nv,
-                                   (const double *)(gm_state + L.y()), 1.0, X, (const Ctl *)ctl);
-                HIPCHK(hipGetLastError());
-            }
+            for (int j0 = 0; j0 < k; j0 += GM_CHUNK)
+                axpy(j0, std::min(GM_CHUNK, k - j0), gm_state + L.y(), 1.0, X, 0);
             ++cycles;
         }
         if (res.status == MSTAB_OK && !res.converged) res.status = MSTAB_NOT_CONVERGED;
@@ -1817,8 +1824,10 @@ mstab_status wg_run(mstab_solver *const *h, int count, const double *const *b, d
         J.b = b[i]; J.x = x[i];
         J.W = E.W; J.R = E.R; J.T = E.Tv;
         J.recU = E.recU; J.recV = E.recV; J.rec_ptv = E.rec_ptv;
-        J.hist_mv = h0->wg_hmv + (size_t)p * wg::HIST;
-        J.hist_res = h0->wg_hres + (size_t)p * wg::HIST;
+        // entry k of job p at k * count + p: the first entries of all jobs lie together
+        J.hist_mv = h0->wg_hmv + p;
+        J.hist_res = h0->wg_hres + p;
+        J.hist_stride = count;
         J.n = hi->n; J.ld = E.ld;
         J.max_mv = hi->opt.max_mv; J.fetch_level = hi->opt.fetch_level;
         J.tol = hi->opt.tol; J.fetch_rel = hi->opt.fetch_rel;
@@ -1848,11 +1857,17 @@ mstab_status wg_run(mstab_solver *const *h, int count, const double *const *b, d
         HIPCHK(hipGetLastError());
         p0 = p1;
     }
-    std::vector<int64_t> hmv((size_t)count * wg::HIST);
-    std::vector<double> hres((size_t)count * wg::HIST);
     HIPCHK(hipMemcpyAsync(jobs.data(), h0->wg_jobs, sizeof(wg::Job) * (size_t)count, hipMemcpyDeviceToHost, st));
-    HIPCHK(hipMemcpyAsync(hmv.data(), h0->wg_hmv, sizeof(int64_t) * hmv.size(), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipMemcpyAsync(hres.data(), h0->wg_hres, sizeof(double) * hres.size(), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    // the histories: only the entries some job filled (one contiguous block)
+    int64_t width = 1;
+    for (int p = 0; p < count; ++p) width = std::max(width, std::min<int64_t>(jobs[(size_t)p].hist_len, wg::HIST));
+    std::vector<int64_t> hmv((size_t)(width * count));
+    std::vector<double> hres((size_t)(width * count));
+    HIPCHK(hipMemcpyAsync(hmv.data(), h0->wg_hmv, sizeof(int64_t) * (size_t)(width * count), hipMemcpyDeviceToHost,
+                          st));
+    HIPCHK(hipMemcpyAsync(hres.data(), h0->wg_hres, sizeof(double) * (size_t)(width * count), hipMemcpyDeviceToHost,
+                          st));
     HIPCHK(hipStreamSynchronize(st));
     const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     mstab_status worst = MSTAB_OK;
@@ -1865,8 +1880,12 @@ mstab_status wg_run(mstab_solver *const *h, int count, const double *const *b, d
         E.rec_level = J.rec_level;
         E.est_cycle = J.est_cycle;
         const int64_t kept = std::min<int64_t>(J.hist_len, wg::HIST);
-        hi->hist_mv.assign(hmv.begin() + (size_t)p * wg::HIST, hmv.begin() + (size_t)p * wg::HIST + kept);
-        hi->hist_res.assign(hres.begin() + (size_t)p * wg::HIST, hres.begin() + (size_t)p * wg::HIST + kept);
+        hi->hist_mv.resize((size_t)kept);
+        hi->hist_res.resize((size_t)kept);
+        for (int64_t k = 0; k < kept; ++k) {
+            hi->hist_mv[(size_t)k] = hmv[(size_t)(k * count + p)];
+            hi->hist_res[(size_t)k] = hres[(size_t)(k * count + p)];
+        }
         hi->hist_mv_all.push_back(hi->hist_mv);
         hi->hist_res_all.push_back(hi->hist_res);
         SolveResult r;

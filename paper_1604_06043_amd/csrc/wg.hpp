@@ -45,8 +45,9 @@ struct Job {
     double *x;                          // x0 in, x out (n entries)
     double *W, *R, *T;                  // s(l+2), l+1 and 1 vectors of ld entries
     double *recU, *recV, *rec_ptv;      // recycle store (s vectors each; MAXS x MAXS)
-    int64_t *hist_mv;                   // HIST entries
+    int64_t *hist_mv;                   // HIST entries, hist_stride apart
     double *hist_res;
+    int64_t hist_stride;
     int64_t n, ld, max_mv, fetch_level;
     double tol, fetch_rel;
     uint32_t pkey;
@@ -784,8 +785,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MSTAB_WG_WAV
     int64_t est_k = -1;
     auto hist = [&](int64_t m, double res) {
         if (threadIdx.x == 0 && hl < HIST) {
-            J.hist_mv[hl] = m;
-            J.hist_res[hl] = res;
+            J.hist_mv[hl * J.hist_stride] = m;
+            J.hist_res[hl * J.hist_stride] = res;
         }
         if (hl >= 1) {
             const double f = res > 0.0 ? est_prev / res : INFINITY;

@@ -239,6 +239,40 @@ def solve_batch(solvers, bs, xs) -> list:
     return [i.as_dict() for i in infos]
 
 
+class Batch:
+    """The argument arrays of mstab_solve_batch prepared once for a fixed set
+    of solvers and vectors (b[i], x[i] device tensors that stay in place), so
+    that a time loop over thousands of handles marshals nothing per step.
+    run() returns the mstab_info array; fields() gives one field of every
+    entry as a NumPy array."""
+
+    def __init__(self, solvers, bs, xs):
+        n = len(solvers)
+        if not (len(bs) == len(xs) == n):
+            raise ValueError("solvers, bs and xs differ in length")
+        _require_cuda(*bs, *xs)
+        P = ctypes.c_void_p
+        self.n = n
+        self.keep = (list(solvers), list(bs), list(xs))
+        self.hs = (P * n)(*[sv.h for sv in solvers])
+        self.bp = (P * n)(*[b.data_ptr() for b in bs])
+        self.xp = (P * n)(*[x.data_ptr() for x in xs])
+        self.infos = (mstab_info * n)()
+
+    def run(self):
+        st = load().mstab_solve_batch(self.hs, self.n, self.bp, self.xp, self.infos)
+        _check(st, None, allow=(OK, NOT_CONVERGED))
+        return self.infos
+
+    def field(self, name: str):
+        import numpy as np
+        f = getattr(mstab_info, name)
+        ct = dict(mstab_info._fields_)[name]
+        dt = np.int32 if ct is ctypes.c_int32 else (np.int64 if ct is ctypes.c_int64 else np.float64)
+        raw = np.frombuffer(self.infos, dtype=np.uint8).reshape(self.n, ctypes.sizeof(mstab_info))
+        return raw[:, f.offset:f.offset + np.dtype(dt).itemsize].copy().view(dt).ravel()
+
+
 def mstab_rcm_order(row_ptr, col_idx):
     """Reverse Cuthill-McKee order (perm[new] = old) of a host CSR pattern (NumPy int32)."""
     import numpy as np

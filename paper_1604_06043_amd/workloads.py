@@ -208,14 +208,15 @@ def batch_workgroup(B: int, systems: int = 10, n: int = 64, s: int = 4, ell: int
     X = torch.zeros((B, N), dtype=torch.float64, device="cuda")
     Bv = torch.empty_like(X)
     xs, bs = [X[i] for i in range(B)], [Bv[i] for i in range(B)]
+    batch = M.Batch(solvers, bs, xs)
     torch.cuda.synchronize()
     mv, t0 = 0, time.perf_counter()
     for _ in range(systems):
         M.mstab_rhs_step(X.view(-1), inv_dt, F.view(-1), Bv.view(-1))
-        infos = M.solve_batch(solvers, bs, xs)
-        if not all(i["converged"] for i in infos):
+        batch.run()
+        if not batch.field("converged").all():
             raise RuntimeError("a batched system did not converge")
-        mv += sum(i["mv_total"] for i in infos)
+        mv += int(batch.field("mv").sum() + batch.field("mv_check").sum())
     torch.cuda.synchronize()
     sec = time.perf_counter() - t0
     for sv in solvers:
