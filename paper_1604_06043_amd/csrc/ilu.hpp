@@ -199,3 +199,80 @@ __global__ __launch_bounds__(BLOCK) void k_ilu_upper_sell(int64_t r0, int64_t r1
 }
 
 }  // namespace mstab
+
+namespace mstab {
+
+// Eisenstat's form of the split operator.  Where ILU(0) modifies no
+// off-diagonal entry (no k < min(i, j) couples rows i and j through both
+// (i, k) and (k, j): a pattern without triangles, such as the 5- and 7-point
+// stencils), the factors are L = I + L_A D_U^-1 and U = D_U + U_A with L_A, U_A
+// the strictly lower and upper parts of A' and D_U the pivots, and
+//   L^-1 A' U^-1 x = L^-1 (x + (D_A - 2 D_U) t) + D_U t,   t = U^-1 x
+// (A' t = L_A t + D_A t + U_A t with U_A t = x - D_U t, and
+// L^-1 L_A D_U^-1 = I - L^-1): the two triangular solves and no product with A'.
+// Equal to the three-step form in exact arithmetic; rounded differently.
+
+// *bad (zero beforehand) is set if some factor entry is not the one the
+// form assumes: a strictly upper entry different from A''s, or a strictly
+// lower one different from a_ik / u_kk (the factorization's own division).
+__global__ __launch_bounds__(BLOCK) void k_ilu_check_eis(int64_t n, const int32_t *__restrict__ rp,
+                                                         const int32_t *__restrict__ ci,
+                                                         const double *__restrict__ va,
+                                                         const double *__restrict__ lu,
+                                                         const int32_t *__restrict__ dpos, int *bad)
+{
+#pragma clang fp contract(off)
+    for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < n; i += (int64_t)gridDim.x * BLOCK) {
+        const int32_t d = dpos[i];
+        bool ok = true;
+        for (int32_t k = rp[i]; k < d; ++k) ok = ok && (lu[k] == va[k] / lu[dpos[ci[k]]]);
+        for (int32_t k = d + 1; k < rp[i + 1]; ++k) ok = ok && (lu[k] == va[k]);
+        if (!ok) __hip_atomic_store(bad, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+// dd = D_A - 2 D_U, du = D_U
+__global__ __launch_bounds__(BLOCK) void k_ilu_eis_diag(int64_t n, const double *__restrict__ va,
+                                                        const double *__restrict__ lu,
+                                                        const int32_t *__restrict__ dpos, double *dd, double *du)
+{
+#pragma clang fp contract(off)
+    for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < n; i += (int64_t)gridDim.x * BLOCK) {
+        const double u = lu[dpos[i]];
+        dd[i] = va[dpos[i]] - 2.0 * u;
+        du[i] = u;
+    }
+}
+
+// w = x + dd t
+__global__ __launch_bounds__(BLOCK) void k_ilu_eis_mid(int64_t n, const double *__restrict__ x,
+                                                       const double *__restrict__ t,
+                                                       const double *__restrict__ dd, double *__restrict__ w)
+{
+#pragma clang fp contract(off)
+    for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < n; i += (int64_t)gridDim.x * BLOCK)
+        w[i] = x[i] + dd[i] * t[i];
+}
+
+// The end of an Eisenstat-form product: y = v + du t (or b minus that for
+// the residual roles), then the projection epilogue and the role's small
+// solve, as k_vec_out.
+template <typename T, int S>
+__global__ __launch_bounds__(SPMV_BLOCK) void k_vec_out_eis(int64_t n, const T *__restrict__ v,
+                                                            const T *__restrict__ t, const T *__restrict__ du,
+                                                            const T *__restrict__ b, T *__restrict__ y,
+                                                            Ctl *ctl, double *part, int stride, SpmvArgs a)
+{
+#pragma clang fp contract(off)
+    if (ctl->st.flags) return;
+    const bool resid = (a.act == ACT_RESID || a.act == ACT_TRUE);
+    double vals[S + 2];
+#pragma unroll
+    for (int q = 0; q < S + 2; ++q) vals[q] = 0.0;
+    for (int64_t r = (int64_t)blockIdx.x * SPMV_BLOCK + threadIdx.x; r < n;
+         r += (int64_t)gridDim.x * SPMV_BLOCK)
+        spmv_row_out<T, S>(r, v[r] + du[r] * t[r], resid, b, y, a.pkey, vals);
+    spmv_finalize<S>(vals, ctl, part, stride, a);
+}
+
+}  // namespace mstab

@@ -683,6 +683,9 @@ struct IluData {
     std::vector<int64_t> cp;                       // first row of each colour, and n
     double *t1 = nullptr, *t2 = nullptr;           // scratch vectors of the operator
     IluSell f;                                     // the factors sliced, for the solves
+    // Eisenstat's form (the factors' off-diagonals are A''s): D_A - 2 D_U and D_U
+    bool eis = false;
+    double *dd = nullptr, *du = nullptr;
 
     int colours() const { return (int)cp.size() - 1; }
     // x := U^-1 z, colour by colour from the last (z and x distinct)
@@ -752,6 +755,9 @@ struct IluData {
         (void)hipFree(f.lsp); (void)hipFree(f.usp); (void)hipFree(f.lcol); (void)hipFree(f.ucol);
         (void)hipFree(f.lval); (void)hipFree(f.uval); (void)hipFree(f.udiag);
         f = IluSell{};
+        (void)hipFree(dd); (void)hipFree(du);
+        dd = du = nullptr;
+        eis = false;
     }
 };
 
@@ -872,9 +878,38 @@ struct Engine {
     }
 
     // y = L^-1 A U^-1 x (or b - that), then the product's epilogue for `act`
+    template <int S>
+    void vec_out_eis_s(int grid, const T *v, const T *t, const T *du, const T *b, T *y, const SpmvArgs &a)
+    {
+        hipLaunchKernelGGL((k_vec_out_eis<T, S>), dim3(grid), dim3(SPMV_BLOCK), 0, stream, n, v, t, du, b, y, ctl,
+                           part, PART_STRIDE, a);
+    }
+
     void ilu_product(const T *x, T *y, const T *b, const SpmvArgs &a)
     {
         if constexpr (sizeof(T) == 8) {
+            if (ilu->eis) {
+                // Eisenstat's form: t1 = U^-1 x, t2 = L^-1 (x + dd t1), y = t2 + du t1
+                ilu->upper_solve(x, ilu->t1, stream);
+                hipLaunchKernelGGL(k_ilu_eis_mid, dim3(grid_for(n, BLOCK, VEC_MAX_BLOCKS)), dim3(BLOCK), 0, stream,
+                                   n, x, (const double *)ilu->t1, (const double *)ilu->dd, ilu->t2);
+                HIPCHK(hipGetLastError());
+                ilu->lower_solve(ilu->t2, stream);
+                const int grid = grid_for(n, SPMV_BLOCK, SPMV_MAX_BLOCKS);
+                const T *t1 = ilu->t1, *t2 = ilu->t2, *du = ilu->du;
+                switch (s) {
+                case 1: vec_out_eis_s<1>(grid, t2, t1, du, b, y, a); break;
+                case 2: vec_out_eis_s<2>(grid, t2, t1, du, b, y, a); break;
+                case 3: vec_out_eis_s<3>(grid, t2, t1, du, b, y, a); break;
+                case 4: vec_out_eis_s<4>(grid, t2, t1, du, b, y, a); break;
+                case 5: vec_out_eis_s<5>(grid, t2, t1, du, b, y, a); break;
+                case 6: vec_out_eis_s<6>(grid, t2, t1, du, b, y, a); break;
+                case 7: vec_out_eis_s<7>(grid, t2, t1, du, b, y, a); break;
+                default: vec_out_eis_s<8>(grid, t2, t1, du, b, y, a); break;
+                }
+                HIPCHK(hipGetLastError());
+                return;
+            }
             ilu->upper_solve(x, ilu->t1, stream);
             SpmvArgs none{ACT_NONE, 0, 0, 0, 1, pkey};
             launch_spmv<T>(grid_for(n, SPMV_BLOCK, SPMV_MAX_BLOCKS), stream, A, ilu->t1, ilu->t2, nullptr,
@@ -900,10 +935,14 @@ struct Engine {
     {
         SpmvArgs a{act, k, q, s, ell, pkey};
         if (ilu) {
-            // factors read twice (lower and upper halves), the product, and the
-            // vectors: x, t1 (write, read), t2 (write, read, write), y (and b)
-            const double lub = 12.0 * (double)ilu->nnz + 8.0 * (double)n;
-            const double bytes = lub + spmv_bytes(A, false, sizeof(T)) + (b ? 8.0 : 6.0) * n * sizeof(T);
+            // the sliced factors (12 B per off-diagonal entry, U's diagonal, the
+            // row pointer and diagonal positions), then either the product and
+            // the vectors x, t1 (write, read), t2 (write, read, write), y (and
+            // b), or (Eisenstat) dd, du and x, t1 (write, 2 reads), t2 (write,
+            // read, write, read), y (and b)
+            const double lub = 12.0 * (double)(ilu->nnz - n) + 8.0 * (double)n + 16.0 * (double)n;
+            const double bytes = ilu->eis ? lub + 16.0 * n + (b ? 10.0 : 9.0) * n * sizeof(T)
+                                          : lub + spmv_bytes(A, false, sizeof(T)) + (b ? 8.0 : 6.0) * n * sizeof(T);
             int slot = prof ? prof->begin(MSTAB_K_SPMV, bytes) : -1;
             ilu_product(x, y, b, a);
             if (prof) prof->end(slot);
@@ -2274,6 +2313,34 @@ mstab_status mstab_create(const mstab_csr *A, int32_t s, int32_t ell, const msta
             HIPCHK(se);
             if (hbad) fail(MSTAB_E_INVALID, "ILU(0): a zero or non-finite pivot");
             L.make_sell(prp, dpos, h->stream);
+            // Eisenstat's form where the factors allow it (no triangles in the pattern)
+            {
+                int *ebad = nullptr;
+                HIPCHK(hipMalloc(&ebad, sizeof(int)));
+                int hb = 1;
+                hipError_t e2 = hipMemsetAsync(ebad, 0, sizeof(int), h->stream);
+                if (e2 == hipSuccess) {
+                    hipLaunchKernelGGL(k_ilu_check_eis, dim3(grid_for(n, BLOCK, VEC_MAX_BLOCKS)), dim3(BLOCK), 0,
+                                       h->stream, n, (const int32_t *)L.rp, (const int32_t *)L.ci,
+                                       (const double *)h->va_perm, (const double *)L.lu,
+                                       (const int32_t *)L.dpos, ebad);
+                    e2 = hipGetLastError();
+                }
+                if (e2 == hipSuccess) e2 = hipMemcpyAsync(&hb, ebad, sizeof(int), hipMemcpyDeviceToHost, h->stream);
+                const hipError_t s2 = hipStreamSynchronize(h->stream);
+                (void)hipFree(ebad);
+                HIPCHK(e2);
+                HIPCHK(s2);
+                if (!hb) {
+                    HIPCHK(hipMalloc(&L.dd, sizeof(double) * (size_t)round_up(n, 256)));
+                    HIPCHK(hipMalloc(&L.du, sizeof(double) * (size_t)round_up(n, 256)));
+                    hipLaunchKernelGGL(k_ilu_eis_diag, dim3(grid_for(n, BLOCK, VEC_MAX_BLOCKS)), dim3(BLOCK), 0,
+                                       h->stream, n, (const double *)h->va_perm, (const double *)L.lu,
+                                       (const int32_t *)L.dpos, L.dd, L.du);
+                    HIPCHK(hipGetLastError());
+                    L.eis = true;
+                }
+            }
         }
         HIPCHK(hipStreamSynchronize(h->stream));   // the host vectors go out of scope
         h->rp = h->rp_perm;
