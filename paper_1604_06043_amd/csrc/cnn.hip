@@ -39,6 +39,7 @@ constexpr int CIN[NL] = {2, 32, 32, 32, 32, 32};
 constexpr int COUT[NL] = {32, 32, 32, 32, 32, 1};
 constexpr int DW_BLOCKS = 1024;  // split-K workgroups of a weight gradient
 constexpr int DW_GROUPS = 8;     // pixel groups of a first/last-layer gradient workgroup
+static_assert(DW_GROUPS < 32, "a pixel group's step must stay below the narrowest row (W >= 32)");
 constexpr int MAX_DIL = 32;      // largest dilation of a layer
 
 constexpr int param_count_layer(int l) { return COUT[l] * CIN[l] * TAPS + COUT[l]; }
@@ -395,17 +396,27 @@ __global__ __launch_bounds__(256) void k_last_bwd_weight(int B, int H, int W, in
 #pragma unroll
     for (int k = 0; k < TAPS; ++k) acc[k] = 0.f;
     float bacc = 0.f;
+    // the row and column of pixel p, advanced by DW_GROUPS < W per step, and
+    // the element offset of each tap from the pixel (a tap inside the image
+    // lies in the pixel's own image; no multiplications per tap)
+    int y = (int)(((p0 + g) / W) % H), x = (int)((p0 + g) % W);
+    int64_t toff[TAPS];
+#pragma unroll
+    for (int tap = 0; tap < TAPS; ++tap) toff[tap] = ((int64_t)(tap / 3 - 1) * d * W + (tap % 3 - 1) * d) * CH;
     for (int64_t p = p0 + g; p < p1; p += DW_GROUPS) {
         const float dv = dout[p];
-        const int64_t img = p / ((int64_t)H * W);
-        const int y = (int)((p / W) % H), x = (int)(p % W);
+        const bf16 *ap = a5 + p * CH + ci;
 #pragma unroll
         for (int tap = 0; tap < TAPS; ++tap) {
             const int yy = y + (tap / 3 - 1) * d, xx = x + (tap % 3 - 1) * d;
-            if (inside(yy, xx, H, W))
-                acc[tap] = fmaf((float)a5[((img * H + yy) * W + xx) * CH + ci], dv, acc[tap]);
+            if (inside(yy, xx, H, W)) acc[tap] = fmaf((float)ap[toff[tap]], dv, acc[tap]);
         }
         bacc += dv;
+        x += DW_GROUPS;
+        if (x >= W) {
+            x -= W;
+            if (++y == H) y = 0;   // the next image
+        }
     }
 #pragma unroll
     for (int tap = 0; tap < TAPS; ++tap) s_acc[g][ci][tap] = acc[tap];
@@ -528,20 +539,30 @@ __global__ __launch_bounds__(256) void k_first_bwd_weight(int B, int H, int W, i
 #pragma unroll
     for (int k = 0; k < 2 * TAPS; ++k) acc[k] = 0.f;
     float bacc = 0.f;
+    // the row and column of pixel p, advanced by DW_GROUPS < W per step, and
+    // the element offset of each tap from the pixel (a tap inside the image
+    // lies in the pixel's own image; no multiplications per tap)
+    int y = (int)(((p0 + g) / W) % H), x = (int)((p0 + g) % W);
+    int64_t toff[TAPS];
+#pragma unroll
+    for (int tap = 0; tap < TAPS; ++tap) toff[tap] = ((int64_t)(tap / 3 - 1) * d * W + (tap % 3 - 1) * d) * 2;
     for (int64_t p = p0 + g; p < p1; p += DW_GROUPS) {
         const float dv = (float)dz0[p * CH + co];
-        const int64_t img = p / ((int64_t)H * W);
-        const int y = (int)((p / W) % H), x = (int)(p % W);
+        const bf16 *ip = in + 2 * p;
 #pragma unroll
         for (int tap = 0; tap < TAPS; ++tap) {
             const int yy = y + (tap / 3 - 1) * d, xx = x + (tap % 3 - 1) * d;
             if (inside(yy, xx, H, W)) {
-                const int64_t q = (img * H + yy) * W + xx;
-                acc[tap * 2] = fmaf((float)in[2 * q], dv, acc[tap * 2]);
-                acc[tap * 2 + 1] = fmaf((float)in[2 * q + 1], dv, acc[tap * 2 + 1]);
+                acc[tap * 2] = fmaf((float)ip[toff[tap]], dv, acc[tap * 2]);
+                acc[tap * 2 + 1] = fmaf((float)ip[toff[tap] + 1], dv, acc[tap * 2 + 1]);
             }
         }
         bacc += dv;
+        x += DW_GROUPS;
+        if (x >= W) {
+            x -= W;
+            if (++y == H) y = 0;   // the next image
+        }
     }
 #pragma unroll
     for (int k = 0; k < 2 * TAPS; ++k) s_acc[g][k][co] = acc[k];
