@@ -38,8 +38,8 @@ constexpr int TAPS = 9;
 constexpr int CIN[NL] = {2, 32, 32, 32, 32, 32};
 constexpr int COUT[NL] = {32, 32, 32, 32, 32, 1};
 constexpr int DW_BLOCKS = 1024;  // split-K workgroups of a weight gradient
-constexpr int DW_GROUPS = 8;     // pixel groups of a first/last-layer gradient workgroup
-static_assert(DW_GROUPS < 32, "a pixel group's step must stay below the narrowest row (W >= 32)");
+constexpr int DW_GROUPS = 32;    // pixel groups of a first/last-layer gradient workgroup (8 threads each)
+static_assert(DW_GROUPS <= 32, "a pixel group's step must not exceed the narrowest row (W >= 32)");
 constexpr int MAX_DIL = 32;      // largest dilation of a layer
 
 constexpr int param_count_layer(int l) { return COUT[l] * CIN[l] * TAPS + COUT[l]; }
@@ -377,39 +377,48 @@ __global__ __launch_bounds__(BLOCK) void k_last_bwd_data(int B, int H, int W, in
     }
 }
 
-// Workgroup b takes a contiguous share of the pixels; thread (g, ci) sums
-// A5[p + off(tap)][ci] dout[p] over every DW_GROUPS-th pixel of it for all
-// taps, then the groups are added in order.  Partials part[block][289]:
-// index ci * 9 + tap, and 288 the bias.
+// Workgroup b takes a contiguous share of the pixels.  Thread (g, c4), g one
+// of DW_GROUPS pixel groups and c4 one of eight channel quads, sums
+// A5[p + off(tap)][4 c4 + j] dout[p] over every DW_GROUPS-th pixel of the
+// share for all taps (one 8-byte load per tap gives its four channels); the
+// groups are then added: the eight groups of a wavefront by a butterfly over
+// the lanes (8, 16, 32 apart), the four wavefronts in order.  Partials
+// part[block][289]: index ci * 9 + tap, and 288 the bias.
 __global__ __launch_bounds__(256) void k_last_bwd_weight(int B, int H, int W, int d,
                                                          const float *__restrict__ dout,
                                                          const bf16 *__restrict__ a5,
                                                          float *__restrict__ part)
 {
-    __shared__ float s_acc[DW_GROUPS][CH][TAPS];
-    __shared__ float s_b[DW_GROUPS];
-    const int t = threadIdx.x, ci = t % CH, g = t / CH;
+    typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+    __shared__ float s_acc[4][CH * TAPS + 1];
+    const int t = threadIdx.x, c4 = t % 8, g = t / 8, lane = t & 63, wave = t >> 6;
     const int64_t npix = (int64_t)B * H * W;
     const int64_t chunk = (npix + gridDim.x - 1) / gridDim.x;
     const int64_t p0 = (int64_t)blockIdx.x * chunk, p1 = min(npix, p0 + chunk);
-    float acc[TAPS];
+    float acc[4][TAPS];
 #pragma unroll
-    for (int k = 0; k < TAPS; ++k) acc[k] = 0.f;
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int k = 0; k < TAPS; ++k) acc[j][k] = 0.f;
     float bacc = 0.f;
-    // the row and column of pixel p, advanced by DW_GROUPS < W per step, and
+    // the row and column of pixel p, advanced by DW_GROUPS <= W per step, and
     // the element offset of each tap from the pixel (a tap inside the image
-    // lies in the pixel's own image; no multiplications per tap)
+    // lies in the pixel's own image)
     int y = (int)(((p0 + g) / W) % H), x = (int)((p0 + g) % W);
     int64_t toff[TAPS];
 #pragma unroll
     for (int tap = 0; tap < TAPS; ++tap) toff[tap] = ((int64_t)(tap / 3 - 1) * d * W + (tap % 3 - 1) * d) * CH;
     for (int64_t p = p0 + g; p < p1; p += DW_GROUPS) {
         const float dv = dout[p];
-        const bf16 *ap = a5 + p * CH + ci;
+        const bf16 *ap = a5 + p * CH + 4 * c4;
 #pragma unroll
         for (int tap = 0; tap < TAPS; ++tap) {
             const int yy = y + (tap / 3 - 1) * d, xx = x + (tap % 3 - 1) * d;
-            if (inside(yy, xx, H, W)) acc[tap] = fmaf((float)ap[toff[tap]], dv, acc[tap]);
+            if (inside(yy, xx, H, W)) {
+                const bf16x4 a = *reinterpret_cast<const bf16x4 *>(ap + toff[tap]);
+#pragma unroll
+                for (int j = 0; j < 4; ++j) acc[j][tap] = fmaf((float)a[j], dv, acc[j][tap]);
+            }
         }
         bacc += dv;
         x += DW_GROUPS;
@@ -418,19 +427,25 @@ __global__ __launch_bounds__(256) void k_last_bwd_weight(int B, int H, int W, in
             if (++y == H) y = 0;   // the next image
         }
     }
+    // the wavefront's eight pixel groups (lanes 8, 16, 32 apart), in a fixed order
 #pragma unroll
-    for (int tap = 0; tap < TAPS; ++tap) s_acc[g][ci][tap] = acc[tap];
-    if (ci == 0) s_b[g] = bacc;
-    __syncthreads();
-    for (int v = t; v <= CH * TAPS; v += 256) {
-        float sum = 0.f;
-        if (v < CH * TAPS) {
-            for (int k = 0; k < DW_GROUPS; ++k) sum += s_acc[k][v / TAPS][v % TAPS];
-        } else {
-            for (int k = 0; k < DW_GROUPS; ++k) sum += s_b[k];
-        }
-        part[(size_t)blockIdx.x * (CH * TAPS + 1) + v] = sum;
+    for (int o = 8; o < 64; o <<= 1) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int k = 0; k < TAPS; ++k) acc[j][k] += __shfl_xor(acc[j][k], o);
+        bacc += __shfl_xor(bacc, o);
     }
+    if (lane < 8) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int k = 0; k < TAPS; ++k) s_acc[wave][(4 * c4 + j) * TAPS + k] = acc[j][k];
+        if (lane == 0) s_acc[wave][CH * TAPS] = bacc;
+    }
+    __syncthreads();
+    for (int v = t; v <= CH * TAPS; v += 256)
+        part[(size_t)blockIdx.x * (CH * TAPS + 1) + v] = ((s_acc[0][v] + s_acc[1][v]) + s_acc[2][v]) + s_acc[3][v];
 }
 
 // ---------------------------------------------------------------------------
@@ -520,44 +535,60 @@ __global__ __launch_bounds__(BLOCK) void k_mid_bwd_weight(int B, int H, int W, i
     }
 }
 
-// Layer 0 weight gradient, like the last layer's: thread (g, co) sums
-// in[p + off(tap)][ci] dz0[p][co] for both input channels and all taps over
-// every DW_GROUPS-th pixel of the workgroup's share.  Partials
+// Layer 0 weight gradient, like the last layer's: thread (g, c4) sums
+// in[p + off(tap)][ci] dz0[p][4 c4 + j] for both input channels (one 4-byte
+// load per tap), all taps and its four output channels over every
+// DW_GROUPS-th pixel of the workgroup's share; the groups are added by a
+// butterfly over the lanes, then the wavefronts in order.  Partials
 // part[block][608]: index (tap * 2 + ci) * 32 + co, then 576 + co the bias.
 __global__ __launch_bounds__(256) void k_first_bwd_weight(int B, int H, int W, int d,
                                                           const bf16 *__restrict__ dz0,
                                                           const bf16 *__restrict__ in,
                                                           float *__restrict__ part)
 {
+    typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+    typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
     constexpr int NW = TAPS * 2 * CH;
-    __shared__ float s_acc[DW_GROUPS][2 * TAPS + 1][CH];
-    const int t = threadIdx.x, co = t % CH, g = t / CH;
+    __shared__ float s_acc[4][NW + CH];
+    const int t = threadIdx.x, c4 = t % 8, g = t / 8, lane = t & 63, wave = t >> 6;
     const int64_t npix = (int64_t)B * H * W;
     const int64_t chunk = (npix + gridDim.x - 1) / gridDim.x;
     const int64_t p0 = (int64_t)blockIdx.x * chunk, p1 = min(npix, p0 + chunk);
-    float acc[2 * TAPS];
+    float acc[4][2 * TAPS], bacc[4];
 #pragma unroll
-    for (int k = 0; k < 2 * TAPS; ++k) acc[k] = 0.f;
-    float bacc = 0.f;
-    // the row and column of pixel p, advanced by DW_GROUPS < W per step, and
+    for (int j = 0; j < 4; ++j) {
+        bacc[j] = 0.f;
+#pragma unroll
+        for (int k = 0; k < 2 * TAPS; ++k) acc[j][k] = 0.f;
+    }
+    // the row and column of pixel p, advanced by DW_GROUPS <= W per step, and
     // the element offset of each tap from the pixel (a tap inside the image
-    // lies in the pixel's own image; no multiplications per tap)
+    // lies in the pixel's own image)
     int y = (int)(((p0 + g) / W) % H), x = (int)((p0 + g) % W);
     int64_t toff[TAPS];
 #pragma unroll
     for (int tap = 0; tap < TAPS; ++tap) toff[tap] = ((int64_t)(tap / 3 - 1) * d * W + (tap % 3 - 1) * d) * 2;
     for (int64_t p = p0 + g; p < p1; p += DW_GROUPS) {
-        const float dv = (float)dz0[p * CH + co];
+        const bf16x4 dz = *reinterpret_cast<const bf16x4 *>(dz0 + p * CH + 4 * c4);
+        float dv[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) dv[j] = (float)dz[j];
         const bf16 *ip = in + 2 * p;
 #pragma unroll
         for (int tap = 0; tap < TAPS; ++tap) {
             const int yy = y + (tap / 3 - 1) * d, xx = x + (tap % 3 - 1) * d;
             if (inside(yy, xx, H, W)) {
-                acc[tap * 2] = fmaf((float)ip[toff[tap]], dv, acc[tap * 2]);
-                acc[tap * 2 + 1] = fmaf((float)ip[toff[tap] + 1], dv, acc[tap * 2 + 1]);
+                const bf16x2 v = *reinterpret_cast<const bf16x2 *>(ip + toff[tap]);
+                const float v0 = (float)v[0], v1 = (float)v[1];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    acc[j][tap * 2] = fmaf(v0, dv[j], acc[j][tap * 2]);
+                    acc[j][tap * 2 + 1] = fmaf(v1, dv[j], acc[j][tap * 2 + 1]);
+                }
             }
         }
-        bacc += dv;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) bacc[j] += dv[j];
         x += DW_GROUPS;
         if (x >= W) {
             x -= W;
@@ -565,15 +596,25 @@ __global__ __launch_bounds__(256) void k_first_bwd_weight(int B, int H, int W, i
         }
     }
 #pragma unroll
-    for (int k = 0; k < 2 * TAPS; ++k) s_acc[g][k][co] = acc[k];
-    s_acc[g][2 * TAPS][co] = bacc;
-    __syncthreads();
-    for (int v = t; v < NW + CH; v += 256) {
-        const int k = v < NW ? v / CH : 2 * TAPS, c = v % CH;
-        float sum = 0.f;
-        for (int gg = 0; gg < DW_GROUPS; ++gg) sum += s_acc[gg][k][c];
-        part[(size_t)blockIdx.x * (NW + CH) + v] = sum;
+    for (int o = 8; o < 64; o <<= 1) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+#pragma unroll
+            for (int k = 0; k < 2 * TAPS; ++k) acc[j][k] += __shfl_xor(acc[j][k], o);
+            bacc[j] += __shfl_xor(bacc[j], o);
+        }
     }
+    if (lane < 8) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+#pragma unroll
+            for (int k = 0; k < 2 * TAPS; ++k) s_acc[wave][k * CH + 4 * c4 + j] = acc[j][k];
+            s_acc[wave][NW + 4 * c4 + j] = bacc[j];
+        }
+    }
+    __syncthreads();
+    for (int v = t; v < NW + CH; v += 256)
+        part[(size_t)blockIdx.x * (NW + CH) + v] = ((s_acc[0][v] + s_acc[1][v]) + s_acc[2][v]) + s_acc[3][v];
 }
 
 // Sum per-workgroup partials into the FP32 gradient array in a fixed order:
