@@ -38,6 +38,7 @@ constexpr int TAPS = 9;
 constexpr int CIN[NL] = {2, 32, 32, 32, 32, 32};
 constexpr int COUT[NL] = {32, 32, 32, 32, 32, 1};
 constexpr int DW_BLOCKS = 1024;  // split-K workgroups of a weight gradient
+constexpr int NXCD = 8;          // accelerator dies (XCDs) of an MI355X, each with its own L2
 constexpr int DW_GROUPS = 32;    // pixel groups of a first/last-layer gradient workgroup (8 threads each)
 static_assert(DW_GROUPS <= 32, "a pixel group's step must not exceed the narrowest row (W >= 32)");
 constexpr int MAX_DIL = 32;      // largest dilation of a layer
@@ -258,9 +259,24 @@ __global__ __launch_bounds__(BLOCK) void k_conv_mid(int B, int H, int W, int d,
 
     const int64_t tiles_per_row = W / 32;
     const int64_t ntiles = (int64_t)B * H * tiles_per_row;
-    const int64_t wave = ((int64_t)blockIdx.x * BLOCK + threadIdx.x) >> 6;
-    const int64_t nwaves = ((int64_t)gridDim.x * BLOCK) >> 6;
-    for (int64_t tile = wave; tile < ntiles; tile += nwaves) {
+    // Workgroups go to the eight XCDs in turn (blockIdx.x mod 8), each XCD with
+    // its own L2.  In the forward pass each XCD's workgroups take one
+    // contiguous band of the tiles (whole image rows), so the rows y - d, y,
+    // y + d that a tile reads are read by the tiles of that same XCD (512^2,
+    // batch 8: HBM reads 318 -> 234 MB, 161.5 -> 152.8 us); the masked
+    // backward pass measured 185 -> 196 us that way and keeps the plain order.
+    // Which wavefront computes a tile changes nothing in its result.
+    int64_t tile1 = ntiles, wave, nwaves;
+    if (MODE == 0 && gridDim.x % NXCD == 0) {
+        const int64_t xcd = blockIdx.x % NXCD, per = gridDim.x / NXCD;
+        tile1 = ntiles * (xcd + 1) / NXCD;
+        wave = ntiles * xcd / NXCD + (((int64_t)(blockIdx.x / NXCD) * BLOCK + threadIdx.x) >> 6);
+        nwaves = (per * BLOCK) >> 6;
+    } else {
+        wave = ((int64_t)blockIdx.x * BLOCK + threadIdx.x) >> 6;
+        nwaves = ((int64_t)gridDim.x * BLOCK) >> 6;
+    }
+    for (int64_t tile = wave; tile < tile1; tile += nwaves) {
         const int64_t img = tile / ((int64_t)H * tiles_per_row);
         const int y = (int)((tile / tiles_per_row) % H);
         const int x = (int)(tile % tiles_per_row) * 32 + col;
@@ -769,7 +785,8 @@ mstab_status run_forward(mstab_cnn *h, const bf16 *in, int B)
     hipLaunchKernelGGL(k_conv_first, dim3(grid_of(npix, 8192)), dim3(BLOCK), 0, h->stream, B, H, W,
                        h->dil[0], in, h->w0, h->bias, h->act[1]);
     const int64_t tiles = npix / 32;
-    const int mid_grid = (int)std::min<int64_t>((tiles + 3) / 4, 4096);
+    // a multiple of the XCD count, for the banded tile order of k_conv_mid
+    const int mid_grid = (int)(((std::min<int64_t>((tiles + 3) / 4, 4096) + NXCD - 1) / NXCD) * NXCD);
     for (int l = 1; l <= 4; ++l)
         hipLaunchKernelGGL(k_conv_mid<0>, dim3(mid_grid), dim3(BLOCK), 0, h->stream, B, H, W,
                            h->dil[l], h->act[l], h->wf + (size_t)(l - 1) * TAPS * CH * CH, h->bias + l * CH,
@@ -949,7 +966,8 @@ mstab_status mstab_cnn_gradient(mstab_cnn *h, const void *input_bf16, const floa
                        h->dil[5], h->dout, h->w5, h->act[5], h->dz[4]);
     // layers 4..1: weight gradient from dz[l], then dz[l - 1]
     const int64_t tiles = npix / 32;
-    const int mid_grid = (int)std::min<int64_t>((tiles + 3) / 4, 4096);
+    // a multiple of the XCD count, for the banded tile order of k_conv_mid
+    const int mid_grid = (int)(((std::min<int64_t>((tiles + 3) / 4, 4096) + NXCD - 1) / NXCD) * NXCD);
     for (int l = 4; l >= 1; --l) {
         hipLaunchKernelGGL(k_mid_bwd_weight, dim3(DW_BLOCKS), dim3(BLOCK), 0, h->stream, B, H, W,
                            h->dil[l], h->dz[l], h->act[l], h->part, h->part_b);
