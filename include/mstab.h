@@ -181,8 +181,6 @@ typedef struct {
     int64_t fetch_level;       /* AT_LEVEL: level j of the fetched U, V */
     uint64_t p_seed;           /* seed of the cut-space basis P (counter-based uniform entries) */
     int32_t max_replacements;  /* true-residual replacements at the end of a solve; default 3 */
-    double inner_tol;          /* reserved (F32_REFINE replaces the FP32 residual by the FP64
-                                  true residual after every cycle and stops on it); default 1e-4 */
     int32_t max_refinements;   /* F32_REFINE: outer correction steps; default 20 */
     int32_t precond;           /* mstab_precond; default NONE */
     int32_t replace_every;     /* F64, F32_MATRIX: k > 0 replaces the recursive residual by the
@@ -204,6 +202,19 @@ typedef struct {
                                   the data stay as fetched.  Default 0. */
     int32_t engine;            /* mstab_engine; default GRID */
     int32_t gmres_restart;     /* METHOD_GMRES: the restart length m, 1..1024; default 30 */
+    const double *p_host;      /* NULL (default): the cut-space basis P is the counter-based one of
+                                  p_seed, regenerated inside the kernels.  Else a host array of
+                                  n x s doubles, column q at p_host + q n, all finite: the P
+                                  that every projection of the handle uses (Section 2.4 leaves P
+                                  arbitrary; Section 4.2 keeps it for the whole sequence).
+                                  Rows are in the caller's order: with a reordering (RCM, or
+                                  the ILU(0) colour order) the library permutes them with A's;
+                                  with a splitting, P acts on the split system's residuals.
+                                  mstab_create copies it to the device (the caller may free it
+                                  afterwards); products then read P (8 s bytes per row) instead
+                                  of regenerating it.  A non-finite entry: E_INVALID.  Recycle
+                                  blobs carry a digest of it and are refused by a handle whose
+                                  P differs. */
 } mstab_options;
 
 typedef struct {

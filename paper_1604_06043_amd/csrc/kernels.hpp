@@ -77,6 +77,23 @@ __device__ __forceinline__ double pval(uint32_t key, uint32_t row, int q)
     return (double)t * 0x1p-23;
 }
 
+// The cut-space basis as the kernels see it: entry (row, q) from the
+// generator above with key, or, when m is set, from a caller's n x s matrix
+// copied to the device (column q at m + q ld).  The choice is uniform across
+// a launch.
+struct PBasis {
+    uint32_t key = 0;
+    const double *m = nullptr;
+    int64_t ld = 0;
+    PBasis() = default;
+    __host__ __device__ PBasis(uint32_t k, const double *mm = nullptr, int64_t l = 0) : key(k), m(mm), ld(l) {}
+};
+
+__device__ __forceinline__ double pval(const PBasis &p, uint32_t row, int q)
+{
+    return p.m ? p.m[(int64_t)q * p.ld + row] : pval(p.key, row, q);
+}
+
 __device__ __forceinline__ double fmaT(double a, double b, double c) { return __builtin_fma(a, b, c); }
 __device__ __forceinline__ float fmaT(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 
@@ -364,7 +381,7 @@ enum : int32_t {
 
 struct SpmvArgs {
     int32_t act, k, q, s, ell;
-    uint32_t pkey;
+    PBasis pkey;
 };
 
 #ifndef MSTAB_SPMV_BLOCK
@@ -571,7 +588,7 @@ __global__ __launch_bounds__(BLOCK) void k_dia_range(int64_t n, int nd, const ui
 // y[r] (and the residual form b[r] - sum) plus the row's share of the partials.
 template <typename T, int S>
 __device__ __forceinline__ void spmv_row_out(int64_t r, T sum, bool resid, const T *__restrict__ b,
-                                             T *__restrict__ y, uint32_t pkey,
+                                             T *__restrict__ y, PBasis pkey,
                                              double (&vals)[S + 2])
 {
 #pragma clang fp contract(off)
@@ -786,7 +803,7 @@ __device__ __forceinline__ void dia_rows(int64_t n, int nd, const DiaOffsets &do
                                          const uint16_t *__restrict__ mask,
                                          const TM *__restrict__ dval, const T *__restrict__ x,
                                          T *__restrict__ y, const T *__restrict__ b, bool resid,
-                                         uint32_t pkey, double (&vals)[S + 2])
+                                         PBasis pkey, double (&vals)[S + 2])
 {
     for (int64_t r = (int64_t)blockIdx.x * SPMV_BLOCK + threadIdx.x; r < n;
          r += (int64_t)gridDim.x * SPMV_BLOCK) {
@@ -816,7 +833,7 @@ template <typename T, int S, int ND, int RPI = MSTAB_DIA_RPI>
 __device__ __forceinline__ void dia_rows_const(int64_t n, const DiaOffsets &doff, const DiaConst &cv,
                                                const uint16_t *__restrict__ mask, const T *__restrict__ x,
                                                T *__restrict__ y, const T *__restrict__ b, bool resid,
-                                               uint32_t pkey, double (&vals)[S + 2])
+                                               PBasis pkey, double (&vals)[S + 2])
 {
 #pragma clang fp contract(off)
     const int32_t n32 = (int32_t)n;
@@ -1291,7 +1308,7 @@ __global__ __launch_bounds__(BLOCK) void k_eta_low_gram(int64_t ld, T *__restric
 template <typename T, int S, int L>
 __global__ __launch_bounds__(BLOCK) void k_poly(int64_t n, int64_t ld, int ell_rt,
                                                 T *__restrict__ W, T *__restrict__ R,
-                                                T *__restrict__ X, uint32_t pkey, Ctl *ctl,
+                                                T *__restrict__ X, PBasis pkey, Ctl *ctl,
                                                 double *part, int stride)
 {
     if (ctl->st.flags) return;
@@ -1595,7 +1612,7 @@ __global__ __launch_bounds__(BLOCK) void k_correct(int64_t n, const float *__res
 // dst 2: prec[q] (fetched V).
 template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_project(int64_t n, const T *__restrict__ y,
-                                                   uint32_t pkey, int s, int dst, int q, Ctl *ctl,
+                                                   PBasis pkey, int s, int dst, int q, Ctl *ctl,
                                                    double *part, int stride)
 {
     double acc[MAXS + 1];

@@ -770,7 +770,7 @@ struct Engine {
     int64_t n = 0, ld = 0, nnz = 0;
     Sell<T> A;                          // sliced copy of the matrix
     bool own_col = true;
-    uint32_t pkey = 0;
+    PBasis pkey;
     hipStream_t stream = nullptr;
 
     T *W = nullptr, *R = nullptr, *X = nullptr, *Tv = nullptr;
@@ -793,7 +793,7 @@ struct Engine {
     T *Rc(int i) const { return R + (int64_t)i * ld; }
 
     // full = false: only what the FP64 outer loop of the mixed mode needs
-    void alloc(int64_t n_, int s_, int ell_, const Sell<T> &A_, bool own_col_, uint32_t key,
+    void alloc(int64_t n_, int s_, int ell_, const Sell<T> &A_, bool own_col_, PBasis key,
                hipStream_t st, Profiler *pr, bool full = true)
     {
         n = n_; s = s_; ell = ell_; A = A_; own_col = own_col_; nnz = A_.nnz;
@@ -1641,6 +1641,11 @@ struct mstab_solver {
     hipStream_t stream = nullptr;
     int device = 0;         // the HIP device current at create
     uint32_t pkey = 0;
+    // with the p_host option: the caller's cut-space basis (n x s, device copy)
+    // and a 64-bit FNV-1a digest of its bytes (recycle blobs carry it)
+    double *pmat = nullptr;
+    uint64_t p_digest = 0;
+    PBasis pbasis() const { return PBasis(pkey, pmat, n); }
     Engine<double> e64;
     Engine<float> e32;
     float *r32 = nullptr;   // F32_REFINE: scaled residual (right-hand side of the inner solve)
@@ -1710,6 +1715,7 @@ void release_handle(mstab_solver *h)
     (void)hipFree(h->va_perm);
     (void)hipFree(h->xwork);
     h->ilu.release();
+    (void)hipFree(h->pmat);
     (void)hipFree(h->wg_jobs);
     (void)hipFree(h->wg_hmv);
     (void)hipFree(h->wg_hres);
@@ -1870,7 +1876,7 @@ mstab_status wg_run(mstab_solver *const *h, int count, const double *const *b, d
         J.n = hi->n; J.ld = E.ld;
         J.max_mv = hi->opt.max_mv; J.fetch_level = hi->opt.fetch_level;
         J.tol = hi->opt.tol; J.fetch_rel = hi->opt.fetch_rel;
-        J.pkey = hi->pkey;
+        J.pkey = hi->pbasis();
         J.s = hi->s; J.ell = hi->ell; J.method = hi->opt.method; J.fetch = hi->opt.fetch;
         J.max_repl = hi->opt.max_replacements; J.replace_every = hi->opt.replace_every;
         J.rec_have = E.rec_have ? 1 : 0; J.rec_level = E.rec_level; J.est_cycle = E.est_cycle;
@@ -2178,7 +2184,6 @@ mstab_status mstab_options_default(mstab_options *o)
     o->fetch_level = -1;
     o->p_seed = 0;
     o->max_replacements = 3;
-    o->inner_tol = 1e-4;
     o->max_refinements = 20;
     o->gmres_restart = 30;
     return MSTAB_OK;
@@ -2245,9 +2250,22 @@ mstab_status mstab_create(const mstab_csr *A, int32_t s, int32_t ell, const msta
     h->stream = (hipStream_t)hip_stream;
     HIPCHK(hipGetDevice(&h->device));
     h->pkey = p_key_from_seed(h->opt.p_seed);
+    if (h->opt.p_host) {
+        // the caller's cut-space basis: n x s, column q at p_host + q n, finite
+        const double *ph = h->opt.p_host;
+        uint64_t dg = 1469598103934665603ull;
+        for (int64_t i = 0; i < h->n * (int64_t)s; ++i) {
+            if (!std::isfinite(ph[i])) fail(MSTAB_E_INVALID, "p_host holds a non-finite value");
+            unsigned char b8[8];
+            memcpy(b8, &ph[i], 8);
+            for (int k = 0; k < 8; ++k) dg = (dg ^ b8[k]) * 1099511628211ull;
+        }
+        h->p_digest = dg;
+    }
     h->prof.init(h->stream);
     check_csr_dev(h->n, h->nnz, h->rp, h->ci, h->stream);
     const bool use_ilu = h->opt.precond == MSTAB_PRECOND_ILU0;
+    std::vector<int32_t> host_perm;   // new row -> the caller's row, when the handle reorders
     if (h->opt.reorder == MSTAB_REORDER_RCM || use_ilu) {
         // host: the order (reverse Cuthill-McKee, or the multicolour order of
         // the ILU(0) splitting) and the symmetrically permuted CSR
@@ -2262,6 +2280,7 @@ mstab_status mstab_create(const mstab_csr *A, int32_t s, int32_t ell, const msta
         const std::vector<int32_t> perm = use_ilu ? multicolour_order(n, rp.data(), ci.data(), cp)
                                                   : rcm_order(n, rp.data(), ci.data());
         if ((int64_t)perm.size() != n) fail(MSTAB_E_INVALID, "reordering lost rows");
+        host_perm = perm;
         std::vector<int32_t> prp, pci;
         std::vector<double> pva;
         permute_csr(n, rp, ci, va, perm, prp, pci, pva);
@@ -2347,6 +2366,24 @@ mstab_status mstab_create(const mstab_csr *A, int32_t s, int32_t ell, const msta
         h->ci = h->ci_perm;
         h->va = h->va_perm;
     }
+    if (h->opt.p_host) {
+        // the device copy of the caller's P, its rows permuted with A's when the
+        // handle reorders (the method is invariant under the joint permutation)
+        const double *ph = h->opt.p_host;
+        const int64_t n = h->n;
+        std::vector<double> pp;
+        if (!host_perm.empty()) {
+            pp.resize((size_t)n * (size_t)s);
+            for (int q = 0; q < s; ++q)
+                for (int64_t i = 0; i < n; ++i) pp[(size_t)q * n + i] = ph[(size_t)q * n + host_perm[i]];
+            ph = pp.data();
+        }
+        HIPCHK(hipMalloc(&h->pmat, sizeof(double) * (size_t)n * (size_t)s));
+        HIPCHK(hipMemcpyAsync(h->pmat, ph, sizeof(double) * (size_t)n * (size_t)s, hipMemcpyHostToDevice,
+                              h->stream));
+        HIPCHK(hipStreamSynchronize(h->stream));
+        h->opt.p_host = nullptr;   // the handle keeps its own copy, not the caller's pointer
+    }
     double *split_val = nullptr;   // L^-1 A R^-1, needed only while the device copies are built
     if (h->opt.precond == MSTAB_PRECOND_JACOBI) {
         const size_t vb = sizeof(double) * (size_t)round_up(h->n, 256);
@@ -2361,7 +2398,7 @@ mstab_status mstab_create(const mstab_csr *A, int32_t s, int32_t ell, const msta
     Sell<double> A64 = make_sell<double, double>(h->n, h->rp, h->ci, h->va, h->stream, nullptr,
                                                  h->opt.matrix_format);
     // the mixed form keeps a full FP64 engine for the FP64 fallback
-    h->e64.alloc(h->n, s, ell, A64, true, h->pkey, h->stream, &h->prof);
+    h->e64.alloc(h->n, s, ell, A64, true, h->pbasis(), h->stream, &h->prof);
     if (use_ilu) h->e64.ilu = &h->ilu;
     if (h->opt.method == MSTAB_METHOD_GMRES) h->e64.alloc_gmres(h->opt.gmres_restart);
     h->e64.replace_every = h->opt.replace_every;
@@ -2375,7 +2412,7 @@ mstab_status mstab_create(const mstab_csr *A, int32_t s, int32_t ell, const msta
         HIPCHK(hipMemsetAsync(h->r32, 0, sizeof(float) * (size_t)round_up(h->n, 256), h->stream));
         HIPCHK(hipMalloc(&h->xbak, sizeof(double) * (size_t)round_up(h->n, 256)));
         Sell<float> A32 = make_sell<float, double>(h->n, h->rp, h->ci, h->va, h->stream, &A64);
-        h->e32.alloc(h->n, s, ell, A32, false, h->pkey, h->stream, &h->prof);
+        h->e32.alloc(h->n, s, ell, A32, false, h->pbasis(), h->stream, &h->prof);
         h->e32.refresh_v = true;
         h->e32.orthonormalize = h->opt.orthonormalize_recycle != 0;
     }
@@ -2507,6 +2544,13 @@ mstab_status mstab_solve_batch(mstab_solver *const *h, int32_t count, const doub
     if (h[0]->workgroup()) {
         for (int i = 0; i < count; ++i)
             if (!h[i]->workgroup()) fail(MSTAB_E_INVALID, "handle %d is not of ENGINE_WORKGROUP like handle 0", i);
+        // the launch runs on h[0]'s device; the caller's current device is restored
+        int prev = 0;
+        HIPCHK(hipGetDevice(&prev));
+        struct Restore {
+            int dev;
+            ~Restore() { (void)hipSetDevice(dev); }
+        } restore{prev};
         HIPCHK(hipSetDevice(h[0]->device));
         const mstab_status w = wg_run(h, count, b, x, info, 0, 0);
         if (w < 0)
@@ -2710,13 +2754,14 @@ struct RecycleBlob {
     int32_t s;
     int64_t n;
     uint64_t p_seed;
+    uint64_t p_digest;   // of a caller's cut-space basis (p_host), else 0
     int32_t precond, reorder;
     int32_t have, pad;
     int64_t level;
     int64_t est_cycle;   // FETCH_ESTIMATE's fetch cycle for the next solve (-1: none)
 };
 constexpr char RECYCLE_MAGIC[8] = {'M', 'S', 'T', 'A', 'B', 'R', 'E', 'C'};
-constexpr uint32_t RECYCLE_VERSION = 2;
+constexpr uint32_t RECYCLE_VERSION = 3;
 
 size_t recycle_blob_size(const mstab_solver *h, bool have)
 {
@@ -2742,6 +2787,7 @@ mstab_status mstab_recycle_export(const mstab_solver *h, void *dst, size_t cap, 
     hd.s = h->s;
     hd.n = h->n;
     hd.p_seed = h->opt.p_seed;
+    hd.p_digest = h->p_digest;
     hd.precond = h->opt.precond;
     hd.reorder = h->opt.reorder;
     hd.have = E.rec_have ? 1 : 0;
@@ -2774,9 +2820,9 @@ mstab_status mstab_recycle_import(mstab_solver *h, const void *src, size_t len)
     memcpy(&hd, src, sizeof hd);
     if (memcmp(hd.magic, RECYCLE_MAGIC, sizeof hd.magic) != 0 || hd.version != RECYCLE_VERSION)
         fail(MSTAB_E_INVALID, "not a recycle blob of this version");
-    if (hd.s != h->s || hd.n != h->n || hd.p_seed != h->opt.p_seed || hd.precond != h->opt.precond ||
-        hd.reorder != h->opt.reorder)
-        fail(MSTAB_E_INVALID, "recycle blob of another problem (s, n, P seed, preconditioner or order differ)");
+    if (hd.s != h->s || hd.n != h->n || hd.p_seed != h->opt.p_seed || hd.p_digest != h->p_digest ||
+        hd.precond != h->opt.precond || hd.reorder != h->opt.reorder)
+        fail(MSTAB_E_INVALID, "recycle blob of another problem (s, n, P, preconditioner or order differ)");
     if (len < recycle_blob_size(h, hd.have != 0)) fail(MSTAB_E_INVALID, "recycle blob truncated");
     Engine<double> &E = h->e64;
     E.est_cycle = hd.est_cycle;

@@ -50,7 +50,7 @@ struct Job {
     int64_t hist_stride;
     int64_t n, ld, max_mv, fetch_level;
     double tol, fetch_rel;
-    uint32_t pkey;
+    PBasis pkey;
     int32_t s, ell, method, fetch, max_repl, replace_every;
     // recycle state, in and out
     int32_t rec_have;
@@ -211,7 +211,7 @@ struct Solver {
         struct Out {
             bool resid;
             double *dst;
-            uint32_t pkey;
+            PBasis pkey;
             double (&vals)[S + 2];
             __device__ __forceinline__ void operator()(int e, double sum, double bv)
             {

@@ -54,11 +54,11 @@ class mstab_options(ctypes.Structure):
                 ("precision", ctypes.c_int32), ("fetch", ctypes.c_int32),
                 ("fetch_rel", ctypes.c_double), ("fetch_level", ctypes.c_int64),
                 ("p_seed", ctypes.c_uint64), ("max_replacements", ctypes.c_int32),
-                ("inner_tol", ctypes.c_double), ("max_refinements", ctypes.c_int32),
+                ("max_refinements", ctypes.c_int32),
                 ("precond", ctypes.c_int32), ("replace_every", ctypes.c_int32),
                 ("reorder", ctypes.c_int32), ("matrix_format", ctypes.c_int32),
                 ("orthonormalize_recycle", ctypes.c_int32), ("engine", ctypes.c_int32),
-                ("gmres_restart", ctypes.c_int32)]
+                ("gmres_restart", ctypes.c_int32), ("p_host", ctypes.c_void_p)]
 
 
 class mstab_info(ctypes.Structure):
@@ -341,11 +341,20 @@ class Solver:
         self.lib = load()
         self.A = A          # keeps the matrix tensors alive
         self.s, self.ell = s, ell
+        p_host = overrides.pop("p_host", None)
         o = options if options is not None else mstab_options_default(**overrides)
+        if p_host is not None:
+            # an (n, s) array: column q contiguous (the header's layout)
+            import numpy as np
+            pm = np.ascontiguousarray(np.asarray(p_host, dtype=np.float64).T)
+            if pm.shape != (s, A.n):
+                raise ValueError(f"p_host must be ({A.n}, {s}), not {tuple(reversed(pm.shape))}")
+            o.p_host = pm.ctypes.data
         h = ctypes.c_void_p()
         st = A.struct()
         _check(self.lib.mstab_create(ctypes.byref(st), s, ell, ctypes.byref(o), _stream(stream),
                                      ctypes.byref(h)))
+        o.p_host = None     # the handle holds its own copy of P
         self.h = h
         self.options = o
 

@@ -338,11 +338,15 @@ def test_sequence_free_running_c1(torch_dev, ms, orc, method, s, ell):
 
 
 def teacher_forced(torch, ms, orc, cd, Ao, Ag, s, ell, seed, method, systems, fetch=0, orth=0,
-                   check_recycle=False, replace_every=0, **opt):
+                   check_recycle=False, replace_every=0, P=None, **opt):
     """Systems 1..systems from the oracle's x^(i) and recycled U, V, each
     compared with the oracle's solve at the teacher-forced bar.  Returns the
-    per-system errors.  opt: further handle options (the engine)."""
-    P = I.p_dense(seed, cd.N, s)
+    per-system errors.  opt: further handle options (the engine); P: a
+    cut-space basis of the caller's (p_host) instead of the seed's."""
+    if P is None:
+        P = I.p_dense(seed, cd.N, s)
+    else:
+        opt = dict(opt, p_host=P)
     solver = ms.Solver(Ag, s, ell, p_seed=seed, method=method, fetch=fetch,
                        orthonormalize_recycle=orth, replace_every=replace_every, **opt)
     xo = np.zeros(cd.N)
@@ -1292,25 +1296,33 @@ def test_batch_matches_sequential(torch_dev, ms, orc):
 # ---------------------------------------------------------------------------
 # Reverse Cuthill-McKee reordering (the handle iterates on P A P^T)
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("jacobi", [False, True])
-def test_reordered_graph_teacher_forced(torch_dev, ms, orc, jacobi):
+@pytest.mark.parametrize("jacobi,caller_p", [(False, False), (True, False), (False, True), (True, True)])
+def test_reordered_graph_teacher_forced(torch_dev, ms, orc, jacobi, caller_p):
     """A reordered handle runs Algorithm 1 on the permuted matrix, which is the
     oracle's iteration on the original matrix with the cut-space basis and the
     recycled U, V carried back through the order (rows of P and U, V permuted):
-    the teacher-forced bar, system by system, on the random-labelled graph."""
+    the teacher-forced bar, system by system, on the random-labelled graph.
+    caller_p: a P of the caller's (p_host) in the original order, which the
+    handle permutes with A; the oracle takes it as it is."""
     torch = torch_dev
     s, ell, seed = 4, 2, 5
     g = I.rgg(20000, seed)
     Ao = orc.CSR(g.row_ptr, g.col, g.val)
     Ag = upload_csr(torch, ms, Ao)
     pc = ms.PRECOND_JACOBI if jacobi else ms.PRECOND_NONE
-    solver = ms.Solver(Ag, s, ell, p_seed=seed, reorder=ms.REORDER_RCM, precond=pc)
-    perm = solver.permutation()
     N = Ao.n
+    extra = {}
+    if caller_p:
+        extra["p_host"] = np.random.default_rng(seed + 100).standard_normal((N, s))
+    solver = ms.Solver(Ag, s, ell, p_seed=seed, reorder=ms.REORDER_RCM, precond=pc, **extra)
+    perm = solver.permutation()
     assert np.array_equal(np.sort(perm), np.arange(N))
     iperm = np.empty_like(perm)
     iperm[perm] = np.arange(N, dtype=perm.dtype)
-    P = I.p_dense(seed, N, s)[iperm]           # row i of the original gets the reordered row's P
+    if caller_p:
+        P = extra["p_host"]
+    else:
+        P = I.p_dense(seed, N, s)[iperm]       # row i of the original gets the reordered row's P
     split = orc.jacobi_split(Ao) if jacobi else None
     rng = np.random.default_rng(seed)
     xo = np.zeros(N)
@@ -1469,3 +1481,62 @@ def test_reordered_stencil_matrix(torch_dev, ms, orc):
         true = np.linalg.norm(b - orc.spmv(Ao, xr)) / np.linalg.norm(b)
         assert inf_r[k]["converged"] and true <= 1e-8 * (1 + 1e-6)
         assert np.linalg.norm(xr - xp) <= 4 * kappa * 1e-8 * np.linalg.norm(xp) * (k + 1)
+
+
+# ---------------------------------------------------------------------------
+# A caller's cut-space basis (p_host)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("engine", [0, 1])
+def test_p_host_equal_to_the_generated_basis_is_bit_identical(torch_dev, ms, orc, engine):
+    """Handing the handle the very P its seed generates (as an n x s array)
+    changes nothing: x bit for bit and the MV counts, on both engines."""
+    torch = torch_dev
+    cd = I.config("c1", seed=0)
+    Ag = gpu_assemble(ms, cd)
+    s, ell = 4, 2
+    P = I.p_dense(3, cd.N, s)
+    a = run_sequence_gpu(torch, ms, Ag, cd, s, ell, 4, 0, seed=3, engine=engine)
+    b = run_sequence_gpu(torch, ms, Ag, cd, s, ell, 4, 0, seed=3, engine=engine, p_host=P)
+    for k in range(4):
+        np.testing.assert_array_equal(a[0][k], b[0][k])
+        assert a[1][k]["mv_total"] == b[1][k]["mv_total"]
+
+
+@pytest.mark.parametrize("engine", [0, 1])
+def test_p_host_arbitrary_basis_against_the_oracle(torch_dev, ms, orc, engine):
+    """A P of the caller's (standard normal entries; Section 2.4 leaves P
+    arbitrary) on the GPU and in the oracle: the teacher-forced bar system by
+    system, recycled U, V included."""
+    torch = torch_dev
+    cd = I.config("c1", seed=1, n=48)
+    Ao = orc.assemble_convdiff(cd.dim, cd.n, cd.beta, cd.inv_dt)
+    Ag = gpu_assemble(ms, cd)
+    P = np.random.default_rng(11).standard_normal((cd.N, 4))
+    teacher_forced(torch, ms, orc, cd, Ao, Ag, 4, 2, 0, 0, 5, P=P, engine=engine)
+
+
+def test_p_host_checks_and_recycle_digest(torch_dev, ms, orc):
+    """A non-finite entry is refused at create; recycle data exported by a
+    handle with one P are refused by a handle with another P and accepted by
+    one with the same P."""
+    torch = torch_dev
+    cd = I.config("c1", seed=0, n=24)
+    Ag = gpu_assemble(ms, cd)
+    P = np.random.default_rng(5).standard_normal((cd.N, 4))
+    bad = P.copy()
+    bad[7, 2] = np.nan
+    with pytest.raises(ms.MstabError, match="p_host"):
+        ms.Solver(Ag, 4, 2, p_host=bad)
+    a = ms.Solver(Ag, 4, 2, p_host=P)
+    x = torch.zeros(cd.N, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(x)
+    ms.mstab_rhs_step(x, cd.inv_dt, dev(torch, cd.f), b)
+    a.solve_next(b, x)
+    blob = a.recycle_export()
+    other = ms.Solver(Ag, 4, 2)
+    with pytest.raises(ms.MstabError):
+        other.recycle_import(blob)
+    same = ms.Solver(Ag, 4, 2, p_host=P.copy())
+    same.recycle_import(blob)
+    for h in (a, other, same):
+        h.close()
