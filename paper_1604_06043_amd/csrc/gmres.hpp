@@ -60,7 +60,7 @@ __global__ __launch_bounds__(BLOCK) void k_gm_dots(int64_t ld, const T *__restri
     }
     block_partials<CH + 1>(acc, CH + 1, part, stride);
     __shared__ double tot[CH + 1];
-    if (!last_block_reduce(part, stride, CH + 1, &ctl->counter[3], tot)) return;
+    if (!last_block_reduce(part, stride, CH + 1, &ctl->counter[3], ctl->gcount[3], tot)) return;
     if (threadIdx.x != 0) return;
     for (int i = 0; i < nv; ++i) out[j0 + i] = tot[i];
     ctl->st.aux = tot[CH];
@@ -93,7 +93,7 @@ __global__ __launch_bounds__(BLOCK) void k_gm_axpy(int64_t ld, const T *__restri
     if (!norm) return;
     block_partials<1>(acc, 1, part, stride);
     __shared__ double tot[1];
-    if (!last_block_reduce(part, stride, 1, &ctl->counter[3], tot)) return;
+    if (!last_block_reduce(part, stride, 1, &ctl->counter[3], ctl->gcount[3], tot)) return;
     if (threadIdx.x != 0) return;
     ctl->st.aux = tot[0];
     if (!isfinite(tot[0])) ctl->st.flags |= FLAG_NONFINITE;

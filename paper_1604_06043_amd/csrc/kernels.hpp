@@ -38,6 +38,8 @@ struct Status {
     int64_t mv;     // products with A performed by the iteration kernels
 };
 
+constexpr int GROUP_PAD = 32;   // unsigned ints per group arrival counter (a 128-byte line)
+
 struct Ctl {
     Status st;
     double thr2;                        // tol^2 ||b||^2, set by the host
@@ -53,6 +55,9 @@ struct Ctl {
     double chol[MAXS][MAXS];            // Cholesky factor L (lower) of U^T U of fetched data
     int32_t chol_ok;                    // U^T U was numerically positive definite
     unsigned int counter[4];            // last-workgroup counters (zero between launches)
+    // per counter, the arrival counters of eight workgroup groups, one
+    // 128-byte line each (zero between launches)
+    alignas(128) unsigned int gcount[4][8 * GROUP_PAD];
 };
 
 // ---------------------------------------------------------------------------
@@ -92,6 +97,20 @@ struct PBasis {
 __device__ __forceinline__ double pval(const PBasis &p, uint32_t row, int q)
 {
     return p.m ? p.m[(int64_t)q * p.ld + row] : pval(p.key, row, q);
+}
+
+// The same with the choice fixed at compile time where a kernel has hoisted
+// it out of its row loop: PM = 1 the caller's matrix, 0 the generator, -1
+// decided per call.
+template <int PM>
+__device__ __forceinline__ double pval_m(const PBasis &p, uint32_t row, int q)
+{
+    if constexpr (PM == 1)
+        return p.m[(int64_t)q * p.ld + row];
+    else if constexpr (PM == 0)
+        return pval(p.key, row, q);
+    else
+        return pval(p, row, q);
 }
 
 __device__ __forceinline__ double fmaT(double a, double b, double c) { return __builtin_fma(a, b, c); }
@@ -265,10 +284,11 @@ __device__ __forceinline__ void wave_store(int m, bool ok, double c, double *out
 // atomic loads and stores, which are coherent across the device's dies
 // without the whole-cache write-back that an agent-scope fence costs here.
 // A writer waits for its partial stores to complete before the workgroup
-// barrier; thread 0 then bumps the counter.  The workgroup that sees the
-// count reach gridDim.x - 1 reads every partial (atomically, agent scope) and
-// adds them in a fixed order, so the totals do not depend on which workgroup
-// finishes last.
+// barrier; thread 0 then arrives, in two stages (its group's counter, and
+// the group's last workgroup the launch's counter: no single address takes
+// every workgroup's atomic).  The workgroup that completes the last group
+// reads every partial (atomically, agent scope) and adds them in a fixed
+// order, so the totals do not depend on which workgroup finishes last.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void part_store(double *p, double v)
 {
@@ -289,21 +309,33 @@ constexpr int MAX_PARTIAL_BLOCKS = 1024;
 
 template <int NT = BLOCK>
 __device__ bool last_block_reduce(const double *part, int stride, int nv, unsigned int *counter,
-                                  double *tot)
+                                  unsigned int *groups, double *tot)
 {
     constexpr int NW = NT / 64;
     __shared__ int s_last;
     __syncthreads();
     if (threadIdx.x == 0) {
-        unsigned int prev = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED,
-                                                   __HIP_MEMORY_SCOPE_AGENT);
-        s_last = (prev == gridDim.x - 1);
+        // arrival in two stages: workgroup b counts on the counter of group
+        // b mod 8, and the last of each group on the launch's counter, so that
+        // no counter takes more than an eighth of the grid's atomics
+        const unsigned G = gridDim.x < 8u ? gridDim.x : 8u;
+        const unsigned g = blockIdx.x % G;
+        const unsigned gs = gridDim.x / G + (g < gridDim.x % G ? 1u : 0u);
+        unsigned int *gc = groups + g * GROUP_PAD;
+        const unsigned prev = __hip_atomic_fetch_add(gc, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        bool last = false;
+        if (prev == gs - 1) {
+            __hip_atomic_store(gc, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const unsigned p2 = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            last = (p2 == G - 1);
+        }
+        s_last = last;
     }
     __syncthreads();
     if (!s_last) return false;
-    // the partials were stored coherently and completed before each counter
-    // increment; one acquire here lets plain (batched) loads see them
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    // the partials were stored coherently and completed before their
+    // workgroups arrived; agent-scope loads read them past this die's cache
+    // (cheaper here than an acquire fence and plain loads)
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int nb = (int)gridDim.x;
     for (int v = wave; v < nv; v += NW) {
@@ -312,7 +344,7 @@ __device__ bool last_block_reduce(const double *part, int stride, int nv, unsign
 #pragma unroll
         for (int m = 0; m < MAX_PARTIAL_BLOCKS / 64; ++m) {
             const int b = lane + 64 * m;
-            a[m] = (b < nb) ? pv[b] : 0.0;
+            a[m] = (b < nb) ? part_load(pv + b) : 0.0;
         }
 #pragma unroll
         for (int h = MAX_PARTIAL_BLOCKS / 128; h > 0; h >>= 1)
@@ -586,7 +618,7 @@ __global__ __launch_bounds__(BLOCK) void k_dia_range(int64_t n, int nd, const ui
 // for all 64 lanes; the row lengths only select which products are added.
 // Adding nothing for a padding entry keeps the CSR-order sum exact.
 // y[r] (and the residual form b[r] - sum) plus the row's share of the partials.
-template <typename T, int S>
+template <typename T, int S, int PM = -1>
 __device__ __forceinline__ void spmv_row_out(int64_t r, T sum, bool resid, const T *__restrict__ b,
                                              T *__restrict__ y, PBasis pkey,
                                              double (&vals)[S + 2])
@@ -602,7 +634,7 @@ __device__ __forceinline__ void spmv_row_out(int64_t r, T sum, bool resid, const
     const double yd = (double)yv;
     vals[S] += yd * yd;
 #pragma unroll
-    for (int j = 0; j < S; ++j) vals[j] += pval(pkey, (uint32_t)r, j) * yd;
+    for (int j = 0; j < S; ++j) vals[j] += pval_m<PM>(pkey, (uint32_t)r, j) * yd;
 }
 
 // The end of every product kernel: workgroup partials of P^T y, ||y||^2 and
@@ -616,7 +648,7 @@ __device__ void spmv_finalize(double (&vals)[S + 2], Ctl *ctl, double *part, int
     const int nv = S + 2;
     block_partials<S + 2, SPMV_BLOCK>(vals, nv, part, stride);
     __shared__ double tot[MAXS + 2];
-    if (!last_block_reduce<SPMV_BLOCK>(part, stride, nv, &ctl->counter[0], tot)) return;
+    if (!last_block_reduce<SPMV_BLOCK>(part, stride, nv, &ctl->counter[0], ctl->gcount[0], tot)) return;
     if (threadIdx.x >= 64) return;   // wavefront 0 finalizes
 
     const int ri = lane >> 3, cj = lane & 7;
@@ -707,26 +739,17 @@ __device__ void spmv_finalize(double (&vals)[S + 2], Ctl *ctl, double *part, int
 
 // TM: type of the stored matrix values (T, or float for FP64 vectors with an
 // FP32 copy of the matrix); each value is converted to T before its product.
-template <typename T, int S, typename TM = T>
-__global__ __launch_bounds__(SPMV_BLOCK) void k_spmv(int64_t n, const int32_t *__restrict__ rp,
-                                                     const int64_t *__restrict__ slice_ptr,
-                                                     const int32_t *__restrict__ scol,
-                                                     const TM *__restrict__ sval,
-                                                     const T *__restrict__ x,
-                                                     T *__restrict__ y,
-                                                     const T *__restrict__ b, Ctl *ctl,
-                                                     double *part, int stride, SpmvArgs a)
+template <typename T, int S, typename TM, int PM>
+__device__ __forceinline__ void sell_rows(int64_t n, const int32_t *__restrict__ rp,
+                                          const int64_t *__restrict__ slice_ptr,
+                                          const int32_t *__restrict__ scol, const TM *__restrict__ sval,
+                                          const T *__restrict__ x, T *__restrict__ y,
+                                          const T *__restrict__ b, bool resid, PBasis pkey,
+                                          double (&vals)[S + 2])
 {
 #pragma clang fp contract(off)
-    if (ctl->st.flags) return;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const bool resid = (a.act == ACT_RESID || a.act == ACT_TRUE);
-
-    double vals[S + 2];
-#pragma unroll
-    for (int v = 0; v < S + 2; ++v) vals[v] = 0.0;
-
     const int64_t nslices = (n + SLICE - 1) / SLICE;
     for (int64_t t = (int64_t)blockIdx.x * (SPMV_BLOCK / SLICE) + wave; t < nslices;
          t += (int64_t)gridDim.x * (SPMV_BLOCK / SLICE)) {
@@ -759,8 +782,30 @@ __global__ __launch_bounds__(SPMV_BLOCK) void k_spmv(int64_t n, const int32_t *_
                     sum = (j0 + j < len) ? nsum : sum;
                 }
         }
-        if (valid) spmv_row_out<T, S>(r, sum, resid, b, y, a.pkey, vals);
+        if (valid) spmv_row_out<T, S, PM>(r, sum, resid, b, y, pkey, vals);
     }
+}
+
+template <typename T, int S, typename TM = T>
+__global__ __launch_bounds__(SPMV_BLOCK) void k_spmv(int64_t n, const int32_t *__restrict__ rp,
+                                                     const int64_t *__restrict__ slice_ptr,
+                                                     const int32_t *__restrict__ scol,
+                                                     const TM *__restrict__ sval,
+                                                     const T *__restrict__ x,
+                                                     T *__restrict__ y,
+                                                     const T *__restrict__ b, Ctl *ctl,
+                                                     double *part, int stride, SpmvArgs a)
+{
+    if (ctl->st.flags) return;
+    const bool resid = (a.act == ACT_RESID || a.act == ACT_TRUE);
+    double vals[S + 2];
+#pragma unroll
+    for (int v = 0; v < S + 2; ++v) vals[v] = 0.0;
+    // the source of P's entries is uniform over the launch: chosen once here
+    if (a.pkey.m)
+        sell_rows<T, S, TM, 1>(n, rp, slice_ptr, scol, sval, x, y, b, resid, a.pkey, vals);
+    else
+        sell_rows<T, S, TM, 0>(n, rp, slice_ptr, scol, sval, x, y, b, resid, a.pkey, vals);
     spmv_finalize<S>(vals, ctl, part, stride, a);
 }
 
@@ -798,7 +843,7 @@ __device__ __forceinline__ void dia_add8(int nd, int d0, uint32_t m, const T (&v
         }
 }
 
-template <bool CST, typename T, int S, typename TM>
+template <bool CST, typename T, int S, typename TM, int PM>
 __device__ __forceinline__ void dia_rows(int64_t n, int nd, const DiaOffsets &doff, const DiaConst &cv,
                                          const uint16_t *__restrict__ mask,
                                          const TM *__restrict__ dval, const T *__restrict__ x,
@@ -814,7 +859,7 @@ __device__ __forceinline__ void dia_rows(int64_t n, int nd, const DiaOffsets &do
             dia_load8<CST, T, TM>(r, n, nd, d0, doff, cv, dval, x, v, xv);
             dia_add8(nd, d0, m, v, xv, sum);
         }
-        spmv_row_out<T, S>(r, sum, resid, b, y, pkey, vals);
+        spmv_row_out<T, S, PM>(r, sum, resid, b, y, pkey, vals);
     }
 }
 
@@ -829,7 +874,7 @@ __device__ __forceinline__ void dia_rows(int64_t n, int nd, const DiaOffsets &do
 #ifndef MSTAB_DIA_RPI
 #define MSTAB_DIA_RPI 1
 #endif
-template <typename T, int S, int ND, int RPI = MSTAB_DIA_RPI>
+template <typename T, int S, int ND, int PM, int RPI = MSTAB_DIA_RPI>
 __device__ __forceinline__ void dia_rows_const(int64_t n, const DiaOffsets &doff, const DiaConst &cv,
                                                const uint16_t *__restrict__ mask, const T *__restrict__ x,
                                                T *__restrict__ y, const T *__restrict__ b, bool resid,
@@ -862,19 +907,27 @@ __device__ __forceinline__ void dia_rows_const(int64_t n, const DiaOffsets &doff
         // the presence mask is needed only by the sum: keep its load behind the
         // gathers, so that waiting for it does not hold their issue back
         asm volatile("" ::: "memory");
+        uint32_t m[RPI];
+#pragma unroll
+        for (int u = 0; u < RPI; ++u) {
+            const int32_t r = r0 + u * stride;
+            m[u] = mask[r < n32 ? r : r0];
+        }
+        // every gather and mask load issued before the first sum: without this
+        // the scheduler starts summing after four gathers and holds the rest back
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int u = 0; u < RPI; ++u) {
             const int32_t r = r0 + u * stride;
             if (u > 0 && r >= n32) break;
-            const uint32_t m = mask[r];
             T sum = (T)0;
 #pragma unroll
             for (int d = 0; d < ND; ++d) {
                 const T prod = cst[d] * xv[u][d];
                 const T nsum = sum + prod;
-                sum = ((m >> d) & 1u) ? nsum : sum;
+                sum = ((m[u] >> d) & 1u) ? nsum : sum;
             }
-            spmv_row_out<T, S>(r, sum, resid, b, y, pkey, vals);
+            spmv_row_out<T, S, PM>(r, sum, resid, b, y, pkey, vals);
         }
     }
 }
@@ -905,7 +958,11 @@ __attribute__((amdgpu_waves_per_eu(sizeof(TM) == 4 ? 8 : 1))) void k_spmv_dia(in
     double vals[S + 2];
 #pragma unroll
     for (int v = 0; v < S + 2; ++v) vals[v] = 0.0;
-    dia_rows<CST, T, S, TM>(n, nd, doff, cv, mask, dval, x, y, b, resid, a.pkey, vals);
+    // the source of P's entries is uniform over the launch: chosen once here
+    if (a.pkey.m)
+        dia_rows<CST, T, S, TM, 1>(n, nd, doff, cv, mask, dval, x, y, b, resid, a.pkey, vals);
+    else
+        dia_rows<CST, T, S, TM, 0>(n, nd, doff, cv, mask, dval, x, y, b, resid, a.pkey, vals);
     spmv_finalize<S>(vals, ctl, part, stride, a);
 }
 
@@ -924,7 +981,11 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 8 : 1))) void k_spmv_dia_con
     double vals[S + 2];
 #pragma unroll
     for (int v = 0; v < S + 2; ++v) vals[v] = 0.0;
-    dia_rows_const<T, S, ND>(n, doff, cv, mask, x, y, b, resid, a.pkey, vals);
+    // the source of P's entries is uniform over the launch: chosen once here
+    if (a.pkey.m)
+        dia_rows_const<T, S, ND, 1>(n, doff, cv, mask, x, y, b, resid, a.pkey, vals);
+    else
+        dia_rows_const<T, S, ND, 0>(n, doff, cv, mask, x, y, b, resid, a.pkey, vals);
     spmv_finalize<S>(vals, ctl, part, stride, a);
 }
 
@@ -1210,7 +1271,7 @@ __device__ void gram_finalize(double (&acc)[(L + 1) * (L + 2) / 2], Ctl *ctl, do
     constexpr int NV = (L + 1) * (L + 2) / 2;
     block_partials<NV>(acc, NV, part, stride);
     __shared__ double tot[NV];
-    if (!last_block_reduce(part, stride, NV, &ctl->counter[1], tot)) return;
+    if (!last_block_reduce(part, stride, NV, &ctl->counter[1], ctl->gcount[1], tot)) return;
     if (threadIdx.x >= 64) return;   // wavefront 0 finalizes
     const int lane = threadIdx.x, ri = lane >> 3, cj = lane & 7;
     // pair (i, j), i <= j, sits at index i*(L+1) - i*(i-1)/2 + (j - i)
@@ -1406,7 +1467,7 @@ __global__ __launch_bounds__(BLOCK) void k_poly(int64_t n, int64_t ld, int ell_r
     }
     block_partials<NV>(acc, NV, part, stride);
     __shared__ double tot[NV];
-    if (!last_block_reduce(part, stride, NV, &ctl->counter[2], tot)) return;
+    if (!last_block_reduce(part, stride, NV, &ctl->counter[2], ctl->gcount[2], tot)) return;
     if (threadIdx.x >= 64) return;   // wavefront 0 finalizes
     const int lane = threadIdx.x, ri = lane >> 3, cj = lane & 7;
     bool finite = true;
@@ -1515,7 +1576,7 @@ __global__ __launch_bounds__(BLOCK) void k_dots(int64_t ld, const T *__restrict_
         if (j == nu) vals[j] = acc[MAXS];
     block_partials<MAXS + 1>(vals, nu + 1, part, stride);
     __shared__ double tot[MAXS + 1];
-    if (!last_block_reduce(part, stride, nu + 1, &ctl->counter[3], tot)) return;
+    if (!last_block_reduce(part, stride, nu + 1, &ctl->counter[3], ctl->gcount[3], tot)) return;
     if (threadIdx.x != 0) return;
     for (int j = 0; j < nu; ++j) ctl->h[j] = tot[j];
     ctl->st.aux = tot[nu];
@@ -1631,7 +1692,7 @@ __global__ __launch_bounds__(BLOCK) void k_project(int64_t n, const T *__restric
     for (int v = 0; v <= MAXS; ++v) vals[v] = (v < s) ? acc[v] : ((v == s) ? acc[MAXS] : 0.0);
     block_partials<MAXS + 1>(vals, s + 1, part, stride);
     __shared__ double tot[MAXS + 1];
-    if (!last_block_reduce(part, stride, s + 1, &ctl->counter[3], tot)) return;
+    if (!last_block_reduce(part, stride, s + 1, &ctl->counter[3], ctl->gcount[3], tot)) return;
     if (threadIdx.x != 0) return;
     if (dst == 0) {
         for (int a = 0; a < s; ++a) ctl->ptv[0][q][a] = tot[a];
@@ -1679,7 +1740,7 @@ __global__ __launch_bounds__(BLOCK) void k_chol_gram(int64_t ld, const T *__rest
     }
     block_partials<NV>(acc, NV, part, stride);
     __shared__ double tot[NV];
-    if (!last_block_reduce(part, stride, NV, &ctl->counter[3], tot)) return;
+    if (!last_block_reduce(part, stride, NV, &ctl->counter[3], ctl->gcount[3], tot)) return;
     if (threadIdx.x != 0) return;
     double G[S][S], L[S][S];
     int v = 0;

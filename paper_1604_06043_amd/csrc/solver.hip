@@ -3089,6 +3089,7 @@ unsigned char *scratch_on_current_device()
 __global__ void k_clear_counters(Ctl *ctl)
 {
     if (threadIdx.x < 4) ctl->counter[threadIdx.x] = 0u;
+    for (int i = threadIdx.x; i < 4 * 8 * GROUP_PAD; i += blockDim.x) (&ctl->gcount[0][0])[i] = 0u;
 }
 
 }  // namespace
