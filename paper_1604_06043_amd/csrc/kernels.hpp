@@ -646,13 +646,27 @@ __device__ void spmv_finalize(double (&vals)[S + 2], Ctl *ctl, double *part, int
 {
     const int lane = threadIdx.x & 63;
     const int nv = S + 2;
+    const int ri = lane >> 3, cj = lane & 7;
+    const int s = a.s;
+    // the small solve's operands that earlier launches wrote (P^T V columns
+    // other than this product's own, P^T r^(k+1)) are loaded before the
+    // reduction, so that the last workgroup does not wait for them after it
+    double pm = 0.0, py = 0.0;
+    if (threadIdx.x < 64) {
+        const bool in = ri < s && cj < s;
+        if (a.act == ACT_R) {
+            if (in) pm = ctl->ptv[a.k][cj][ri];
+        } else if (a.act == ACT_V && (a.q + 1 < s || a.k + 1 < a.ell)) {
+            if (in && cj != a.q)
+                pm = (a.q + 1 < s && cj > a.q) ? ctl->ptv[a.k][cj][ri] : ctl->ptv[a.k + 1][cj][ri];
+            if (ri < s) py = ctl->ptr[a.k + 1][ri];
+        }
+    }
     block_partials<S + 2, SPMV_BLOCK>(vals, nv, part, stride);
     __shared__ double tot[MAXS + 2];
     if (!last_block_reduce<SPMV_BLOCK>(part, stride, nv, &ctl->counter[0], ctl->gcount[0], tot)) return;
     if (threadIdx.x >= 64) return;   // wavefront 0 finalizes
 
-    const int ri = lane >> 3, cj = lane & 7;
-    const int s = a.s;
     bool finite = true;
     for (int v = 0; v < nv; ++v) finite = finite && isfinite(tot[v]);
     int32_t flags = finite ? 0 : FLAG_NONFINITE, where = WHERE_NONE;
@@ -689,8 +703,7 @@ __device__ void spmv_finalize(double (&vals)[S + 2], Ctl *ctl, double *part, int
         if (lane < s) ctl->ptr[a.k + 1][lane] = tot[lane];
         if (lane == 0) ctl->st.mv += 1;
         if (!flags) {
-            const bool in = ri < s && cj < s;
-            const double m = in ? ctl->ptv[a.k][cj][ri] : 0.0;
+            const double m = pm;   // (P^T V^(k))[ri][cj], zero outside s x s
             const double yv = ri < s ? tot[ri] : 0.0;
             double c;
             const bool ok = wave_lu(s, m, yv, c);
@@ -708,19 +721,18 @@ __device__ void spmv_finalize(double (&vals)[S + 2], Ctl *ctl, double *part, int
             double m = 0.0, yv = 0.0;
             double *out;
             int w;
+            // eta_{q+1} at level k: columns p <= q from level k+1, p > q from
+            // level k; gamma of level k+1: (P^T V^(k+1)) gamma = P^T r^(k+1).
+            // Column q is this product's; the others were preloaded (pm).
+            if (in) m = (cj == a.q) ? tot[ri] : pm;
             if (a.q + 1 < s) {
-                // eta_{q+1} at level k: columns p <= q from level k+1, p > q from level k
-                if (in) m = (cj == a.q) ? tot[ri] : (cj < a.q ? ctl->ptv[a.k + 1][cj][ri]
-                                                              : ctl->ptv[a.k][cj][ri]);
                 out = ctl->eta;
                 w = WHERE_ETA;
             } else {
-                // gamma of level k+1: (P^T V^(k+1)) gamma = P^T r^(k+1)
-                if (in) m = (cj == a.q) ? tot[ri] : ctl->ptv[a.k + 1][cj][ri];
                 out = ctl->gamma;
                 w = WHERE_GAMMA;
             }
-            if (ri < s) yv = ctl->ptr[a.k + 1][ri];
+            yv = py;
             double c;
             const bool ok = wave_lu(s, m, yv, c);
             wave_store(s, ok, c, out);
