@@ -101,7 +101,10 @@ def cpu_baseline(cd, s, ell, mvs_per_system, threads):
 
 def class_kernels(cls: str, s: int, ell: int):
     """The kernels of one timing class of the FP64 solver."""
-    return {"spmv": [f"k_spmv_dia_const<double, {s}, 7>", f"k_spmv_dia_const<double, {s}, 5>",
+    return {"spmv": [f"k_spmv_dia_pair<double, {s}, double, true, 7>", f"k_spmv_dia_pair<double, {s}, double, true, 5>",
+                     f"k_spmv_dia_pair<double, {s}, double, false, 7>",
+                     f"k_spmv_dia_pair<double, {s}, double, false, 5>",
+                     f"k_spmv_dia_const<double, {s}, 7>", f"k_spmv_dia_const<double, {s}, 5>",
                      f"k_spmv_dia<double, {s}, double, true>", f"k_spmv_dia<double, {s}, double, false>",
                      f"k_spmv<double, {s}, double>"],
             "eta": [f"k_eta<double, {s}>", f"k_eta_low<double, {s}>", f"k_eta_low_gamma<double, {s}>"],
@@ -316,6 +319,8 @@ def main():
         for key, prec in (("f32_refine", ms.PREC_F32_REFINE), ("f32_matrix", ms.PREC_F32_MATRIX)):
             rec, xv = variant(key, method=ms.METHOD_MSTAB, precision=prec)
             rec["rel_err_vs_f64_path_last_system"] = float(torch.linalg.norm(xv - x64) / torch.linalg.norm(x64))
+            log(f"[bench] {key}: |x - x64| {float(torch.linalg.norm(xv - x64)):.3e}, |x64| "
+                f"{float(torch.linalg.norm(x64)):.3e}, max |x - x64| {float((xv - x64).abs().max()):.3e}")
             variants[key] = rec
     c3 = None
     if not args.no_c3:

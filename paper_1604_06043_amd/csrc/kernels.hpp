@@ -944,6 +944,125 @@ __device__ __forceinline__ void dia_rows_const(int64_t n, const DiaOffsets &doff
     }
 }
 
+// two-element vectors of the compiler's own (usable with the nontemporal loads)
+typedef double pair_d __attribute__((ext_vector_type(2)));
+typedef float pair_f __attribute__((ext_vector_type(2)));
+template <typename T> struct Vec2;
+template <> struct Vec2<double> { using type = pair_d; };
+template <> struct Vec2<float> { using type = pair_f; };
+
+// One row's share of the partials, in spmv_row_out's order (no memory
+// operations: the caller has loaded b and stores y).
+template <typename T, int S, int PM>
+__device__ __forceinline__ void row_acc(int64_t r, T yv, T bv, bool resid, PBasis pkey, double (&vals)[S + 2])
+{
+#pragma clang fp contract(off)
+    if (resid) vals[S + 1] += (double)bv * (double)bv;
+    const double yd = (double)yv;
+    vals[S] += yd * yd;
+#pragma unroll
+    for (int j = 0; j < S; ++j) vals[j] += pval_m<PM>(pkey, (uint32_t)r, j) * yd;
+}
+
+// Diagonal storage with ND diagonals (7 or 5), two consecutive rows per
+// thread: each even offset's two x values are one 8- or 16-byte load, and the
+// offsets -1, 0, +1 of both rows come from three aligned pairs; with values
+// streamed (CST false) each diagonal's two values are one load too.  Half the
+// memory instructions of one row per thread.  Needs n even, the offsets -1, 0,
+// +1 in the middle and every other offset even (pairs_ok on the host).  Each
+// row's products and sum are those of dia_rows and dia_rows_const, so y is
+// the same bit for bit; the partials add row 2p before row 2p + 1.
+template <bool CST, typename T, int S, typename TM, int ND, int PM>
+__device__ __forceinline__ void dia_pairs(int64_t n, const DiaOffsets &doff, const DiaConst &cv,
+                                          const uint16_t *__restrict__ mask, const TM *__restrict__ dval,
+                                          const T *__restrict__ x, T *__restrict__ y,
+                                          const T *__restrict__ b, bool resid, PBasis pkey,
+                                          double (&vals)[S + 2])
+{
+#pragma clang fp contract(off)
+    using V2 = typename Vec2<T>::type;
+    using M2 = typename Vec2<TM>::type;
+    constexpr int C = ND / 2;
+    const int32_t n32 = (int32_t)n;
+    const int32_t np = n32 / 2;
+    int32_t off[ND];
+    T cst[ND];
+#pragma unroll
+    for (int d = 0; d < ND; ++d) {
+        off[d] = (d == C - 1) ? -2 : (d == C + 1) ? 2 : (int32_t)doff.off[d];
+        cst[d] = (T)cv.c[d];
+    }
+    const int32_t stride = (int32_t)(gridDim.x * SPMV_BLOCK);
+    for (int32_t p = (int32_t)(blockIdx.x * SPMV_BLOCK + threadIdx.x); p < np; p += stride) {
+        const int32_t r0 = 2 * p;
+        V2 xo[ND];
+        M2 mv[ND];
+#pragma unroll
+        for (int d = 0; d < ND; ++d) {
+            const uint32_t c = (uint32_t)(r0 + off[d]);
+            xo[d] = *reinterpret_cast<const V2 *>(x + (c < (uint32_t)n32 ? c : (uint32_t)r0));
+            if constexpr (!CST)   // the matrix is streamed once per product: keep it out of the caches
+                mv[d] = __builtin_nontemporal_load(reinterpret_cast<const M2 *>(dval + dia_index(r0, d, ND)));
+        }
+        // the mask, b and the sums come after every load has been issued
+        asm volatile("" ::: "memory");
+        const uint32_t m2 = *reinterpret_cast<const uint32_t *>(mask + r0);
+        V2 bv;
+        if (resid) bv = *reinterpret_cast<const V2 *>(b + r0);
+        __builtin_amdgcn_sched_barrier(0);
+        T x0[ND], x1[ND];
+#pragma unroll
+        for (int d = 0; d < ND; ++d) {
+            if (d == C - 1) { x0[d] = xo[C - 1].y; x1[d] = xo[C].x; }
+            else if (d == C) { x0[d] = xo[C].x; x1[d] = xo[C].y; }
+            else if (d == C + 1) { x0[d] = xo[C].y; x1[d] = xo[C + 1].x; }
+            else { x0[d] = xo[d].x; x1[d] = xo[d].y; }
+        }
+        const uint32_t m0 = m2 & 0xFFFFu, m1 = m2 >> 16;
+        T s0 = (T)0, s1 = (T)0;
+#pragma unroll
+        for (int d = 0; d < ND; ++d) {
+            const T a0 = CST ? cst[d] : (T)mv[d].x, a1 = CST ? cst[d] : (T)mv[d].y;
+            const T p0 = a0 * x0[d], p1 = a1 * x1[d];
+            const T n0 = s0 + p0, n1 = s1 + p1;
+            s0 = ((m0 >> d) & 1u) ? n0 : s0;
+            s1 = ((m1 >> d) & 1u) ? n1 : s1;
+        }
+        V2 yv;
+        yv.x = resid ? bv.x - s0 : s0;
+        yv.y = resid ? bv.y - s1 : s1;
+        *reinterpret_cast<V2 *>(y + r0) = yv;
+        row_acc<T, S, PM>(r0, yv.x, resid ? bv.x : (T)0, resid, pkey, vals);
+        row_acc<T, S, PM>(r0 + 1, yv.y, resid ? bv.y : (T)0, resid, pkey, vals);
+    }
+}
+
+template <typename T, int S, typename TM, bool CST, int ND>
+__global__ __launch_bounds__(SPMV_BLOCK)
+__attribute__((amdgpu_waves_per_eu(sizeof(TM) == 4 ? 8 : 1))) void k_spmv_dia_pair(int64_t n, DiaOffsets doff,
+                                                                                    DiaConst cv,
+                                                                                    const uint16_t *__restrict__ mask,
+                                                                                    const TM *__restrict__ dval,
+                                                                                    const T *__restrict__ x,
+                                                                                    T *__restrict__ y,
+                                                                                    const T *__restrict__ b, Ctl *ctl,
+                                                                                    double *part, int stride,
+                                                                                    SpmvArgs a)
+{
+    if (ctl->st.flags) return;
+    const bool resid = (a.act == ACT_RESID || a.act == ACT_TRUE);
+    double vals[S + 2];
+#pragma unroll
+    for (int v = 0; v < S + 2; ++v) vals[v] = 0.0;
+    // the source of P's entries is uniform over the launch: chosen once here
+    if (a.pkey.m)
+        dia_pairs<CST, T, S, TM, ND, 1>(n, doff, cv, mask, dval, x, y, b, resid, a.pkey, vals);
+    else
+        dia_pairs<CST, T, S, TM, ND, 0>(n, doff, cv, mask, dval, x, y, b, resid, a.pkey, vals);
+    spmv_finalize<S>(vals, ctl, part, stride, a);
+}
+
+
 // The same product for a matrix in diagonal storage (stencil matrices): one
 // thread per row, the diagonals' values of 64 consecutive rows one 512-byte
 // read each (or, for constant diagonals, no matrix reads at all beyond the

@@ -594,12 +594,48 @@ double spmv_bytes(const Sell<TM> &A, bool with_b, double vsize)
            vecs;
 }
 
+// The two-rows-per-thread product applies: diagonal storage, n even, the
+// offsets -1, 0, +1 in the middle and the others even, and the vectors, the
+// mask and the values aligned for pair loads.
+template <typename T, typename TM>
+bool pairs_ok(const Sell<TM> &A, const T *x, const T *y, const T *b)
+{
+    if (A.nd != 7 && A.nd != 5) return false;
+    const int C = A.nd / 2;
+    if (A.n % 2 || A.doff.off[C] != 0 || A.doff.off[C - 1] != -1 || A.doff.off[C + 1] != 1) return false;
+    for (int d = 0; d < A.nd; ++d)
+        if (d != C - 1 && d != C + 1 && (A.doff.off[d] % 2)) return false;
+    const uintptr_t al = 2 * sizeof(T);
+    return (uintptr_t)x % al == 0 && (uintptr_t)y % al == 0 && (!b || (uintptr_t)b % al == 0) &&
+           (uintptr_t)A.dmask % 4 == 0 && (A.dconst || (uintptr_t)A.dval % (2 * sizeof(TM)) == 0);
+}
+
 // TM: value type of the stored matrix (T, or float for an FP32 copy used with
 // FP64 vectors)
 template <typename T, typename TM = T>
 void launch_spmv(int grid, hipStream_t stream, const Sell<TM> &A, const T *x, T *y, const T *b,
                  Ctl *ctl, double *part, SpmvArgs a)
 {
+    if ((A.nd == 7 || A.nd == 5) && pairs_ok(A, x, y, b)) {
+        // two rows per thread (constant or streamed diagonals, 7 or 5 of them)
+        switch (a.s) {
+#define LAUNCH(S, CST, ND)                                                                            \
+    hipLaunchKernelGGL((k_spmv_dia_pair<T, S, TM, CST, ND>), dim3(grid), dim3(SPMV_BLOCK), 0, stream, \
+                       A.n, A.doff, A.cv, A.dmask, (const TM *)A.dval, x, y, b, ctl, part, PART_STRIDE, a)
+#define CASE(S)                                                                                       \
+    case S:                                                                                           \
+        if (A.dconst) {                                                                               \
+            if (A.nd == 7) LAUNCH(S, true, 7); else LAUNCH(S, true, 5);                               \
+        } else {                                                                                      \
+            if (A.nd == 7) LAUNCH(S, false, 7); else LAUNCH(S, false, 5);                             \
+        }                                                                                             \
+        break;
+            CASE(0) CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
+#undef CASE
+#undef LAUNCH
+        }
+        return;
+    }
     if (A.nd > 0 && A.dconst && (A.nd == 7 || A.nd == 5)) {
         switch (a.s) {
 #define CASE(S)                                                                                      \
