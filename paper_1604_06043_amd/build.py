@@ -1,19 +1,21 @@
 """Build the HIP library libmstab.so for gfx950 (in-tree).
 
 ``python -m paper_1604_06043_amd.build`` or :func:`build`.  Every call
-compiles from scratch.
+compiles from scratch: each source to an object in parallel (in a temporary
+folder), then one link.
 """
 from __future__ import annotations
 
 import os
 import shutil
 import subprocess
+import tempfile
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmstab.so")
-SOURCES = ["solver.hip", "assemble.hip", "cnn.hip"]
+SOURCES = ["solver.hip", "wg.hip", "assemble.hip", "cnn.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
@@ -31,13 +33,26 @@ def hipcc() -> str:
 
 
 def build(verbose: bool = False) -> str:
-    srcs = [os.path.join(CSRC, s) for s in SOURCES]
+    cc = hipcc()
+    inc = ["-I", os.path.join(ROOT, "include"), "-I", CSRC]
+    compile_flags = [f for f in HIPCC_FLAGS if f != "-shared"]
     tmp = LIB + ".tmp"
-    cmd = [hipcc(), *HIPCC_FLAGS, "-I", os.path.join(ROOT, "include"), "-I", CSRC,
-           "-o", tmp, *srcs]
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    subprocess.run(cmd, check=True)
+    with tempfile.TemporaryDirectory(prefix="mstab_build_") as td:
+        objs, procs = [], []
+        for src in SOURCES:
+            obj = os.path.join(td, os.path.splitext(src)[0] + ".o")
+            cmd = [cc, *compile_flags, *inc, "-c", "-o", obj, os.path.join(CSRC, src)]
+            if verbose:
+                print(" ".join(cmd), flush=True)
+            procs.append((src, subprocess.Popen(cmd)))
+            objs.append(obj)
+        failed = [src for src, p in procs if p.wait() != 0]
+        if failed:
+            raise subprocess.CalledProcessError(1, f"hipcc -c {' '.join(failed)}")
+        cmd = [cc, *HIPCC_FLAGS, "-o", tmp, *objs]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.run(cmd, check=True)
     os.replace(tmp, LIB)
     return LIB
 

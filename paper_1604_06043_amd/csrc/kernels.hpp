@@ -469,7 +469,7 @@ struct Sell {
 // its row.  The row pointer has already been checked on the host (rp[0] = 0,
 // non-decreasing, rp[n] = nnz), so every read stays inside col_idx[0, nnz).
 // *bad (zero beforehand) is set to 1 on the first violation.
-__global__ __launch_bounds__(BLOCK) void k_csr_check(int64_t n, const int32_t *__restrict__ rp,
+static __global__ __launch_bounds__(BLOCK) void k_csr_check(int64_t n, const int32_t *__restrict__ rp,
                                                      const int32_t *__restrict__ ci, int *bad)
 {
     for (int64_t r = (int64_t)blockIdx.x * BLOCK + threadIdx.x; r < n;
@@ -510,7 +510,7 @@ __global__ __launch_bounds__(BLOCK) void k_to_sell(int64_t n, const int32_t *__r
 // table of MAX_DIAG slots.  Every thread probes the slots in the same order
 // and claims an empty one by compare-and-swap, so a value enters once; a
 // value that finds no slot sets *overflow.
-__global__ __launch_bounds__(BLOCK) void k_dia_offsets(int64_t n, const int32_t *__restrict__ rp,
+static __global__ __launch_bounds__(BLOCK) void k_dia_offsets(int64_t n, const int32_t *__restrict__ rp,
                                                        const int32_t *__restrict__ ci,
                                                        unsigned long long *table, int *overflow)
 {
@@ -1633,13 +1633,13 @@ enum : int32_t {
     SMALL_CLEAR = 2            // clear flags
 };
 
-__global__ void k_set_thr2(Ctl *ctl, double thr2)
+static __global__ void k_set_thr2(Ctl *ctl, double thr2)
 {
     if (threadIdx.x == 0 && blockIdx.x == 0) ctl->thr2 = thr2;
 }
 
 // One wavefront (launch with 64 threads).
-__global__ void k_small(Ctl *ctl, int s, int what)
+static __global__ void k_small(Ctl *ctl, int s, int what)
 {
     const int lane = threadIdx.x, ri = lane >> 3, cj = lane & 7;
     if (what == SMALL_CLEAR) {
@@ -1783,7 +1783,7 @@ __global__ __launch_bounds__(BLOCK) void k_fill(int64_t n, T *dst, T v)
 }
 
 // r32 = (float)(r64 * inv_sigma)
-__global__ __launch_bounds__(BLOCK) void k_scale_to_f32(int64_t n, const double *__restrict__ r,
+static __global__ __launch_bounds__(BLOCK) void k_scale_to_f32(int64_t n, const double *__restrict__ r,
                                                         double inv_sigma, float *__restrict__ out)
 {
     for (int64_t e = (int64_t)blockIdx.x * BLOCK + threadIdx.x; e < n;
@@ -1792,7 +1792,7 @@ __global__ __launch_bounds__(BLOCK) void k_scale_to_f32(int64_t n, const double 
 }
 
 // x64 += sigma * (double)d32
-__global__ __launch_bounds__(BLOCK) void k_correct(int64_t n, const float *__restrict__ d,
+static __global__ __launch_bounds__(BLOCK) void k_correct(int64_t n, const float *__restrict__ d,
                                                    double sigma, double *__restrict__ x)
 {
     for (int64_t e = (int64_t)blockIdx.x * BLOCK + threadIdx.x; e < n;
@@ -1938,7 +1938,7 @@ __global__ __launch_bounds__(BLOCK) void k_chol_apply(int64_t ld, T *__restrict_
 }
 
 // Implicit Euler right-hand side b = x inv_dt + f, multiply then add (no contraction).
-__global__ __launch_bounds__(BLOCK) void k_rhs_step(int64_t n, const double *__restrict__ x,
+static __global__ __launch_bounds__(BLOCK) void k_rhs_step(int64_t n, const double *__restrict__ x,
                                                     double inv_dt, const double *__restrict__ f,
                                                     double *__restrict__ b)
 {
@@ -1953,7 +1953,7 @@ __global__ __launch_bounds__(BLOCK) void k_rhs_step(int64_t n, const double *__r
 // Split diagonal preconditioning (Section 5.1's split form, L = R = |D|^(1/2)):
 // e_i = sqrt(|a_ii|) and d_i = 1 / e_i, both correctly rounded.  A row whose
 // diagonal entry is not stored, zero or not finite sets *bad (and gets 1).
-__global__ __launch_bounds__(BLOCK) void k_jacobi_diag(int64_t n, const int32_t *__restrict__ rp,
+static __global__ __launch_bounds__(BLOCK) void k_jacobi_diag(int64_t n, const int32_t *__restrict__ rp,
                                                        const int32_t *__restrict__ ci,
                                                        const double *__restrict__ va,
                                                        double *__restrict__ d,
@@ -1973,7 +1973,7 @@ __global__ __launch_bounds__(BLOCK) void k_jacobi_diag(int64_t n, const int32_t 
 }
 
 // Values of L^-1 A R^-1: out_k = (a_ij d_i) d_j, two roundings, no contraction.
-__global__ __launch_bounds__(BLOCK) void k_jacobi_scale(int64_t n, const int32_t *__restrict__ rp,
+static __global__ __launch_bounds__(BLOCK) void k_jacobi_scale(int64_t n, const int32_t *__restrict__ rp,
                                                         const int32_t *__restrict__ ci,
                                                         const double *__restrict__ va,
                                                         const double *__restrict__ d,
@@ -1991,7 +1991,7 @@ __global__ __launch_bounds__(BLOCK) void k_jacobi_scale(int64_t n, const int32_t
 }
 
 // y = x * w elementwise (y may alias x).
-__global__ __launch_bounds__(BLOCK) void k_mul(int64_t n, const double *x,
+static __global__ __launch_bounds__(BLOCK) void k_mul(int64_t n, const double *x,
                                                const double *__restrict__ w, double *y)
 {
     for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < n;

@@ -1853,16 +1853,6 @@ mstab_status solve_f64(mstab_solver *h, const double *b, double *x, mstab_info *
 // and the launch is synchronized before the results are filed.
 int wg_lc(int ell) { return ell <= 2 ? 2 : (ell <= 4 ? 4 : 8); }
 
-template <int S>
-void wg_launch(int count, int lc, wg::Job *jobs, hipStream_t st)
-{
-    switch (lc) {
-    case 2: hipLaunchKernelGGL((wg::k_solve<S, 2>), dim3(count), dim3(wg::NT), 0, st, jobs); break;
-    case 4: hipLaunchKernelGGL((wg::k_solve<S, 4>), dim3(count), dim3(wg::NT), 0, st, jobs); break;
-    default: hipLaunchKernelGGL((wg::k_solve<S, 8>), dim3(count), dim3(wg::NT), 0, st, jobs); break;
-    }
-}
-
 mstab_status wg_run(mstab_solver *const *h, int count, const double *const *b, double *const *x,
                     mstab_info *info, int extra_checks, int accepted)
 {
@@ -1925,16 +1915,7 @@ mstab_status wg_run(mstab_solver *const *h, int count, const double *const *b, d
         int p1 = p0;
         while (p1 < count && key(order[(size_t)p1]) == kv) ++p1;
         wg::Job *jp = h0->wg_jobs + p0;
-        switch (sv) {
-        case 1: wg_launch<1>(p1 - p0, lc, jp, st); break;
-        case 2: wg_launch<2>(p1 - p0, lc, jp, st); break;
-        case 3: wg_launch<3>(p1 - p0, lc, jp, st); break;
-        case 4: wg_launch<4>(p1 - p0, lc, jp, st); break;
-        case 5: wg_launch<5>(p1 - p0, lc, jp, st); break;
-        case 6: wg_launch<6>(p1 - p0, lc, jp, st); break;
-        case 7: wg_launch<7>(p1 - p0, lc, jp, st); break;
-        default: wg_launch<8>(p1 - p0, lc, jp, st); break;
-        }
+        wg::launch(sv, lc, p1 - p0, jp, st);
         HIPCHK(hipGetLastError());
         p0 = p1;
     }

@@ -130,7 +130,9 @@ __device__ __forceinline__ double rfl(double v)
 }
 
 // S: s; LC: a bound on l (l <= LC <= MAXL) that sizes the per-thread arrays
-template <int S, int LC>
+// PM: where P's entries come from (pval_m: 1 the caller's matrix, 0 the
+// generator), fixed per instantiation so that the row loops do not test it.
+template <int S, int LC, int PM>
 struct Solver {
     // rows a thread loads before it uses any of them (rows NT apart)
     static constexpr int U = S <= 4 ? MSTAB_WG_U : (MSTAB_WG_U + 1) / 2;
@@ -139,9 +141,11 @@ struct Solver {
     int n, ell;
     int64_t ld;
     double *W, *R;
+    PBasis pk;
 
     __device__ Solver(const Job &j, Shared &s) : J(j), sh(s)
     {
+        pk = j.pkey;
         n = (int)j.n;
         ld = j.ld;
         ell = j.ell;
@@ -224,9 +228,9 @@ struct Solver {
                 dst[e] = yv;
                 vals[S] += yv * yv;
 #pragma unroll
-                for (int a = 0; a < S; ++a) vals[a] += pval(pkey, (uint32_t)e, a) * yv;
+                for (int a = 0; a < S; ++a) vals[a] += pval_m<PM>(pkey, (uint32_t)e, a) * yv;
             }
-        } out{resid, dst, J.pkey, vals};
+        } out{resid, dst, pk, vals};
         if (nd > 0 && nd <= 8) {
             if (A.dconst) dia_block<true, U>(A, nd, src, out);
             else dia_block<false, 2>(A, nd, src, out);
@@ -533,7 +537,7 @@ struct Solver {
                     J.x[e] = xa[u];
                     Rc(0)[e] = ra;
 #pragma unroll
-                    for (int a = 0; a < S; ++a) acc[a] += pval(J.pkey, (uint32_t)e, a) * ra;
+                    for (int a = 0; a < S; ++a) acc[a] += pval_m<PM>(pk, (uint32_t)e, a) * ra;
                     acc[S] += ra * ra;
                 }
             }
@@ -571,7 +575,7 @@ struct Solver {
                     Wc(-1, q)[e] = ua;
                     Wc(0, q)[e] = va;
 #pragma unroll
-                    for (int a = 0; a < S; ++a) acc[a] += pval(J.pkey, (uint32_t)e, a) * va;
+                    for (int a = 0; a < S; ++a) acc[a] += pval_m<PM>(pk, (uint32_t)e, a) * va;
                 }
             }
             reduce<S>(acc, S, sh);
@@ -756,12 +760,10 @@ struct Solver {
 #ifndef MSTAB_WG_WAVES
 #define MSTAB_WG_WAVES 2
 #endif
-template <int S, int LC>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MSTAB_WG_WAVES))) void k_solve(Job *jobs)
+template <int S, int LC, int PM>
+__device__ __forceinline__ void solve_job(Job &J, Shared &sh)
 {
-    __shared__ Shared sh;
-    Job &J = jobs[blockIdx.x];
-    Solver<S, LC> E(J, sh);
+    Solver<S, LC, PM> E(J, sh);
     const int n = E.n;
     if (threadIdx.x == 0) {
         sh.flags = 0;
@@ -973,6 +975,22 @@ done:
         J.est_cycle = est_out;
     }
 }
+
+template <int S, int LC>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MSTAB_WG_WAVES))) void k_solve(Job *jobs)
+{
+    __shared__ Shared sh;
+    Job &J = jobs[blockIdx.x];
+    if (J.pkey.m)
+        solve_job<S, LC, 1>(J, sh);
+    else
+        solve_job<S, LC, 0>(J, sh);
+}
+
+// k_solve<s, lc> over count jobs (device array) on st; lc is 2, 4 or 8 (the
+// bound on l the kernel is built for).  Defined in wg.hip, a translation unit
+// of its own.
+void launch(int s, int lc, int count, Job *jobs, hipStream_t st);
 
 }  // namespace wg
 }  // namespace mstab
