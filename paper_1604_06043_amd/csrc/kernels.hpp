@@ -944,6 +944,31 @@ __device__ __forceinline__ void dia_rows_const(int64_t n, const DiaOffsets &doff
     }
 }
 
+// v of lane l - 1 (dpp_shr1) or lane l + 1 (dpp_shl1) across the wavefront
+// (DPP wavefront shifts; the end lane receives 0)
+__device__ __forceinline__ double dpp_shr1(double v)
+{
+    const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(u & 0xFFFFFFFFu), 0x138, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(u >> 32), 0x138, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+__device__ __forceinline__ double dpp_shl1(double v)
+{
+    const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(u & 0xFFFFFFFFu), 0x130, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(u >> 32), 0x130, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+__device__ __forceinline__ float dpp_shr1(float v)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x138, 0xF, 0xF, false));
+}
+__device__ __forceinline__ float dpp_shl1(float v)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x130, 0xF, 0xF, false));
+}
+
 // two-element vectors of the compiler's own (usable with the nontemporal loads)
 typedef double pair_d __attribute__((ext_vector_type(2)));
 typedef float pair_f __attribute__((ext_vector_type(2)));
@@ -966,7 +991,8 @@ __device__ __forceinline__ void row_acc(int64_t r, T yv, T bv, bool resid, PBasi
 
 // Diagonal storage with ND diagonals (7 or 5), two consecutive rows per
 // thread: each even offset's two x values are one 8- or 16-byte load, and the
-// offsets -1, 0, +1 of both rows come from three aligned pairs; with values
+// offsets -1, 0, +1 of both rows come from the thread's own pair and one value
+// of each neighbouring lane's (DPP shifts); with values
 // streamed (CST false) each diagonal's two values are one load too.  Half the
 // memory instructions of one row per thread.  Needs n even, the offsets -1, 0,
 // +1 in the middle and every other offset even (pairs_ok on the host).  Each
@@ -997,10 +1023,20 @@ __device__ __forceinline__ void dia_pairs(int64_t n, const DiaOffsets &doff, con
         const int32_t r0 = 2 * p;
         V2 xo[ND];
         M2 mv[ND];
+        // x[r0 - 1] and x[r0 + 2] are the neighbouring lanes' centre values:
+        // only the wavefront's end lanes load them
+        const int lane = threadIdx.x & 63;
+        T xm1 = (T)0, xp2 = (T)0;
 #pragma unroll
         for (int d = 0; d < ND; ++d) {
             const uint32_t c = (uint32_t)(r0 + off[d]);
-            xo[d] = *reinterpret_cast<const V2 *>(x + (c < (uint32_t)n32 ? c : (uint32_t)r0));
+            if (d == C - 1) {
+                if (lane == 0) xm1 = x[c < (uint32_t)n32 ? c + 1 : (uint32_t)r0];
+            } else if (d == C + 1) {
+                if (lane == 63) xp2 = x[c < (uint32_t)n32 ? c : (uint32_t)r0];
+            } else {
+                xo[d] = *reinterpret_cast<const V2 *>(x + (c < (uint32_t)n32 ? c : (uint32_t)r0));
+            }
             if constexpr (!CST)   // the matrix is streamed once per product: keep it out of the caches
                 mv[d] = __builtin_nontemporal_load(reinterpret_cast<const M2 *>(dval + dia_index(r0, d, ND)));
         }
@@ -1010,6 +1046,13 @@ __device__ __forceinline__ void dia_pairs(int64_t n, const DiaOffsets &doff, con
         V2 bv;
         if (resid) bv = *reinterpret_cast<const V2 *>(b + r0);
         __builtin_amdgcn_sched_barrier(0);
+        {
+            // x[r0 - 1] is the left lane's xo[C].y, x[r0 + 2] the right lane's xo[C].x
+            // (lanes past the end of the rows hold values whose entries the masks drop)
+            const T ly = dpp_shr1(xo[C].y), rx = dpp_shl1(xo[C].x);
+            xo[C - 1].y = lane == 0 ? xm1 : ly;
+            xo[C + 1].x = lane == 63 ? xp2 : rx;
+        }
         T x0[ND], x1[ND];
 #pragma unroll
         for (int d = 0; d < ND; ++d) {
