@@ -93,7 +93,10 @@ constexpr int SPMV_MAX_BLOCKS = MSTAB_SPMV_MAX_BLOCKS;
 // The constant-diagonal product: two workgroups per compute unit, all
 // resident at once, eight rows per thread (24.1 us against 28.0 us with 1024
 // workgroups at 128^3; fewer partials for its final reduction, too).
-constexpr int SPMV_CONST_MAX_BLOCKS = 512;
+#ifndef MSTAB_SPMV_CONST_BLOCKS
+#define MSTAB_SPMV_CONST_BLOCKS 512
+#endif
+constexpr int SPMV_CONST_MAX_BLOCKS = MSTAB_SPMV_CONST_BLOCKS;
 constexpr int VEC_MAX_BLOCKS = 8192;
 constexpr int GRAM_MAX_BLOCKS = 1024;
 constexpr int POLY_MAX_BLOCKS = 1024;
