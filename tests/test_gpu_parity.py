@@ -109,8 +109,11 @@ def test_rhs_step_bit_exact(torch_dev, ms, orc):
 # ---------------------------------------------------------------------------
 # Sparse product and projection: within the rounding bound of the sums
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("name,n", [("c1", 64), ("c2", 12), ("c3", 16), ("c2", 128)])
+@pytest.mark.parametrize("name,n", [("c1", 64), ("c2", 12), ("c3", 16), ("c2", 128), ("c1", 63), ("c2", 13),
+                                    ("c3", 15)])
 def test_spmv_parity(torch_dev, ms, orc, name, n):
+    """Even row counts take the two-rows-per-thread product, odd ones the one-row
+    form; both bit-exact against the oracle's CSR product."""
     torch = torch_dev
     print(f"[spmv {name} n={n}]", flush=True)
     cd = I.config(name, seed=0, n=n)
@@ -122,6 +125,26 @@ def test_spmv_parity(torch_dev, ms, orc, name, n):
     ref = orc.spmv(Ao, x)
     # products rounded, then added in CSR order on both sides: bit-exact
     assert np.array_equal(y.cpu().numpy().view(np.uint64), ref.view(np.uint64))
+
+
+@pytest.mark.parametrize("name,n", [("c1", 64), ("c3", 16)])
+def test_spmv_unaligned_vectors(torch_dev, ms, orc, name, n):
+    """x and y as views one element into larger buffers (8-byte, not 16-byte
+    aligned): the product falls back to one row per thread, still bit-exact,
+    and writes nothing outside y."""
+    torch = torch_dev
+    cd = I.config(name, seed=0, n=n)
+    Ao = orc.assemble_convdiff(cd.dim, cd.n, cd.beta, cd.inv_dt, cd.kappa)
+    Ag = upload_csr(torch, ms, Ao)
+    x = np.random.default_rng(2).standard_normal(Ao.n)
+    xb = torch.zeros(Ao.n + 1, dtype=torch.float64, device="cuda")
+    xb[1:] = dev(torch, x)
+    yb = torch.full((Ao.n + 2,), 5.0, dtype=torch.float64, device="cuda")
+    ms.mstab_spmv(Ag, xb[1:], yb[1:Ao.n + 1])
+    ref = orc.spmv(Ao, x)
+    got = yb.cpu().numpy()
+    assert np.array_equal(got[1:Ao.n + 1].view(np.uint64), ref.view(np.uint64))
+    assert got[0] == 5.0 and got[-1] == 5.0
 
 
 def test_spmv_ragged_rows(torch_dev, ms, orc):
@@ -408,6 +431,8 @@ def teacher_forced(torch, ms, orc, cd, Ao, Ag, s, ell, seed, method, systems, fe
     ("c1", 64, 0, 4, 2, 0, 0, 0), ("c1", 64, 0, 4, 2, 1, 0, 0), ("c1", 64, 0, 8, 4, 0, 0, 0),
     ("c1", 64, 0, 2, 1, 0, 0, 0), ("c1", 64, 1, 3, 3, 0, 0, 0), ("c1", 48, 2, 1, 1, 0, 0, 0),
     ("c2", 16, 3, 4, 2, 0, 0, 0), ("c3", 14, 4, 8, 4, 0, 0, 0),
+    # odd row counts: the product with one row per thread (even ones pair rows)
+    ("c1", 63, 0, 4, 2, 0, 0, 0), ("c2", 15, 3, 4, 2, 0, 0, 0), ("c3", 13, 4, 4, 2, 0, 0, 0),
     # the other fetch policies (Section 5, choosing the fetch point)
     ("c1", 64, 0, 4, 2, 0, 3, 0), ("c1", 64, 0, 4, 2, 0, 2, 0), ("c2", 16, 3, 4, 2, 0, 2, 0),
     ("c1", 64, 0, 4, 2, 0, 5, 0), ("c2", 16, 3, 4, 2, 0, 5, 0), ("c1", 64, 1, 2, 1, 0, 5, 0),
