@@ -101,12 +101,10 @@ def cpu_baseline(cd, s, ell, mvs_per_system, threads):
 
 def class_kernels(cls: str, s: int, ell: int):
     """The kernels of one timing class of the FP64 solver."""
-    return {"spmv": [f"k_spmv_dia_pair<double, {s}, double, true, 7>", f"k_spmv_dia_pair<double, {s}, double, true, 5>",
-                     f"k_spmv_dia_pair<double, {s}, double, false, 7>",
-                     f"k_spmv_dia_pair<double, {s}, double, false, 5>",
-                     f"k_spmv_dia_const<double, {s}, 7>", f"k_spmv_dia_const<double, {s}, 5>",
-                     f"k_spmv_dia<double, {s}, double, true>", f"k_spmv_dia<double, {s}, double, false>",
-                     f"k_spmv<double, {s}, double>"],
+    return {"spmv": [f"k_spmv_dia_pair<double, {s}, double, {c}, {nd}, 0>" for c in ("true", "false") for nd in (7, 5)]
+            + [f"k_spmv_dia_const<double, {s}, {nd}, 0>" for nd in (7, 5)]
+            + [f"k_spmv_dia<double, {s}, double, {c}, 0>" for c in ("true", "false")]
+            + [f"k_spmv<double, {s}, double, 0>"],
             "eta": [f"k_eta<double, {s}>", f"k_eta_low<double, {s}>", f"k_eta_low_gamma<double, {s}>"],
             "gamma": [f"k_gamma<double, {s}>"],
             "poly": [f"k_poly<double, {s}, {ell}>"],

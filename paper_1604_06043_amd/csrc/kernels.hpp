@@ -798,7 +798,9 @@ __device__ __forceinline__ void sell_rows(int64_t n, const int32_t *__restrict__
     }
 }
 
-template <typename T, int S, typename TM = T>
+// PM (all product kernels): where P's entries come from (pval_m), chosen by
+// the host per launch, so that each variant is register-allocated on its own.
+template <typename T, int S, typename TM, int PM>
 __global__ __launch_bounds__(SPMV_BLOCK) void k_spmv(int64_t n, const int32_t *__restrict__ rp,
                                                      const int64_t *__restrict__ slice_ptr,
                                                      const int32_t *__restrict__ scol,
@@ -813,11 +815,7 @@ __global__ __launch_bounds__(SPMV_BLOCK) void k_spmv(int64_t n, const int32_t *_
     double vals[S + 2];
 #pragma unroll
     for (int v = 0; v < S + 2; ++v) vals[v] = 0.0;
-    // the source of P's entries is uniform over the launch: chosen once here
-    if (a.pkey.m)
-        sell_rows<T, S, TM, 1>(n, rp, slice_ptr, scol, sval, x, y, b, resid, a.pkey, vals);
-    else
-        sell_rows<T, S, TM, 0>(n, rp, slice_ptr, scol, sval, x, y, b, resid, a.pkey, vals);
+    sell_rows<T, S, TM, PM>(n, rp, slice_ptr, scol, sval, x, y, b, resid, a.pkey, vals);
     spmv_finalize<S>(vals, ctl, part, stride, a);
 }
 
@@ -1080,7 +1078,7 @@ __device__ __forceinline__ void dia_pairs(int64_t n, const DiaOffsets &doff, con
     }
 }
 
-template <typename T, int S, typename TM, bool CST, int ND>
+template <typename T, int S, typename TM, bool CST, int ND, int PM>
 __global__ __launch_bounds__(SPMV_BLOCK)
 __attribute__((amdgpu_waves_per_eu(sizeof(TM) == 4 ? 8 : 1))) void k_spmv_dia_pair(int64_t n, DiaOffsets doff,
                                                                                     DiaConst cv,
@@ -1097,11 +1095,7 @@ __attribute__((amdgpu_waves_per_eu(sizeof(TM) == 4 ? 8 : 1))) void k_spmv_dia_pa
     double vals[S + 2];
 #pragma unroll
     for (int v = 0; v < S + 2; ++v) vals[v] = 0.0;
-    // the source of P's entries is uniform over the launch: chosen once here
-    if (a.pkey.m)
-        dia_pairs<CST, T, S, TM, ND, 1>(n, doff, cv, mask, dval, x, y, b, resid, a.pkey, vals);
-    else
-        dia_pairs<CST, T, S, TM, ND, 0>(n, doff, cv, mask, dval, x, y, b, resid, a.pkey, vals);
+    dia_pairs<CST, T, S, TM, ND, PM>(n, doff, cv, mask, dval, x, y, b, resid, a.pkey, vals);
     spmv_finalize<S>(vals, ctl, part, stride, a);
 }
 
@@ -1116,7 +1110,7 @@ __attribute__((amdgpu_waves_per_eu(sizeof(TM) == 4 ? 8 : 1))) void k_spmv_dia_pa
 // With FP32 values, 8 wavefronts per SIMD fit without spills; left alone the
 // register allocator settles on 7 for some s, which cost a sequence on the
 // FP32 copy of a 256^3 matrix 12% of its throughput.
-template <typename T, int S, typename TM, bool CST>
+template <typename T, int S, typename TM, bool CST, int PM>
 __global__ __launch_bounds__(SPMV_BLOCK)
 __attribute__((amdgpu_waves_per_eu(sizeof(TM) == 4 ? 8 : 1))) void k_spmv_dia(int64_t n, int nd, DiaOffsets doff,
                                                          DiaConst cv,
@@ -1132,16 +1126,13 @@ __attribute__((amdgpu_waves_per_eu(sizeof(TM) == 4 ? 8 : 1))) void k_spmv_dia(in
     double vals[S + 2];
 #pragma unroll
     for (int v = 0; v < S + 2; ++v) vals[v] = 0.0;
-    // the source of P's entries is uniform over the launch: chosen once here
-    if (a.pkey.m)
-        dia_rows<CST, T, S, TM, 1>(n, nd, doff, cv, mask, dval, x, y, b, resid, a.pkey, vals);
-    else
-        dia_rows<CST, T, S, TM, 0>(n, nd, doff, cv, mask, dval, x, y, b, resid, a.pkey, vals);
+    dia_rows<CST, T, S, TM, PM>(n, nd, doff, cv, mask, dval, x, y, b, resid, a.pkey, vals);
     spmv_finalize<S>(vals, ctl, part, stride, a);
 }
 
-// Constant diagonals, ND of them (5 or 7): the product's common case.
-template <typename T, int S, int ND>
+// Constant diagonals, ND of them (5 or 7), one row per thread (where the
+// paired form does not apply).
+template <typename T, int S, int ND, int PM>
 __global__ __launch_bounds__(SPMV_BLOCK)
 __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 8 : 1))) void k_spmv_dia_const(int64_t n, DiaOffsets doff, DiaConst cv,
                                                                const uint16_t *__restrict__ mask,
@@ -1155,11 +1146,7 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 8 : 1))) void k_spmv_dia_con
     double vals[S + 2];
 #pragma unroll
     for (int v = 0; v < S + 2; ++v) vals[v] = 0.0;
-    // the source of P's entries is uniform over the launch: chosen once here
-    if (a.pkey.m)
-        dia_rows_const<T, S, ND, 1>(n, doff, cv, mask, x, y, b, resid, a.pkey, vals);
-    else
-        dia_rows_const<T, S, ND, 0>(n, doff, cv, mask, x, y, b, resid, a.pkey, vals);
+    dia_rows_const<T, S, ND, PM>(n, doff, cv, mask, x, y, b, resid, a.pkey, vals);
     spmv_finalize<S>(vals, ctl, part, stride, a);
 }
 

@@ -614,16 +614,16 @@ bool pairs_ok(const Sell<TM> &A, const T *x, const T *y, const T *b)
 }
 
 // TM: value type of the stored matrix (T, or float for an FP32 copy used with
-// FP64 vectors)
-template <typename T, typename TM = T>
-void launch_spmv(int grid, hipStream_t stream, const Sell<TM> &A, const T *x, T *y, const T *b,
-                 Ctl *ctl, double *part, SpmvArgs a)
+// FP64 vectors); PM: P from the generator (0) or the caller's matrix (1)
+template <int PM, typename T, typename TM>
+void launch_spmv_pm(int grid, hipStream_t stream, const Sell<TM> &A, const T *x, T *y, const T *b,
+                    Ctl *ctl, double *part, SpmvArgs a)
 {
     if ((A.nd == 7 || A.nd == 5) && pairs_ok(A, x, y, b)) {
         // two rows per thread (constant or streamed diagonals, 7 or 5 of them)
         switch (a.s) {
 #define LAUNCH(S, CST, ND)                                                                            \
-    hipLaunchKernelGGL((k_spmv_dia_pair<T, S, TM, CST, ND>), dim3(grid), dim3(SPMV_BLOCK), 0, stream, \
+    hipLaunchKernelGGL((k_spmv_dia_pair<T, S, TM, CST, ND, PM>), dim3(grid), dim3(SPMV_BLOCK), 0, stream, \
                        A.n, A.doff, A.cv, A.dmask, (const TM *)A.dval, x, y, b, ctl, part, PART_STRIDE, a)
 #define CASE(S)                                                                                       \
     case S:                                                                                           \
@@ -644,10 +644,10 @@ void launch_spmv(int grid, hipStream_t stream, const Sell<TM> &A, const T *x, T 
 #define CASE(S)                                                                                      \
     case S:                                                                                          \
         if (A.nd == 7)                                                                               \
-            hipLaunchKernelGGL((k_spmv_dia_const<T, S, 7>), dim3(grid), dim3(SPMV_BLOCK), 0, stream, \
+            hipLaunchKernelGGL((k_spmv_dia_const<T, S, 7, PM>), dim3(grid), dim3(SPMV_BLOCK), 0, stream, \
                                A.n, A.doff, A.cv, A.dmask, x, y, b, ctl, part, PART_STRIDE, a);      \
         else                                                                                         \
-            hipLaunchKernelGGL((k_spmv_dia_const<T, S, 5>), dim3(grid), dim3(SPMV_BLOCK), 0, stream, \
+            hipLaunchKernelGGL((k_spmv_dia_const<T, S, 5, PM>), dim3(grid), dim3(SPMV_BLOCK), 0, stream, \
                                A.n, A.doff, A.cv, A.dmask, x, y, b, ctl, part, PART_STRIDE, a);      \
         break;
             CASE(0) CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
@@ -660,11 +660,11 @@ void launch_spmv(int grid, hipStream_t stream, const Sell<TM> &A, const T *x, T 
 #define CASE(S)                                                                                   \
     case S:                                                                                       \
         if (A.dconst)                                                                             \
-            hipLaunchKernelGGL((k_spmv_dia<T, S, TM, true>), dim3(grid), dim3(SPMV_BLOCK), 0, stream, \
+            hipLaunchKernelGGL((k_spmv_dia<T, S, TM, true, PM>), dim3(grid), dim3(SPMV_BLOCK), 0, stream, \
                                A.n, A.nd, A.doff, A.cv, A.dmask, (const TM *)A.dval, x, y, b, ctl,    \
                                part, PART_STRIDE, a);                                                 \
         else                                                                                      \
-            hipLaunchKernelGGL((k_spmv_dia<T, S, TM, false>), dim3(grid), dim3(SPMV_BLOCK), 0, stream,\
+            hipLaunchKernelGGL((k_spmv_dia<T, S, TM, false, PM>), dim3(grid), dim3(SPMV_BLOCK), 0, stream,\
                                A.n, A.nd, A.doff, A.cv, A.dmask, (const TM *)A.dval, x, y, b, ctl,    \
                                part, PART_STRIDE, a);                                                 \
         break;
@@ -676,12 +676,22 @@ void launch_spmv(int grid, hipStream_t stream, const Sell<TM> &A, const T *x, T 
     switch (a.s) {
 #define CASE(S)                                                                                \
     case S:                                                                                    \
-        hipLaunchKernelGGL((k_spmv<T, S, TM>), dim3(grid), dim3(SPMV_BLOCK), 0, stream, A.n, A.rp, \
+        hipLaunchKernelGGL((k_spmv<T, S, TM, PM>), dim3(grid), dim3(SPMV_BLOCK), 0, stream, A.n, A.rp, \
                            A.slice_ptr, A.col, A.val, x, y, b, ctl, part, PART_STRIDE, a);     \
         break;
         CASE(0) CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
 #undef CASE
     }
+}
+
+template <typename T, typename TM = T>
+void launch_spmv(int grid, hipStream_t stream, const Sell<TM> &A, const T *x, T *y, const T *b,
+                 Ctl *ctl, double *part, SpmvArgs a)
+{
+    if (a.pkey.m)
+        launch_spmv_pm<1>(grid, stream, A, x, y, b, ctl, part, a);
+    else
+        launch_spmv_pm<0>(grid, stream, A, x, y, b, ctl, part, a);
 }
 
 // The fetch point "shortly before the residual drops" (Section 5, how to
