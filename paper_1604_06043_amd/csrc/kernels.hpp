@@ -775,21 +775,27 @@ __device__ __forceinline__ void sell_rows(int64_t n, const int32_t *__restrict__
         T sum = (T)0;
         for (int32_t j0 = 0; j0 < w; j0 += 8) {
             int32_t c[8];
-            T v[8], xv[8];
+            TM v[8];
+            T xv[8];
 #pragma unroll
             for (int j = 0; j < 8; ++j)
                 if (j0 + j < w) {
                     // the matrix is streamed once per product: keep it out of the caches
                     c[j] = __builtin_nontemporal_load(cp + (int64_t)(j0 + j) * SLICE);
-                    v[j] = (T)__builtin_nontemporal_load(vp + (int64_t)(j0 + j) * SLICE);
+                    v[j] = __builtin_nontemporal_load(vp + (int64_t)(j0 + j) * SLICE);
                 }
+            // every index and value load in flight before the first is used: with
+            // FP32 values the scheduler otherwise converts each value as it
+            // arrives and waits on the loads one pair at a time
+            __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int j = 0; j < 8; ++j)
                 if (j0 + j < w) xv[j] = x[c[j]];
+            __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int j = 0; j < 8; ++j)
                 if (j0 + j < w) {
-                    const T prod = v[j] * xv[j];
+                    const T prod = (T)v[j] * xv[j];
                     const T nsum = sum + prod;
                     sum = (j0 + j < len) ? nsum : sum;
                 }
