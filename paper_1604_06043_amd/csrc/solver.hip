@@ -1896,7 +1896,8 @@ mstab_status wg_run(mstab_solver *const *h, int count, const double *const *b, d
     // job p is handle order[p]: grouped by s and the bound on l
     std::vector<int> order((size_t)count);
     for (int i = 0; i < count; ++i) order[(size_t)i] = i;
-    auto key = [&](int i) { return h[i]->s * 16 + wg_lc(h[i]->ell); };
+    // one launch per kernel variant: s, the bound on l, and the source of P
+    auto key = [&](int i) { return (h[i]->s * 16 + wg_lc(h[i]->ell)) * 2 + (h[i]->pmat ? 1 : 0); };
     std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return key(a) < key(c); });
     std::vector<wg::Job> jobs((size_t)count);
     for (int p = 0; p < count; ++p) {
@@ -1928,7 +1929,7 @@ mstab_status wg_run(mstab_solver *const *h, int count, const double *const *b, d
         int p1 = p0;
         while (p1 < count && key(order[(size_t)p1]) == kv) ++p1;
         wg::Job *jp = h0->wg_jobs + p0;
-        wg::launch(sv, lc, p1 - p0, jp, st);
+        wg::launch(sv, lc, h[order[(size_t)p0]]->pmat != nullptr, p1 - p0, jp, st);
         HIPCHK(hipGetLastError());
         p0 = p1;
     }

@@ -976,21 +976,19 @@ done:
     }
 }
 
-template <int S, int LC>
+// PM: every job of the launch takes P's entries from the generator (0) or
+// from its handle's matrix (1); the host groups the jobs accordingly.
+template <int S, int LC, int PM>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MSTAB_WG_WAVES))) void k_solve(Job *jobs)
 {
     __shared__ Shared sh;
-    Job &J = jobs[blockIdx.x];
-    if (J.pkey.m)
-        solve_job<S, LC, 1>(J, sh);
-    else
-        solve_job<S, LC, 0>(J, sh);
+    solve_job<S, LC, PM>(jobs[blockIdx.x], sh);
 }
 
-// k_solve<s, lc> over count jobs (device array) on st; lc is 2, 4 or 8 (the
-// bound on l the kernel is built for).  Defined in wg.hip, a translation unit
-// of its own.
-void launch(int s, int lc, int count, Job *jobs, hipStream_t st);
+// k_solve<s, lc, pm> over count jobs (device array) on st; lc is 2, 4 or 8
+// (the bound on l the kernel is built for), pm whether the jobs' P is a
+// matrix.  Defined in wg.hip, a translation unit of its own.
+void launch(int s, int lc, bool pm, int count, Job *jobs, hipStream_t st);
 
 }  // namespace wg
 }  // namespace mstab
