@@ -107,7 +107,7 @@ def class_kernels(cls: str, s: int, ell: int):
             + [f"k_spmv<double, {s}, double, 0>"],
             "eta": [f"k_eta<double, {s}>", f"k_eta_low<double, {s}>", f"k_eta_low_gamma<double, {s}>"],
             "gamma": [f"k_gamma<double, {s}>"],
-            "poly": [f"k_poly<double, {s}, {ell}>"],
+            "poly": [f"k_poly<double, {s}, {ell}, 0>"],
             "gram": [f"k_gram<double, {ell}>", f"k_eta_low_gram<double, {s}, {ell}>"]}[cls]
 
 

@@ -997,8 +997,9 @@ __device__ __forceinline__ void row_acc(int64_t r, T yv, T bv, bool resid, PBasi
 // thread: each even offset's two x values are one 8- or 16-byte load, and the
 // offsets -1, 0, +1 of both rows come from the thread's own pair and one value
 // of each neighbouring lane's (DPP shifts); with values
-// streamed (CST false) each diagonal's two values are one load too.  Half the
-// memory instructions of one row per thread.  Needs n even, the offsets -1, 0,
+// streamed (CST false) each diagonal's two values are one load too: five
+// 16-byte x loads per two rows where one row per thread takes fourteen 8-byte
+// ones.  Needs n even, the offsets -1, 0,
 // +1 in the middle and every other offset even (pairs_ok on the host).  Each
 // row's products and sum are those of dia_rows and dia_rows_const, so y is
 // the same bit for bit; the partials add row 2p before row 2p + 1.
@@ -1533,7 +1534,7 @@ __global__ __launch_bounds__(BLOCK) void k_eta_low_gram(int64_t ld, T *__restric
 // with the epilogue P^T r, P^T v_q, ||r||^2, then gamma of level 0 of the next
 // cycle (only when the residual is still above the threshold).
 // ---------------------------------------------------------------------------
-template <typename T, int S, int L>
+template <typename T, int S, int L, int PM>
 __global__ __launch_bounds__(BLOCK) void k_poly(int64_t n, int64_t ld, int ell_rt,
                                                 T *__restrict__ W, T *__restrict__ R,
                                                 T *__restrict__ X, PBasis pkey, Ctl *ctl,
@@ -1552,7 +1553,7 @@ __global__ __launch_bounds__(BLOCK) void k_poly(int64_t n, int64_t ld, int ell_r
          e += (int64_t)gridDim.x * BLOCK) {
         double p[S];
 #pragma unroll
-        for (int a = 0; a < S; ++a) p[a] = (e < n) ? pval(pkey, (uint32_t)e, a) : 0.0;
+        for (int a = 0; a < S; ++a) p[a] = (e < n) ? pval_m<PM>(pkey, (uint32_t)e, a) : 0.0;
         if (L > 0 && S <= 4) {
             // every level of every column of this element in registers first
             constexpr int LL = L > 0 ? L : 1;

@@ -1135,21 +1135,31 @@ struct Engine {
         if (prof) prof->end(slot);
     }
 
-    template <int S>
-    void poly_s(int grid)
+    template <int S, int PM>
+    void poly_sp(int grid)
     {
         switch (ell) {
-#define CASE(L)                                                                              \
-    case L:                                                                                  \
-        hipLaunchKernelGGL((k_poly<T, S, L>), dim3(grid), dim3(BLOCK), 0, stream, n, ld, ell, \
-                           W, R, X, pkey, ctl, part, PART_STRIDE);                           \
+#define CASE(L)                                                                                  \
+    case L:                                                                                      \
+        hipLaunchKernelGGL((k_poly<T, S, L, PM>), dim3(grid), dim3(BLOCK), 0, stream, n, ld, ell, \
+                           W, R, X, pkey, ctl, part, PART_STRIDE);                               \
         break;
             CASE(1) CASE(2) CASE(3) CASE(4)
 #undef CASE
         default:
-            hipLaunchKernelGGL((k_poly<T, S, 0>), dim3(grid), dim3(BLOCK), 0, stream, n, ld, ell,
+            hipLaunchKernelGGL((k_poly<T, S, 0, PM>), dim3(grid), dim3(BLOCK), 0, stream, n, ld, ell,
                                W, R, X, pkey, ctl, part, PART_STRIDE);
         }
+    }
+
+    // P's source (generator or the caller's matrix) picks the kernel variant
+    template <int S>
+    void poly_s(int grid)
+    {
+        if (pkey.m)
+            poly_sp<S, 1>(grid);
+        else
+            poly_sp<S, 0>(grid);
     }
 
     void poly()
