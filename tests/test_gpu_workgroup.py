@@ -146,3 +146,33 @@ def test_workgroup_edge_cases(torch_dev, ms, orc):
     assert float(torch.linalg.norm(xw - x) / torch.linalg.norm(x)) <= 1e-7
     g.close()
     w.close()
+
+
+def test_workgroup_batch_mixes_sources_of_p(torch_dev, ms, orc):
+    """One batch with handles whose P is generated and handles given the same P
+    as an array (one kernel launch for each): every handle's x and MV count
+    equal its solve alone, and the two kinds agree bit for bit."""
+    torch = torch_dev
+    cd = I.config("c1", seed=4, n=40)
+    Ag = gpu_assemble(ms, cd)
+    s, ell = 4, 2
+    P = I.p_dense(3, cd.N, s)
+    f = dev(torch, cd.f)
+    kinds = [{}, {"p_host": P}, {}, {"p_host": P}]
+    solvers = [ms.Solver(Ag, s, ell, p_seed=3, **WG, **k) for k in kinds]
+    xs = [torch.zeros(cd.N, dtype=torch.float64, device="cuda") for _ in kinds]
+    bs = [torch.empty_like(xs[0]) for _ in kinds]
+    ref = ms.Solver(Ag, s, ell, p_seed=3, **WG)
+    xr = torch.zeros(cd.N, dtype=torch.float64, device="cuda")
+    br = torch.empty_like(xr)
+    for step in range(3):
+        for x, b in zip(xs, bs):
+            ms.mstab_rhs_step(x, cd.inv_dt, f, b)
+        infos = ms.solve_batch(solvers, bs, xs)
+        ms.mstab_rhs_step(xr, cd.inv_dt, f, br)
+        ir = ref.solve_next(br, xr)
+        for x, info in zip(xs, infos):
+            np.testing.assert_array_equal(x.cpu().numpy(), xr.cpu().numpy())
+            assert info["mv_total"] == ir["mv_total"], (step, info, ir)
+    for sv in solvers + [ref]:
+        sv.close()
